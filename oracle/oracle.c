@@ -1,0 +1,184 @@
+/*
+ * oracle.c -- plain CPU reference for the sparse matrix-vector product and
+ * for conjugate gradients.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the GPU library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the library's product path never does.  It
+ * shares no code, header or helper with the GPU library.
+ *
+ * Precision: binary64 throughout, compiled with -ffp-contract=off so every
+ * product and sum is rounded separately, in ascending index order, single
+ * threaded.  Obviously correct beats fast here.
+ *
+ * What is computed and where it comes from:
+ *
+ *  oracle_spmv     y = A x for A in CSR (values, column indices, row
+ *                  pointers; binary64 values and 4-byte column indices as in
+ *                  the paper's storage format, Sec. 4.2).  The paper's naive
+ *                  and cached kernels (Secs. 4.3, 5.1, 5.2) are
+ *                  reorganisations of this same per-row sum: reordering
+ *                  keeps the coefficients (Sec. 4.1), padding adds exact
+ *                  zeros (Sec. 4.2, 5.2) and the cache-relative indices only
+ *                  change addressing (Sec. 5.1).  So the oracle is the
+ *                  definition: y_i = sum_k values[k] * x[col_idx[k]].
+ *                  It also returns bound_i = sum_k |values[k]| * |x[col_idx[k]]|,
+ *                  the scale of the dot-product forward error bound
+ *                  (|fl(y_i) - y_i| <= gamma_m * bound_i, Higham, Accuracy and
+ *                  Stability of Numerical Algorithms, Sec. 3.1).
+ *  oracle_spmv_rows  the same for a list of sampled rows only.
+ *  oracle_bsr3_spmm  Y = A X for a 3x3 block-CSR A and k right-hand sides
+ *                  (X row-major, n_cols*3 by k); per scalar row the same sum
+ *                  over the row's stored blocks and their three columns.
+ *  oracle_cg       Hestenes-Stiefel conjugate gradients (Hestenes & Stiefel,
+ *                  J. Res. NBS 49, 1952) for SPD A.  The paper names only "the
+ *                  linear solver" (Sec. 2); this is the textbook method with
+ *                  x0 given, stopping on the recursive residual and confirming
+ *                  with the true residual b - A x before returning.
+ *
+ * Pins (tests, independent of this code): exact rational brute force,
+ * dyadic inputs whose results are exact in binary64, zero row sums of the
+ * pure-Neumann Laplacian, symmetry x.(Ay) = y.(Ax), permutation
+ * equivariance, linearity, a dense library product, CG closed forms and a
+ * dense LAPACK solve.
+ */
+#include <stdint.h>
+#include <math.h>
+
+/* y_i and bound_i for one row */
+static void row_sum(const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+                    const double *x, int32_t i, double *yi, double *bi) {
+    double s = 0.0, b = 0.0;
+    for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        double a = values[k];
+        double xv = x[col_idx[k]];
+        double p = a * xv;
+        s = s + p;
+        b = b + fabs(a) * fabs(xv);
+    }
+    *yi = s;
+    *bi = b;
+}
+
+void oracle_spmv(int32_t n_rows, const int32_t *row_ptr, const int32_t *col_idx,
+                 const double *values, const double *x, double *y, double *bound) {
+    for (int32_t i = 0; i < n_rows; ++i) {
+        double yi, bi;
+        row_sum(row_ptr, col_idx, values, x, i, &yi, &bi);
+        y[i] = yi;
+        if (bound) bound[i] = bi;
+    }
+}
+
+void oracle_spmv_rows(int32_t n_sample, const int32_t *rows, const int32_t *row_ptr,
+                      const int32_t *col_idx, const double *values, const double *x,
+                      double *y, double *bound) {
+    for (int32_t t = 0; t < n_sample; ++t) {
+        double yi, bi;
+        row_sum(row_ptr, col_idx, values, x, rows[t], &yi, &bi);
+        y[t] = yi;
+        if (bound) bound[t] = bi;
+    }
+}
+
+/* Block row br, block k holds the 3x3 block at (br, bcol[k]) stored row-major
+ * in bval[9k .. 9k+9).  Scalar row 3*br + r of Y, column j:
+ *   Y[3br+r][j] = sum_k sum_c bval[9k + 3r + c] * X[3*bcol[k] + c][j]. */
+void oracle_bsr3_spmm(int32_t nb_rows, const int32_t *brow_ptr, const int32_t *bcol,
+                      const double *bval, int32_t k, const double *X, double *Y,
+                      double *bound) {
+    for (int32_t br = 0; br < nb_rows; ++br)
+        for (int32_t r = 0; r < 3; ++r)
+            for (int32_t j = 0; j < k; ++j) {
+                double s = 0.0, b = 0.0;
+                for (int32_t q = brow_ptr[br]; q < brow_ptr[br + 1]; ++q)
+                    for (int32_t c = 0; c < 3; ++c) {
+                        double a = bval[9 * (int64_t)q + 3 * r + c];
+                        double xv = X[(3 * (int64_t)bcol[q] + c) * k + j];
+                        s = s + a * xv;
+                        b = b + fabs(a) * fabs(xv);
+                    }
+                Y[(3 * (int64_t)br + r) * k + j] = s;
+                if (bound) bound[(3 * (int64_t)br + r) * k + j] = b;
+            }
+}
+
+static double dot(int32_t n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s = s + a[i] * b[i];
+    return s;
+}
+
+double oracle_dot(int32_t n, const double *a, const double *b) { return dot(n, a, b); }
+
+/* r = b - A x */
+static void residual(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *values, const double *b, const double *x, double *r) {
+    for (int32_t i = 0; i < n; ++i) {
+        double yi, bi;
+        row_sum(row_ptr, col_idx, values, x, i, &yi, &bi);
+        r[i] = b[i] - yi;
+    }
+}
+
+/*
+ * Conjugate gradients.  Work arrays r, p, q (n each) are supplied by the
+ * caller.  x holds x0 on entry and the last iterate on exit.
+ *
+ *   r = b - A x;  p = r;  rho = r.r
+ *   repeat:  q = A p;  alpha = rho / (p.q)
+ *            x = x + alpha p;  r = r - alpha q;  rho' = r.r
+ *            if sqrt(rho') <= tol ||b||: confirm with the true residual;
+ *               stop if it passes, otherwise continue from r = b - A x
+ *            beta = rho' / rho;  p = r + beta p;  rho = rho'
+ *
+ * Returns 0 when converged, 1 when max_iter was reached, 2 on breakdown
+ * (p.q <= 0 or not finite).  *iters is the number of iterations done and
+ * *rel_res the true relative residual ||b - A x|| / ||b|| at exit.  When
+ * alphas/betas are non-NULL they receive the coefficients of each iteration
+ * (max_iter entries), from which the Lanczos tridiagonal follows.
+ */
+int oracle_cg(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+              const double *b, double *x, double tol, int32_t max_iter,
+              double *r, double *p, double *q,
+              int32_t *iters, double *rel_res, double *alphas, double *betas) {
+    double nb = sqrt(dot(n, b, b));
+    *iters = 0;
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        *rel_res = 0.0;
+        return 0;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    for (int32_t i = 0; i < n; ++i) p[i] = r[i];
+    double rho = dot(n, r, r);
+    int status = 1;
+    if (sqrt(rho) <= tol * nb) status = 0;
+    for (int32_t it = 1; it <= max_iter && status != 0; ++it) {
+        for (int32_t i = 0; i < n; ++i) {
+            double yi, bi;
+            row_sum(row_ptr, col_idx, values, p, i, &yi, &bi);
+            q[i] = yi;
+        }
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = 2; *iters = it - 1; break; }
+        double alpha = rho / pq;
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        double rho_new = dot(n, r, r);
+        *iters = it;
+        if (alphas) alphas[it - 1] = alpha;
+        if (sqrt(rho_new) <= tol * nb) {
+            residual(n, row_ptr, col_idx, values, b, x, r);
+            rho_new = dot(n, r, r);
+            if (sqrt(rho_new) <= tol * nb) { status = 0; if (betas) betas[it - 1] = 0.0; break; }
+        }
+        double beta = rho_new / rho;
+        if (betas) betas[it - 1] = beta;
+        for (int32_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        rho = rho_new;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    *rel_res = sqrt(dot(n, r, r)) / nb;
+    return status;
+}

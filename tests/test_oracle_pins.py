@@ -1,0 +1,319 @@
+"""Pins for the CPU oracle: each check is fixed by mathematics or by an
+independent implementation, never by re-running the oracle's own formula.
+
+* exact rational brute force (fractions.Fraction) on irregular CSR with empty
+  rows, a dense row, duplicate entries and unsorted columns;
+* dyadic inputs whose every product and partial sum is exact in binary64, so
+  the oracle must equal the rational result bit for bit;
+* the pure-Neumann Laplacian (shift 0) annihilates constants, and with shift
+  s, A(c 1) = s c 1;
+* symmetry x.(Ay) = y.(Ax) of the mesh matrices;
+* permutation equivariance (P A P^T)(P x) = P (A x) (reordering keeps the
+  coefficients, paper Sec. 4.1);
+* linearity; scipy's CSR product and numpy's dense product (independent code);
+* CG: one-step closed form on A 1 = s 1, termination in d steps for d
+  distinct eigenvalues, a dense LAPACK solve, Ritz values from the alpha/beta
+  recurrences;
+* planted mistakes (dropped term, wrong sign, transposed operand, shifted
+  column) are caught by the pins above.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import meshgen as mg
+import oracle
+
+
+def exact_rows(A, x):
+    """Exact y_i (Fraction) and exact bound_i for every row."""
+    ys, bs = [], []
+    xf = [Fraction(float(v)) for v in x]
+    for i in range(A.n_rows):
+        s = Fraction(0)
+        b = Fraction(0)
+        for k in range(int(A.row_ptr[i]), int(A.row_ptr[i + 1])):
+            a = Fraction(float(A.values[k]))
+            xv = xf[int(A.col_idx[k])]
+            s += a * xv
+            b += abs(a) * abs(xv)
+        ys.append(s)
+        bs.append(b)
+    return ys, bs
+
+
+def bruteforce_ok(A, x, y) -> bool:
+    """|y_i - exact_i| <= gamma_m * exact_bound_i for every row (m = row length)."""
+    ys, bs = exact_rows(A, x)
+    lens = np.diff(A.row_ptr)
+    for i in range(A.n_rows):
+        g = Fraction(float(oracle.gamma(max(int(lens[i]), 1)))) * Fraction(1000001, 1000000)
+        if abs(Fraction(float(y[i])) - ys[i]) > g * bs[i]:
+            return False
+    return True
+
+
+CASES = [
+    dict(n_rows=40, n_cols=37, seed=1, dense_rows=1),
+    dict(n_rows=64, n_cols=64, seed=2, duplicates=True),
+    dict(n_rows=50, n_cols=30, seed=3, unsorted=True, empty_frac=0.3),
+    dict(n_rows=33, n_cols=60, seed=4, duplicates=True, unsorted=True, dense_rows=2),
+    dict(n_rows=1, n_cols=1, seed=5, empty_frac=0.0),
+    dict(n_rows=20, n_cols=20, seed=6, empty_frac=1.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_spmv_bruteforce_exact(case):
+    A = mg.random_csr(**case)
+    x = np.random.default_rng(case["seed"] + 100).uniform(-1, 1, A.n_cols)
+    y, bound = oracle.spmv(A, x)
+    assert bruteforce_ok(A, x, y)
+    _, bs = exact_rows(A, x)
+    lens = np.maximum(np.diff(A.row_ptr), 1)
+    for i in range(A.n_rows):
+        assert abs(Fraction(float(bound[i])) - bs[i]) <= Fraction(float(oracle.gamma(lens[i]))) * bs[i]
+    # empty rows give exactly zero
+    empty = np.diff(A.row_ptr) == 0
+    assert np.all(y[empty] == 0.0) and np.all(bound[empty] == 0.0)
+
+
+def _dyadic_mats():
+    return [
+        mg.lattice(6, 5, 4, "extras", seed=11, dyadic=True),
+        mg.lattice(5, 5, 5, "stencil27", seed=12, dyadic=True),
+        mg.knn(5, seed=13, dyadic=True),
+        mg.reorder(mg.lattice(6, 6, 3, "extras", seed=14, dyadic=True), "rcm", 14),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_spmv_dyadic_bitwise(idx):
+    A = _dyadic_mats()[idx]
+    x = mg.dyadic_x(A.n_cols, seed=idx)
+    y, _ = oracle.spmv(A, x)
+    ys, _ = exact_rows(A, x)
+    assert all(Fraction(float(y[i])) == ys[i] for i in range(A.n_rows))
+
+
+def test_neumann_rows_sum_to_zero():
+    A = mg.lattice(7, 6, 5, "extras", seed=21, shift=0.0, dyadic=True)
+    y, _ = oracle.spmv(A, np.full(A.n_cols, 0.375))
+    assert np.all(y == 0.0)
+    B = mg.knn(8, seed=22, shift=0.0)
+    y, b = oracle.spmv(B, np.full(B.n_cols, -1.25))
+    assert np.all(np.abs(y) <= 1e-12 * b)
+
+
+def test_shifted_constant_closed_form():
+    A = mg.lattice(7, 6, 5, "stencil27", seed=23, dyadic=True)
+    y, _ = oracle.spmv(A, np.full(A.n_cols, 3.0))
+    assert np.all(y == 3.0 * 2.0 ** -10)
+    B = mg.config0()
+    y, b = oracle.spmv(B, np.full(B.n_cols, 2.0))
+    assert np.all(np.abs(y - 2e-3) <= 1e-12 * b)
+
+
+def test_symmetry_xAy_equals_yAx():
+    for A in (mg.config0(), mg.knn(12, seed=31), mg.lattice(10, 9, 8, "stencil27", seed=32)):
+        x = mg.uniform(A.n_cols, 1, 0)
+        z = mg.uniform(A.n_cols, 2, 0)
+        Az, bz = oracle.spmv(A, z)
+        Ax, _ = oracle.spmv(A, x)
+        lhs = float(np.dot(x, Az))
+        rhs = float(np.dot(z, Ax))
+        scale = float(np.dot(np.abs(x), bz))
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("ordering", ["rcm", "random"])
+def test_permutation_equivariance(ordering):
+    A = mg.lattice(8, 7, 6, "extras", seed=41, dyadic=True)
+    perm = mg.rcm_perm(A) if ordering == "rcm" else mg.random_perm(A.n_rows, 41)
+    B = mg.permute(A, perm)
+    x = mg.dyadic_x(A.n_cols, seed=3)
+    yA, _ = oracle.spmv(A, x)
+    yB, _ = oracle.spmv(B, x[perm])
+    assert np.array_equal(yB, yA[perm])
+    # non-dyadic: within the bound
+    A2 = mg.knn(10, seed=42)
+    perm2 = mg.random_perm(A2.n_rows, 5)
+    B2 = mg.permute(A2, perm2)
+    x2 = mg.uniform(A2.n_cols, 7, 0)
+    y2, b2 = oracle.spmv(A2, x2)
+    yp, _ = oracle.spmv(B2, x2[perm2])
+    assert np.all(np.abs(yp - y2[perm2]) <= 1e-12 * b2[perm2])
+
+
+def test_linearity():
+    A = mg.knn(10, seed=51)
+    x = mg.uniform(A.n_cols, 8, 0)
+    z = mg.uniform(A.n_cols, 9, 0)
+    a = -0.7
+    y1, b1 = oracle.spmv(A, a * x + z)
+    yx, bx = oracle.spmv(A, x)
+    yz, bz = oracle.spmv(A, z)
+    assert np.all(np.abs(y1 - (a * yx + yz)) <= 1e-12 * (abs(a) * bx + bz))
+
+
+@pytest.mark.parametrize("case", CASES[:4])
+def test_against_scipy_csr(case):
+    A = mg.random_csr(**case)
+    x = np.random.default_rng(7).uniform(-1, 1, A.n_cols)
+    S = sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    y, b = oracle.spmv(A, x)
+    m = np.maximum(np.diff(A.row_ptr), 1)
+    assert np.all(np.abs(y - S @ x) <= 2 * oracle.gamma(m) * b + 0.0)
+
+
+def test_spmv_rows_matches_full():
+    A = mg.config0()
+    x = mg.uniform(A.n_cols, 4, 0)
+    y, b = oracle.spmv(A, x)
+    rows = np.array([0, 5, A.n_rows - 1, 1234, 1234], np.int32)
+    ys, bs = oracle.spmv_rows(A, x, rows)
+    assert np.array_equal(ys, y[rows]) and np.array_equal(bs, b[rows])
+
+
+def _dense_bsr(A):
+    n = A.n_rows
+    D = np.zeros((3 * n, 3 * A.n_cols))
+    for br in range(n):
+        for q in range(A.row_ptr[br], A.row_ptr[br + 1]):
+            bc = A.col_idx[q]
+            D[3 * br:3 * br + 3, 3 * bc:3 * bc + 3] += A.values[q]
+    return D
+
+
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_bsr3_against_dense(k):
+    A = mg.bsr3(6, 5, 4, seed=61)
+    X = mg.uniform(3 * A.n_cols * k, 10, 0).reshape(3 * A.n_cols, k)
+    Y, B = oracle.bsr3_spmm(A, X)
+    D = _dense_bsr(A)
+    lens = 3 * np.repeat(np.diff(A.row_ptr), 3)[:, None]
+    assert np.all(np.abs(Y - D @ X) <= 2 * oracle.gamma(lens) * B)
+    # each right-hand side equals the one-column product of that column
+    for j in range(k):
+        yj, _ = oracle.bsr3_spmm(A, X[:, j:j + 1].copy())
+        assert np.array_equal(yj[:, 0], Y[:, j])
+
+
+def test_bsr3_generator_diagonal_dominance():
+    A = mg.bsr3(5, 4, 3, seed=62)
+    D = _dense_bsr(A)
+    off = np.abs(D).sum(axis=1) - np.abs(np.diag(D))
+    assert np.allclose(np.diag(D), 1.0 + off, rtol=1e-13)
+
+
+# --------------------------------------------------------------- CG pins
+
+def test_cg_closed_form_one_step_dyadic():
+    A = mg.lattice(6, 6, 5, "extras", seed=71, dyadic=True)
+    b = np.ones(A.n_rows)
+    r = oracle.cg(A, b, tol=1e-12, max_iter=50)
+    assert r.status == 0 and r.iterations == 1
+    assert np.all(r.x == 2.0 ** 10)
+    assert r.rel_residual == 0.0
+
+
+def test_cg_closed_form_one_step():
+    A = mg.config0()
+    r = oracle.cg(A, np.ones(A.n_rows), tol=1e-10, max_iter=50)
+    assert r.status == 0 and r.iterations == 1
+    assert np.allclose(r.x, 1000.0, rtol=1e-9)
+
+
+def test_cg_terminates_in_d_steps_for_d_eigenvalues():
+    n, evals = 60, np.array([1.0, 2.5, 4.0, 7.0])
+    d = np.repeat(evals, n // len(evals))
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = mg.uniform(n, 3, 0)
+    r = oracle.cg(A, b, tol=1e-12, max_iter=100)
+    assert r.status == 0 and r.iterations <= len(evals)
+    assert np.allclose(r.x, b / d, rtol=1e-11)
+
+
+def _dense(A):
+    S = sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols))
+    return S.toarray()
+
+
+def test_cg_against_dense_lapack_solve():
+    A = mg.lattice(5, 4, 4, "extras", seed=81, shift=0.05)
+    D = _dense(A)
+    b = mg.uniform(A.n_rows, 81, 1)
+    tol = 1e-10
+    r = oracle.cg(A, b, tol=tol, max_iter=1000)
+    xs = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert r.status == 0
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) <= 2 * kappa * tol
+    # self-certification with an independent (dense) residual
+    assert np.linalg.norm(b - D @ r.x) / np.linalg.norm(b) <= tol * 1.01
+    assert abs(r.rel_residual - np.linalg.norm(b - D @ r.x) / np.linalg.norm(b)) <= 1e-3 * tol
+
+
+def test_cg_ritz_values_match_extreme_eigenvalues():
+    A = mg.lattice(6, 5, 5, "stencil27", seed=91, shift=0.1)
+    D = _dense(A)
+    b = mg.uniform(A.n_rows, 91, 1)
+    r = oracle.cg(A, b, tol=1e-14, max_iter=400)
+    k = r.iterations
+    al, be = r.alphas, r.betas
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / al[j] + (be[j - 1] / al[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(be[j]) / al[j]
+    ritz = np.linalg.eigvalsh(T)
+    ev = np.linalg.eigvalsh(D)
+    assert abs(ritz[-1] - ev[-1]) <= 1e-8 * ev[-1]
+    assert abs(ritz[0] - ev[0]) <= 1e-6 * ev[-1]
+
+
+def test_cg_zero_rhs_and_max_iter():
+    A = mg.config0()
+    r = oracle.cg(A, np.zeros(A.n_rows), tol=1e-10)
+    assert r.status == 0 and r.iterations == 0 and np.all(r.x == 0)
+    b = mg.uniform(A.n_rows, 5, 1)
+    r = oracle.cg(A, b, tol=1e-12, max_iter=3)
+    assert r.status == 1 and r.iterations == 3 and r.rel_residual > 1e-12
+
+
+# -------------------------------------------------- planted mistakes
+
+def _mutant_dropped_term(A):
+    keep = np.ones(A.nnz, bool)
+    ends = A.row_ptr[1:][np.diff(A.row_ptr) > 0] - 1
+    keep[ends] = False
+    rp = np.concatenate([[0], np.cumsum(np.diff(A.row_ptr) - (np.diff(A.row_ptr) > 0))]).astype(np.int32)
+    return mg.CSR(A.n_rows, A.n_cols, rp, A.col_idx[keep], A.values[keep])
+
+
+def _mutant_sign(A):
+    v = A.values.copy()
+    v[A.nnz // 2] = -v[A.nnz // 2]
+    return mg.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, v)
+
+
+def _mutant_shifted_col(A):
+    return mg.CSR(A.n_rows, A.n_cols, A.row_ptr, (A.col_idx + 1) % A.n_cols, A.values)
+
+
+def _mutant_transpose(A):
+    S = sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols)).T.tocsr()
+    return mg.CSR(S.shape[0], S.shape[1], S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+
+
+@pytest.mark.parametrize("mutant", [_mutant_dropped_term, _mutant_sign, _mutant_shifted_col,
+                                    _mutant_transpose])
+def test_pins_catch_planted_mistakes(mutant):
+    A = mg.random_csr(48, 48, seed=99, mean_len=5.0, empty_frac=0.05)
+    x = np.random.default_rng(3).uniform(-1, 1, A.n_cols)
+    y_bad, _ = oracle.spmv(mutant(A), x)
+    assert not bruteforce_ok(A, x, y_bad)
+    y_good, _ = oracle.spmv(A, x)
+    assert bruteforce_ok(A, x, y_good)
