@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 CSR SpMV effective HBM bandwidth on the 16M-row mesh matrix.
+
+One step = one y = A x (binary64) over the 252^3 hex-dominant 27-point-subset
+mesh matrix in RCM order (16,003,008 rows, ~270 M stored entries), inputs
+resident in HBM.  `value` = algorithmic bytes / time:
+    B_alg = nnz * (8 + 4) + 4 * (n + 1) + 8 * n_cols + 8 * n
+(values, column indices, row pointers, x read once, y written once).
+
+Besides the JSON fields the driver needs, the line carries:
+  roofline      for the dominant kernel (the row-tile kernel), HBM bound
+  cpu_baseline  the CPU oracle timed on this host on the same matrix
+  extras        FP32 SpMV bandwidth, FP64 vs mixed-precision CG to 1e-10,
+                copy-kernel HBM ceiling (measured outside the timed region)
+Progress goes to stderr; stdout gets exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMV effective HBM GB/s (% of peak) FP64 vs mixed; CG solves/s + p99 latency"
+PEAK_HBM_GBS = 8000.0
+DOMINANT_KERNEL = "k_stream<double, double, double, double, 4096, 0>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_fp64_hex27_16M_rcm_traffic.txt")
+KERNEL_SOURCES = ["paper_2107_12371_amd/csrc/spmv_kernels.hip", "paper_2107_12371_amd/csrc/device.h",
+                  "paper_2107_12371_amd/csrc/launch.h"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(hash_now: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != hash_now:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def alg_bytes(n_rows, n_cols, nnz, val_bytes, x_bytes, y_bytes):
+    return nnz * (val_bytes + 4) + 4 * (n_rows + 1) + x_bytes * n_cols + y_bytes * n_rows
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Average seconds per call of fn() over `steps` calls, HIP events on the
+    current stream (the stream every launch goes to)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def cpu_baseline(A, x, budget_s: float):
+    import oracle
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.spmv(A, x)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 50:
+            break
+    per = el / reps
+    gbs = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8) / per / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full FP64 SpMVs of the same 16M-row matrix, single-threaded plain C "
+                      f"oracle, {per * 1e3:.1f} ms each"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--m", type=int, default=252, help="lattice edge (252 -> 16,003,008 rows)")
+    ap.add_argument("--ordering", default="rcm", choices=["rcm", "natural", "random"])
+    ap.add_argument("--tile-nnz", type=int, default=0)
+    ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32/CG/copy lines")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "row partition with halo exchange is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import meshgen as mg
+    import paper_2107_12371_amd as spmv
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    spmv.lib()
+    t0 = time.perf_counter()
+    A = mg.config2(m=args.m, ordering=args.ordering)
+    log(f"matrix n={A.n_rows} nnz={A.nnz} ({time.perf_counter() - t0:.1f} s)")
+    x_h = mg.uniform(A.n_cols, mg.seed_for(2), 1)
+    params = {"tile_nnz": args.tile_nnz} if args.tile_nnz else None
+    M = spmv.Matrix.from_csr(A, fp32=not args.no_extras, params=params, xcd_remap=not args.no_xcd_remap)
+    info = M.info
+    log(f"resident: {info['device_bytes'] / 1e9:.2f} GB, tiles={info['n_tiles']} "
+        f"(tile_nnz={info['tile_nnz']}, window tiles={info['n_window_tiles']})")
+    x = torch.as_tensor(x_h, device="cuda")
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+
+    B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+    torch.cuda.synchronize()
+    t_step = time_launches(lambda: M.apply(x, y), args.steps, args.warmup, torch)
+    gbs = B / t_step / 1e9
+    log(f"FP64 SpMV: {t_step * 1e3:.4f} ms/step, {gbs:.1f} GB/s ({100 * gbs / PEAK_HBM_GBS:.1f}% of 8 TB/s)")
+
+    traffic = read_traffic(kernel_source_hash())
+    roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": DOMINANT_KERNEL, "alg_bytes_per_launch": B}
+
+    extras = {}
+    if not args.no_extras:
+        x32 = x.float()
+        y32 = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
+        t32 = time_launches(lambda: M.apply_f32(x32, y32), max(10, args.steps // 2), 3, torch)
+        B32 = alg_bytes(A.n_rows, A.n_cols, A.nnz, 4, 4, 4)
+        extras["fp32_spmv_GBs"] = round(B32 / t32 / 1e9, 2)
+        extras["fp32_spmv_ms"] = round(t32 * 1e3, 4)
+        extras["fp32_spmv_frac_of_peak"] = round(B32 / t32 / 1e9 / PEAK_HBM_GBS, 4)
+        extras["fp64_spmv_GFLOPs"] = round(2 * A.nnz / t_step / 1e9, 2)
+        log(f"FP32 SpMV: {t32 * 1e3:.4f} ms, {extras['fp32_spmv_GBs']} GB/s")
+        # HBM ceiling of a plain device copy (1 GiB each way)
+        buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(buf)
+        tc = time_launches(lambda: dst.copy_(buf), 10, 2, torch)
+        extras["copy_GBs_read_plus_write"] = round(2 * buf.numel() * 8 / tc / 1e9, 1)
+        del buf, dst
+        b = torch.as_tensor(mg.uniform(A.n_rows, mg.seed_for(2), 2), device="cuda")
+        for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32)):
+            xs, ci = M.cg(b, tol=1e-10, max_iter=20000, mode=mode, raise_on_error=False)
+            extras[f"cg_{name}_seconds"] = round(ci.seconds, 4)
+            extras[f"cg_{name}_iterations"] = ci.iterations
+            extras[f"cg_{name}_refinements"] = ci.refinements
+            extras[f"cg_{name}_rel_residual"] = ci.rel_residual
+            extras[f"cg_{name}_status"] = ci.status
+            log(f"CG {name}: {ci.seconds:.3f} s, {ci.iterations} it, rel res {ci.rel_residual:.3e}")
+            if name == "fp64":
+                x64 = xs.clone()
+            else:
+                extras["cg_mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs - x64) / torch.linalg.norm(x64))
+            del xs
+        extras["cg_solves_per_s_fp64"] = round(1.0 / extras["cg_fp64_seconds"], 4)
+        extras["cg_solves_per_s_mixed"] = round(1.0 / extras["cg_mixed_seconds"], 4)
+        extras["cg_mixed_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_mixed_seconds"], 3)
+    if args.copy_calibration:
+        buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(buf)
+        for _ in range(3):
+            dst.copy_(buf)
+        torch.cuda.synchronize()
+        del buf, dst
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline ...")
+        cpu = cpu_baseline(A, x_h, args.cpu_seconds)
+        log(f"CPU oracle: {cpu['value']} GB/s")
+
+    M.close()
+    out = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hex27-subset mesh {args.m}^3 ({A.n_rows} rows, {A.nnz} nnz), "
+                               f"{args.ordering} order, FP64 CSR y=Ax",
+                   "rows": A.n_rows, "nnz": A.nnz, "tile_nnz": info["tile_nnz"],
+                   "xcd_remap": not args.no_xcd_remap},
+        "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * spmv.h -- C ABI of the MI355X (gfx950) sparse matrix-vector product and
+ * conjugate-gradient library for finite-volume mesh matrices.
+ *
+ * The operation (paper Sec. 2 and Sec. 4.2): y = A x for a square or
+ * rectangular sparse matrix A stored in CSR -- binary64 coefficients and
+ * 4-byte column indices -- where row i is mesh cell i and its column indices
+ * are the neighbouring cells, so the product gathers x indirectly.  The paper
+ * expresses the call as a task spmv(double *A, int *cols, double *x,
+ * double *b) that reads A, cols and x and produces b (Sec. 3.2); here the
+ * matrix is uploaded once and kept resident (the matrix is constant over the
+ * simulation and its transfer is a preprocessing cost, Secs. 2 and 3.1), and
+ * each product is an asynchronous call on a HIP stream.
+ *
+ * Conventions for every entry point:
+ *  - Return value: SPMV_OK (0) or a negative spmv_status.  A human-readable
+ *    message for the calling thread's last failure is spmv_last_error().
+ *  - Errors detectable on the host (bad sizes, bad CSR, null or aliasing
+ *    pointers) are returned synchronously and nothing is launched.  Device
+ *    failures are returned as SPMV_EDEVICE when the HIP runtime reports them.
+ *  - Vectors (x, y, b, X, Y) are caller-owned DEVICE pointers (for example
+ *    torch tensors' data_ptr()), contiguous, properly aligned for their type.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Products are asynchronous on that stream; CG solves synchronise on it.
+ *  - Matrix handles are immutable after creation: concurrent products with
+ *    one handle on different streams are allowed.  spmv_destroy requires that
+ *    no work using the handle is still in flight.
+ *  - The library holds no global state besides the per-thread error message
+ *    and per-device properties; it needs no init call.
+ */
+#ifndef PAPER_2107_12371_AMD_SPMV_H
+#define PAPER_2107_12371_AMD_SPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spmv_status {
+    SPMV_OK = 0,
+    SPMV_EINVAL = -1,   /* invalid argument or malformed CSR */
+    SPMV_ENOMEM = -2,   /* host or device allocation failed */
+    SPMV_EDEVICE = -3,  /* HIP runtime error */
+    SPMV_ENOTCONV = -4, /* iterative solve did not reach tol within max_iter */
+    SPMV_EBUDGET = -5,  /* serving: request exceeds the device-memory budget */
+    SPMV_ENOTSUP = -6,  /* operation not available for this handle */
+    SPMV_EBREAK = -7    /* CG breakdown: p.q <= 0 or not finite (A not SPD) */
+} spmv_status;
+
+typedef struct spmv_matrix spmv_matrix;
+
+/* ------------------------------------------------------------ create flags */
+#define SPMV_VALUES_FP32 0x1u   /* also keep an FP32 copy of the values */
+#define SPMV_VALUES_BF16 0x2u   /* also keep a BF16 copy of the values */
+#define SPMV_NO_XCD_REMAP 0x4u  /* keep launch order = tile order (no XCD grouping) */
+
+/* Window policy for the LDS x-window path (the GPU counterpart of the
+ * paper's circular vector cache, Sec. 5.1). */
+#define SPMV_WINDOW_AUTO 0  /* use the window where the staged words are few */
+#define SPMV_WINDOW_OFF 1   /* direct L2 gathers everywhere */
+#define SPMV_WINDOW_FORCE 2 /* window wherever it fits in the LDS ring */
+
+/* Analysis parameters; zero fields take the defaults (shown). */
+typedef struct spmv_params {
+    int32_t tile_nnz;      /* max stored entries per row tile: 1024, 2048 or 4096
+                              (0: chosen from nnz; rows longer than this take the
+                              long-row path) */
+    int32_t tile_rows;     /* max rows per tile, <= 512 (0: 512) */
+    int32_t window_mode;   /* SPMV_WINDOW_* (0: AUTO) */
+    int32_t ring_words;    /* LDS ring capacity in x words, a power of two in
+                              [256, 8192] (0: 4096) */
+    int32_t window_block;  /* adjacent tiles walked by one window workgroup
+                              (0: chosen from the tile count) */
+    double window_ratio;   /* AUTO uses the window for a block when staged words
+                              <= window_ratio * stored entries (0: 0.25) */
+} spmv_params;
+
+/* Summary of a handle's analysis plan and resident storage. */
+typedef struct spmv_info {
+    int32_t n_rows, n_cols;
+    int64_t nnz;
+    int32_t tile_nnz, tile_rows;
+    int32_t n_tiles;        /* all row segments (stream tiles + long rows) */
+    int32_t n_stream_tiles; /* tiles on the direct-gather path */
+    int32_t n_long_rows;    /* rows longer than tile_nnz */
+    int32_t n_window_tiles; /* tiles on the LDS-window path */
+    int32_t n_window_blocks;
+    int32_t ring_words;
+    int64_t window_words;   /* x words staged into LDS per product */
+    int32_t has_fp32, has_bf16;
+    int64_t device_bytes;   /* bytes of device memory held by the handle */
+} spmv_info;
+
+/*
+ * spmv_create: validate a host CSR matrix, build the analysis plan and copy
+ * everything the products need to device memory.
+ *   n_rows, n_cols  >= 0
+ *   nnz             stored entries, 0 <= nnz <= 2^31 - 64
+ *   row_ptr         host int32[n_rows + 1]: row_ptr[0] = 0, non-decreasing,
+ *                   row_ptr[n_rows] = nnz
+ *   col_idx         host int32[nnz], each in [0, n_cols); unsorted columns and
+ *                   duplicate (row, col) entries are accepted (all are summed)
+ *   values          host double[nnz] (any values, including NaN/Inf)
+ *   flags           SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP
+ *   params          NULL for defaults
+ *   out             receives the new handle (NULL on failure)
+ * The caller keeps ownership of its arrays.  The device is the current HIP
+ * device.  Errors: SPMV_EINVAL (malformed input), SPMV_ENOMEM, SPMV_EDEVICE.
+ */
+int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                const int32_t *col_idx, const double *values, uint32_t flags,
+                const spmv_params *params, spmv_matrix **out);
+
+/* Release a handle and its device memory (no work may be in flight). NULL is a no-op. */
+int spmv_destroy(spmv_matrix *A);
+
+int spmv_get_info(const spmv_matrix *A, spmv_info *info);
+
+/*
+ * spmv_apply: y = A x in binary64 (paper Secs. 2, 4.2).  x: device
+ * double[n_cols]; y: device double[n_rows], fully overwritten (never read).
+ * x and y must not overlap (SPMV_EINVAL).  Each y_i is summed in a fixed
+ * order that depends only on the handle, so results are bitwise reproducible
+ * and independent of concurrent work.  Per row the result meets
+ * |y_i - exact_i| <= gamma_m * sum_k |a_ik||x_k| (m = row length).
+ */
+int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
+
+/* y = A32 x with the FP32 copy of the values, FP32 x/y, FP32 accumulation
+ * (needs SPMV_VALUES_FP32, else SPMV_ENOTSUP). */
+int spmv_apply_f32(const spmv_matrix *A, const float *x, float *y, void *stream);
+
+/* y = A32 x with FP32 values but binary64 x, y and accumulation
+ * (needs SPMV_VALUES_FP32). */
+int spmv_apply_f32v(const spmv_matrix *A, const double *x, double *y, void *stream);
+
+/* y = A16 x with the BF16 copy of the values, FP32 x/y, FP32 accumulation
+ * (needs SPMV_VALUES_BF16). */
+int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream);
+
+/* ------------------------------------------------------------------- CG */
+#define CG_FP64 0       /* binary64 values, vectors, dots and scalars */
+#define CG_MIXED_FP32 1 /* iterative refinement: binary64 residual r = b - A x
+                           with binary64 values; inner CG with FP32 values,
+                           FP32 vectors and FP32 SpMV accumulation, dots and
+                           scalar recurrences in binary64 (needs SPMV_VALUES_FP32) */
+
+typedef struct cg_info {
+    int32_t iterations;        /* total CG iterations (inner iterations for MIXED) */
+    int32_t refinements;       /* outer refinement steps (MIXED), residual replacements (FP64) */
+    double rel_residual;       /* true ||b - A x||_2 / ||b||_2 in binary64 at exit */
+    double seconds;            /* wall time of the solve on the host clock */
+} cg_info;
+
+/*
+ * cg_solve: solve A x = b for symmetric positive definite A with conjugate
+ * gradients (the paper's "linear solver", Sec. 2; Hestenes-Stiefel 1952).
+ *   b          device double[n]   (A must be square, n = n_rows)
+ *   x          device double[n], in: initial guess, out: last iterate
+ *   tol        stop when ||b - A x||_2 <= tol * ||b||_2 (true residual)
+ *   max_iter   iteration cap (total inner iterations for MIXED)
+ *   mode       CG_FP64 or CG_MIXED_FP32
+ *   info       optional, filled on return (also on ENOTCONV / EBREAK)
+ * b = 0 gives x = 0 and 0 iterations.  Returns SPMV_ENOTCONV when the cap is
+ * reached (x is the last iterate).  Blocks the host until done; work runs on
+ * `stream`, reductions are two-stage in a fixed order (reproducible).
+ */
+int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
+             int32_t mode, cg_info *info, void *stream);
+
+/* Thread-local message describing the calling thread's last failure ("" if none). */
+const char *spmv_last_error(void);
+
+/* ------------------------------------------------ host-only plan inspection */
+/*
+ * spmv_plan_inspect: run the analysis plan on host arrays without touching
+ * the GPU (for tests and tools).  Validates like spmv_create.  Outputs are
+ * optional (NULL skips); pass arrays sized from a first call's *n_tiles_out:
+ *   seg_bound   int32[n_tiles + 1] row boundaries of the tiles
+ *   seg_kind    int32[n_tiles]: 0 direct-gather tile, 1 long row, 2 window tile
+ *   win_off     int32[n_tiles]: first x word staged before the tile (window)
+ *   win_cnt     int32[n_tiles]: number of x words staged (window), else 0
+ *   win_block   int32[n_tiles]: window block id, -1 if not a window tile
+ *   info        plan summary (device_bytes is an estimate)
+ */
+int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                      const int32_t *col_idx, const spmv_params *params, int32_t *n_tiles_out,
+                      int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
+                      int32_t *win_block, spmv_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

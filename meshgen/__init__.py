@@ -247,6 +247,27 @@ def bandwidth(A: CSR) -> tuple[int, int]:
 
 # ----------------------------------------------------------- workloads
 
+def _cached(name: str, build_fn) -> CSR:
+    """Build a workload, or load it from ``$SPMV_CACHE_DIR/<name>.npz`` when
+    that directory is set (lets several processes of one run share a large
+    generated matrix).  Plain arrays only; no pickles."""
+    d = os.environ.get("SPMV_CACHE_DIR")
+    if not d:
+        return build_fn()
+    path = os.path.join(d, name + ".npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return CSR(int(z["n_rows"]), int(z["n_cols"]), z["row_ptr"], z["col_idx"], z["values"],
+                       int(z["block"]))
+    A = build_fn()
+    os.makedirs(d, exist_ok=True)
+    tmp = path + f".tmp{os.getpid()}.npz"
+    np.savez(tmp, n_rows=A.n_rows, n_cols=A.n_cols, row_ptr=A.row_ptr, col_idx=A.col_idx,
+             values=A.values, block=A.block)
+    os.replace(tmp, path)
+    return A
+
+
 def config0(seed: int | None = None, dyadic: bool = False, ordering: str = "rcm") -> CSR:
     """32^3 lattice with 0-4 extras (32768 rows), RCM-ordered."""
     s = seed_for(0) if seed is None else seed
@@ -258,16 +279,16 @@ def config1(ordering: str = "rcm", m: int = 126, seed: int | None = None,
             dyadic: bool = False) -> CSR:
     """Jittered-lattice kNN matrix (m=126: 2,000,376 rows) in RCM or random order."""
     s = seed_for(1) if seed is None else seed
-    A = knn(m, s, dyadic=dyadic)
-    return reorder(A, ordering, s)
+    return _cached(f"cfg1_m{m}_{ordering}_s{s}_d{int(dyadic)}",
+                   lambda: reorder(knn(m, s, dyadic=dyadic), ordering, s))
 
 
 def config2(m: int = 252, ordering: str = "rcm", seed: int | None = None,
             dyadic: bool = False) -> CSR:
     """27-point-subset lattice (m=252: 16,003,008 rows, 7-27 nnz/row), RCM."""
     s = seed_for(2) if seed is None else seed
-    A = lattice(m, m, m, "stencil27", s, dyadic=dyadic)
-    return reorder(A, ordering, s)
+    return _cached(f"cfg2_m{m}_{ordering}_s{s}_d{int(dyadic)}",
+                   lambda: reorder(lattice(m, m, m, "stencil27", s, dyadic=dyadic), ordering, s))
 
 
 def config3(nx: int = 200, ny: int = 200, nz: int = 100, seed: int | None = None) -> CSR:

@@ -1,0 +1,281 @@
+"""MI355X (gfx950) sparse matrix-vector product and CG for finite-volume mesh
+matrices -- thin Python binding over the C ABI in ``include/spmv.h``.
+
+The binding only marshals arguments: every step of a product or a solve runs
+in the HIP library ``libspmv_gfx950.so`` built next to this file.  PyTorch
+provides device memory (tensors' ``data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``); nothing falls back to the CPU.
+If the library cannot be loaded, every call raises.
+
+Entry points mirror the C names: ``spmv_create`` (``Matrix(...)``),
+``spmv_apply`` (``Matrix.apply``), ``spmv_apply_f32`` / ``spmv_apply_f32v`` /
+``spmv_apply_bf16``, ``cg_solve`` (``Matrix.cg``), ``spmv_get_info``
+(``Matrix.info``), ``spmv_plan_inspect`` (``plan_inspect``, host only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmv_gfx950.so")
+
+SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE = 0, -1, -2, -3
+SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
+SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP = 0x1, 0x2, 0x4
+WINDOW_AUTO, WINDOW_OFF, WINDOW_FORCE = 0, 1, 2
+CG_FP64, CG_MIXED_FP32 = 0, 1
+
+EXPORTED = [
+    "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
+    "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
+]
+
+
+class SpmvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class spmv_params(ctypes.Structure):
+    _fields_ = [("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
+                ("window_block", ctypes.c_int32), ("window_ratio", ctypes.c_double)]
+
+
+class spmv_info(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("n_tiles", ctypes.c_int32), ("n_stream_tiles", ctypes.c_int32),
+                ("n_long_rows", ctypes.c_int32), ("n_window_tiles", ctypes.c_int32),
+                ("n_window_blocks", ctypes.c_int32), ("ring_words", ctypes.c_int32),
+                ("window_words", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
+                ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class cg_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def build() -> str:
+    from . import _build
+    return _build.build()
+
+
+def lib():
+    """The loaded HIP library (built first if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_double)
+        L.spmv_create.restype = ctypes.c_int
+        L.spmv_create.argtypes = [i32, i32, i64, vp, vp, vp, u32, ctypes.POINTER(spmv_params),
+                                  ctypes.POINTER(vp)]
+        L.spmv_destroy.restype = ctypes.c_int
+        L.spmv_destroy.argtypes = [vp]
+        L.spmv_get_info.restype = ctypes.c_int
+        L.spmv_get_info.argtypes = [vp, ctypes.POINTER(spmv_info)]
+        for f in ("spmv_apply", "spmv_apply_f32", "spmv_apply_f32v", "spmv_apply_bf16"):
+            getattr(L, f).restype = ctypes.c_int
+            getattr(L, f).argtypes = [vp, vp, vp, vp]
+        L.cg_solve.restype = ctypes.c_int
+        L.cg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(cg_info), vp]
+        L.spmv_last_error.restype = ctypes.c_char_p
+        L.spmv_last_error.argtypes = []
+        L.spmv_plan_inspect.restype = ctypes.c_int
+        L.spmv_plan_inspect.argtypes = [i32, i32, i64, vp, vp, ctypes.POINTER(spmv_params),
+                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp,
+                                        ctypes.POINTER(spmv_info)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != SPMV_OK:
+        msg = lib().spmv_last_error().decode(errors="replace")
+        raise SpmvError(rc, f"{what}: {msg}")
+
+
+def _params(p: dict | None):
+    if not p:
+        return None
+    sp = spmv_params()
+    for k, v in p.items():
+        setattr(sp, k, v)
+    return ctypes.byref(sp)
+
+
+def _host_csr(row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = None if values is None else np.ascontiguousarray(values, dtype=np.float64)
+    return rp, ci, va
+
+
+def _ptr(a):
+    return None if a is None or a.size == 0 else a.ctypes.data
+
+
+def _info_dict(inf: spmv_info) -> dict:
+    return {k: getattr(inf, k) for k, _ in spmv_info._fields_}
+
+
+def plan_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, params: dict | None = None) -> dict:
+    """Run the analysis plan on the host (no GPU).  Returns tile boundaries,
+    kinds (0 direct, 1 long row, 2 window), window offsets/counts/blocks and
+    the summary."""
+    rp, ci, _ = _host_csr(row_ptr, col_idx, None)
+    L = lib()
+    nt = ctypes.c_int32(0)
+    inf = spmv_info()
+    _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
+                               ctypes.byref(nt), None, None, None, None, None, ctypes.byref(inf)),
+           "spmv_plan_inspect")
+    n = nt.value
+    out = {k: np.zeros(n + (1 if k == "seg_bound" else 0), np.int32)
+           for k in ("seg_bound", "seg_kind", "win_off", "win_cnt", "win_block")}
+    _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
+                               ctypes.byref(nt), out["seg_bound"].ctypes.data,
+                               out["seg_kind"].ctypes.data, out["win_off"].ctypes.data,
+                               out["win_cnt"].ctypes.data, out["win_block"].ctypes.data,
+                               ctypes.byref(inf)), "spmv_plan_inspect")
+    out["info"] = _info_dict(inf)
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_vec(t, dtype, n: int, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+
+
+@dataclass
+class CGInfo:
+    iterations: int
+    refinements: int
+    rel_residual: float
+    seconds: float
+    status: int
+
+
+class Matrix:
+    """A resident CSR matrix (``spmv_create``).  Host arrays are copied to the
+    current GPU; the handle is immutable and freed by ``close()``."""
+
+    def __init__(self, n_rows: int, n_cols: int, row_ptr, col_idx, values, *,
+                 fp32: bool = False, bf16: bool = False, xcd_remap: bool = True,
+                 params: dict | None = None):
+        rp, ci, va = _host_csr(row_ptr, col_idx, values)
+        flags = (SPMV_VALUES_FP32 if fp32 else 0) | (SPMV_VALUES_BF16 if bf16 else 0)
+        flags |= 0 if xcd_remap else SPMV_NO_XCD_REMAP
+        h = ctypes.c_void_p()
+        L = lib()
+        _check(L.spmv_create(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _ptr(va), flags,
+                             _params(params), ctypes.byref(h)), "spmv_create")
+        self._h = h
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, int(ci.shape[0])
+
+    @classmethod
+    def from_csr(cls, A, **kw) -> "Matrix":
+        return cls(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.values, **kw)
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("matrix handle is closed")
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        inf = spmv_info()
+        _check(lib().spmv_get_info(self.handle, ctypes.byref(inf)), "spmv_get_info")
+        return _info_dict(inf)
+
+    def _apply(self, fn: str, x, y, xdt, ydt, stream):
+        torch = _torch()
+        _check_vec(x, xdt, self.n_cols, "x")
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=ydt, device=x.device)
+        _check_vec(y, ydt, self.n_rows, "y")
+        _check(getattr(lib(), fn)(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)), fn)
+        return y
+
+    def apply(self, x, y=None, stream=None):
+        """y = A x in binary64 (``spmv_apply``)."""
+        torch = _torch()
+        return self._apply("spmv_apply", x, y, torch.float64, torch.float64, stream)
+
+    def apply_f32(self, x, y=None, stream=None):
+        torch = _torch()
+        return self._apply("spmv_apply_f32", x, y, torch.float32, torch.float32, stream)
+
+    def apply_f32v(self, x, y=None, stream=None):
+        torch = _torch()
+        return self._apply("spmv_apply_f32v", x, y, torch.float64, torch.float64, stream)
+
+    def apply_bf16(self, x, y=None, stream=None):
+        torch = _torch()
+        return self._apply("spmv_apply_bf16", x, y, torch.float32, torch.float32, stream)
+
+    def cg(self, b, x=None, tol: float = 1e-10, max_iter: int = 20000, mode: int = CG_FP64,
+           stream=None, raise_on_error: bool = True):
+        """Solve A x = b (``cg_solve``); returns (x, CGInfo)."""
+        torch = _torch()
+        _check_vec(b, torch.float64, self.n_rows, "b")
+        if x is None:
+            x = torch.zeros(self.n_rows, dtype=torch.float64, device=b.device)
+        _check_vec(x, torch.float64, self.n_rows, "x")
+        inf = cg_info()
+        rc = lib().cg_solve(self.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            tol, max_iter, mode, ctypes.byref(inf), _stream_ptr(stream))
+        if raise_on_error and rc not in (SPMV_OK,):
+            _check(rc, "cg_solve")
+        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().spmv_destroy(self._h), "spmv_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,225 @@
+// C ABI: matrix handles (create / destroy / info) and the product entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+#include "launch.h"
+#include "matrix.h"
+
+namespace spmvlib {
+
+namespace {
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// round-to-nearest-even FP32 -> BF16 bit pattern (NaN kept quiet)
+uint16_t to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    if (!na || !nb) return false;
+    auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? SPMV_ENOMEM : SPMV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T> static int dev_upload(spmv_matrix *A, T **dst, const T *src, size_t n, size_t alloc_n) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (alloc_n ? alloc_n : 1));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    A->allocs.push_back(p);
+    A->bytes += (int64_t)(sizeof(T) * (alloc_n ? alloc_n : 1));
+    if (alloc_n > n) {
+        e = hipMemset(static_cast<T *>(p) + n, 0, sizeof(T) * (alloc_n - n));
+        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    }
+    if (n) {
+        e = hipMemcpy(p, src, sizeof(T) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    *dst = static_cast<T *>(p);
+    return SPMV_OK;
+}
+
+static int check_apply(const spmv_matrix *A, const void *x, size_t xs, const void *y, size_t ys) {
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (A->M.n_rows > 0 && !y) return fail(SPMV_EINVAL, "y is NULL");
+    if (A->M.n_rows > 0 && A->M.nnz > 0 && !x) return fail(SPMV_EINVAL, "x is NULL");
+    if (x && y && overlaps(x, xs * (size_t)A->M.n_cols, y, ys * (size_t)A->M.n_rows))
+        return fail(SPMV_EINVAL, "x and y overlap");
+    return SPMV_OK;
+}
+
+template <typename V, typename X, typename Y, typename Acc>
+static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, void *stream) {
+    clear_error();
+    int rc = check_apply(A, x, sizeof(X), y, sizeof(Y));
+    if (rc) return rc;
+    if (A->M.n_rows == 0) return SPMV_OK;
+    DeviceGuard g(A->device);
+    hipError_t e = launch_spmv<V, X, Y, Acc>(A->M, val, x, y, EPI_PLAIN, nullptr, nullptr, nullptr,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "spmv launch");
+    return SPMV_OK;
+}
+
+}  // namespace spmvlib
+
+using namespace spmvlib;
+
+extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                           const int32_t *col_idx, const double *values, uint32_t flags,
+                           const spmv_params *params, spmv_matrix **out) {
+    clear_error();
+    if (!out) return fail(SPMV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP))
+        return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
+    int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    if (rc) return rc;
+    if (nnz > 0 && !values) return fail(SPMV_EINVAL, "values is NULL with nnz > 0");
+    Plan P;
+    rc = build_plan(n_rows, n_cols, nnz, row_ptr, col_idx, params, P);
+    if (rc) return rc;
+
+    auto *A = new (std::nothrow) spmv_matrix();
+    if (!A) return fail(SPMV_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) {
+        delete A;
+        return hip_fail(e, "hipGetDevice");
+    }
+    DevMatrix &M = A->M;
+    M.n_rows = n_rows;
+    M.n_cols = n_cols;
+    M.nnz = nnz;
+    M.tile_nnz = P.tile_nnz;
+    M.ring_words = P.ring_words;
+    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    const size_t nz = (size_t)nnz, nz_pad = ((nz + 3) & ~(size_t)3) + kPad;
+    rc = dev_upload(A, &M.row_ptr, row_ptr, (size_t)n_rows + 1, (size_t)n_rows + 1);
+    if (!rc) rc = dev_upload(A, &M.col, col_idx, nz, nz_pad);
+    if (!rc) rc = dev_upload(A, &M.val64, values, nz, nz_pad);
+    if (!rc && (flags & SPMV_VALUES_FP32)) {
+        std::vector<float> v32(nz);
+        for (size_t k = 0; k < nz; ++k) v32[k] = (float)values[k];
+        rc = dev_upload(A, &M.val32, v32.data(), nz, nz_pad);
+    }
+    if (!rc && (flags & SPMV_VALUES_BF16)) {
+        std::vector<uint16_t> v16(nz);
+        for (size_t k = 0; k < nz; ++k) v16[k] = to_bf16((float)values[k]);
+        rc = dev_upload(A, &M.val16, v16.data(), nz, nz_pad);
+    }
+    M.n_seg = P.n_seg();
+    if (!rc) rc = dev_upload(A, &M.seg_bound, P.seg_bound.data(), P.seg_bound.size(), P.seg_bound.size());
+    M.n_stream = (int32_t)P.stream_list.size();
+    if (!rc && M.n_stream) rc = dev_upload(A, &M.stream_list, P.stream_list.data(), P.stream_list.size(), 0);
+    M.n_long = (int32_t)P.long_list.size();
+    if (!rc && M.n_long) rc = dev_upload(A, &M.long_list, P.long_list.data(), P.long_list.size(), 0);
+    M.n_blk = P.win_blk_ptr.empty() ? 0 : (int32_t)P.win_blk_ptr.size() - 1;
+    if (!rc && M.n_blk) {
+        std::vector<int32_t> off, cnt;
+        for (int32_t s : P.win_list) {
+            off.push_back(P.win_off[s]);
+            cnt.push_back(P.win_cnt[s]);
+        }
+        rc = dev_upload(A, &M.win_list, P.win_list.data(), P.win_list.size(), 0);
+        if (!rc) rc = dev_upload(A, &M.win_blk_ptr, P.win_blk_ptr.data(), P.win_blk_ptr.size(), 0);
+        if (!rc) rc = dev_upload(A, &M.win_off, off.data(), off.size(), 0);
+        if (!rc) rc = dev_upload(A, &M.win_cnt, cnt.data(), cnt.size(), 0);
+    }
+    if (!rc && M.n_blk) {
+        hipError_t e2 = prepare_window_kernels();
+        if (e2 != hipSuccess) rc = hip_fail(e2, "window kernel LDS opt-in");
+    }
+    if (rc) {
+        for (void *p : A->allocs) (void)hipFree(p);
+        delete A;
+        return rc;
+    }
+    spmv_info &I = A->info;
+    std::memset(&I, 0, sizeof I);
+    I.n_rows = n_rows;
+    I.n_cols = n_cols;
+    I.nnz = nnz;
+    I.tile_nnz = P.tile_nnz;
+    I.tile_rows = P.tile_rows;
+    I.n_tiles = P.n_seg();
+    I.n_stream_tiles = M.n_stream;
+    I.n_long_rows = M.n_long;
+    I.n_window_tiles = (int32_t)P.win_list.size();
+    I.n_window_blocks = M.n_blk;
+    I.ring_words = P.ring_words;
+    I.window_words = P.window_words;
+    I.has_fp32 = M.val32 != nullptr;
+    I.has_bf16 = M.val16 != nullptr;
+    I.device_bytes = A->bytes;
+    *out = A;
+    return SPMV_OK;
+}
+
+extern "C" int spmv_destroy(spmv_matrix *A) {
+    clear_error();
+    if (!A) return SPMV_OK;
+    int rc = SPMV_OK;
+    {
+        DeviceGuard g(A->device);
+        for (void *p : A->allocs) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess && rc == SPMV_OK) rc = hip_fail(e, "hipFree");
+        }
+    }
+    delete A;
+    return rc;
+}
+
+extern "C" int spmv_get_info(const spmv_matrix *A, spmv_info *info) {
+    clear_error();
+    if (!A || !info) return fail(SPMV_EINVAL, "NULL argument");
+    *info = A->info;
+    return SPMV_OK;
+}
+
+extern "C" int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream) {
+    return apply_typed<double, double, double, double>(A, A ? A->M.val64 : nullptr, x, y, stream);
+}
+
+extern "C" int spmv_apply_f32(const spmv_matrix *A, const float *x, float *y, void *stream) {
+    if (A && !A->M.val32) return fail(SPMV_ENOTSUP, "matrix has no FP32 copy (create with SPMV_VALUES_FP32)");
+    return apply_typed<float, float, float, float>(A, A ? A->M.val32 : nullptr, x, y, stream);
+}
+
+extern "C" int spmv_apply_f32v(const spmv_matrix *A, const double *x, double *y, void *stream) {
+    if (A && !A->M.val32) return fail(SPMV_ENOTSUP, "matrix has no FP32 copy (create with SPMV_VALUES_FP32)");
+    return apply_typed<float, double, double, double>(A, A ? A->M.val32 : nullptr, x, y, stream);
+}
+
+extern "C" int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream) {
+    if (A && !A->M.val16) return fail(SPMV_ENOTSUP, "matrix has no BF16 copy (create with SPMV_VALUES_BF16)");
+    return apply_typed<uint16_t, float, float, float>(A, A ? A->M.val16 : nullptr, x, y, stream);
+}

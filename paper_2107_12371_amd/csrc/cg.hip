@@ -1,0 +1,488 @@
+// Conjugate gradients on the GPU (the paper's "linear solver", Sec. 2),
+// Hestenes & Stiefel (1952):
+//
+//   r = b - A x;  p = r;  rho = r.r
+//   repeat:  q = A p;  alpha = rho / (p.q)
+//            x += alpha p;  r -= alpha q;  rho' = r.r
+//            if rho' <= tol^2 ||b||^2: confirm with the true residual b - A x;
+//               stop if it passes, else continue from r = b - A x
+//            beta = rho' / rho;  p = r + beta p;  rho = rho'
+//
+// One iteration is five launches: the SpMV with the p.q partial fused into
+// its epilogue, a one-workgroup reduction that forms alpha on the device,
+// the fused x/r update with the r.r partial, a reduction that forms beta and
+// the convergence flag, and the p update.  All scalars live on the device;
+// every kernel returns at once when the device flag `done` is set, so a
+// captured graph of several iterations can be replayed blindly and the host
+// synchronises once per replay.  Reductions are two-stage with a fixed
+// partition and a fixed order, so a solve is bitwise reproducible.
+//
+// Mixed precision (CG_MIXED_FP32): iterative refinement (Wilkinson; Moler
+// 1967).  The residual r = b - A x is formed with binary64 values and
+// vectors; the correction solve A d = r / ||r|| runs CG with the FP32 copy
+// of A, FP32 vectors and FP32 SpMV accumulation, while its dot products and
+// scalar recurrences stay in binary64; x += ||r|| d in binary64.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "device.h"
+#include "internal.h"
+#include "launch.h"
+#include "matrix.h"
+
+namespace spmvlib {
+
+struct CgState {
+    double rho, rho_new, pq, alpha, beta, bb, tol2, rt2;
+    int32_t iter, max_iter, done, flags;
+};
+
+enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4 };
+enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4 };
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ part, int n, CgState *st, int mode) {
+    __shared__ double sh[kBlock / kWave];
+    if ((mode == R_ALPHA || mode == R_BETA) && st->done) return;
+    double s = 0.0;
+    for (int i = (int)threadIdx.x; i < n; i += kBlock) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+        case R_BB: st->bb = t; break;
+        case R_RHO0: st->rho = t; break;
+        case R_TRUE: st->rt2 = t; break;
+        case R_ALPHA:
+            st->pq = t;
+            if (!(t > 0.0) || !isfinite(t)) {
+                st->flags |= F_BREAKDOWN;
+                st->done = 1;
+            } else {
+                st->alpha = st->rho / t;
+            }
+            break;
+        case R_BETA:
+            st->rho_new = t;
+            st->iter += 1;
+            if (!isfinite(t)) {
+                st->flags |= F_BREAKDOWN;
+                st->done = 1;
+            } else if (t <= st->tol2) {
+                st->flags |= F_CONVERGED;
+                st->done = 1;
+            } else {
+                st->beta = t / st->rho;
+                st->rho = t;
+                if (st->iter >= st->max_iter) {
+                    st->flags |= F_MAXITER;
+                    st->done = 1;
+                }
+            }
+            break;
+    }
+}
+
+// After a failed true-residual check: continue from r = b - A x.
+__global__ void k_replace(CgState *st) {
+    st->beta = st->rt2 / st->rho;
+    st->rho = st->rt2;
+    st->flags = 0;
+    st->done = st->iter >= st->max_iter ? 1 : 0;
+    if (st->done) st->flags = F_MAXITER;
+}
+
+__global__ void k_init_state(CgState *st, double tol, int max_iter) {
+    st->tol2 = tol * tol * st->bb;
+    st->iter = 0;
+    st->max_iter = max_iter;
+    st->flags = 0;
+    st->done = 0;
+    st->alpha = st->beta = st->pq = st->rho_new = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_xr(int n, int chunk, T *__restrict__ x, T *__restrict__ r,
+                                                      const T *__restrict__ p, const T *__restrict__ q,
+                                                      const CgState *st, double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->done) return;
+    const T a = static_cast<T>(st->alpha);
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double d = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const T xi = x[i] + a * p[i];
+        const T ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        d += static_cast<double>(ri) * static_cast<double>(ri);
+    }
+    const double t = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_p(int n, T *__restrict__ p, const T *__restrict__ r,
+                                                     const CgState *st) {
+    if (st->done) return;
+    const T b = static_cast<T>(st->beta);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = r[i] + b * p[i];
+}
+
+// Unconditional p = r + beta p (used after a residual replacement).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_p_force(int n, T *__restrict__ p, const T *__restrict__ r,
+                                                           const CgState *st) {
+    const T b = static_cast<T>(st->beta);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = r[i] + b * p[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot_part(int n, int chunk, const T *__restrict__ a,
+                                                     const T *__restrict__ b, double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double d = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) d += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    const double t = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename D, typename S>
+__global__ __launch_bounds__(kBlock) void k_copy(int n, D *__restrict__ d, const S *__restrict__ s) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = static_cast<D>(s[i]);
+}
+
+template <typename T> __global__ __launch_bounds__(kBlock) void k_zero(int n, T *__restrict__ d) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = T(0);
+}
+
+// r32 = r64 / sqrt(rt2)   (unit-norm right-hand side of the correction solve)
+__global__ __launch_bounds__(kBlock) void k_scale_to_f32(int n, float *__restrict__ d, const double *__restrict__ s,
+                                                         const CgState *st) {
+    const double inv = 1.0 / sqrt(st->rt2);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = static_cast<float>(s[i] * inv);
+}
+
+// x64 += sqrt(rt2) * d32
+__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *__restrict__ x, const float *__restrict__ d,
+                                                           const CgState *st) {
+    const double sc = sqrt(st->rt2);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        x[i] = x[i] + sc * static_cast<double>(d[i]);
+}
+
+// ------------------------------------------------------------ host driver
+
+namespace {
+
+int grid_for(int n) { return std::max(1, std::min(4096, (n + kBlock - 1) / kBlock)); }
+
+struct Buffers {
+    std::vector<void *> dev;
+    void *host = nullptr;
+    ~Buffers() {
+        for (void *p : dev) (void)hipFree(p);
+        if (host) (void)hipHostFree(host);
+    }
+    template <typename T> hipError_t alloc(T **p, size_t n) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(n, 1));
+        if (e == hipSuccess) {
+            dev.push_back(q);
+            *p = static_cast<T *>(q);
+        }
+        return e;
+    }
+};
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+// One CG solve with vectors of type T and values of type V on workspace
+// vectors (x, r, p, q).  On entry x holds x0 and `st->bb` holds ||b||^2.
+template <typename T, typename V> struct CgCore {
+    const DevMatrix &M;
+    const V *val;
+    int n;
+    T *x, *r, *p, *q;
+    double *part_seg, *part_vec;
+    CgState *st;        // device
+    CgState *hst;       // pinned host mirror
+    int n_wg, chunk, graph_iters;
+    hipStream_t s;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+
+    CgCore(const DevMatrix &M_, const V *val_, int n_, hipStream_t s_) : M(M_), val(val_), n(n_), s(s_) {
+        n_wg = std::max(1, std::min(2048, (n + 4 * kBlock - 1) / (4 * kBlock)));
+        chunk = (n + n_wg - 1) / n_wg;
+        graph_iters = n >= (1 << 20) ? 8 : (n >= (1 << 16) ? 16 : 32);
+    }
+    ~CgCore() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+
+    hipError_t iteration(hipStream_t t) {
+        const int *done = &st->done;
+        hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part_seg, M.n_seg, st, (int)R_ALPHA);
+        hipLaunchKernelGGL((k_update_xr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_vec);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part_vec, n_wg, st, (int)R_BETA);
+        hipLaunchKernelGGL((k_update_p<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st);
+        return hipGetLastError();
+    }
+
+    int capture() {
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < graph_iters && e == hipSuccess; ++i) e = iteration(cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return hip_fail(e, "CG graph capture");
+        return SPMV_OK;
+    }
+
+    int read_state() {
+        HIP_TRY(hipMemcpyAsync(hst, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
+
+    // r = b - A x and its squared norm into st->rt2 (values of type V)
+    hipError_t true_residual(const T *b) {
+        hipError_t e = launch_spmv<V, T, T, T>(M, val, x, r, EPI_RESID, b, part_seg, nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_seg, M.n_seg, st, (int)R_TRUE);
+        return hipGetLastError();
+    }
+
+    // Runs CG to tol (relative to sqrt(st->bb)).  Returns SPMV_OK, ENOTCONV or
+    // EBREAK; *iters and *replacements are accumulated.
+    int solve(const T *b, double tol, int max_iter, int *iters, int *replacements) {
+        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol, max_iter);
+        HIP_TRY(true_residual(b));
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_seg, M.n_seg, st, (int)R_RHO0);
+        hipLaunchKernelGGL((k_copy<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r);
+        HIP_TRY(hipGetLastError());
+        int rc = read_state();
+        if (rc) return rc;
+        if (hst->rho <= hst->tol2) return SPMV_OK;
+        if (max_iter <= 0) return SPMV_ENOTCONV;
+        if (!exec) {
+            rc = capture();
+            if (rc) return rc;
+        }
+        int done_iters = 0;
+        for (;;) {
+            HIP_TRY(hipGraphLaunch(exec, s));
+            rc = read_state();
+            if (rc) return rc;
+            done_iters = hst->iter;
+            if (hst->flags & F_BREAKDOWN) {
+                *iters += done_iters;
+                return SPMV_EBREAK;
+            }
+            if (hst->flags & F_CONVERGED) {
+                HIP_TRY(true_residual(b));
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->rt2 <= hst->tol2) break;
+                // recursive residual drifted from the true one: replace it
+                ++*replacements;
+                hipLaunchKernelGGL(k_replace, dim3(1), dim3(1), 0, s, st);
+                hipLaunchKernelGGL((k_update_p_force<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r, st);
+                HIP_TRY(hipGetLastError());
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->flags & F_MAXITER) {
+                    *iters += hst->iter;
+                    return SPMV_ENOTCONV;
+                }
+                continue;
+            }
+            if ((hst->flags & F_MAXITER) || hst->iter >= max_iter) {
+                *iters += hst->iter;
+                return SPMV_ENOTCONV;
+            }
+        }
+        *iters += done_iters;
+        return SPMV_OK;
+    }
+};
+
+template <typename T, typename V>
+int alloc_core(Buffers &B, CgCore<T, V> &C) {
+    HIP_TRY(B.alloc(&C.x, C.n));
+    HIP_TRY(B.alloc(&C.r, C.n));
+    HIP_TRY(B.alloc(&C.p, C.n));
+    HIP_TRY(B.alloc(&C.q, C.n));
+    HIP_TRY(B.alloc(&C.part_seg, (size_t)std::max(C.M.n_seg, 1)));
+    HIP_TRY(B.alloc(&C.part_vec, (size_t)C.n_wg));
+    HIP_TRY(B.alloc(&C.st, 1));
+    return SPMV_OK;
+}
+
+}  // namespace
+
+static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
+                   hipStream_t s) {
+    const DevMatrix &M = A->M;
+    const int n = M.n_rows;
+    Buffers B;
+    CgCore<double, double> C(M, M.val64, n, s);
+    int rc = alloc_core(B, C);
+    if (rc) return rc;
+    HIP_TRY(hipHostMalloc(&B.host, sizeof(CgState), hipHostMallocDefault));
+    C.hst = static_cast<CgState *>(B.host);
+    // ||b||^2
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
+    HIP_TRY(hipGetLastError());
+    rc = C.read_state();
+    if (rc) return rc;
+    if (C.hst->bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    int iters = 0, repl = 0;
+    rc = C.solve(b, tol, max_iter, &iters, &repl);
+    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
+    int rc2;
+    HIP_TRY(C.true_residual(b));
+    if ((rc2 = C.read_state())) return rc2;
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, C.x);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->refinements = repl;
+        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
+    }
+    if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (p.q <= 0 or not finite): matrix not SPD?");
+    return SPMV_OK;
+}
+
+static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
+                    hipStream_t s, double inner_tol) {
+    const DevMatrix &M = A->M;
+    const int n = M.n_rows;
+    Buffers B;
+    // outer (binary64) residual machinery reuses a CgCore for its buffers
+    CgCore<double, double> O(M, M.val64, n, s);
+    CgCore<float, float> I(M, M.val32, n, s);
+    int rc = alloc_core(B, O);
+    if (!rc) rc = alloc_core(B, I);
+    if (rc) return rc;
+    HIP_TRY(hipHostMalloc(&B.host, 2 * sizeof(CgState), hipHostMallocDefault));
+    O.hst = static_cast<CgState *>(B.host);
+    I.hst = O.hst + 1;
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(O.n_wg), dim3(kBlock), 0, s, n, O.chunk, b, b, O.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, O.part_vec, O.n_wg, O.st, (int)R_BB);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, O.x, x);
+    HIP_TRY(hipGetLastError());
+    rc = O.read_state();
+    if (rc) return rc;
+    const double bb = O.hst->bb;
+    if (bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    float *rhs = nullptr;  // the correction solve's right-hand side (kept intact)
+    HIP_TRY(B.alloc(&rhs, (size_t)n));
+    int iters = 0, outer = 0, repl = 0;
+    int status = SPMV_ENOTCONV;
+    for (;;) {
+        HIP_TRY(O.true_residual(b));
+        rc = O.read_state();
+        if (rc) return rc;
+        if (O.hst->rt2 <= tol * tol * bb) {
+            status = SPMV_OK;
+            break;
+        }
+        if (iters >= max_iter || outer >= 200) break;
+        // correction solve A32 d = r / ||r|| from d = 0; its "b" is I.r after scaling
+        hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.q, O.r, O.st);
+        hipLaunchKernelGGL((k_zero<float>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.x);
+        hipLaunchKernelGGL((k_dot_part<float>), dim3(I.n_wg), dim3(kBlock), 0, s, n, I.chunk, I.q, I.q, I.part_vec);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, I.part_vec, I.n_wg, I.st, (int)R_BB);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_copy<float, float>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, rhs, I.q);
+        int it_inner = 0;
+        rc = I.solve(rhs, inner_tol, max_iter - iters, &it_inner, &repl);
+        iters += it_inner;
+        if (rc == SPMV_EBREAK) {
+            status = SPMV_EBREAK;
+            break;
+        }
+        if (rc != SPMV_OK && rc != SPMV_ENOTCONV) return rc;
+        hipLaunchKernelGGL(k_add_correction, dim3(grid_for(n)), dim3(kBlock), 0, s, n, O.x, I.x, O.st);
+        HIP_TRY(hipGetLastError());
+        ++outer;
+    }
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, O.x);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->refinements = outer;
+        info->rel_residual = std::sqrt(O.hst->rt2 / bb);
+    }
+    if (status == SPMV_ENOTCONV) return fail(status, "mixed CG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (status == SPMV_EBREAK) return fail(status, "CG breakdown in the FP32 correction solve");
+    return SPMV_OK;
+}
+
+}  // namespace spmvlib
+
+using namespace spmvlib;
+
+extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
+                        int32_t mode, cg_info *info, void *stream) {
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (info) std::memset(info, 0, sizeof *info);
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
+    if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
+    if (mode != CG_FP64 && mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
+    if (mode == CG_MIXED_FP32 && !A->M.val32)
+        return fail(SPMV_ENOTSUP, "CG_MIXED_FP32 needs the FP32 copy (create with SPMV_VALUES_FP32)");
+    const int n = A->M.n_rows;
+    if (n == 0) return SPMV_OK;
+    if (!b || !x) return fail(SPMV_EINVAL, "b or x is NULL");
+    if (reinterpret_cast<uintptr_t>(b) < reinterpret_cast<uintptr_t>(x) + sizeof(double) * n &&
+        reinterpret_cast<uintptr_t>(x) < reinterpret_cast<uintptr_t>(b) + sizeof(double) * n)
+        return fail(SPMV_EINVAL, "b and x overlap");
+    int dev_prev = -1;
+    if (hipGetDevice(&dev_prev) == hipSuccess && dev_prev != A->device) (void)hipSetDevice(A->device);
+    else dev_prev = -1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc;
+    if (mode == CG_FP64) {
+        rc = cg_fp64(A, b, x, tol, max_iter, info, s);
+    } else {
+        const char *env = std::getenv("SPMV_CG_INNER_TOL");
+        double inner = env ? std::atof(env) : 1e-4;
+        rc = cg_mixed(A, b, x, tol, max_iter, info, s, inner);
+    }
+    if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}

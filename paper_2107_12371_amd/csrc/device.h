@@ -1,0 +1,110 @@
+// Device-side helpers and the resident-matrix layout shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spmvlib {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
+constexpr int kWave = 64;
+constexpr int kEntriesPerLane = 4; // stored entries a lane streams per pass
+constexpr int kPad = 16;           // padding entries after col/val arrays
+
+// Epilogues of the row-tile kernels.
+enum Epilogue : int {
+    EPI_PLAIN = 0,  // y_i = (A x)_i
+    EPI_DOT = 1,    // y_i = (A x)_i and per-tile partial of sum_i x_i y_i (CG's p.q)
+    EPI_RESID = 2   // y_i = b_i - (A x)_i and per-tile partial of sum_i y_i^2
+};
+
+// Resident matrix and its plan in device memory.  Owned by spmv_matrix.
+struct DevMatrix {
+    int32_t n_rows = 0, n_cols = 0;
+    int64_t nnz = 0;
+    int32_t tile_nnz = 0;
+    int32_t *row_ptr = nullptr;      // n_rows + 1
+    int32_t *col = nullptr;          // nnz + padding (padding columns are 0)
+    double *val64 = nullptr;         // nnz + padding
+    float *val32 = nullptr;          // optional FP32 copy
+    uint16_t *val16 = nullptr;       // optional BF16 copy (upper half of an FP32)
+    int32_t n_seg = 0;
+    int32_t *seg_bound = nullptr;    // n_seg + 1
+    int32_t n_stream = 0;
+    int32_t *stream_list = nullptr;  // segment ids on the direct-gather path
+    int32_t n_long = 0;
+    int32_t *long_list = nullptr;    // segment ids of long rows
+    int32_t n_blk = 0;
+    int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_list
+    int32_t *win_list = nullptr;     // window segment ids
+    int32_t *win_off = nullptr;      // per win_list entry: first staged word
+    int32_t *win_cnt = nullptr;      // per win_list entry: staged words
+    int32_t ring_words = 0;
+    bool xcd_remap = true;
+};
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Four consecutive stored values, loaded with non-temporal (streaming) hints
+// so the matrix stream does not evict x from L2.
+template <typename V> struct Val4;
+template <> struct Val4<double> {
+    f64x2 a, b;
+    __device__ __forceinline__ void load(const double *p) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+        b = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p + 2));
+    }
+    __device__ __forceinline__ void zero() { a = f64x2{0.0, 0.0}; b = a; }
+    template <int J> __device__ __forceinline__ double get() const { return J < 2 ? a[J & 1] : b[J & 1]; }
+};
+template <> struct Val4<float> {
+    f32x4 a;
+    __device__ __forceinline__ void load(const float *p) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    }
+    __device__ __forceinline__ void zero() { a = f32x4{0.f, 0.f, 0.f, 0.f}; }
+    template <int J> __device__ __forceinline__ float get() const { return a[J]; }
+};
+template <> struct Val4<uint16_t> {  // bfloat16 bit patterns
+    u32x2 a;
+    __device__ __forceinline__ void load(const uint16_t *p) {
+        a = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    }
+    __device__ __forceinline__ void zero() { a = u32x2{0u, 0u}; }
+    template <int J> __device__ __forceinline__ float get() const {
+        unsigned w = a[J >> 1];
+        unsigned bits = (J & 1) ? (w & 0xffff0000u) : (w << 16);
+        return __uint_as_float(bits);
+    }
+};
+
+__device__ __forceinline__ i32x4 load_col4(const int32_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(p));
+}
+
+// Fixed-shape wavefront sum: a butterfly over lane distances 32..1.  Lane 0's
+// result depends only on the inputs' lane positions, never on timing.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Workgroup sum in a fixed order (waves' lane-0 results added in wave order).
+// Valid in thread 0.  `sh` holds kBlock / kWave doubles.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / kWave; ++i) t += sh[i];
+    return t;
+}
+
+}  // namespace spmvlib

@@ -1,0 +1,48 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "spmv.h"
+
+namespace spmvlib {
+
+// Thread-local error message; returns `code` for convenient `return fail(...)`.
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+// Host-side CSR validation (paper Sec. 4.2 storage: int32 columns, row
+// pointers).  Returns SPMV_OK or SPMV_EINVAL with a message.
+int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                 const int32_t *col_idx);
+
+// Segment kinds of the analysis plan.
+enum SegKind : int32_t { SEG_STREAM = 0, SEG_LONG = 1, SEG_WINDOW = 2 };
+
+// Analysis plan built once per matrix (the matrix is constant, so its
+// preprocessing is amortised -- paper Sec. 2).
+struct Plan {
+    int32_t n_rows = 0, n_cols = 0;
+    int64_t nnz = 0;
+    int32_t tile_nnz = 0, tile_rows = 0;
+    int32_t window_mode = 0, ring_words = 0, window_block = 0;
+    double window_ratio = 0.0;
+    std::vector<int32_t> seg_bound;  // n_seg + 1 row boundaries
+    std::vector<int32_t> seg_kind;   // SegKind per segment
+    std::vector<int32_t> win_off;    // first staged x word (window segments)
+    std::vector<int32_t> win_cnt;    // staged x words (window segments)
+    std::vector<int32_t> win_block;  // window block id or -1
+    std::vector<int32_t> stream_list;  // segment ids on the direct-gather path
+    std::vector<int32_t> long_list;    // segment ids of long rows
+    std::vector<int32_t> win_list;     // window segment ids, grouped by block
+    std::vector<int32_t> win_blk_ptr;  // n_blocks + 1 offsets into win_list
+    int64_t window_words = 0;
+    int32_t n_seg() const { return (int32_t)seg_kind.size(); }
+};
+
+int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+               const int32_t *col_idx, const spmv_params *params, Plan &plan);
+
+}  // namespace spmvlib

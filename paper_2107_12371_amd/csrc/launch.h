@@ -1,0 +1,43 @@
+// Kernel argument blocks and launcher declarations (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.h"
+
+namespace spmvlib {
+
+template <typename V, typename X, typename Y> struct SpmvArgs {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const V *val;
+    const X *x;
+    Y *y;
+    const Y *b;           // EPI_RESID: right-hand side
+    double *part;         // EPI_DOT / EPI_RESID: one partial per segment
+    const int32_t *seg_bound;
+    const int32_t *list;  // segment ids (direct / long) or window segment ids
+    int32_t n_list;
+    int32_t per_xcd;      // > 0: XCD-grouped tile order (grid = 8 * per_xcd)
+    const int *done;      // optional: non-zero makes the launch a no-op (CG)
+    const int32_t *win_blk_ptr;
+    const int32_t *win_off;
+    const int32_t *win_cnt;
+    int32_t ring_words;
+};
+
+// y = A x over all segments of M (direct tiles, long rows, window blocks),
+// launched on `st`.  V: stored value type (double, float, uint16_t = bf16),
+// X/Y: vector types, A: accumulation type.  `part` must hold M.n_seg doubles
+// when epi != EPI_PLAIN.
+template <typename V, typename X, typename Y, typename A>
+hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
+                       double *part, const int *done, hipStream_t st);
+
+// Opts every window-kernel instantiation into up to 8192 ring words of
+// dynamic LDS.  Called once when a matrix with window blocks is created.
+hipError_t prepare_window_kernels();
+
+}  // namespace spmvlib

@@ -1,0 +1,228 @@
+// Host-side analysis plan: row tiles, long-row bin and the LDS x-window
+// metadata.  Pure C++ (no HIP calls) so it runs and is tested on the CPU.
+//
+// Tiles.  Rows are cut into consecutive tiles holding at most tile_nnz
+// stored entries and tile_rows rows; one workgroup streams a tile's values
+// and column indices with coalesced loads (the paper's slices of S rows,
+// Sec. 5.1, sized here for a 256-lane workgroup instead of an FPGA pipeline).
+// A row longer than tile_nnz becomes its own segment on the long-row path.
+//
+// Window.  For each tile the first and last column it touches are the
+// paper's col_start_i / col_end_i (Sec. 5.1).  A window workgroup walks a
+// block of adjacent tiles in order and keeps x[...] in an LDS ring of
+// ring_words entries (word w in slot w mod ring_words, the paper's circular
+// list).  Before tile i it stages only the words not yet resident: the
+// range (colend_{i-1}, colend_i], i.e. count_i = colend_i - colend_{i-1} words
+// starting at offset colend_{i-1} + 1, the paper's per-block metadata
+// (Sec. 5.1; we read "offset_i = colend_{i-1}" as the last resident word, so
+// loading starts one past it).  When a tile needs a word that has already
+// been overwritten (or lies below the block's first tile), the ring restarts
+// with the tile's full range [col_start_i, col_end_i].
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace spmvlib {
+
+static thread_local char g_err[512];
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+const char *last_error() { return g_err; }
+
+int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                 const int32_t *col_idx) {
+    if (n_rows < 0 || n_cols < 0) return fail(SPMV_EINVAL, "negative dimension (%d x %d)", n_rows, n_cols);
+    if (nnz < 0 || nnz > (int64_t)INT32_MAX - 64)
+        return fail(SPMV_EINVAL, "nnz = %lld outside [0, 2^31 - 64]", (long long)nnz);
+    if (!row_ptr) return fail(SPMV_EINVAL, "row_ptr is NULL");
+    if (nnz > 0 && !col_idx) return fail(SPMV_EINVAL, "col_idx is NULL with nnz > 0");
+    if (row_ptr[0] != 0) return fail(SPMV_EINVAL, "row_ptr[0] = %d, expected 0", row_ptr[0]);
+    for (int32_t i = 0; i < n_rows; ++i)
+        if (row_ptr[i + 1] < row_ptr[i])
+            return fail(SPMV_EINVAL, "row_ptr decreases at row %d (%d -> %d)", i, row_ptr[i], row_ptr[i + 1]);
+    if ((int64_t)row_ptr[n_rows] != nnz)
+        return fail(SPMV_EINVAL, "row_ptr[n_rows] = %d differs from nnz = %lld", row_ptr[n_rows], (long long)nnz);
+    for (int64_t k = 0; k < nnz; ++k)
+        if (col_idx[k] < 0 || col_idx[k] >= n_cols)
+            return fail(SPMV_EINVAL, "col_idx[%lld] = %d outside [0, %d)", (long long)k, col_idx[k], n_cols);
+    return SPMV_OK;
+}
+
+static int default_tile_nnz(int64_t nnz) {
+    // Enough tiles to give every CU several workgroups (256 CUs on MI355X).
+    if (nnz >= (int64_t)4096 * 4096) return 4096;
+    if (nnz >= (int64_t)2048 * 2048) return 2048;
+    return 1024;
+}
+
+int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+               const int32_t *col_idx, const spmv_params *params, Plan &P) {
+    spmv_params p{};
+    if (params) p = *params;
+    int tnz = p.tile_nnz ? p.tile_nnz : default_tile_nnz(nnz);
+    if (tnz != 1024 && tnz != 2048 && tnz != 4096)
+        return fail(SPMV_EINVAL, "tile_nnz = %d must be 1024, 2048 or 4096", tnz);
+    int trows = p.tile_rows ? p.tile_rows : 512;
+    if (trows < 1 || trows > 512) return fail(SPMV_EINVAL, "tile_rows = %d outside [1, 512]", trows);
+    int wmode = p.window_mode;
+    if (wmode < SPMV_WINDOW_AUTO || wmode > SPMV_WINDOW_FORCE)
+        return fail(SPMV_EINVAL, "window_mode = %d unknown", wmode);
+    int ring = p.ring_words ? p.ring_words : 4096;
+    if (ring < 256 || ring > 8192 || (ring & (ring - 1)))
+        return fail(SPMV_EINVAL, "ring_words = %d must be a power of two in [256, 8192]", ring);
+    double ratio = p.window_ratio > 0.0 ? p.window_ratio : 0.25;
+    if (p.window_block < 0) return fail(SPMV_EINVAL, "window_block = %d < 0", p.window_block);
+
+    P = Plan{};
+    P.n_rows = n_rows; P.n_cols = n_cols; P.nnz = nnz;
+    P.tile_nnz = tnz; P.tile_rows = trows; P.window_mode = wmode; P.ring_words = ring;
+    P.window_ratio = ratio;
+
+    // ---- segmentation into stream tiles and long rows
+    int32_t r = 0;
+    while (r < n_rows) {
+        int64_t len = (int64_t)row_ptr[r + 1] - row_ptr[r];
+        if (len > tnz) {
+            P.seg_bound.push_back(r);
+            P.seg_kind.push_back(SEG_LONG);
+            ++r;
+            continue;
+        }
+        int32_t r1 = r;
+        int64_t acc = 0;
+        while (r1 < n_rows && r1 - r < trows) {
+            int64_t l = (int64_t)row_ptr[r1 + 1] - row_ptr[r1];
+            if (l > tnz || acc + l > tnz) break;
+            acc += l;
+            ++r1;
+        }
+        P.seg_bound.push_back(r);
+        P.seg_kind.push_back(SEG_STREAM);
+        r = r1;
+    }
+    P.seg_bound.push_back(n_rows);
+    const int32_t nseg = P.n_seg();
+    P.win_off.assign(nseg, 0);
+    P.win_cnt.assign(nseg, 0);
+    P.win_block.assign(nseg, -1);
+
+    // ---- window analysis
+    if (wmode != SPMV_WINDOW_OFF && nseg > 0) {
+        std::vector<int32_t> cmin(nseg, INT32_MAX), cmax(nseg, -1);
+        int32_t n_stream = 0;
+        for (int32_t s = 0; s < nseg; ++s) {
+            if (P.seg_kind[s] != SEG_STREAM) continue;
+            ++n_stream;
+            for (int64_t k = row_ptr[P.seg_bound[s]]; k < row_ptr[P.seg_bound[s + 1]]; ++k) {
+                cmin[s] = std::min(cmin[s], col_idx[k]);
+                cmax[s] = std::max(cmax[s], col_idx[k]);
+            }
+        }
+        int B = p.window_block;
+        if (B == 0) B = std::max(1, std::min(64, n_stream / 512));
+        P.window_block = B;
+        int32_t blk_id = 0;
+        int32_t s = 0;
+        while (s < nseg) {
+            if (P.seg_kind[s] != SEG_STREAM) { ++s; continue; }
+            // a chunk of up to B consecutive stream segments
+            int32_t e = s;
+            while (e < nseg && e - s < B && P.seg_kind[e] == SEG_STREAM) ++e;
+            bool ok = true;
+            int64_t staged = 0, entries = 0;
+            int64_t H = -1, vlo = 0;
+            bool first = true;
+            std::vector<int32_t> off(e - s, 0), cnt(e - s, 0);
+            for (int32_t t = s; t < e; ++t) {
+                int64_t ent = (int64_t)row_ptr[P.seg_bound[t + 1]] - row_ptr[P.seg_bound[t]];
+                entries += ent;
+                if (ent == 0) continue;
+                int64_t lo = cmin[t], hi = cmax[t], span = hi - lo + 1;
+                if (span > ring) { ok = false; break; }
+                int64_t Hn = std::max(H, hi);
+                if (!first && lo >= std::max(vlo, Hn - ring + 1)) {
+                    off[t - s] = (int32_t)(H + 1);
+                    cnt[t - s] = (int32_t)(Hn - H);
+                    H = Hn;
+                } else {
+                    off[t - s] = (int32_t)lo;
+                    cnt[t - s] = (int32_t)span;
+                    vlo = lo;
+                    H = hi;
+                    first = false;
+                }
+                staged += cnt[t - s];
+            }
+            bool use = ok && !first &&
+                       (wmode == SPMV_WINDOW_FORCE || (double)staged <= ratio * (double)entries);
+            if (use) {
+                P.win_blk_ptr.push_back((int32_t)P.win_list.size());
+                for (int32_t t = s; t < e; ++t) {
+                    P.seg_kind[t] = SEG_WINDOW;
+                    P.win_off[t] = off[t - s];
+                    P.win_cnt[t] = cnt[t - s];
+                    P.win_block[t] = blk_id;
+                    P.win_list.push_back(t);
+                }
+                P.window_words += staged;
+                ++blk_id;
+            }
+            s = e;
+        }
+        if (!P.win_list.empty()) P.win_blk_ptr.push_back((int32_t)P.win_list.size());
+    }
+    for (int32_t s = 0; s < nseg; ++s) {
+        if (P.seg_kind[s] == SEG_STREAM) P.stream_list.push_back(s);
+        else if (P.seg_kind[s] == SEG_LONG) P.long_list.push_back(s);
+    }
+    return SPMV_OK;
+}
+
+}  // namespace spmvlib
+
+extern "C" const char *spmv_last_error(void) { return spmvlib::last_error(); }
+
+extern "C" int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                                 const int32_t *col_idx, const spmv_params *params, int32_t *n_tiles_out,
+                                 int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
+                                 int32_t *win_block, spmv_info *info) {
+    using namespace spmvlib;
+    clear_error();
+    int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    if (rc) return rc;
+    Plan P;
+    rc = build_plan(n_rows, n_cols, nnz, row_ptr, col_idx, params, P);
+    if (rc) return rc;
+    const int32_t ns = P.n_seg();
+    if (n_tiles_out) *n_tiles_out = ns;
+    if (seg_bound) std::memcpy(seg_bound, P.seg_bound.data(), sizeof(int32_t) * (ns + 1));
+    if (seg_kind && ns) std::memcpy(seg_kind, P.seg_kind.data(), sizeof(int32_t) * ns);
+    if (win_off && ns) std::memcpy(win_off, P.win_off.data(), sizeof(int32_t) * ns);
+    if (win_cnt && ns) std::memcpy(win_cnt, P.win_cnt.data(), sizeof(int32_t) * ns);
+    if (win_block && ns) std::memcpy(win_block, P.win_block.data(), sizeof(int32_t) * ns);
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->n_rows = n_rows; info->n_cols = n_cols; info->nnz = nnz;
+        info->tile_nnz = P.tile_nnz; info->tile_rows = P.tile_rows;
+        info->n_tiles = ns;
+        info->n_stream_tiles = (int32_t)P.stream_list.size();
+        info->n_long_rows = (int32_t)P.long_list.size();
+        info->n_window_tiles = (int32_t)P.win_list.size();
+        info->n_window_blocks = P.win_blk_ptr.empty() ? 0 : (int32_t)P.win_blk_ptr.size() - 1;
+        info->ring_words = P.ring_words;
+        info->window_words = P.window_words;
+    }
+    return SPMV_OK;
+}

@@ -1,0 +1,285 @@
+// Sparse matrix-vector product kernels for gfx950 (CDNA4).
+//
+// y_i = sum_{k in row i} a_k * x[c_k]   (paper Sec. 2 and 4.2: FP64 values,
+// 4-byte column indices; the column index must be read before the x
+// element it selects, Sec. 4.3).  The bandwidth-bound stream is the matrix
+// (12 bytes per stored entry in FP64); x is gathered through L2/MALL or,
+// on the window path, from an LDS ring that plays the part of the paper's
+// circular BRAM vector cache (Sec. 5.1).
+//
+// Three kernels share one row-tile scheme:
+//  * k_stream  (direct gathers): one workgroup per row tile.  Pass 1 streams
+//    the tile's values and column indices with 16-byte non-temporal loads,
+//    4 consecutive entries per lane, all passes issued before any gather
+//    so many loads are in flight; it gathers x and writes each product into
+//    LDS.  Pass 2 sums each row's products in ascending entry order (one
+//    lane per row) and writes y.  Tiles are assigned so that each XCD (its
+//    own L2) walks a contiguous range of rows, which keeps the band of x it
+//    needs resident in that L2.
+//  * k_long    one workgroup per row longer than a tile: strided partial sums
+//    per lane and a fixed-shape workgroup reduction.
+//  * k_window  one workgroup walks a block of adjacent tiles in order,
+//    staging into an LDS ring only the x words the previous tiles did not
+//    bring in, then gathers x from LDS.
+// Every y_i is summed in an order fixed by the plan alone, so results are
+// bitwise reproducible and do not depend on what else runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "launch.h"
+
+namespace spmvlib {
+
+template <typename A, typename V> __device__ __forceinline__ A to_acc(V v) { return static_cast<A>(v); }
+template <> __device__ __forceinline__ float to_acc<float, uint16_t>(uint16_t v) {
+    return __uint_as_float(static_cast<unsigned>(v) << 16);
+}
+
+// Pass 1: products of the tile's entries [s, e) into prod[k - s4], s4 = s & ~3.
+template <typename V, typename X, typename A, int NT, class Gather>
+__device__ __forceinline__ void tile_products(const int32_t *__restrict__ col, const V *__restrict__ val,
+                                              int s, int e, A *__restrict__ prod, Gather gather) {
+    constexpr int kPass = kEntriesPerLane * kBlock;
+    constexpr int kMaxPass = (NT + 3 + kPass - 1) / kPass;
+    const int s4 = s & ~3;
+    const int npass = (e - s4 + kPass - 1) / kPass;
+    const int lane0 = kEntriesPerLane * threadIdx.x;
+    i32x4 c[kMaxPass];
+    Val4<V> v[kMaxPass];
+#pragma unroll
+    for (int p = 0; p < kMaxPass; ++p) {
+        const int k = s4 + p * kPass + lane0;
+        c[p] = i32x4{0, 0, 0, 0};
+        v[p].zero();
+        if (p < npass && k < e) {
+            c[p] = load_col4(col + k);
+            v[p].load(val + k);
+        }
+    }
+    A xv[kMaxPass][4];
+#pragma unroll
+    for (int p = 0; p < kMaxPass; ++p) {
+        const int k = s4 + p * kPass + lane0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool ok = p < npass && k + j >= s && k + j < e;
+            xv[p][j] = ok ? static_cast<A>(gather(c[p][j])) : A(0);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kMaxPass; ++p) {
+        const int k = s4 + p * kPass + lane0;
+        if (p < npass && k < e) {
+            A *d = prod + (k - s4);
+            d[0] = to_acc<A>(v[p].template get<0>()) * xv[p][0];
+            d[1] = to_acc<A>(v[p].template get<1>()) * xv[p][1];
+            d[2] = to_acc<A>(v[p].template get<2>()) * xv[p][2];
+            d[3] = to_acc<A>(v[p].template get<3>()) * xv[p][3];
+        }
+    }
+}
+
+// Pass 2: per-row sums of the tile's rows [r0, r1), epilogue, optional partial.
+template <typename X, typename Y, typename A, int EPI>
+__device__ __forceinline__ void tile_rows(const int32_t *__restrict__ row_ptr, int r0, int r1, int s4,
+                                          const A *__restrict__ prod, const X *__restrict__ x,
+                                          Y *__restrict__ y, const Y *__restrict__ b,
+                                          double *__restrict__ part, int seg, double *sh) {
+    double dot = 0.0;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        const int a = row_ptr[r] - s4, z = row_ptr[r + 1] - s4;
+        A sum = A(0);
+        for (int k = a; k < z; ++k) sum += prod[k];
+        if (EPI == EPI_RESID) {
+            const Y res = static_cast<Y>(b[r] - static_cast<Y>(sum));
+            y[r] = res;
+            dot += static_cast<double>(res) * static_cast<double>(res);
+        } else {
+            y[r] = static_cast<Y>(sum);
+            if (EPI == EPI_DOT) dot += static_cast<double>(sum) * static_cast<double>(x[r]);
+        }
+    }
+    if (EPI != EPI_PLAIN) {
+        const double t = block_sum(dot, sh);
+        if (threadIdx.x == 0) part[seg] = t;
+    }
+}
+
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+__global__ __launch_bounds__(kBlock) void k_stream(SpmvArgs<V, X, Y> g) {
+    __shared__ A prod[NT + 8];
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int b = blockIdx.x;
+    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    if (li >= g.n_list) return;
+    const int seg = g.list[li];
+    const int r0 = g.seg_bound[seg], r1 = g.seg_bound[seg + 1];
+    const int s = g.row_ptr[r0], e = g.row_ptr[r1];
+    const X *__restrict__ x = g.x;
+    tile_products<V, X, A, NT>(g.col, g.val, s, e, prod, [x](int c) { return x[c]; });
+    __syncthreads();
+    tile_rows<X, Y, A, EPI>(g.row_ptr, r0, r1, s & ~3, prod, g.x, g.y, g.b, g.part, seg, sh);
+}
+
+template <typename V, typename X, typename Y, typename A, int EPI>
+__global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int seg = g.list[blockIdx.x];
+    const int r = g.seg_bound[seg];
+    const int s = g.row_ptr[r], e = g.row_ptr[r + 1];
+    A acc = A(0);
+    for (int k = s + (int)threadIdx.x; k < e; k += kBlock)
+        acc += to_acc<A>(g.val[k]) * static_cast<A>(g.x[g.col[k]]);
+    // Fixed-shape reduction in double, then rounded to the accumulator type.
+    const double t = block_sum(static_cast<double>(acc), sh);
+    if (threadIdx.x == 0) {
+        const A sum = static_cast<A>(t);
+        double dot;
+        if (EPI == EPI_RESID) {
+            const Y res = static_cast<Y>(g.b[r] - static_cast<Y>(sum));
+            g.y[r] = res;
+            dot = static_cast<double>(res) * static_cast<double>(res);
+        } else {
+            g.y[r] = static_cast<Y>(sum);
+            dot = static_cast<double>(sum) * static_cast<double>(g.x[r]);
+        }
+        if (EPI != EPI_PLAIN) g.part[seg] = dot;
+    }
+}
+
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+__global__ __launch_bounds__(kBlock) void k_window(SpmvArgs<V, X, Y> g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ A prod[NT + 8];
+    __shared__ double sh[kBlock / kWave];
+    X *ring = reinterpret_cast<X *>(smem);
+    if (g.done && *g.done) return;
+    const int mask = g.ring_words - 1;
+    const int t0 = g.win_blk_ptr[blockIdx.x], t1 = g.win_blk_ptr[blockIdx.x + 1];
+    for (int t = t0; t < t1; ++t) {
+        const int seg = g.list[t];
+        const int r0 = g.seg_bound[seg], r1 = g.seg_bound[seg + 1];
+        const int s = g.row_ptr[r0], e = g.row_ptr[r1];
+        // stage the words this tile needs that are not resident yet
+        const int off = g.win_off[t], cnt = g.win_cnt[t];
+        for (int w = (int)threadIdx.x; w < cnt; w += kBlock) ring[(off + w) & mask] = g.x[off + w];
+        __syncthreads();
+        const X *rg = ring;
+        tile_products<V, X, A, NT>(g.col, g.val, s, e, prod, [rg, mask](int c) { return rg[c & mask]; });
+        __syncthreads();
+        tile_rows<X, Y, A, EPI>(g.row_ptr, r0, r1, s & ~3, prod, g.x, g.y, g.b, g.part, seg, sh);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- launch
+
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
+    if (M.n_stream > 0) {
+        SpmvArgs<V, X, Y> a = g;
+        a.list = M.stream_list;
+        a.n_list = M.n_stream;
+        int grid = M.n_stream;
+        a.per_xcd = 0;
+        if (M.xcd_remap && M.n_stream >= 16) {
+            a.per_xcd = (M.n_stream + 7) / 8;
+            grid = 8 * a.per_xcd;
+        }
+        hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
+    }
+    if (M.n_long > 0) {
+        SpmvArgs<V, X, Y> a = g;
+        a.list = M.long_list;
+        a.n_list = M.n_long;
+        hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
+    }
+    if (M.n_blk > 0) {
+        SpmvArgs<V, X, Y> a = g;
+        a.list = M.win_list;
+        a.win_blk_ptr = M.win_blk_ptr;
+        a.win_off = M.win_off;
+        a.win_cnt = M.win_cnt;
+        a.ring_words = M.ring_words;
+        const size_t lds = sizeof(X) * (size_t)M.ring_words;
+        hipLaunchKernelGGL((k_window<V, X, Y, A, NT, EPI>), dim3(M.n_blk), dim3(kBlock), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename V, typename X, typename Y, typename A, int EPI>
+static hipError_t launch_epi(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
+    switch (M.tile_nnz) {
+        case 1024: return launch_nt<V, X, Y, A, 1024, EPI>(M, g, st);
+        case 2048: return launch_nt<V, X, Y, A, 2048, EPI>(M, g, st);
+        default: return launch_nt<V, X, Y, A, 4096, EPI>(M, g, st);
+    }
+}
+
+template <typename V, typename X, typename Y, typename A>
+hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
+                       double *part, const int *done, hipStream_t st) {
+    SpmvArgs<V, X, Y> g{};
+    g.row_ptr = M.row_ptr;
+    g.col = M.col;
+    g.val = val;
+    g.x = x;
+    g.y = y;
+    g.b = b;
+    g.part = part;
+    g.seg_bound = M.seg_bound;
+    g.done = done;
+    switch (epi) {
+        case EPI_DOT: return launch_epi<V, X, Y, A, EPI_DOT>(M, g, st);
+        case EPI_RESID: return launch_epi<V, X, Y, A, EPI_RESID>(M, g, st);
+        default: return launch_epi<V, X, Y, A, EPI_PLAIN>(M, g, st);
+    }
+}
+
+template <typename V, typename X, typename Y, typename A, int NT>
+static hipError_t opt_in_lds() {
+    const int bytes = 8192 * (int)sizeof(X);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_window<V, X, Y, A, NT, EPI_PLAIN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_window<V, X, Y, A, NT, EPI_DOT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_window<V, X, Y, A, NT, EPI_RESID>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+template <typename V, typename X, typename Y, typename A> static hipError_t opt_in_lds_all_nt() {
+    hipError_t e = opt_in_lds<V, X, Y, A, 1024>();
+    if (e == hipSuccess) e = opt_in_lds<V, X, Y, A, 2048>();
+    if (e == hipSuccess) e = opt_in_lds<V, X, Y, A, 4096>();
+    return e;
+}
+
+hipError_t prepare_window_kernels() {
+    // Idempotent; called before any window launch so no attribute call ever
+    // happens during stream capture.
+    hipError_t e = opt_in_lds_all_nt<double, double, double, double>();
+    if (e == hipSuccess) e = opt_in_lds_all_nt<float, float, float, float>();
+    if (e == hipSuccess) e = opt_in_lds_all_nt<float, double, double, double>();
+    if (e == hipSuccess) e = opt_in_lds_all_nt<uint16_t, float, float, float>();
+    return e;
+}
+
+template hipError_t launch_spmv<double, double, double, double>(const DevMatrix &, const double *, const double *,
+                                                                double *, int, const double *, double *,
+                                                                const int *, hipStream_t);
+template hipError_t launch_spmv<float, float, float, float>(const DevMatrix &, const float *, const float *,
+                                                            float *, int, const float *, double *, const int *,
+                                                            hipStream_t);
+template hipError_t launch_spmv<float, double, double, double>(const DevMatrix &, const float *, const double *,
+                                                               double *, int, const double *, double *,
+                                                               const int *, hipStream_t);
+template hipError_t launch_spmv<uint16_t, float, float, float>(const DevMatrix &, const uint16_t *,
+                                                               const float *, float *, int, const float *,
+                                                               double *, const int *, hipStream_t);
+
+}  // namespace spmvlib

@@ -1,0 +1,153 @@
+"""Host-side tests of the C-ABI library: it loads, exports every declared
+symbol, validates its inputs, and builds a correct analysis plan.  None of
+these touch a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2107_12371_amd as spmv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\([^;{]*\)\s*;", text, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "spmv_create" in names and "cg_solve" in names and "spmv_apply" in names
+    L = ctypes.CDLL(spmv.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(spmv.EXPORTED) <= set(names)
+
+
+def _bad(n_rows, n_cols, rp, ci, params=None):
+    with pytest.raises(spmv.SpmvError) as e:
+        spmv.plan_inspect(n_rows, n_cols, rp, ci, params)
+    return e.value
+
+
+def test_validation_errors():
+    assert _bad(2, 2, [1, 1, 2], [0, 1]).code == spmv.SPMV_EINVAL           # row_ptr[0] != 0
+    assert _bad(2, 2, [0, 2, 1], [0, 1]).code == spmv.SPMV_EINVAL           # decreasing
+    assert _bad(2, 2, [0, 1, 3], [0, 1]).code == spmv.SPMV_EINVAL           # row_ptr[n] != nnz
+    assert _bad(2, 2, [0, 1, 2], [0, 2]).code == spmv.SPMV_EINVAL           # column out of range
+    assert _bad(2, 2, [0, 1, 2], [-1, 0]).code == spmv.SPMV_EINVAL          # negative column
+    assert _bad(-1, 2, [0], []).code == spmv.SPMV_EINVAL                    # negative dimension
+    assert _bad(2, 2, [0, 1, 2], [0, 1], {"tile_nnz": 1000}).code == spmv.SPMV_EINVAL
+    assert _bad(2, 2, [0, 1, 2], [0, 1], {"ring_words": 3000}).code == spmv.SPMV_EINVAL
+    assert _bad(2, 2, [0, 1, 2], [0, 1], {"window_mode": 7}).code == spmv.SPMV_EINVAL
+    assert "row_ptr" in str(_bad(2, 2, [0, 2, 1], [0, 1]))
+
+
+def test_create_rejects_malformed_input_before_touching_the_device():
+    L = spmv.lib()
+    h = ctypes.c_void_p()
+    rp = np.array([0, 1, 3], np.int32)
+    ci = np.array([0, 5, 1], np.int32)
+    va = np.ones(3)
+    rc = L.spmv_create(2, 2, 3, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, 0, None, ctypes.byref(h))
+    assert rc == spmv.SPMV_EINVAL and not h.value
+    rc = L.spmv_create(2, 2, 3, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, 0x80, None, ctypes.byref(h))
+    assert rc == spmv.SPMV_EINVAL
+    assert L.spmv_apply(None, None, None, None) == spmv.SPMV_EINVAL
+    assert L.cg_solve(None, None, None, 1e-8, 10, 0, None, None) == spmv.SPMV_EINVAL
+    assert L.spmv_destroy(None) == spmv.SPMV_OK
+    assert L.spmv_get_info(None, None) == spmv.SPMV_EINVAL
+
+
+def check_plan(A, params=None):
+    P = spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, params)
+    info = P["info"]
+    sb, kind = P["seg_bound"], P["seg_kind"]
+    tnz, trows = info["tile_nnz"], info["tile_rows"]
+    rp = A.row_ptr.astype(np.int64)
+    # every row in exactly one segment
+    assert sb[0] == 0 and sb[-1] == A.n_rows
+    assert np.all(np.diff(sb) > 0)
+    seg_nnz = rp[sb[1:]] - rp[sb[:-1]]
+    seg_rows = np.diff(sb)
+    lng = kind == 1
+    assert np.all(seg_rows[lng] == 1) and np.all(seg_nnz[lng] > tnz)
+    assert np.all(seg_nnz[~lng] <= tnz) and np.all(seg_rows[~lng] <= trows)
+    # every row longer than a tile is a long-row segment
+    long_rows = np.nonzero(np.diff(rp) > tnz)[0]
+    assert set(long_rows) == set(sb[:-1][lng])
+    # window tiles: replay the staging of each block and check every column
+    # a tile reads is resident, with the paper's count_i = colend_i - colend_{i-1}
+    R = info["ring_words"]
+    win = np.nonzero(kind == 2)[0]
+    staged = 0
+    for blk in np.unique(P["win_block"][win]):
+        segs = win[P["win_block"][win] == blk]
+        assert np.all(np.diff(segs) == 1)          # adjacent tiles, walked in order
+        ring = {}
+        hi_prev = None
+        for s in segs:
+            off, cnt = int(P["win_off"][s]), int(P["win_cnt"][s])
+            for w in range(off, off + cnt):
+                ring[w % R] = w
+            staged += cnt
+            cols = A.col_idx[rp[sb[s]]:rp[sb[s + 1]]]
+            if cols.size == 0:
+                continue
+            for c in np.unique(cols):
+                assert ring.get(int(c) % R) == int(c)
+            if hi_prev is not None and cnt and off == hi_prev + 1:
+                assert off + cnt - 1 == cols.max()   # loads exactly up to colend_i
+            hi_prev = max(hi_prev if hi_prev is not None else -1, int(cols.max()))
+    assert staged == info["window_words"]
+    assert info["n_window_tiles"] == win.size
+    return P
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_plan_invariants_mesh(tile):
+    A = mg.config0()
+    check_plan(A, {"tile_nnz": tile})
+
+
+def test_plan_invariants_edge_cases():
+    A = mg.random_csr(3000, 3000, seed=1, mean_len=3.0, empty_frac=0.3, dense_rows=2)
+    P = check_plan(A, {"tile_nnz": 1024})
+    assert P["info"]["n_long_rows"] == 2
+    # all rows empty
+    n = 700
+    P = spmv.plan_inspect(n, 5, np.zeros(n + 1, np.int32), np.zeros(0, np.int32))
+    assert P["seg_bound"][-1] == n and np.all(P["seg_kind"] == 0)
+    # no rows at all
+    P = spmv.plan_inspect(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32))
+    assert P["info"]["n_tiles"] == 0
+
+
+@pytest.mark.parametrize("ring", [256, 1024, 4096])
+def test_plan_window_forced_ring_sizes(ring):
+    A = mg.lattice(16, 16, 16, "faces", seed=3)         # bandwidth 256: many tiles fit
+    P = check_plan(A, {"tile_nnz": 1024, "window_mode": spmv.WINDOW_FORCE, "ring_words": ring,
+                       "window_block": 8})
+    if ring >= 1024:
+        assert P["info"]["n_window_tiles"] > 0
+        # walking blocks of 8 adjacent tiles stages far fewer words than the tiles' spans
+        assert P["info"]["window_words"] < A.nnz
+
+
+def test_plan_window_off_and_auto():
+    A = mg.lattice(16, 16, 16, "faces", seed=3)
+    P = check_plan(A, {"window_mode": spmv.WINDOW_OFF})
+    assert P["info"]["n_window_tiles"] == 0
+    P = check_plan(A, {"window_mode": spmv.WINDOW_AUTO, "window_block": 16, "tile_nnz": 1024})
+    assert P["info"]["window_words"] <= 0.25 * A.nnz + 1

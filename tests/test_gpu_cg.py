@@ -1,0 +1,120 @@
+"""GPU CG against the CPU oracle's CG.
+
+Several answers are correct (iterates depend on rounding order), so the rule
+compares what is fixed:
+  1. the true relative residual ||b - A x_gpu|| / ||b||, recomputed with the
+     oracle's SpMV, is within tol (5% slack for the residual's own rounding,
+     at most u * kappa relative to tol);
+  2. ||x_gpu - x_ref|| / ||x_ref|| <= 2 * kappa * tol, with kappa bounded by
+     Gershgorin: (max_i (a_ii + sum_j |a_ij|)) / shift for these
+     diagonally dominant Laplacians (smallest eigenvalue = shift);
+  3. FP64 iteration counts within 10% of the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+import oracle
+import paper_2107_12371_amd as spmv
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gershgorin_kappa(A, shift):
+    v = np.abs(A.values)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    return np.bincount(rows, weights=v, minlength=A.n_rows).max() / shift
+
+
+def true_rel_residual(A, x, b):
+    Ax, _ = oracle.spmv(A, x)
+    return np.linalg.norm(b - Ax) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    A = mg.config0()
+    b = mg.uniform(A.n_rows, mg.seed_for(0), 3)
+    ref = oracle.cg(A, b, tol=1e-10, max_iter=20000)
+    assert ref.status == 0
+    return A, b, ref
+
+
+@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32])
+def test_cg_config0_against_oracle(cfg0, mode):
+    A, b, ref = cfg0
+    tol = 1e-10
+    with spmv.Matrix.from_csr(A, fp32=True) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=tol, mode=mode)
+    x = x.cpu().numpy()
+    assert info.status == 0
+    rr = true_rel_residual(A, x, b)
+    assert rr <= 1.05 * tol
+    assert abs(info.rel_residual - rr) <= 0.05 * tol
+    kappa = gershgorin_kappa(A, 1e-3)
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 2 * kappa * tol
+    if mode == spmv.CG_FP64:
+        assert abs(info.iterations - ref.iterations) <= 0.1 * ref.iterations
+    else:
+        assert info.refinements >= 1
+
+
+def test_cg_closed_form_one_iteration():
+    A = mg.config0()
+    with spmv.Matrix.from_csr(A) as M:
+        x, info = M.cg(torch.ones(A.n_rows, dtype=torch.float64, device=DEV), tol=1e-10)
+    assert info.iterations == 1
+    assert np.allclose(x.cpu().numpy(), 1000.0, rtol=1e-9)
+    Ad = mg.config0(dyadic=True)
+    with spmv.Matrix.from_csr(Ad) as M:
+        x, info = M.cg(torch.ones(Ad.n_rows, dtype=torch.float64, device=DEV), tol=1e-12)
+    assert info.iterations == 1 and bool(torch.all(x == 1024.0))
+
+
+def test_cg_reproducible_bitwise(cfg0):
+    A, b, _ = cfg0
+    with spmv.Matrix.from_csr(A) as M:
+        bt = torch.as_tensor(b, device=DEV)
+        x1, i1 = M.cg(bt, tol=1e-8)
+        x2, i2 = M.cg(bt, tol=1e-8)
+    assert i1.iterations == i2.iterations and torch.equal(x1, x2)
+
+
+def test_cg_warm_start_zero_rhs_and_max_iter(cfg0):
+    A, b, ref = cfg0
+    with spmv.Matrix.from_csr(A) as M:
+        bt = torch.as_tensor(b, device=DEV)
+        x, info = M.cg(torch.zeros_like(bt), x=torch.ones_like(bt))
+        assert info.iterations == 0 and bool(torch.all(x == 0))
+        x, info = M.cg(bt, tol=1e-12, max_iter=5, raise_on_error=False)
+        assert info.status == spmv.SPMV_ENOTCONV and info.iterations == 5
+        # resume from the last iterate (warm start)
+        x2, info2 = M.cg(bt, x=x, tol=1e-10)
+        assert info2.status == 0
+        assert true_rel_residual(A, x2.cpu().numpy(), b) <= 1.05e-10
+
+
+def test_cg_rejects_bad_input():
+    A = mg.random_csr(50, 40, seed=1)
+    with spmv.Matrix.from_csr(A) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.zeros(50, dtype=torch.float64, device=DEV))
+        assert e.value.code == spmv.SPMV_EINVAL
+    B = mg.config0()
+    with spmv.Matrix.from_csr(B) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_MIXED_FP32)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+
+
+def test_cg_breakdown_on_indefinite_matrix():
+    n = 64
+    d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = np.zeros(n)
+    b[0], b[1] = 1.0, 1.0   # p.q = 1 - 1 = 0 at the first step
+    with spmv.Matrix.from_csr(A) as M:
+        _, info = M.cg(torch.as_tensor(b, device=DEV), raise_on_error=False)
+    assert info.status == spmv.SPMV_EBREAK

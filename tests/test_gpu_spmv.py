@@ -1,0 +1,227 @@
+"""GPU parity of the SpMV paths against the CPU oracle, element by element.
+
+Acceptance (binary64): |y_gpu - y_ref| <= 1e-12 * sum_k |a_ik||x_k| per row
+(rows with a zero bound must be exactly zero; NaN/Inf compared by class).
+Dyadic inputs make every partial sum exact, so there the GPU must equal the
+oracle bit for bit.  Reduced-precision paths are held to first-order bounds
+derived from their arithmetic:
+  FP32 values, x, accumulation:  (m + 2) * 2^-24 * bound
+  FP32 values, binary64 x/acc:   (2^-24 + m * 2^-53) * bound
+  BF16 values, FP32 x/acc:       (2^-8 + (m + 1) * 2^-24) * bound
+with m the row length and a 1% slack for the second-order terms.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+import oracle
+import paper_2107_12371_amd as spmv
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def run64(A, x, **kw):
+    with spmv.Matrix.from_csr(A, **kw) as M:
+        y = M.apply(to_dev(x))
+        torch.cuda.synchronize()
+        return y.cpu().numpy(), M.info
+
+
+def assert_parity(y, A, x, rtol=oracle.SPMV_RTOL):
+    y_ref, bound = oracle.spmv(A, x)
+    ok = oracle.spmv_accept(y, y_ref, bound, rtol)
+    if not ok.all():
+        i = int(np.nonzero(~ok)[0][0])
+        raise AssertionError(f"{(~ok).sum()} rows fail; first row {i}: gpu={y[i]!r} ref={y_ref[i]!r} "
+                             f"bound={bound[i]!r}")
+
+
+EDGE = {
+    "empty_rows": dict(n_rows=5000, n_cols=5000, seed=1, mean_len=4.0, empty_frac=0.4),
+    "dense_rows_long_path": dict(n_rows=3000, n_cols=20000, seed=2, mean_len=6.0, dense_rows=3),
+    "duplicates_unsorted": dict(n_rows=4099, n_cols=777, seed=3, mean_len=9.0, duplicates=True,
+                                unsorted=True),
+    "rectangular_wide": dict(n_rows=1025, n_cols=70000, seed=4, mean_len=30.0),
+    "rectangular_tall": dict(n_rows=70001, n_cols=33, seed=5, mean_len=3.0),
+    "single_row": dict(n_rows=1, n_cols=10, seed=6, empty_frac=0.0),
+    "all_empty": dict(n_rows=3000, n_cols=3000, seed=7, empty_frac=1.0),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+@pytest.mark.parametrize("tile", [1024, 4096])
+def test_edge_cases_fp64(name, tile):
+    A = mg.random_csr(**EDGE[name])
+    x = mg.uniform(A.n_cols, 11, 0)
+    y, info = run64(A, x, params={"tile_nnz": tile})
+    assert_parity(y, A, x)
+    if name == "dense_rows_long_path":
+        assert info["n_long_rows"] == 3
+
+
+def test_zero_nnz_and_zero_rows():
+    A = mg.CSR(4, 3, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    y, _ = run64(A, np.ones(3))
+    assert np.all(y == 0.0)
+    A = mg.CSR(0, 3, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    with spmv.Matrix.from_csr(A) as M:
+        y = M.apply(to_dev(np.ones(3)))
+        assert y.numel() == 0
+
+
+def test_long_row_of_100k_entries():
+    n = 300
+    rows = [np.arange(3) for _ in range(n)]
+    rows[17] = np.arange(100_000)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    A = mg.CSR(n, 100_000, rp, np.concatenate(rows).astype(np.int32),
+               mg.uniform(int(rp[-1]), 5, 2))
+    x = mg.uniform(A.n_cols, 6, 0)
+    y, info = run64(A, x)
+    assert info["n_long_rows"] == 1
+    assert_parity(y, A, x)
+
+
+def test_nan_inf_propagate_like_the_oracle():
+    A = mg.random_csr(500, 500, seed=8, mean_len=5.0, empty_frac=0.0)
+    x = mg.uniform(A.n_cols, 9, 0)
+    x[[3, 77]] = np.nan
+    x[[10]] = np.inf
+    y, _ = run64(A, x)
+    assert_parity(y, A, x)
+
+
+@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("remap", [True, False])
+def test_mesh_config0_paths(mode, tile, remap):
+    A = mg.config0()
+    x = mg.uniform(A.n_cols, 12, 0)
+    y, info = run64(A, x, xcd_remap=remap,
+                    params={"tile_nnz": tile, "window_mode": mode, "window_block": 8, "ring_words": 8192})
+    if mode == spmv.WINDOW_FORCE:
+        assert info["n_window_tiles"] > 0
+    assert_parity(y, A, x)
+
+
+@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
+def test_dyadic_bitwise(mode):
+    for A in (mg.config0(dyadic=True), mg.config1("rcm", m=40, dyadic=True),
+              mg.lattice(30, 30, 30, "stencil27", seed=5, dyadic=True)):
+        x = mg.dyadic_x(A.n_cols, seed=4)
+        y, _ = run64(A, x, params={"window_mode": mode, "window_block": 4, "ring_words": 8192,
+                                   "tile_nnz": 1024})
+        y_ref, _ = oracle.spmv(A, x)
+        assert np.array_equal(y, y_ref)
+
+
+def test_ring_window_small_ring_and_restarts():
+    # 7-point lattice: band nx*ny = 1024; a 1024-word ring forces restarts
+    A = mg.lattice(32, 32, 40, "faces", seed=9)
+    x = mg.uniform(A.n_cols, 13, 0)
+    for ring in (1024, 2048, 8192):
+        y, info = run64(A, x, params={"window_mode": spmv.WINDOW_FORCE, "ring_words": ring,
+                                      "window_block": 32, "tile_nnz": 1024})
+        assert info["n_window_tiles"] > 0
+        assert_parity(y, A, x)
+
+
+def test_reproducible_and_independent_of_concurrent_work():
+    A = mg.config0()
+    B = mg.config1("random", m=48)
+    x = to_dev(mg.uniform(A.n_cols, 14, 0))
+    xb = to_dev(mg.uniform(B.n_cols, 15, 0))
+    with spmv.Matrix.from_csr(A) as M, spmv.Matrix.from_csr(B) as N:
+        y1 = M.apply(x)
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = []
+        for _ in range(5):
+            with torch.cuda.stream(s1):
+                ya = M.apply(x, stream=s1)
+            with torch.cuda.stream(s2):
+                N.apply(xb, stream=s2)
+            outs.append(ya)
+        torch.cuda.synchronize()
+        for ya in outs:
+            assert torch.equal(ya, y1)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return {o: mg.config1(o) for o in ("rcm", "random")}
+
+
+@pytest.mark.parametrize("ordering", ["rcm", "random"])
+def test_config1_full_size_and_permutation_equivariance(cfg1, ordering):
+    A = cfg1[ordering]
+    assert A.n_rows == 126 ** 3
+    x = mg.uniform(A.n_cols, 16, 0)
+    y, _ = run64(A, x)
+    assert_parity(y, A, x)
+
+
+def test_config1_orderings_agree(cfg1):
+    # the same operator in two orderings: both are the RCM / random
+    # renumbering of one natural-order matrix, so y must agree after mapping
+    nat = mg.knn(126, seed=mg.seed_for(1))
+    p_rcm = mg.rcm_perm(nat)
+    x = mg.uniform(nat.n_cols, 17, 0)
+    y_rcm, _ = run64(cfg1["rcm"], x[p_rcm])
+    y_nat, _ = oracle.spmv(nat, x)
+    _, bound = oracle.spmv(nat, x)
+    assert np.all(np.abs(y_rcm - y_nat[p_rcm]) <= 1e-12 * bound[p_rcm])
+
+
+def _bounds(A, x):
+    y_ref, bound = oracle.spmv(A, x)
+    m = np.diff(A.row_ptr).astype(np.float64)
+    return y_ref, bound, m
+
+
+def test_fp32_paths_within_derived_bounds():
+    A = mg.config0()
+    x = mg.uniform(A.n_cols, 18, 0)
+    y_ref, bound, m = _bounds(A, x)
+    with spmv.Matrix.from_csr(A, fp32=True, bf16=True) as M:
+        y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+        yv = M.apply_f32v(to_dev(x)).cpu().numpy()
+        y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    u32, u16 = 2.0 ** -24, 2.0 ** -8
+    assert np.all(np.abs(y32 - y_ref) <= 1.01 * (m + 2) * u32 * bound)
+    assert np.all(np.abs(yv - y_ref) <= 1.01 * (u32 + m * 2.0 ** -53) * bound)
+    assert np.all(np.abs(y16 - y_ref) <= 1.01 * (u16 + (m + 1) * u32) * bound)
+    # the reduced-precision results are not just the binary64 result rounded
+    assert np.max(np.abs(y32 - y_ref) / np.maximum(bound, 1e-300)) > 1e-9
+
+
+def test_fp32_dyadic_bitwise():
+    A = mg.config0(dyadic=True)
+    x = mg.dyadic_x32(A.n_cols, seed=3)
+    y_ref, _ = oracle.spmv(A, x)
+    with spmv.Matrix.from_csr(A, fp32=True) as M:
+        y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y32, y_ref)
+
+
+def test_missing_copies_and_bad_arguments():
+    A = mg.config0()
+    with spmv.Matrix.from_csr(A) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.apply_f32(torch.zeros(A.n_cols, dtype=torch.float32, device=DEV))
+        assert e.value.code == spmv.SPMV_ENOTSUP
+        buf = torch.zeros(A.n_rows + A.n_cols, dtype=torch.float64, device=DEV)
+        with pytest.raises(spmv.SpmvError) as e:
+            M.apply(buf[:A.n_cols], buf[A.n_cols - 5:A.n_cols - 5 + A.n_rows])
+        assert e.value.code == spmv.SPMV_EINVAL
+        with pytest.raises(TypeError):
+            M.apply(torch.zeros(A.n_cols, dtype=torch.float32, device=DEV))
+        with pytest.raises(ValueError):
+            M.apply(torch.zeros(A.n_cols + 1, dtype=torch.float64, device=DEV))
