@@ -48,7 +48,10 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(e == hipErrorOutOfMemory ? SPMV_ENOMEM : SPMV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Allocates max(alloc_n, n, 1) elements, zero-fills the tail beyond n and
+// copies n elements from the host.
 template <typename T> static int dev_upload(spmv_matrix *A, T **dst, const T *src, size_t n, size_t alloc_n) {
+    if (alloc_n < n) alloc_n = n;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, sizeof(T) * (alloc_n ? alloc_n : 1));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");

@@ -122,15 +122,36 @@ def test_dyadic_bitwise(mode):
         assert np.array_equal(y, y_ref)
 
 
-def test_ring_window_small_ring_and_restarts():
-    # 7-point lattice: band nx*ny = 1024; a 1024-word ring forces restarts
+def test_ring_window_sizes_and_restarts():
+    # 7-point lattice: band nx*ny = 1024, so a tile of ~150 rows spans ~2200
+    # columns: rings of 1024/2048 words cannot hold a tile (direct path), 4096
+    # and 8192 can.
     A = mg.lattice(32, 32, 40, "faces", seed=9)
     x = mg.uniform(A.n_cols, 13, 0)
-    for ring in (1024, 2048, 8192):
+    for ring in (1024, 2048, 4096, 8192):
         y, info = run64(A, x, params={"window_mode": spmv.WINDOW_FORCE, "ring_words": ring,
                                       "window_block": 32, "tile_nnz": 1024})
-        assert info["n_window_tiles"] > 0
+        assert (info["n_window_tiles"] > 0) == (ring >= 4096)
         assert_parity(y, A, x)
+    # reversing 2048-row chunks makes consecutive tiles jump across the matrix,
+    # forcing ring restarts inside a block
+    n = A.n_rows
+    perm = np.concatenate([np.arange(min(n, s + 2048) - 1, s - 1, -1) for s in range(0, n, 2048)])
+    B = mg.permute(A, perm.astype(np.int32))
+    P = spmv.plan_inspect(B.n_rows, B.n_cols, B.row_ptr, B.col_idx,
+                          {"window_mode": spmv.WINDOW_FORCE, "ring_words": 8192, "window_block": 32,
+                           "tile_nnz": 1024})
+    win = P["seg_kind"] == 2
+    spans = np.array([B.col_idx[B.row_ptr[a]:B.row_ptr[b]].max() - B.col_idx[B.row_ptr[a]:B.row_ptr[b]].min() + 1
+                      for a, b in zip(P["seg_bound"][:-1], P["seg_bound"][1:])])
+    restarts = np.sum(win & (P["win_cnt"] == spans))
+    blocks = len(np.unique(P["win_block"][win]))
+    assert restarts > blocks          # more full reloads than one per block
+    xb = x[perm]
+    y, info = run64(B, xb, params={"window_mode": spmv.WINDOW_FORCE, "ring_words": 8192,
+                                   "window_block": 32, "tile_nnz": 1024})
+    assert info["n_window_tiles"] > 0
+    assert_parity(y, B, xb)
 
 
 def test_reproducible_and_independent_of_concurrent_work():
