@@ -75,6 +75,8 @@ typedef struct spmv_params {
                               (0: chosen from the tile count) */
     double window_ratio;   /* AUTO uses the window for a block when staged words
                               <= window_ratio * stored entries (0: 0.25) */
+    int32_t kernel;        /* direct-gather kernel: 0 auto (pipelined), 1 one
+                              workgroup per tile, 2 pipelined persistent */
 } spmv_params;
 
 /* Summary of a handle's analysis plan and resident storage. */
@@ -91,6 +93,7 @@ typedef struct spmv_info {
     int64_t window_words;   /* x words staged into LDS per product */
     int32_t has_fp32, has_bf16;
     int64_t device_bytes;   /* bytes of device memory held by the handle */
+    int32_t block_size;     /* 1: scalar CSR, 3: 3x3 block CSR (n_rows/n_cols/nnz count blocks) */
 } spmv_info;
 
 /*
@@ -139,6 +142,40 @@ int spmv_apply_f32v(const spmv_matrix *A, const double *x, double *y, void *stre
 /* y = A16 x with the BF16 copy of the values, FP32 x/y, FP32 accumulation
  * (needs SPMV_VALUES_BF16). */
 int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream);
+
+/* ------------------------------------------------------ 3x3 block CSR */
+/*
+ * spmv_create_bsr3: a matrix of dense 3x3 blocks in block-CSR form, as
+ * produced by coupled three-component operators on a mesh (velocity u, v, w
+ * per cell; paper Sec. 2: row i = cell i, its blocks = neighbour cells).
+ *   n_block_rows, n_block_cols >= 0; nnz_blocks stored blocks
+ *   brow_ptr   host int32[n_block_rows + 1] (same rules as CSR row_ptr)
+ *   bcol_idx   host int32[nnz_blocks] in [0, n_block_cols)
+ *   bvalues    host double[9 * nnz_blocks], each block row-major
+ *   flags      SPMV_VALUES_FP32 keeps an FP32 copy; SPMV_NO_XCD_REMAP
+ * The scalar matrix is (3 n_block_rows) x (3 n_block_cols).  spmv_apply and
+ * spmv_apply_f32 on such a handle compute the k = 1 product; cg_solve,
+ * spmv_apply_f32v and spmv_apply_bf16 return SPMV_ENOTSUP.
+ */
+int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int64_t nnz_blocks,
+                     const int32_t *brow_ptr, const int32_t *bcol_idx, const double *bvalues,
+                     uint32_t flags, spmv_matrix **out);
+
+/*
+ * bsr3_spmm: Y = A X for a block-CSR handle with k >= 1 right-hand sides.
+ *   X  device double[(3 n_block_cols) * k], row-major (the k values of one
+ *      scalar row are contiguous)
+ *   Y  device double[(3 n_block_rows) * k], row-major, fully overwritten
+ * Each output is summed over the row's blocks in ascending order, then over
+ * the block's three columns; column j of Y equals the k = 1 product of
+ * column j of X bit for bit.  X and Y must not overlap.  SPMV_ENOTSUP on a
+ * scalar CSR handle.
+ */
+int bsr3_spmm(const spmv_matrix *A, int32_t k, const double *X, double *Y, void *stream);
+
+/* bsr3_spmm with the FP32 copy of the blocks, FP32 X/Y and FP32 accumulation
+ * (needs SPMV_VALUES_FP32). */
+int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, void *stream);
 
 /* ------------------------------------------------------------------- CG */
 #define CG_FP64 0       /* binary64 values, vectors, dots and scalars */

@@ -32,6 +32,7 @@ CG_FP64, CG_MIXED_FP32 = 0, 1
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
     "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
+    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32",
 ]
 
 
@@ -44,7 +45,8 @@ class SpmvError(RuntimeError):
 class spmv_params(ctypes.Structure):
     _fields_ = [("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
-                ("window_block", ctypes.c_int32), ("window_ratio", ctypes.c_double)]
+                ("window_block", ctypes.c_int32), ("window_ratio", ctypes.c_double),
+                ("kernel", ctypes.c_int32)]
 
 
 class spmv_info(ctypes.Structure):
@@ -54,7 +56,8 @@ class spmv_info(ctypes.Structure):
                 ("n_long_rows", ctypes.c_int32), ("n_window_tiles", ctypes.c_int32),
                 ("n_window_blocks", ctypes.c_int32), ("ring_words", ctypes.c_int32),
                 ("window_words", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
-                ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("block_size", ctypes.c_int32)]
 
 
 class cg_info(ctypes.Structure):
@@ -89,6 +92,11 @@ def lib():
         for f in ("spmv_apply", "spmv_apply_f32", "spmv_apply_f32v", "spmv_apply_bf16"):
             getattr(L, f).restype = ctypes.c_int
             getattr(L, f).argtypes = [vp, vp, vp, vp]
+        L.spmv_create_bsr3.restype = ctypes.c_int
+        L.spmv_create_bsr3.argtypes = [i32, i32, i64, vp, vp, vp, u32, ctypes.POINTER(vp)]
+        for f in ("bsr3_spmm", "bsr3_spmm_f32"):
+            getattr(L, f).restype = ctypes.c_int
+            getattr(L, f).argtypes = [vp, i32, vp, vp, vp]
         L.cg_solve.restype = ctypes.c_int
         L.cg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(cg_info), vp]
         L.spmv_last_error.restype = ctypes.c_char_p
@@ -207,7 +215,49 @@ class Matrix:
 
     @classmethod
     def from_csr(cls, A, **kw) -> "Matrix":
+        if getattr(A, "block", 1) == 3:
+            return cls.from_bsr3(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.values, **kw)
         return cls(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.values, **kw)
+
+    @classmethod
+    def from_bsr3(cls, n_block_rows: int, n_block_cols: int, brow_ptr, bcol_idx, bvalues, *,
+                  fp32: bool = False, xcd_remap: bool = True) -> "Matrix":
+        """A resident 3x3 block-CSR matrix (``spmv_create_bsr3``); bvalues has
+        9 row-major values per block."""
+        rp, ci, _ = _host_csr(brow_ptr, bcol_idx, None)
+        va = np.ascontiguousarray(bvalues, dtype=np.float64).reshape(-1)
+        if va.shape[0] != 9 * ci.shape[0]:
+            raise ValueError("bvalues must hold 9 values per block")
+        flags = (SPMV_VALUES_FP32 if fp32 else 0) | (0 if xcd_remap else SPMV_NO_XCD_REMAP)
+        h = ctypes.c_void_p()
+        _check(lib().spmv_create_bsr3(n_block_rows, n_block_cols, ci.shape[0], _ptr(rp), _ptr(ci),
+                                      _ptr(va), flags, ctypes.byref(h)), "spmv_create_bsr3")
+        self = cls.__new__(cls)
+        self._h = h
+        self.n_rows, self.n_cols, self.nnz = 3 * n_block_rows, 3 * n_block_cols, int(ci.shape[0])
+        return self
+
+    def spmm(self, X, Y=None, stream=None):
+        """Y = A X for a block-CSR handle, X of shape (3 n_block_cols, k) (``bsr3_spmm``)."""
+        torch = _torch()
+        return self._spmm("bsr3_spmm", X, Y, torch.float64, stream)
+
+    def spmm_f32(self, X, Y=None, stream=None):
+        torch = _torch()
+        return self._spmm("bsr3_spmm_f32", X, Y, torch.float32, stream)
+
+    def _spmm(self, fn, X, Y, dt, stream):
+        torch = _torch()
+        if X.dim() == 1:
+            X = X.view(-1, 1)
+        k = X.shape[1]
+        _check_vec(X, dt, self.n_cols * k, "X")
+        if Y is None:
+            Y = torch.empty((self.n_rows, k), dtype=dt, device=X.device)
+        _check_vec(Y, dt, self.n_rows * k, "Y")
+        _check(getattr(lib(), fn)(self.handle, k, ctypes.c_void_p(X.data_ptr()),
+                                  ctypes.c_void_p(Y.data_ptr()), _stream_ptr(stream)), fn)
+        return Y
 
     @property
     def handle(self):

@@ -139,23 +139,34 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         rc = dev_upload(A, &M.val16, v16.data(), nz, nz_pad);
     }
     M.n_seg = P.n_seg();
-    if (!rc) rc = dev_upload(A, &M.seg_bound, P.seg_bound.data(), P.seg_bound.size(), P.seg_bound.size());
+    M.kernel = P.kernel;
+    auto desc_of = [&](int32_t sg) {
+        TileDesc d{};
+        d.r0 = P.seg_bound[sg];
+        d.r1 = P.seg_bound[sg + 1];
+        d.s = row_ptr[d.r0];
+        d.e = row_ptr[d.r1];
+        d.seg = sg;
+        d.woff = P.win_off[sg];
+        d.wcnt = P.win_cnt[sg];
+        return d;
+    };
+    auto upload_descs = [&](const std::vector<int32_t> &list, TileDesc **dst) {
+        std::vector<TileDesc> v;
+        v.reserve(list.size());
+        for (int32_t sg : list) v.push_back(desc_of(sg));
+        return dev_upload(A, dst, v.data(), v.size(), 0);
+    };
     M.n_stream = (int32_t)P.stream_list.size();
-    if (!rc && M.n_stream) rc = dev_upload(A, &M.stream_list, P.stream_list.data(), P.stream_list.size(), 0);
+    if (!rc && M.n_stream) rc = upload_descs(P.stream_list, &M.stream_desc);
     M.n_long = (int32_t)P.long_list.size();
-    if (!rc && M.n_long) rc = dev_upload(A, &M.long_list, P.long_list.data(), P.long_list.size(), 0);
+    if (!rc && M.n_long) rc = upload_descs(P.long_list, &M.long_desc);
     M.n_blk = P.win_blk_ptr.empty() ? 0 : (int32_t)P.win_blk_ptr.size() - 1;
     if (!rc && M.n_blk) {
-        std::vector<int32_t> off, cnt;
-        for (int32_t s : P.win_list) {
-            off.push_back(P.win_off[s]);
-            cnt.push_back(P.win_cnt[s]);
-        }
-        rc = dev_upload(A, &M.win_list, P.win_list.data(), P.win_list.size(), 0);
+        rc = upload_descs(P.win_list, &M.win_desc);
         if (!rc) rc = dev_upload(A, &M.win_blk_ptr, P.win_blk_ptr.data(), P.win_blk_ptr.size(), 0);
-        if (!rc) rc = dev_upload(A, &M.win_off, off.data(), off.size(), 0);
-        if (!rc) rc = dev_upload(A, &M.win_cnt, cnt.data(), cnt.size(), 0);
     }
+    if (!rc) prepare_launch_queries();
     if (!rc && M.n_blk) {
         hipError_t e2 = prepare_window_kernels();
         if (e2 != hipSuccess) rc = hip_fail(e2, "window kernel LDS opt-in");
@@ -182,6 +193,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     I.has_fp32 = M.val32 != nullptr;
     I.has_bf16 = M.val16 != nullptr;
     I.device_bytes = A->bytes;
+    I.block_size = 1;
     *out = A;
     return SPMV_OK;
 }
@@ -208,21 +220,109 @@ extern "C" int spmv_get_info(const spmv_matrix *A, spmv_info *info) {
     return SPMV_OK;
 }
 
+template <typename V, typename T>
+static int spmm_typed(const spmv_matrix *A, const V *val, int32_t k, const T *X, T *Y, void *stream) {
+    clear_error();
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (A->M.block != 3) return fail(SPMV_ENOTSUP, "not a 3x3 block-CSR handle");
+    if (k < 1) return fail(SPMV_EINVAL, "k = %d must be >= 1", k);
+    const size_t nx = (size_t)3 * A->M.n_cols * k, ny = (size_t)3 * A->M.n_rows * k;
+    if (ny && !Y) return fail(SPMV_EINVAL, "Y is NULL");
+    if (ny && A->M.nnz && !X) return fail(SPMV_EINVAL, "X is NULL");
+    if (X && Y && overlaps(X, nx * sizeof(T), Y, ny * sizeof(T))) return fail(SPMV_EINVAL, "X and Y overlap");
+    if (ny == 0) return SPMV_OK;
+    DeviceGuard g(A->device);
+    hipError_t e = launch_bsr3<V, T>(A->M, val, k, X, Y, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "bsr3 launch");
+    return SPMV_OK;
+}
+
 extern "C" int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream) {
+    if (A && A->M.block == 3) return spmm_typed<double, double>(A, A->M.val64, 1, x, y, stream);
     return apply_typed<double, double, double, double>(A, A ? A->M.val64 : nullptr, x, y, stream);
 }
 
 extern "C" int spmv_apply_f32(const spmv_matrix *A, const float *x, float *y, void *stream) {
     if (A && !A->M.val32) return fail(SPMV_ENOTSUP, "matrix has no FP32 copy (create with SPMV_VALUES_FP32)");
+    if (A && A->M.block == 3) return spmm_typed<float, float>(A, A->M.val32, 1, x, y, stream);
     return apply_typed<float, float, float, float>(A, A ? A->M.val32 : nullptr, x, y, stream);
 }
 
 extern "C" int spmv_apply_f32v(const spmv_matrix *A, const double *x, double *y, void *stream) {
+    if (A && A->M.block == 3) return fail(SPMV_ENOTSUP, "not available for block-CSR handles");
     if (A && !A->M.val32) return fail(SPMV_ENOTSUP, "matrix has no FP32 copy (create with SPMV_VALUES_FP32)");
     return apply_typed<float, double, double, double>(A, A ? A->M.val32 : nullptr, x, y, stream);
 }
 
 extern "C" int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream) {
+    if (A && A->M.block == 3) return fail(SPMV_ENOTSUP, "not available for block-CSR handles");
     if (A && !A->M.val16) return fail(SPMV_ENOTSUP, "matrix has no BF16 copy (create with SPMV_VALUES_BF16)");
     return apply_typed<uint16_t, float, float, float>(A, A ? A->M.val16 : nullptr, x, y, stream);
+}
+
+extern "C" int bsr3_spmm(const spmv_matrix *A, int32_t k, const double *X, double *Y, void *stream) {
+    return spmm_typed<double, double>(A, A ? A->M.val64 : nullptr, k, X, Y, stream);
+}
+
+extern "C" int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, void *stream) {
+    if (A && A->M.block == 3 && !A->M.val32)
+        return fail(SPMV_ENOTSUP, "matrix has no FP32 copy (create with SPMV_VALUES_FP32)");
+    return spmm_typed<float, float>(A, A ? A->M.val32 : nullptr, k, X, Y, stream);
+}
+
+extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int64_t nnz_blocks,
+                                const int32_t *brow_ptr, const int32_t *bcol_idx, const double *bvalues,
+                                uint32_t flags, spmv_matrix **out) {
+    clear_error();
+    if (!out) return fail(SPMV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP)) return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
+    if (nnz_blocks > (int64_t)(INT32_MAX / 9) - 64) return fail(SPMV_EINVAL, "too many blocks");
+    int rc = validate_csr(n_block_rows, n_block_cols, nnz_blocks, brow_ptr, bcol_idx);
+    if (rc) return rc;
+    if ((int64_t)n_block_rows * 3 > INT32_MAX || (int64_t)n_block_cols * 3 > INT32_MAX)
+        return fail(SPMV_EINVAL, "scalar dimension exceeds int32");
+    if (nnz_blocks > 0 && !bvalues) return fail(SPMV_EINVAL, "bvalues is NULL with nnz_blocks > 0");
+    std::vector<int32_t> tiles = build_bsr_tiles(n_block_rows, brow_ptr, kBsrRows, kBsrBlocks);
+    auto *A = new (std::nothrow) spmv_matrix();
+    if (!A) return fail(SPMV_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) {
+        delete A;
+        return hip_fail(e, "hipGetDevice");
+    }
+    DevMatrix &M = A->M;
+    M.block = 3;
+    M.n_rows = n_block_rows;
+    M.n_cols = n_block_cols;
+    M.nnz = nnz_blocks;
+    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    const size_t nb = (size_t)nnz_blocks;
+    rc = dev_upload(A, &M.row_ptr, brow_ptr, (size_t)n_block_rows + 1, 0);
+    if (!rc) rc = dev_upload(A, &M.col, bcol_idx, nb, nb + kPad);
+    if (!rc) rc = dev_upload(A, &M.val64, bvalues, 9 * nb, 9 * nb + kPad);
+    if (!rc && (flags & SPMV_VALUES_FP32)) {
+        std::vector<float> v32(9 * nb);
+        for (size_t k = 0; k < 9 * nb; ++k) v32[k] = (float)bvalues[k];
+        rc = dev_upload(A, &M.val32, v32.data(), 9 * nb, 9 * nb + kPad);
+    }
+    M.n_bsr_tiles = (int32_t)tiles.size() - 1;
+    if (!rc) rc = dev_upload(A, &M.bsr_tiles, tiles.data(), tiles.size(), 0);
+    if (rc) {
+        for (void *p : A->allocs) (void)hipFree(p);
+        delete A;
+        return rc;
+    }
+    spmv_info &I = A->info;
+    std::memset(&I, 0, sizeof I);
+    I.n_rows = n_block_rows;
+    I.n_cols = n_block_cols;
+    I.nnz = nnz_blocks;
+    I.n_tiles = M.n_bsr_tiles;
+    I.n_stream_tiles = M.n_bsr_tiles;
+    I.has_fp32 = M.val32 != nullptr;
+    I.device_bytes = A->bytes;
+    I.block_size = 3;
+    *out = A;
+    return SPMV_OK;
 }

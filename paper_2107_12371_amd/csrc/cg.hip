@@ -462,6 +462,7 @@ extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double
     auto t0 = std::chrono::steady_clock::now();
     if (info) std::memset(info, 0, sizeof *info);
     if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (A->M.block != 1) return fail(SPMV_ENOTSUP, "cg_solve needs a scalar CSR handle");
     if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
     if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
     if (mode != CG_FP64 && mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown CG mode %d", mode);

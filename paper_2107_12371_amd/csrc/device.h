@@ -19,6 +19,19 @@ enum Epilogue : int {
     EPI_RESID = 2   // y_i = b_i - (A x)_i and per-tile partial of sum_i y_i^2
 };
 
+// Per-tile launch descriptor (one 32-byte scalar load per tile).
+struct TileDesc {
+    int32_t r0, r1;   // rows [r0, r1)
+    int32_t s, e;     // stored entries [s, e) = [row_ptr[r0], row_ptr[r1])
+    int32_t seg;      // segment id (index of the tile's dot-product partial)
+    int32_t woff;     // window tiles: first x word staged before the tile
+    int32_t wcnt;     // window tiles: number of x words staged
+    int32_t pad;
+};
+
+// Kernel variants for the direct-gather tiles.
+enum KernelVariant : int32_t { KV_AUTO = 0, KV_ONE_TILE = 1, KV_PIPELINED = 2 };
+
 // Resident matrix and its plan in device memory.  Owned by spmv_matrix.
 struct DevMatrix {
     int32_t n_rows = 0, n_cols = 0;
@@ -30,18 +43,19 @@ struct DevMatrix {
     float *val32 = nullptr;          // optional FP32 copy
     uint16_t *val16 = nullptr;       // optional BF16 copy (upper half of an FP32)
     int32_t n_seg = 0;
-    int32_t *seg_bound = nullptr;    // n_seg + 1
     int32_t n_stream = 0;
-    int32_t *stream_list = nullptr;  // segment ids on the direct-gather path
+    TileDesc *stream_desc = nullptr; // direct-gather tiles, in row order
     int32_t n_long = 0;
-    int32_t *long_list = nullptr;    // segment ids of long rows
+    TileDesc *long_desc = nullptr;   // rows longer than a tile
     int32_t n_blk = 0;
-    int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_list
-    int32_t *win_list = nullptr;     // window segment ids
-    int32_t *win_off = nullptr;      // per win_list entry: first staged word
-    int32_t *win_cnt = nullptr;      // per win_list entry: staged words
+    int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_desc
+    TileDesc *win_desc = nullptr;    // window tiles, grouped by block
     int32_t ring_words = 0;
     bool xcd_remap = true;
+    int32_t kernel = KV_AUTO;        // direct-gather kernel variant
+    int32_t block = 1;                // 1: scalar CSR, 3: 3x3 block CSR
+    int32_t n_bsr_tiles = 0;
+    int32_t *bsr_tiles = nullptr;     // block-row tile boundaries (block CSR)
 };
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));

@@ -27,7 +27,7 @@ struct Plan {
     int32_t n_rows = 0, n_cols = 0;
     int64_t nnz = 0;
     int32_t tile_nnz = 0, tile_rows = 0;
-    int32_t window_mode = 0, ring_words = 0, window_block = 0;
+    int32_t window_mode = 0, ring_words = 0, window_block = 0, kernel = 0;
     double window_ratio = 0.0;
     std::vector<int32_t> seg_bound;  // n_seg + 1 row boundaries
     std::vector<int32_t> seg_kind;   // SegKind per segment
@@ -41,6 +41,12 @@ struct Plan {
     int64_t window_words = 0;
     int32_t n_seg() const { return (int32_t)seg_kind.size(); }
 };
+
+// Tiles of consecutive block rows for the 3x3 block kernel: at most
+// max_rows block rows and max_blocks stored blocks per tile; a longer block
+// row forms a tile of its own.  Returns n_tiles + 1 boundaries.
+std::vector<int32_t> build_bsr_tiles(int32_t n_block_rows, const int32_t *brow_ptr, int max_rows,
+                                     int max_blocks);
 
 int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                const int32_t *col_idx, const spmv_params *params, Plan &plan);

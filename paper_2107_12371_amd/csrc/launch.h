@@ -15,18 +15,35 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     const V *val;
     const X *x;
     Y *y;
-    const Y *b;           // EPI_RESID: right-hand side
-    double *part;         // EPI_DOT / EPI_RESID: one partial per segment
-    const int32_t *seg_bound;
-    const int32_t *list;  // segment ids (direct / long) or window segment ids
-    int32_t n_list;
-    int32_t per_xcd;      // > 0: XCD-grouped tile order (grid = 8 * per_xcd)
-    const int *done;      // optional: non-zero makes the launch a no-op (CG)
+    const Y *b;             // EPI_RESID: right-hand side
+    double *part;           // EPI_DOT / EPI_RESID: one partial per segment
+    const TileDesc *desc;   // tiles of this launch
+    int32_t n_list;         // number of tiles
+    int32_t per_xcd;        // > 0: tiles [x*per_xcd, (x+1)*per_xcd) belong to XCD x
+    int32_t wg_per_xcd;     // pipelined kernel: workgroups per XCD
+    const int *done;        // optional: non-zero makes the launch a no-op (CG)
     const int32_t *win_blk_ptr;
-    const int32_t *win_off;
-    const int32_t *win_cnt;
     int32_t ring_words;
 };
+
+constexpr int kBsrRows = 85;     // block rows per tile (3 lanes each)
+constexpr int kBsrBlocks = 512;  // stored 3x3 blocks staged in LDS per tile
+
+template <typename V, typename T> struct BsrArgs {
+    const int32_t *brow_ptr;
+    const int32_t *col;
+    const V *val;      // 9 values per block, row-major
+    const T *X;        // (3 n_cols) x ldx, row-major
+    T *Y;              // (3 n_rows) x ldy, row-major
+    const int32_t *tiles;  // n_tiles + 1 block-row boundaries
+    int32_t n_tiles;
+    int32_t per_xcd;
+    int32_t ldx, ldy, off;  // leading dimensions and first column of this launch
+};
+
+// Y = A X for a 3x3 block-CSR handle, k right-hand sides (row-major).
+template <typename V, typename T>
+hipError_t launch_bsr3(const DevMatrix &M, const V *val, int k, const T *X, T *Y, hipStream_t st);
 
 // y = A x over all segments of M (direct tiles, long rows, window blocks),
 // launched on `st`.  V: stored value type (double, float, uint16_t = bf16),
@@ -39,5 +56,9 @@ hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int e
 // Opts every window-kernel instantiation into up to 8192 ring words of
 // dynamic LDS.  Called once when a matrix with window blocks is created.
 hipError_t prepare_window_kernels();
+
+// Caches the device's CU count and each kernel's occupancy so no runtime
+// query is made later (for example while a CG graph is being captured).
+void prepare_launch_queries();
 
 }  // namespace spmvlib

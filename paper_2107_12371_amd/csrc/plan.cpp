@@ -60,6 +60,26 @@ int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row
     return SPMV_OK;
 }
 
+std::vector<int32_t> build_bsr_tiles(int32_t n_block_rows, const int32_t *brow_ptr, int max_rows,
+                                     int max_blocks) {
+    std::vector<int32_t> t;
+    int32_t r = 0;
+    while (r < n_block_rows) {
+        t.push_back(r);
+        int32_t r1 = r + 1;
+        int64_t acc = (int64_t)brow_ptr[r + 1] - brow_ptr[r];
+        while (r1 < n_block_rows && r1 - r < max_rows) {
+            int64_t l = (int64_t)brow_ptr[r1 + 1] - brow_ptr[r1];
+            if (acc + l > max_blocks) break;
+            acc += l;
+            ++r1;
+        }
+        r = r1;
+    }
+    t.push_back(n_block_rows);
+    return t;
+}
+
 static int default_tile_nnz(int64_t nnz) {
     // Enough tiles to give every CU several workgroups (256 CUs on MI355X).
     if (nnz >= (int64_t)4096 * 4096) return 4096;
@@ -84,11 +104,13 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
         return fail(SPMV_EINVAL, "ring_words = %d must be a power of two in [256, 8192]", ring);
     double ratio = p.window_ratio > 0.0 ? p.window_ratio : 0.25;
     if (p.window_block < 0) return fail(SPMV_EINVAL, "window_block = %d < 0", p.window_block);
+    if (p.kernel < 0 || p.kernel > 2) return fail(SPMV_EINVAL, "kernel = %d unknown", p.kernel);
 
     P = Plan{};
     P.n_rows = n_rows; P.n_cols = n_cols; P.nnz = nnz;
     P.tile_nnz = tnz; P.tile_rows = trows; P.window_mode = wmode; P.ring_words = ring;
     P.window_ratio = ratio;
+    P.kernel = p.kernel;
 
     // ---- segmentation into stream tiles and long rows
     int32_t r = 0;
@@ -182,6 +204,18 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
             s = e;
         }
         if (!P.win_list.empty()) P.win_blk_ptr.push_back((int32_t)P.win_list.size());
+        // AUTO keeps the window only when it covers most of the matrix: a few
+        // window blocks next to many direct tiles would run as a serial tail.
+        if (wmode == SPMV_WINDOW_AUTO && 2 * (int64_t)P.win_list.size() < (int64_t)n_stream) {
+            for (int32_t t : P.win_list) {
+                P.seg_kind[t] = SEG_STREAM;
+                P.win_off[t] = P.win_cnt[t] = 0;
+                P.win_block[t] = -1;
+            }
+            P.win_list.clear();
+            P.win_blk_ptr.clear();
+            P.window_words = 0;
+        }
     }
     for (int32_t s = 0; s < nseg; ++s) {
         if (P.seg_kind[s] == SEG_STREAM) P.stream_list.push_back(s);

@@ -7,7 +7,8 @@
 // on the window path, from an LDS ring that plays the part of the paper's
 // circular BRAM vector cache (Sec. 5.1).
 //
-// Three kernels share one row-tile scheme:
+// Four kernels share one row-tile scheme:
+//  * k_pipe    (direct gathers, default): persistent workgroups, see below.
 //  * k_stream  (direct gathers): one workgroup per row tile.  Pass 1 streams
 //    the tile's values and column indices with 16-byte non-temporal loads,
 //    4 consecutive entries per lane, all passes issued before any gather
@@ -28,6 +29,8 @@
 #include "device.h"
 #include "launch.h"
 
+#include <algorithm>
+
 namespace spmvlib {
 
 template <typename A, typename V> __device__ __forceinline__ A to_acc(V v) { return static_cast<A>(v); }
@@ -35,49 +38,67 @@ template <> __device__ __forceinline__ float to_acc<float, uint16_t>(uint16_t v)
     return __uint_as_float(static_cast<unsigned>(v) << 16);
 }
 
-// Pass 1: products of the tile's entries [s, e) into prod[k - s4], s4 = s & ~3.
-template <typename V, typename X, typename A, int NT, class Gather>
-__device__ __forceinline__ void tile_products(const int32_t *__restrict__ col, const V *__restrict__ val,
-                                              int s, int e, A *__restrict__ prod, Gather gather) {
-    constexpr int kPass = kEntriesPerLane * kBlock;
-    constexpr int kMaxPass = (NT + 3 + kPass - 1) / kPass;
-    const int s4 = s & ~3;
-    const int npass = (e - s4 + kPass - 1) / kPass;
-    const int lane0 = kEntriesPerLane * threadIdx.x;
+// A tile's stored entries [s, e) held in registers: each lane owns 4
+// consecutive entries per pass (16-byte loads), s4 = s & ~3 aligns the
+// first pass.  load() issues every pass's loads before anything waits.
+template <typename V, int NT> struct TileRegs {
+    static constexpr int kPass = kEntriesPerLane * kBlock;
+    static constexpr int kMaxPass = (NT + 3 + kPass - 1) / kPass;
     i32x4 c[kMaxPass];
     Val4<V> v[kMaxPass];
+
+    __device__ __forceinline__ void load(const int32_t *__restrict__ col, const V *__restrict__ val, int s, int e) {
+        const int s4 = s & ~3;
+        const int npass = (e - s4 + kPass - 1) / kPass;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
 #pragma unroll
-    for (int p = 0; p < kMaxPass; ++p) {
-        const int k = s4 + p * kPass + lane0;
-        c[p] = i32x4{0, 0, 0, 0};
-        v[p].zero();
-        if (p < npass && k < e) {
-            c[p] = load_col4(col + k);
-            v[p].load(val + k);
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k = s4 + p * kPass + lane0;
+            c[p] = i32x4{0, 0, 0, 0};
+            v[p].zero();
+            if (p < npass && k < e) {
+                c[p] = load_col4(col + k);
+                v[p].load(val + k);
+            }
         }
     }
-    A xv[kMaxPass][4];
+
+    // x[c] for the lane's entries that lie in [s, e) (0 elsewhere)
+    template <typename A, class Gather>
+    __device__ __forceinline__ void gather(int s, int e, Gather g, A (&xv)[kMaxPass][4]) const {
+        const int s4 = s & ~3;
+        const int npass = (e - s4 + kPass - 1) / kPass;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
 #pragma unroll
-    for (int p = 0; p < kMaxPass; ++p) {
-        const int k = s4 + p * kPass + lane0;
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k = s4 + p * kPass + lane0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool ok = p < npass && k + j >= s && k + j < e;
-            xv[p][j] = ok ? static_cast<A>(gather(c[p][j])) : A(0);
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = p < npass && k + j >= s && k + j < e;
+                xv[p][j] = ok ? static_cast<A>(g(c[p][j])) : A(0);
+            }
         }
     }
+
+    // products a_k * x[c_k] into prod[k - s4]
+    template <typename A>
+    __device__ __forceinline__ void products(int s, int e, const A (&xv)[kMaxPass][4], A *__restrict__ prod) const {
+        const int s4 = s & ~3;
+        const int npass = (e - s4 + kPass - 1) / kPass;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
 #pragma unroll
-    for (int p = 0; p < kMaxPass; ++p) {
-        const int k = s4 + p * kPass + lane0;
-        if (p < npass && k < e) {
-            A *d = prod + (k - s4);
-            d[0] = to_acc<A>(v[p].template get<0>()) * xv[p][0];
-            d[1] = to_acc<A>(v[p].template get<1>()) * xv[p][1];
-            d[2] = to_acc<A>(v[p].template get<2>()) * xv[p][2];
-            d[3] = to_acc<A>(v[p].template get<3>()) * xv[p][3];
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k = s4 + p * kPass + lane0;
+            if (p < npass && k < e) {
+                A *d = prod + (k - s4);
+                d[0] = to_acc<A>(v[p].template get<0>()) * xv[p][0];
+                d[1] = to_acc<A>(v[p].template get<1>()) * xv[p][1];
+                d[2] = to_acc<A>(v[p].template get<2>()) * xv[p][2];
+                d[3] = to_acc<A>(v[p].template get<3>()) * xv[p][3];
+            }
         }
     }
-}
+};
 
 // Pass 2: per-row sums of the tile's rows [r0, r1), epilogue, optional partial.
 template <typename X, typename Y, typename A, int EPI>
@@ -105,6 +126,7 @@ __device__ __forceinline__ void tile_rows(const int32_t *__restrict__ row_ptr, i
     }
 }
 
+// One workgroup per tile.
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 __global__ __launch_bounds__(kBlock) void k_stream(SpmvArgs<V, X, Y> g) {
     __shared__ A prod[NT + 8];
@@ -113,24 +135,66 @@ __global__ __launch_bounds__(kBlock) void k_stream(SpmvArgs<V, X, Y> g) {
     const int b = blockIdx.x;
     const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
     if (li >= g.n_list) return;
-    const int seg = g.list[li];
-    const int r0 = g.seg_bound[seg], r1 = g.seg_bound[seg + 1];
-    const int s = g.row_ptr[r0], e = g.row_ptr[r1];
+    const TileDesc d = g.desc[li];
     const X *__restrict__ x = g.x;
-    tile_products<V, X, A, NT>(g.col, g.val, s, e, prod, [x](int c) { return x[c]; });
+    TileRegs<V, NT> t;
+    t.load(g.col, g.val, d.s, d.e);
+    A xv[TileRegs<V, NT>::kMaxPass][4];
+    t.gather(d.s, d.e, [x](int c) { return x[c]; }, xv);
+    t.products(d.s, d.e, xv, prod);
     __syncthreads();
-    tile_rows<X, Y, A, EPI>(g.row_ptr, r0, r1, s & ~3, prod, g.x, g.y, g.b, g.part, seg, sh);
+    tile_rows<X, Y, A, EPI>(g.row_ptr, d.r0, d.r1, d.s & ~3, prod, g.x, g.y, g.b, g.part, d.seg, sh);
+}
+
+// Pipelined: a workgroup walks the tiles x*per_xcd + j, + W, + 2W, ... of
+// its XCD's range (the XCD's workgroups advance through the range together,
+// so x stays hot in that XCD's L2) and issues the next tile's stream loads
+// right after the current tile's gathers, so the matrix stream stays in
+// flight while the gathers, the LDS products and the row sums run.
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+__global__ __launch_bounds__(kBlock) void k_pipe(SpmvArgs<V, X, Y> g) {
+    __shared__ A prod[NT + 8];
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int end = min(g.n_list, (xcd + 1) * g.per_xcd);
+    const int W = g.wg_per_xcd;
+    int li = xcd * g.per_xcd + j;
+    if (li >= end) return;
+    const X *__restrict__ x = g.x;
+    TileDesc d = g.desc[li];
+    TileRegs<V, NT> cur;
+    cur.load(g.col, g.val, d.s, d.e);
+    for (;;) {
+        const int ln = li + W;
+        const bool more = ln < end;
+        A xv[TileRegs<V, NT>::kMaxPass][4];
+        cur.gather(d.s, d.e, [x](int c) { return x[c]; }, xv);
+        TileDesc dn = d;
+        TileRegs<V, NT> nxt;
+        if (more) {
+            dn = g.desc[ln];
+            nxt.load(g.col, g.val, dn.s, dn.e);
+        }
+        cur.products(d.s, d.e, xv, prod);
+        __syncthreads();
+        tile_rows<X, Y, A, EPI>(g.row_ptr, d.r0, d.r1, d.s & ~3, prod, g.x, g.y, g.b, g.part, d.seg, sh);
+        __syncthreads();
+        if (!more) break;
+        cur = nxt;
+        d = dn;
+        li = ln;
+    }
 }
 
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
-    const int seg = g.list[blockIdx.x];
-    const int r = g.seg_bound[seg];
-    const int s = g.row_ptr[r], e = g.row_ptr[r + 1];
+    const TileDesc d = g.desc[blockIdx.x];
+    const int r = d.r0;
     A acc = A(0);
-    for (int k = s + (int)threadIdx.x; k < e; k += kBlock)
+    for (int k = d.s + (int)threadIdx.x; k < d.e; k += kBlock)
         acc += to_acc<A>(g.val[k]) * static_cast<A>(g.x[g.col[k]]);
     // Fixed-shape reduction in double, then rounded to the accumulator type.
     const double t = block_sum(static_cast<double>(acc), sh);
@@ -145,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
             g.y[r] = static_cast<Y>(sum);
             dot = static_cast<double>(sum) * static_cast<double>(g.x[r]);
         }
-        if (EPI != EPI_PLAIN) g.part[seg] = dot;
+        if (EPI != EPI_PLAIN) g.part[d.seg] = dot;
     }
 }
 
@@ -159,49 +223,81 @@ __global__ __launch_bounds__(kBlock) void k_window(SpmvArgs<V, X, Y> g) {
     const int mask = g.ring_words - 1;
     const int t0 = g.win_blk_ptr[blockIdx.x], t1 = g.win_blk_ptr[blockIdx.x + 1];
     for (int t = t0; t < t1; ++t) {
-        const int seg = g.list[t];
-        const int r0 = g.seg_bound[seg], r1 = g.seg_bound[seg + 1];
-        const int s = g.row_ptr[r0], e = g.row_ptr[r1];
+        const TileDesc d = g.desc[t];
+        TileRegs<V, NT> regs;
+        regs.load(g.col, g.val, d.s, d.e);
         // stage the words this tile needs that are not resident yet
-        const int off = g.win_off[t], cnt = g.win_cnt[t];
-        for (int w = (int)threadIdx.x; w < cnt; w += kBlock) ring[(off + w) & mask] = g.x[off + w];
+        for (int w = (int)threadIdx.x; w < d.wcnt; w += kBlock) ring[(d.woff + w) & mask] = g.x[d.woff + w];
         __syncthreads();
         const X *rg = ring;
-        tile_products<V, X, A, NT>(g.col, g.val, s, e, prod, [rg, mask](int c) { return rg[c & mask]; });
+        A xv[TileRegs<V, NT>::kMaxPass][4];
+        regs.gather(d.s, d.e, [rg, mask](int c) { return rg[c & mask]; }, xv);
+        regs.products(d.s, d.e, xv, prod);
         __syncthreads();
-        tile_rows<X, Y, A, EPI>(g.row_ptr, r0, r1, s & ~3, prod, g.x, g.y, g.b, g.part, seg, sh);
+        tile_rows<X, Y, A, EPI>(g.row_ptr, d.r0, d.r1, d.s & ~3, prod, g.x, g.y, g.b, g.part, d.seg, sh);
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- launch
 
+// Resident workgroups per CU of the pipelined kernel (queried once per
+// instantiation; every thread that races here computes the same value).
+template <typename V, typename X, typename Y, typename A, int NT, int EPI> static int pipe_occupancy() {
+    static int occ = 0;
+    if (occ == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<V, X, Y, A, NT, EPI>, kBlock, 0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        occ = n;
+    }
+    return occ;
+}
+
+static int cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 8)
+            n = 256;
+        cus = n;
+    }
+    return cus;
+}
+
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
     if (M.n_stream > 0) {
         SpmvArgs<V, X, Y> a = g;
-        a.list = M.stream_list;
+        a.desc = M.stream_desc;
         a.n_list = M.n_stream;
-        int grid = M.n_stream;
-        a.per_xcd = 0;
-        if (M.xcd_remap && M.n_stream >= 16) {
+        const bool pipe = M.kernel != KV_ONE_TILE && M.n_stream >= 64;
+        if (pipe) {
             a.per_xcd = (M.n_stream + 7) / 8;
-            grid = 8 * a.per_xcd;
+            const int resident = pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
+            a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
+            hipLaunchKernelGGL((k_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st, a);
+        } else {
+            int grid = M.n_stream;
+            a.per_xcd = 0;
+            if (M.xcd_remap && M.n_stream >= 16) {
+                a.per_xcd = (M.n_stream + 7) / 8;
+                grid = 8 * a.per_xcd;
+            }
+            hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
-        hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
     }
     if (M.n_long > 0) {
         SpmvArgs<V, X, Y> a = g;
-        a.list = M.long_list;
+        a.desc = M.long_desc;
         a.n_list = M.n_long;
         hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
     }
     if (M.n_blk > 0) {
         SpmvArgs<V, X, Y> a = g;
-        a.list = M.win_list;
+        a.desc = M.win_desc;
         a.win_blk_ptr = M.win_blk_ptr;
-        a.win_off = M.win_off;
-        a.win_cnt = M.win_cnt;
         a.ring_words = M.ring_words;
         const size_t lds = sizeof(X) * (size_t)M.ring_words;
         hipLaunchKernelGGL((k_window<V, X, Y, A, NT, EPI>), dim3(M.n_blk), dim3(kBlock), lds, st, a);
@@ -229,7 +325,6 @@ hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int e
     g.y = y;
     g.b = b;
     g.part = part;
-    g.seg_bound = M.seg_bound;
     g.done = done;
     switch (epi) {
         case EPI_DOT: return launch_epi<V, X, Y, A, EPI_DOT>(M, g, st);
@@ -257,6 +352,22 @@ template <typename V, typename X, typename Y, typename A> static hipError_t opt_
     if (e == hipSuccess) e = opt_in_lds<V, X, Y, A, 2048>();
     if (e == hipSuccess) e = opt_in_lds<V, X, Y, A, 4096>();
     return e;
+}
+
+template <typename V, typename X, typename Y, typename A> static void warm_types() {
+    pipe_occupancy<V, X, Y, A, 1024, EPI_PLAIN>(); pipe_occupancy<V, X, Y, A, 1024, EPI_DOT>();
+    pipe_occupancy<V, X, Y, A, 1024, EPI_RESID>(); pipe_occupancy<V, X, Y, A, 2048, EPI_PLAIN>();
+    pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
+    pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
+    pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
+}
+
+void prepare_launch_queries() {
+    cu_count();
+    warm_types<double, double, double, double>();
+    warm_types<float, float, float, float>();
+    warm_types<float, double, double, double>();
+    warm_types<uint16_t, float, float, float>();
 }
 
 hipError_t prepare_window_kernels() {

@@ -100,12 +100,13 @@ def test_nan_inf_propagate_like_the_oracle():
 
 @pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
-@pytest.mark.parametrize("remap", [True, False])
-def test_mesh_config0_paths(mode, tile, remap):
+@pytest.mark.parametrize("kernel,remap", [(1, True), (1, False), (2, True)])
+def test_mesh_config0_paths(mode, tile, kernel, remap):
     A = mg.config0()
     x = mg.uniform(A.n_cols, 12, 0)
     y, info = run64(A, x, xcd_remap=remap,
-                    params={"tile_nnz": tile, "window_mode": mode, "window_block": 8, "ring_words": 8192})
+                    params={"tile_nnz": tile, "window_mode": mode, "window_block": 8, "ring_words": 8192,
+                            "kernel": kernel})
     if mode == spmv.WINDOW_FORCE:
         assert info["n_window_tiles"] > 0
     assert_parity(y, A, x)
@@ -181,12 +182,21 @@ def cfg1():
 
 
 @pytest.mark.parametrize("ordering", ["rcm", "random"])
-def test_config1_full_size_and_permutation_equivariance(cfg1, ordering):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_config1_full_size_and_permutation_equivariance(cfg1, ordering, kernel):
     A = cfg1[ordering]
     assert A.n_rows == 126 ** 3
     x = mg.uniform(A.n_cols, 16, 0)
-    y, _ = run64(A, x)
+    y, _ = run64(A, x, params={"kernel": kernel})
     assert_parity(y, A, x)
+
+
+def test_kernel_variants_bitwise_identical(cfg1):
+    # the variants differ only in scheduling: every row's sum has the same order
+    A = cfg1["rcm"]
+    x = mg.uniform(A.n_cols, 19, 0)
+    ys = [run64(A, x, params={"kernel": k, "tile_nnz": 2048})[0] for k in (1, 2)]
+    assert np.array_equal(ys[0], ys[1])
 
 
 def test_config1_orderings_agree(cfg1):
@@ -246,3 +256,73 @@ def test_missing_copies_and_bad_arguments():
             M.apply(torch.zeros(A.n_cols, dtype=torch.float32, device=DEV))
         with pytest.raises(ValueError):
             M.apply(torch.zeros(A.n_cols + 1, dtype=torch.float64, device=DEV))
+
+
+# ------------------------------------------------------------ 3x3 block CSR
+
+def _bsr_bound_check(Y, A, X, rel):
+    Yr, Bd = oracle.bsr3_spmm(A, X)
+    assert np.all(np.abs(Y - Yr) <= rel * Bd), float(np.max(np.abs(Y - Yr) / np.maximum(Bd, 1e-300)))
+    return Yr
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 13])
+def test_bsr3_multi_rhs_fp64(k):
+    A = mg.bsr3(23, 17, 11, seed=5)
+    X = mg.uniform(3 * A.n_cols * k, 20 + k, 0).reshape(3 * A.n_cols, k)
+    with spmv.Matrix.from_csr(A) as M:
+        Y = M.spmm(to_dev(X)).cpu().numpy()
+        if k == 1:
+            y1 = M.apply(to_dev(X[:, 0])).cpu().numpy()
+            assert np.array_equal(y1, Y[:, 0])
+        # each column equals the one-column product of that column
+        for j in (0, k - 1):
+            yj = M.spmm(to_dev(X[:, j:j + 1].copy())).cpu().numpy()
+            assert np.array_equal(yj[:, 0], Y[:, j])
+    _bsr_bound_check(Y, A, X, 1e-12)
+
+
+def test_bsr3_fp32_storage_and_long_block_rows():
+    A = mg.bsr3(20, 20, 10, seed=6)
+    X = mg.uniform(3 * A.n_cols * 4, 30, 0).reshape(3 * A.n_cols, 4)
+    with spmv.Matrix.from_csr(A, fp32=True) as M:
+        Y = M.spmm_f32(to_dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+    m = 3 * np.repeat(np.diff(A.row_ptr), 3)[:, None].astype(np.float64)
+    _bsr_bound_check(Y, A, X, 1.01 * (m + 2) * 2.0 ** -24)
+    # a block row with 700 blocks (more than one tile can stage)
+    nbr, nbc = 40, 800
+    lens = np.full(nbr, 3)
+    lens[7] = 700
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    rng = np.random.default_rng(1)
+    ci = np.concatenate([np.sort(rng.choice(nbc, size=L, replace=False)) for L in lens]).astype(np.int32)
+    va = rng.uniform(-1, 1, (ci.shape[0], 3, 3))
+    B = mg.CSR(nbr, nbc, rp, ci, va, 3)
+    Xb = mg.uniform(3 * nbc * 8, 31, 0).reshape(3 * nbc, 8)
+    with spmv.Matrix.from_csr(B) as M:
+        Yb = M.spmm(to_dev(Xb)).cpu().numpy()
+    _bsr_bound_check(Yb, B, Xb, 1e-12)
+
+
+def test_bsr3_config3_shape_bitwise_dyadic():
+    A = mg.bsr3(40, 40, 20, seed=7)
+    # dyadic copy of the values: multiples of 2^-10 in [-2, 2]
+    A.values = np.round(A.values * 1024) / 1024
+    X = (np.floor(mg.uniform(3 * A.n_cols * 8, 32, 0, 0.0, 1.0) * 2049) - 1024).reshape(3 * A.n_cols, 8) / 1024
+    with spmv.Matrix.from_csr(A) as M:
+        Y = M.spmm(to_dev(X)).cpu().numpy()
+    Yr, _ = oracle.bsr3_spmm(A, X)
+    assert np.array_equal(Y, Yr)
+
+
+def test_bsr3_rejects_misuse():
+    A = mg.bsr3(5, 5, 5, seed=8)
+    with spmv.Matrix.from_csr(A) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.ones(3 * A.n_rows, dtype=torch.float64, device=DEV))
+        assert e.value.code == spmv.SPMV_ENOTSUP
+    C = mg.config0()
+    with spmv.Matrix.from_csr(C) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.spmm(torch.ones((C.n_cols, 1), dtype=torch.float64, device=DEV))
+        assert e.value.code == spmv.SPMV_ENOTSUP
