@@ -64,9 +64,9 @@ typedef struct spmv_matrix spmv_matrix;
 
 /* Analysis parameters; zero fields take the defaults (shown). */
 typedef struct spmv_params {
-    int32_t tile_nnz;      /* max stored entries per row tile: 1024, 2048 or 4096
-                              (0: chosen from nnz; rows longer than this take the
-                              long-row path) */
+    int32_t tile_nnz;      /* row-tile capacity: 1024, 2048 or 4096; a tile holds
+                              at most tile_nnz - 3 stored entries (0: chosen from
+                              nnz; longer rows take the long-row path) */
     int32_t tile_rows;     /* max rows per tile, <= 512 (0: 512) */
     int32_t window_mode;   /* SPMV_WINDOW_* (0: AUTO) */
     int32_t ring_words;    /* LDS ring capacity in x words, a power of two in
@@ -75,8 +75,9 @@ typedef struct spmv_params {
                               (0: chosen from the tile count) */
     double window_ratio;   /* AUTO uses the window for a block when staged words
                               <= window_ratio * stored entries (0: 0.25) */
-    int32_t kernel;        /* direct-gather kernel: 0 auto (pipelined), 1 one
-                              workgroup per tile, 2 pipelined persistent */
+    int32_t kernel;        /* direct-gather kernel: 0 auto, 1 one workgroup per
+                              tile, 2 pipelined persistent workgroups, 3 persistent
+                              wavefront tiles (tile_nnz 1024, <= 128 rows) */
 } spmv_params;
 
 /* Summary of a handle's analysis plan and resident storage. */

@@ -104,11 +104,23 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
         return fail(SPMV_EINVAL, "ring_words = %d must be a power of two in [256, 8192]", ring);
     double ratio = p.window_ratio > 0.0 ? p.window_ratio : 0.25;
     if (p.window_block < 0) return fail(SPMV_EINVAL, "window_block = %d < 0", p.window_block);
-    if (p.kernel < 0 || p.kernel > 2) return fail(SPMV_EINVAL, "kernel = %d unknown", p.kernel);
+    if (p.kernel < 0 || p.kernel > 3) return fail(SPMV_EINVAL, "kernel = %d unknown", p.kernel);
+    if (p.kernel == 3) {
+        // wavefront tiles: 1024-entry capacity, two rows per lane
+        if (p.tile_nnz && p.tile_nnz != 1024)
+            return fail(SPMV_EINVAL, "kernel 3 (wavefront tiles) needs tile_nnz = 1024");
+        if (p.tile_rows > 128) return fail(SPMV_EINVAL, "kernel 3 (wavefront tiles) allows at most 128 rows");
+        tnz = 1024;
+        trows = p.tile_rows ? p.tile_rows : 128;
+    }
 
     P = Plan{};
     P.n_rows = n_rows; P.n_cols = n_cols; P.nnz = nnz;
     P.tile_nnz = tnz; P.tile_rows = trows; P.window_mode = wmode; P.ring_words = ring;
+    // A tile's first entry may sit up to 3 past a 4-aligned boundary and the
+    // kernels stream whole aligned groups, so a tile holds at most tnz - 3
+    // entries (its aligned span then fits tnz exactly).
+    const int cap = tnz - 3;
     P.window_ratio = ratio;
     P.kernel = p.kernel;
 
@@ -116,7 +128,7 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
     int32_t r = 0;
     while (r < n_rows) {
         int64_t len = (int64_t)row_ptr[r + 1] - row_ptr[r];
-        if (len > tnz) {
+        if (len > cap) {
             P.seg_bound.push_back(r);
             P.seg_kind.push_back(SEG_LONG);
             ++r;
@@ -126,7 +138,7 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
         int64_t acc = 0;
         while (r1 < n_rows && r1 - r < trows) {
             int64_t l = (int64_t)row_ptr[r1 + 1] - row_ptr[r1];
-            if (l > tnz || acc + l > tnz) break;
+            if (l > cap || acc + l > cap) break;
             acc += l;
             ++r1;
         }

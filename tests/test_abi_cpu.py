@@ -82,10 +82,13 @@ def check_plan(A, params=None):
     seg_nnz = rp[sb[1:]] - rp[sb[:-1]]
     seg_rows = np.diff(sb)
     lng = kind == 1
-    assert np.all(seg_rows[lng] == 1) and np.all(seg_nnz[lng] > tnz)
-    assert np.all(seg_nnz[~lng] <= tnz) and np.all(seg_rows[~lng] <= trows)
+    cap = tnz - 3                     # a tile's 4-aligned span must fit tnz
+    assert np.all(seg_rows[lng] == 1) and np.all(seg_nnz[lng] > cap)
+    assert np.all(seg_nnz[~lng] <= cap) and np.all(seg_rows[~lng] <= trows)
+    s4 = rp[sb[:-1]] & ~3
+    assert np.all(rp[sb[1:]][~lng] - s4[~lng] <= tnz)
     # every row longer than a tile is a long-row segment
-    long_rows = np.nonzero(np.diff(rp) > tnz)[0]
+    long_rows = np.nonzero(np.diff(rp) > cap)[0]
     assert set(long_rows) == set(sb[:-1][lng])
     # window tiles: replay the staging of each block and check every column
     # a tile reads is resident, with the paper's count_i = colend_i - colend_{i-1}

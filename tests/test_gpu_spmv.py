@@ -100,13 +100,13 @@ def test_nan_inf_propagate_like_the_oracle():
 
 @pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
-@pytest.mark.parametrize("kernel,remap", [(1, True), (1, False), (2, True)])
+@pytest.mark.parametrize("kernel,remap", [(1, True), (1, False), (2, True), (3, True)])
 def test_mesh_config0_paths(mode, tile, kernel, remap):
     A = mg.config0()
     x = mg.uniform(A.n_cols, 12, 0)
     y, info = run64(A, x, xcd_remap=remap,
-                    params={"tile_nnz": tile, "window_mode": mode, "window_block": 8, "ring_words": 8192,
-                            "kernel": kernel})
+                    params={"tile_nnz": 1024 if kernel == 3 else tile, "window_mode": mode, "window_block": 8,
+                            "ring_words": 8192, "kernel": kernel})
     if mode == spmv.WINDOW_FORCE:
         assert info["n_window_tiles"] > 0
     assert_parity(y, A, x)
@@ -182,7 +182,7 @@ def cfg1():
 
 
 @pytest.mark.parametrize("ordering", ["rcm", "random"])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_config1_full_size_and_permutation_equivariance(cfg1, ordering, kernel):
     A = cfg1[ordering]
     assert A.n_rows == 126 ** 3
@@ -195,8 +195,8 @@ def test_kernel_variants_bitwise_identical(cfg1):
     # the variants differ only in scheduling: every row's sum has the same order
     A = cfg1["rcm"]
     x = mg.uniform(A.n_cols, 19, 0)
-    ys = [run64(A, x, params={"kernel": k, "tile_nnz": 2048})[0] for k in (1, 2)]
-    assert np.array_equal(ys[0], ys[1])
+    ys = [run64(A, x, params={"kernel": k, "tile_nnz": 1024 if k == 3 else 2048})[0] for k in (1, 2, 3)]
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
 
 
 def test_config1_orderings_agree(cfg1):
