@@ -11,7 +11,9 @@ Besides the JSON fields the driver needs, the line carries:
   roofline      for the dominant kernel (the row-tile kernel), HBM bound
   cpu_baseline  the CPU oracle timed on this host on the same matrix
   extras        FP32 SpMV bandwidth, FP64 vs mixed-precision CG to 1e-10,
-                copy-kernel HBM ceiling (measured outside the timed region)
+                copy-kernel HBM ceiling, and a serving run (Poisson request
+                stream over a pool of mesh matrices: p50/p99 latency and
+                throughput) -- all measured outside the timed region
 Progress goes to stderr; stdout gets exactly one JSON line.
 """
 from __future__ import annotations
@@ -32,8 +34,8 @@ METRIC = "SpMV effective HBM GB/s (% of peak) FP64 vs mixed; CG solves/s + p99 l
 PEAK_HBM_GBS = 8000.0
 DOMINANT_KERNEL = "k_stream<double, double, double, double, 4096, 0>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_fp64_hex27_16M_rcm_traffic.txt")
-KERNEL_SOURCES = ["paper_2107_12371_amd/csrc/spmv_kernels.hip", "paper_2107_12371_amd/csrc/device.h",
-                  "paper_2107_12371_amd/csrc/launch.h"]
+KERNEL_SOURCES = ["paper_2107_12371_amd/csrc/spmv_kernels.hip", "paper_2107_12371_amd/csrc/tile.h",
+                  "paper_2107_12371_amd/csrc/device.h", "paper_2107_12371_amd/csrc/launch.h"]
 
 
 def log(*a):
@@ -103,6 +105,98 @@ def cpu_baseline(A, x, budget_s: float):
                       f"oracle, {per * 1e3:.1f} ms each"}
 
 
+def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=log):
+    """Request stream: a pool of 32^3-style mesh matrices with log-uniform
+    10^3..10^6 rows; each request picks a matrix uniformly and asks for
+    k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  Arrivals are Poisson at
+    0.7x the closed-loop capacity measured on a first burst."""
+    import threading
+
+    import meshgen as mg
+    import paper_2107_12371_amd as spmv
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(1e6), pool_size)).astype(int)
+    t0 = time.perf_counter()
+    pool = [mg.serving_matrix(int(n), seed ^ (i + 1)) for i, n in enumerate(sizes)]
+    log(f"serving pool: {pool_size} matrices, {sum(A.n_rows for A in pool)} rows "
+        f"({time.perf_counter() - t0:.1f} s)")
+
+    def make(i):
+        r = np.random.default_rng(seed * 7919 + i)
+        mid = int(r.integers(pool_size))
+        A = pool[mid]
+        if r.random() < 0.5:
+            k = int(r.integers(1, 65))
+            return ("spmv", mid, r.uniform(-1, 1, (k, A.n_cols)))
+        return ("cg", mid, r.uniform(-1, 1, A.n_rows))
+
+    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode)
+    for A in pool:
+        srv.add_matrix(A)
+
+    def submit(r):
+        kind, mid, data = r
+        return srv.submit_spmv(mid, data) if kind == "spmv" else srv.submit_cg(mid, data, tol=1e-8)
+
+    # closed-loop capacity: a burst (also uploads the pool on first touch)
+    burst = [make(-1 - i) for i in range(min(64, n_requests))]
+    tb = time.perf_counter()
+    for t in [submit(r) for r in burst]:
+        srv.wait(t)
+    burst2 = [make(-1000 - i) for i in range(min(64, n_requests))]
+    tb = time.perf_counter()
+    for t in [submit(r) for r in burst2]:
+        srv.wait(t)
+    cap = len(burst2) / (time.perf_counter() - tb)
+    lam = 0.7 * cap
+    reqs = [make(i) for i in range(n_requests)]
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / lam, n_requests)
+    tickets = [None] * n_requests
+
+    def driver():
+        start = time.perf_counter()
+        due = start
+        for i, r in enumerate(reqs):
+            due += gaps[i]
+            d = due - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = submit(r)
+
+    th = threading.Thread(target=driver)
+    t1 = time.perf_counter()
+    th.start()
+    th.join()
+    lat, lat_cg, lat_spmv, iters, fails = [], [], [], [], 0
+    for r, t in zip(reqs, tickets):
+        _, res = srv.wait(t)
+        if res.status != 0:
+            fails += 1
+            continue
+        lat.append(res.latency_s)
+        (lat_cg if r[0] == "cg" else lat_spmv).append(res.latency_s)
+        if r[0] == "cg":
+            iters.append(res.iterations)
+    wall = time.perf_counter() - t1
+    st = srv.stats()
+    srv.close()
+    q = lambda a, f: float(np.quantile(np.array(a), f)) if a else None
+    out = {"requests": n_requests, "pool": pool_size, "arrival_rate_rps": round(lam, 2),
+           "closed_loop_capacity_rps": round(cap, 2), "cg_mode": "mixed" if cg_mode else "fp64",
+           "p50_ms": round(1e3 * q(lat, 0.5), 3), "p99_ms": round(1e3 * q(lat, 0.99), 3),
+           "p50_cg_ms": round(1e3 * q(lat_cg, 0.5), 3) if lat_cg else None,
+           "p99_cg_ms": round(1e3 * q(lat_cg, 0.99), 3) if lat_cg else None,
+           "p50_spmv_ms": round(1e3 * q(lat_spmv, 0.5), 3) if lat_spmv else None,
+           "p99_spmv_ms": round(1e3 * q(lat_spmv, 0.99), 3) if lat_spmv else None,
+           "throughput_rps": round(len(lat) / wall, 2), "cg_solves_per_s": round(len(lat_cg) / wall, 2),
+           "mean_cg_iterations": round(float(np.mean(iters)), 1) if iters else None,
+           "failed": fails, "rounds": st["rounds"], "uploads": st["uploads"],
+           "evictions": st["evictions"], "peak_budget_bytes": st["peak_bytes"]}
+    log(f"serving: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, {out['throughput_rps']} req/s "
+        f"at {out['arrival_rate_rps']} req/s offered")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +211,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the serving stream (the full workload is 4096)")
+    ap.add_argument("--serve-pool", type=int, default=32,
+                    help="matrices in the serving pool (1024 in the full workload)")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -195,6 +294,12 @@ def main():
             dst.copy_(buf)
         torch.cuda.synchronize()
         del buf, dst
+
+    if not args.no_extras and not args.no_serve:
+        M.close()
+        del x, y
+        torch.cuda.empty_cache()
+        extras["serving"] = serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64)
 
     cpu = None
     if not args.no_cpu:

@@ -208,6 +208,83 @@ typedef struct cg_info {
 int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
              int32_t mode, cg_info *info, void *stream);
 
+/* ------------------------------------------------------------- serving */
+/*
+ * A request server over resident matrices with continuous batching.
+ * Requests (k SpMVs, or a CG solve) are submitted at any time from any
+ * thread; a scheduler thread admits them as device memory and solver slots
+ * free up, uploading a registered matrix on first use and evicting the least
+ * recently used idle matrices to stay within hbm_budget_bytes.  Admitted SpMV
+ * requests join the next round, in which one multi-matrix kernel launch
+ * covers all of the round's vectors; CG requests run on solver slots (one
+ * stream each, graph-captured iterations) concurrently with the rounds.
+ * A request's result is bitwise identical alone and in any mix.
+ * Latency is measured from srv_submit until the result is in `out`.
+ */
+typedef struct spmv_server spmv_server;
+
+#define SRV_SPMV 0   /* out[j*n_rows..] = A in[j*n_cols..] for j < k */
+#define SRV_CG 1     /* out = x with A x = in (x0 = 0), stop at tol */
+
+typedef struct srv_config {
+    uint64_t hbm_budget_bytes; /* resident matrices + request buffers (0: 200 GiB) */
+    int32_t n_slots;           /* concurrent CG solves, <= 64 (0: 8) */
+    int32_t cg_mode;           /* CG_FP64 or CG_MIXED_FP32 for solve requests */
+    int32_t max_round_tiles;   /* cap on workgroups per SpMV round (0: 2^20) */
+} srv_config;
+
+typedef struct srv_result {
+    int32_t done;         /* 1 when finished */
+    int32_t status;       /* SPMV_OK or the error (SPMV_EBUDGET, SPMV_ENOTCONV, ...) */
+    int32_t iterations;   /* CG iterations */
+    int32_t op;           /* SRV_SPMV or SRV_CG */
+    double rel_residual;  /* CG: true relative residual */
+    double latency_s;     /* submit -> result in the caller's buffer */
+    double queue_s;       /* submit -> admission */
+} srv_result;
+
+typedef struct srv_stats {
+    int64_t submitted, completed, failed, rounds, uploads, evictions;
+    int64_t used_bytes, peak_bytes; /* budget accounting */
+    double p50_s, p99_s, mean_s, max_s; /* latency of completed requests */
+    double wall_s;          /* first submit -> last completion */
+    double throughput_rps;  /* completed / wall_s */
+} srv_stats;
+
+/* Creates the server on the current device (cfg NULL: defaults). */
+int srv_create(const srv_config *cfg, spmv_server **out);
+/* Registers a host CSR matrix (copied; uploaded on first use).  *matrix_id is
+ * its handle for srv_submit.  Validation as in spmv_create. */
+int srv_add_matrix(spmv_server *srv, int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                   const int32_t *col_idx, const double *values, int32_t *matrix_id);
+/* Submits a request.  in/out are HOST buffers (SRV_SPMV: k*n_cols in,
+ * k*n_rows out, vector-major; SRV_CG: n in (b), n out (x)) that must stay
+ * valid until the request is done.  k is ignored for SRV_CG.  Returns at once
+ * with a ticket.  SPMV_EINVAL for bad ids, sizes or pointers. */
+int srv_submit(spmv_server *srv, int32_t matrix_id, int32_t op, int32_t k, const double *in, double *out,
+               double tol, int32_t max_iter, uint64_t *ticket);
+/* Non-blocking status of a ticket. */
+int srv_poll(spmv_server *srv, uint64_t ticket, srv_result *res);
+/* Blocks until the ticket is done (res may be NULL). */
+int srv_wait(spmv_server *srv, uint64_t ticket, srv_result *res);
+/* Blocks until every submitted request is done. */
+int srv_drain(spmv_server *srv);
+int srv_get_stats(spmv_server *srv, srv_stats *st);
+/* Drains, stops the threads and frees everything. */
+int srv_destroy(spmv_server *srv);
+
+/*
+ * srv_policy_simulate: replays the server's admission policy on the host
+ * (no GPU), for tests.  Matrices need mat_bytes[i] when resident.  Op t is
+ * an admission (op_kind 0) or a release (1) of a request on matrix op_mat[t]
+ * holding op_extra[t] bytes of buffers.  Per op: verdict (0 admit, 1 wait,
+ * 2 never; -1 for releases), number of evicted matrices, whether the matrix
+ * is uploaded, and the bytes in use afterwards.
+ */
+int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64_t *mat_bytes, int32_t n_ops,
+                        const int32_t *op_kind, const int32_t *op_mat, const uint64_t *op_extra,
+                        int32_t *verdict, int32_t *n_evicted, int32_t *uploaded, uint64_t *used);
+
 /* Thread-local message describing the calling thread's last failure ("" if none). */
 const char *spmv_last_error(void);
 

@@ -329,3 +329,160 @@ class Matrix:
 
     def __exit__(self, *a):
         self.close()
+
+
+# ------------------------------------------------------------------ serving
+
+SRV_SPMV, SRV_CG = 0, 1
+
+
+class srv_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
+                ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32)]
+
+
+class srv_result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("op", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("queue_s", ctypes.c_double)]
+
+
+class srv_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("uploads", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("used_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("p50_s", ctypes.c_double),
+                ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("throughput_rps", ctypes.c_double)]
+
+
+EXPORTED += ["srv_create", "srv_add_matrix", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
+             "srv_get_stats", "srv_destroy", "srv_policy_simulate"]
+
+
+def _serve_lib():
+    L = lib()
+    if not getattr(L, "_serve_ready", False):
+        vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_double)
+        L.srv_create.restype = ctypes.c_int
+        L.srv_create.argtypes = [ctypes.POINTER(srv_config), ctypes.POINTER(vp)]
+        L.srv_add_matrix.restype = ctypes.c_int
+        L.srv_add_matrix.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(i32)]
+        L.srv_submit.restype = ctypes.c_int
+        L.srv_submit.argtypes = [vp, i32, i32, i32, vp, vp, dbl, i32, ctypes.POINTER(u64)]
+        for f in ("srv_poll", "srv_wait"):
+            getattr(L, f).restype = ctypes.c_int
+            getattr(L, f).argtypes = [vp, u64, ctypes.POINTER(srv_result)]
+        L.srv_drain.restype = ctypes.c_int
+        L.srv_drain.argtypes = [vp]
+        L.srv_get_stats.restype = ctypes.c_int
+        L.srv_get_stats.argtypes = [vp, ctypes.POINTER(srv_stats)]
+        L.srv_destroy.restype = ctypes.c_int
+        L.srv_destroy.argtypes = [vp]
+        L.srv_policy_simulate.restype = ctypes.c_int
+        L.srv_policy_simulate.argtypes = [u64, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L._serve_ready = True
+    return L
+
+
+def policy_simulate(budget: int, mat_bytes, ops) -> list[tuple[int, int, int, int]]:
+    """Replay the server's admission policy on the host.  ops: list of
+    (kind, matrix, extra_bytes) with kind 0 = admit, 1 = release.  Returns per
+    op (verdict, n_evicted, uploaded, used_bytes)."""
+    L = _serve_lib()
+    mb = np.ascontiguousarray(mat_bytes, np.uint64)
+    kind = np.ascontiguousarray([o[0] for o in ops], np.int32)
+    mat = np.ascontiguousarray([o[1] for o in ops], np.int32)
+    ext = np.ascontiguousarray([o[2] for o in ops], np.uint64)
+    n = len(ops)
+    v, ne, up = (np.zeros(n, np.int32) for _ in range(3))
+    used = np.zeros(n, np.uint64)
+    _check(L.srv_policy_simulate(budget, mb.shape[0], _ptr(mb), n, _ptr(kind), _ptr(mat), _ptr(ext),
+                                 _ptr(v), _ptr(ne), _ptr(up), _ptr(used)), "srv_policy_simulate")
+    return [(int(a), int(b), int(c), int(d)) for a, b, c, d in zip(v, ne, up, used)]
+
+
+class Server:
+    """Continuous-batching request server (``srv_*``).  Host numpy buffers are
+    kept alive until their request is reported done."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, n_slots: int = 0, cg_mode: int = CG_FP64,
+                 max_round_tiles: int = 0):
+        L = _serve_lib()
+        cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles)
+        h = ctypes.c_void_p()
+        _check(L.srv_create(ctypes.byref(cfg), ctypes.byref(h)), "srv_create")
+        self._h = h
+        self._shapes = []
+        self._live = {}
+
+    def add_matrix(self, A) -> int:
+        rp, ci, va = _host_csr(A.row_ptr, A.col_idx, A.values)
+        mid = ctypes.c_int32()
+        _check(_serve_lib().srv_add_matrix(self._h, A.n_rows, A.n_cols, ci.shape[0], _ptr(rp), _ptr(ci),
+                                           _ptr(va), ctypes.byref(mid)), "srv_add_matrix")
+        self._shapes.append((A.n_rows, A.n_cols))
+        return mid.value
+
+    def submit_spmv(self, mid: int, X) -> int:
+        """X: (k, n_cols) float64; the result is (k, n_rows)."""
+        if not 0 <= mid < len(self._shapes):
+            dummy = np.zeros(1)
+            return self._submit(mid, SRV_SPMV, 1, dummy, dummy, 0.0, 0)   # the library rejects the id
+        n_rows, n_cols = self._shapes[mid]
+        X = np.ascontiguousarray(np.atleast_2d(X), np.float64)
+        if X.shape[1] != n_cols:
+            raise ValueError("X must have n_cols columns")
+        Y = np.empty((X.shape[0], n_rows), np.float64)
+        return self._submit(mid, SRV_SPMV, X.shape[0], X, Y, 0.0, 0)
+
+    def submit_cg(self, mid: int, b, tol: float = 1e-8, max_iter: int = 20000) -> int:
+        n_rows, _ = self._shapes[mid]
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.empty(n_rows, np.float64)
+        return self._submit(mid, SRV_CG, 1, b, x, tol, max_iter)
+
+    def _submit(self, mid, op, k, inp, out, tol, max_iter) -> int:
+        t = ctypes.c_uint64()
+        _check(_serve_lib().srv_submit(self._h, mid, op, k, _ptr(inp), _ptr(out), tol, max_iter,
+                                       ctypes.byref(t)), "srv_submit")
+        self._live[t.value] = (inp, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        r = srv_result()
+        _check(_serve_lib().srv_poll(self._h, ticket, ctypes.byref(r)), "srv_poll")
+        return r
+
+    def wait(self, ticket: int):
+        """Blocks; returns (output array, srv_result)."""
+        r = srv_result()
+        _check(_serve_lib().srv_wait(self._h, ticket, ctypes.byref(r)), "srv_wait")
+        inp, out = self._live.pop(ticket)
+        return out, r
+
+    def drain(self):
+        _check(_serve_lib().srv_drain(self._h), "srv_drain")
+
+    def stats(self) -> dict:
+        s = srv_stats()
+        _check(_serve_lib().srv_get_stats(self._h, ctypes.byref(s)), "srv_get_stats")
+        return {k: getattr(s, k) for k, _ in srv_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_serve_lib().srv_destroy(self._h), "srv_destroy")
+        self._h = None
+        self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

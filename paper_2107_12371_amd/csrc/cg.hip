@@ -180,21 +180,37 @@ namespace {
 
 int grid_for(int n) { return std::max(1, std::min(4096, (n + kBlock - 1) / kBlock)); }
 
+// Device workspace allocated stream-ordered (hipMallocAsync on the solve's
+// stream, freed with hipFreeAsync), so concurrent solves on different
+// streams never synchronise the device through an allocation.  The pinned
+// host mirror of the device scalars is either owned here or lent by the
+// caller (serving slots keep one per slot).
 struct Buffers {
+    hipStream_t s;
     std::vector<void *> dev;
     void *host = nullptr;
+    bool own_host = false;
+    explicit Buffers(hipStream_t s_) : s(s_) {}
     ~Buffers() {
-        for (void *p : dev) (void)hipFree(p);
-        if (host) (void)hipHostFree(host);
+        for (void *p : dev) (void)hipFreeAsync(p, s);
+        if (own_host && host) (void)hipHostFree(host);
     }
     template <typename T> hipError_t alloc(T **p, size_t n) {
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(n, 1));
+        hipError_t e = hipMallocAsync(&q, sizeof(T) * std::max<size_t>(n, 1), s);
         if (e == hipSuccess) {
             dev.push_back(q);
             *p = static_cast<T *>(q);
         }
         return e;
+    }
+    hipError_t host_state(void *lent, size_t bytes) {
+        if (lent) {
+            host = lent;
+            return hipSuccess;
+        }
+        own_host = true;
+        return hipHostMalloc(&host, bytes, hipHostMallocDefault);
     }
 };
 
@@ -341,14 +357,14 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
 }  // namespace
 
 static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
-                   hipStream_t s) {
+                   hipStream_t s, void *pinned) {
     const DevMatrix &M = A->M;
     const int n = M.n_rows;
-    Buffers B;
+    Buffers B(s);
     CgCore<double, double> C(M, M.val64, n, s);
     int rc = alloc_core(B, C);
     if (rc) return rc;
-    HIP_TRY(hipHostMalloc(&B.host, sizeof(CgState), hipHostMallocDefault));
+    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
     C.hst = static_cast<CgState *>(B.host);
     // ||b||^2
     hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
@@ -382,17 +398,17 @@ static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol,
 }
 
 static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
-                    hipStream_t s, double inner_tol) {
+                    hipStream_t s, double inner_tol, void *pinned) {
     const DevMatrix &M = A->M;
     const int n = M.n_rows;
-    Buffers B;
+    Buffers B(s);
     // outer (binary64) residual machinery reuses a CgCore for its buffers
     CgCore<double, double> O(M, M.val64, n, s);
     CgCore<float, float> I(M, M.val32, n, s);
     int rc = alloc_core(B, O);
     if (!rc) rc = alloc_core(B, I);
     if (rc) return rc;
-    HIP_TRY(hipHostMalloc(&B.host, 2 * sizeof(CgState), hipHostMallocDefault));
+    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
     O.hst = static_cast<CgState *>(B.host);
     I.hst = O.hst + 1;
     hipLaunchKernelGGL((k_dot_part<double>), dim3(O.n_wg), dim3(kBlock), 0, s, n, O.chunk, b, b, O.part_vec);
@@ -452,13 +468,10 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
     return SPMV_OK;
 }
 
-}  // namespace spmvlib
 
-using namespace spmvlib;
 
-extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
-                        int32_t mode, cg_info *info, void *stream) {
-    clear_error();
+int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter, int32_t mode,
+           cg_info *info, hipStream_t s, void *pinned_state) {
     auto t0 = std::chrono::steady_clock::now();
     if (info) std::memset(info, 0, sizeof *info);
     if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
@@ -477,16 +490,23 @@ extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double
     int dev_prev = -1;
     if (hipGetDevice(&dev_prev) == hipSuccess && dev_prev != A->device) (void)hipSetDevice(A->device);
     else dev_prev = -1;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     int rc;
     if (mode == CG_FP64) {
-        rc = cg_fp64(A, b, x, tol, max_iter, info, s);
+        rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);
     } else {
         const char *env = std::getenv("SPMV_CG_INNER_TOL");
         double inner = env ? std::atof(env) : 1e-4;
-        rc = cg_mixed(A, b, x, tol, max_iter, info, s, inner);
+        rc = cg_mixed(A, b, x, tol, max_iter, info, s, inner, pinned_state);
     }
     if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
     if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
+}
+
+}  // namespace spmvlib
+
+extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
+                        int32_t mode, cg_info *info, void *stream) {
+    spmvlib::clear_error();
+    return spmvlib::cg_run(A, b, x, tol, max_iter, mode, info, static_cast<hipStream_t>(stream), nullptr);
 }

@@ -19,4 +19,9 @@ struct spmv_matrix {
 namespace spmvlib {
 // Maps a HIP error to SPMV_ENOMEM / SPMV_EDEVICE with a message.
 int hip_fail(hipError_t e, const char *what);
+
+// cg_solve on an explicit stream; pinned_state (optional) is a caller-owned
+// pinned host buffer of at least 256 bytes for the solver's scalar mirror.
+int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter, int32_t mode,
+           cg_info *info, hipStream_t s, void *pinned_state);
 }  // namespace spmvlib

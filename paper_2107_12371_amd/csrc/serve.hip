@@ -1,0 +1,622 @@
+// Request server with continuous batching over resident mesh matrices.
+//
+// Requests (k SpMVs, or a CG solve) arrive at any time through srv_submit.
+// A scheduler thread admits them as device memory and solver slots free up
+// (BudgetLRU: resident matrices + request buffers within an HBM budget,
+// least-recently-used idle matrices evicted), and runs rounds:
+//  * every admitted SpMV request joins the next round, and one launch of the
+//    multi-matrix kernel k_multi covers the tiles of all of the round's
+//    vectors, whatever matrix each belongs to (a workgroup finds its item by
+//    binary search over the round's tile offsets);
+//  * each admitted CG request runs on a solver slot: a worker thread with
+//    its own stream drives the graph-captured CG iterations, overlapping
+//    with the rounds and with the other slots.
+// Every row of every result is summed in the order fixed by its matrix's
+// plan, and CG reductions have a fixed partition, so a request's result is
+// bitwise the same alone and in any mix.  Latency is measured from
+// srv_submit to the moment the result is in the caller's host buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+#include "launch.h"
+#include "matrix.h"
+#include "serve_policy.h"
+#include "tile.h"
+
+namespace spmvlib {
+
+struct MultiItem {
+    const TileDesc *desc;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const double *x;
+    double *y;
+    int32_t tile_begin;  // first workgroup of this item in the launch
+    int32_t n_tiles;
+};
+
+constexpr int kServeTile = 1024;  // tile capacity of server matrices
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_multi(const MultiItem *__restrict__ items, int n_items, int total) {
+    __shared__ double prod[TileRegs<double, NT>::kProd];
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    if (b >= total) return;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const MultiItem it = items[lo];
+    const TileDesc d = it.desc[b - it.tile_begin];
+    const double *__restrict__ x = it.x;
+    TileRegs<double, NT> t;
+    t.load(it.col, it.val, d.s, d.e);
+    RowPre<double, EPI_PLAIN> pre;
+    pre.load(it.row_ptr, x, static_cast<const double *>(nullptr), d.r0, d.r1, d.s & ~3);
+    double xv[TileRegs<double, NT>::kMaxPass][4];
+    t.gather([x](int c) { return x[c]; }, xv);
+    t.products(xv, prod);
+    __syncthreads();
+    tile_rows<double, double, EPI_PLAIN>(pre, d.r0, d.r1, prod, it.y, nullptr, 0, sh);
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t mid = 0, op = 0, k = 1, max_iter = 0;
+    const spmv_matrix *A = nullptr;  // resident handle, set at admission (pinned until done)
+    const double *in = nullptr;
+    double *out = nullptr;
+    double tol = 0.0;
+    uint64_t extra = 0;
+    Clock::time_point t_submit, t_start, t_done;
+    bool done = false;
+    int status = SPMV_OK;
+    int iterations = 0;
+    double rel_residual = 0.0;
+};
+
+struct MatrixEntry {
+    int32_t n_rows = 0, n_cols = 0;
+    std::vector<int32_t> row_ptr, col_idx;
+    std::vector<double> values;
+    spmv_matrix *dev = nullptr;
+};
+
+struct Slot {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    void *pinned = nullptr;
+    Request *job = nullptr;
+};
+
+double seconds(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+}  // namespace
+
+struct Server {
+    srv_config cfg{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done, cv_slot;
+    std::deque<Request *> incoming, pending;
+    std::unordered_map<uint64_t, Request *> all;
+    std::deque<MatrixEntry> mats;  // stable element addresses; read under `mu`
+    BudgetLRU policy;
+    std::vector<Slot> slots;
+    std::thread scheduler;
+    hipStream_t batch = nullptr;
+    MultiItem *items_host = nullptr;
+    size_t items_cap = 0;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0, failed = 0, rounds = 0;
+    int in_flight_spmv = 0;
+    bool stop = false;
+    std::vector<double> latencies;
+    Clock::time_point t_first{}, t_last{};
+    bool any_submit = false;
+
+    explicit Server(const srv_config &c) : cfg(c), policy(c.hbm_budget_bytes) {}
+
+    uint64_t matrix_bytes(const MatrixEntry &m) const {
+        const uint64_t nz = m.col_idx.size(), pad = ((nz + 3) & ~(uint64_t)3) + kPad;
+        uint64_t b = 4ull * (m.n_rows + 1) + 12ull * pad + 64ull * (nz / 512 + 16);
+        if (cfg.cg_mode == CG_MIXED_FP32) b += 4ull * pad;
+        return b;
+    }
+
+    uint64_t request_bytes(const Request &r) const {
+        const MatrixEntry &m = mats[r.mid];
+        if (r.op == SRV_SPMV) return 8ull * (uint64_t)r.k * (uint64_t)(m.n_rows + m.n_cols);
+        // b, x and the solver workspace (4 vectors + partials), FP32 copies for MIXED
+        uint64_t b = 8ull * m.n_rows * 7 + 8ull * (m.col_idx.size() / 1000 + 4096);
+        if (cfg.cg_mode == CG_MIXED_FP32) b += 4ull * m.n_rows * 5;
+        return b;
+    }
+
+    void finish_locked(Request *r, int status) {
+        r->status = status;
+        r->t_done = Clock::now();
+        r->done = true;
+        if (status == SPMV_OK) {
+            ++completed;
+            latencies.push_back(seconds(r->t_submit, r->t_done));
+        } else {
+            ++failed;
+        }
+        t_last = r->t_done;
+        cv_done.notify_all();
+    }
+
+    int upload_locked(int mid) {
+        MatrixEntry &m = mats[mid];
+        spmv_params p{};
+        p.tile_nnz = kServeTile;
+        p.window_mode = SPMV_WINDOW_OFF;
+        p.kernel = KV_ONE_TILE;
+        const uint32_t flags = cfg.cg_mode == CG_MIXED_FP32 ? SPMV_VALUES_FP32 : 0u;
+        int rc = spmv_create(m.n_rows, m.n_cols, (int64_t)m.col_idx.size(), m.row_ptr.data(),
+                             m.col_idx.empty() ? nullptr : m.col_idx.data(),
+                             m.values.empty() ? nullptr : m.values.data(), flags, &p, &m.dev);
+        if (rc == SPMV_OK) policy.resize(mid, (uint64_t)m.dev->bytes);
+        return rc;
+    }
+
+    // One round: every SpMV vector of the admitted requests in one launch.
+    void run_round(std::vector<Request *> &round) {
+        std::vector<MultiItem> items;
+        std::vector<std::pair<Request *, std::pair<double *, double *>>> bufs;
+        int total = 0;
+        int err = SPMV_OK;
+        for (Request *r : round) {
+            const DevMatrix &M = r->A->M;
+            double *din = nullptr, *dout = nullptr;
+            const size_t nin = (size_t)r->k * M.n_cols, nout = (size_t)r->k * M.n_rows;
+            hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&din), 8 * std::max<size_t>(nin, 1), batch);
+            if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&dout), 8 * std::max<size_t>(nout, 1), batch);
+            if (e == hipSuccess && nin) e = hipMemcpyAsync(din, r->in, 8 * nin, hipMemcpyHostToDevice, batch);
+            if (e != hipSuccess) err = hip_fail(e, "server round buffers");
+            bufs.push_back({r, {din, dout}});
+            for (int j = 0; j < r->k && e == hipSuccess; ++j) {
+                const double *x = din + (size_t)j * M.n_cols;
+                double *y = dout + (size_t)j * M.n_rows;
+                if (M.n_long > 0) {
+                    // rows longer than a tile: the matrix's own launch sequence
+                    e = launch_spmv<double, double, double, double>(M, M.val64, x, y, EPI_PLAIN, nullptr, nullptr,
+                                                                    nullptr, batch);
+                    if (e != hipSuccess) err = hip_fail(e, "server spmv");
+                    continue;
+                }
+                if (M.n_stream == 0) continue;
+                MultiItem it{M.stream_desc, M.row_ptr, M.col, M.val64, x, y, total, M.n_stream};
+                items.push_back(it);
+                total += M.n_stream;
+            }
+        }
+        if (err == SPMV_OK && !items.empty()) {
+            if (items.size() > items_cap) {
+                if (items_host) (void)hipHostFree(items_host);
+                items_cap = std::max<size_t>(items.size(), 2 * items_cap);
+                hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&items_host), items_cap * sizeof(MultiItem),
+                                             hipHostMallocDefault);
+                if (e != hipSuccess) {
+                    items_host = nullptr;
+                    items_cap = 0;
+                    err = hip_fail(e, "server item staging");
+                }
+            }
+            if (err == SPMV_OK) {
+                std::memcpy(items_host, items.data(), items.size() * sizeof(MultiItem));
+                MultiItem *ditems = nullptr;
+                hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&ditems), items.size() * sizeof(MultiItem), batch);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(ditems, items_host, items.size() * sizeof(MultiItem), hipMemcpyHostToDevice, batch);
+                if (e == hipSuccess) {
+                    hipLaunchKernelGGL((k_multi<kServeTile>), dim3(total), dim3(kBlock), 0, batch, ditems,
+                                       (int)items.size(), total);
+                    e = hipGetLastError();
+                }
+                if (ditems) (void)hipFreeAsync(ditems, batch);
+                if (e != hipSuccess) err = hip_fail(e, "server round launch");
+            }
+        }
+        for (auto &b : bufs) {
+            Request *r = b.first;
+            const size_t nout = (size_t)r->k * r->A->M.n_rows;
+            if (err == SPMV_OK && nout) {
+                hipError_t e = hipMemcpyAsync(r->out, b.second.second, 8 * nout, hipMemcpyDeviceToHost, batch);
+                if (e != hipSuccess) err = hip_fail(e, "server result copy");
+            }
+        }
+        hipError_t e = hipStreamSynchronize(batch);
+        if (e != hipSuccess && err == SPMV_OK) err = hip_fail(e, "server round");
+        for (auto &b : bufs) {
+            if (b.second.first) (void)hipFreeAsync(b.second.first, batch);
+            if (b.second.second) (void)hipFreeAsync(b.second.second, batch);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ++rounds;
+        for (Request *r : round) {
+            policy.release(r->mid, r->extra);
+            --in_flight_spmv;
+            finish_locked(r, err);
+        }
+        cv_sched.notify_all();
+    }
+
+    void solver_loop(int si) {
+        hipSetDevice(device);
+        Slot &sl = slots[si];
+        for (;;) {
+            Request *r;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_slot.wait(lk, [&] { return stop || sl.job != nullptr; });
+                if (sl.job == nullptr) return;
+                r = sl.job;
+            }
+            const spmv_matrix *A = r->A;
+            const int n = A->M.n_rows;
+            double *db = nullptr, *dx = nullptr;
+            int rc = SPMV_OK;
+            hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&db), 8 * (size_t)std::max(n, 1), sl.stream);
+            if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&dx), 8 * (size_t)std::max(n, 1), sl.stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(db, r->in, 8 * (size_t)n, hipMemcpyHostToDevice, sl.stream);
+            if (e == hipSuccess) e = hipMemsetAsync(dx, 0, 8 * (size_t)n, sl.stream);
+            cg_info info{};
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "server solve buffers");
+            } else {
+                rc = cg_run(A, db, dx, r->tol, r->max_iter, cfg.cg_mode, &info, sl.stream, sl.pinned);
+                if (rc == SPMV_OK || rc == SPMV_ENOTCONV) {
+                    e = hipMemcpyAsync(r->out, dx, 8 * (size_t)n, hipMemcpyDeviceToHost, sl.stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
+                    if (e != hipSuccess) rc = hip_fail(e, "server solve result");
+                }
+            }
+            if (db) (void)hipFreeAsync(db, sl.stream);
+            if (dx) (void)hipFreeAsync(dx, sl.stream);
+            (void)hipStreamSynchronize(sl.stream);
+            std::lock_guard<std::mutex> lk(mu);
+            r->iterations = info.iterations;
+            r->rel_residual = info.rel_residual;
+            policy.release(r->mid, r->extra);
+            sl.job = nullptr;
+            finish_locked(r, rc);
+            cv_sched.notify_all();
+        }
+    }
+
+    int free_slot_locked() const {
+        for (size_t i = 0; i < slots.size(); ++i)
+            if (!slots[i].job) return (int)i;
+        return -1;
+    }
+
+    void scheduler_loop() {
+        hipSetDevice(device);
+        std::vector<int> evict;
+        for (;;) {
+            std::vector<Request *> round;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_sched.wait_for(lk, std::chrono::microseconds(500),
+                                  [&] { return stop || !incoming.empty() || !pending.empty(); });
+                if (stop && incoming.empty() && pending.empty()) return;
+                while (!incoming.empty()) {
+                    pending.push_back(incoming.front());
+                    incoming.pop_front();
+                }
+                int64_t round_tiles = 0;
+                for (auto it = pending.begin(); it != pending.end();) {
+                    Request *r = *it;
+                    int slot = -1;
+                    if (r->op == SRV_CG) {
+                        slot = free_slot_locked();
+                        if (slot < 0) { ++it; continue; }
+                    } else {
+                        const int64_t est = (int64_t)r->k * (int64_t)(mats[r->mid].col_idx.size() / kServeTile + 1);
+                        if (!round.empty() && round_tiles + est > cfg.max_round_tiles) { ++it; continue; }
+                    }
+                    bool upload = false;
+                    const auto v = policy.admit(r->mid, r->extra, evict, upload);
+                    if (v == BudgetLRU::NEVER) {
+                        it = pending.erase(it);
+                        finish_locked(r, fail(SPMV_EBUDGET, "request needs more than the device budget"));
+                        continue;
+                    }
+                    if (v == BudgetLRU::WAIT) { ++it; continue; }
+                    for (int m : evict) {
+                        if (mats[m].dev) (void)spmv_destroy(mats[m].dev);
+                        mats[m].dev = nullptr;
+                    }
+                    if (upload) {
+                        const int rc = upload_locked(r->mid);
+                        if (rc != SPMV_OK) {
+                            policy.release(r->mid, r->extra);
+                            it = pending.erase(it);
+                            finish_locked(r, rc);
+                            continue;
+                        }
+                    }
+                    it = pending.erase(it);
+                    r->t_start = Clock::now();
+                    r->A = mats[r->mid].dev;
+                    if (r->op == SRV_CG) {
+                        slots[slot].job = r;
+                        cv_slot.notify_all();
+                    } else {
+                        round.push_back(r);
+                        ++in_flight_spmv;
+                        round_tiles += (int64_t)r->k * r->A->M.n_stream;
+                    }
+                }
+            }
+            if (!round.empty()) run_round(round);
+        }
+    }
+};
+
+}  // namespace spmvlib
+
+using namespace spmvlib;
+
+struct spmv_server {
+    Server *s;
+};
+
+extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
+    clear_error();
+    if (!out) return fail(SPMV_EINVAL, "out is NULL");
+    *out = nullptr;
+    srv_config cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.hbm_budget_bytes == 0) cfg.hbm_budget_bytes = 200ull << 30;
+    if (cfg.n_slots <= 0) cfg.n_slots = 8;
+    if (cfg.n_slots > 64) return fail(SPMV_EINVAL, "n_slots = %d exceeds 64", cfg.n_slots);
+    if (cfg.max_round_tiles <= 0) cfg.max_round_tiles = 1 << 20;
+    if (cfg.cg_mode != CG_FP64 && cfg.cg_mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown cg_mode");
+    auto *S = new (std::nothrow) Server(cfg);
+    if (!S) return fail(SPMV_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&S->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->batch, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete S;
+        return hip_fail(e, "server stream");
+    }
+    S->slots.resize(cfg.n_slots);
+    for (auto &sl : S->slots) {
+        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.pinned, 256, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "server slot");
+    }
+    for (int i = 0; i < cfg.n_slots; ++i) S->slots[i].th = std::thread([S, i] { S->solver_loop(i); });
+    S->scheduler = std::thread([S] { S->scheduler_loop(); });
+    *out = new spmv_server{S};
+    return SPMV_OK;
+}
+
+extern "C" int srv_add_matrix(spmv_server *srv, int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const double *values, int32_t *matrix_id) {
+    clear_error();
+    if (!srv || !matrix_id) return fail(SPMV_EINVAL, "NULL argument");
+    int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
+    if (rc) return rc;
+    if (nnz > 0 && !values) return fail(SPMV_EINVAL, "values is NULL with nnz > 0");
+    Server *S = srv->s;
+    MatrixEntry m;
+    m.n_rows = n_rows;
+    m.n_cols = n_cols;
+    m.row_ptr.assign(row_ptr, row_ptr + n_rows + 1);
+    m.col_idx.assign(col_idx, col_idx + nnz);
+    m.values.assign(values, values + nnz);
+    std::lock_guard<std::mutex> lk(S->mu);
+    const uint64_t bytes = S->matrix_bytes(m);
+    S->mats.push_back(std::move(m));
+    *matrix_id = S->policy.add_matrix(bytes);
+    return SPMV_OK;
+}
+
+extern "C" int srv_submit(spmv_server *srv, int32_t matrix_id, int32_t op, int32_t k, const double *in, double *out,
+                          double tol, int32_t max_iter, uint64_t *ticket) {
+    clear_error();
+    if (!srv || !ticket) return fail(SPMV_EINVAL, "NULL argument");
+    Server *S = srv->s;
+    auto *r = new (std::nothrow) Request();
+    if (!r) return fail(SPMV_ENOMEM, "host allocation failed");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (matrix_id < 0 || matrix_id >= (int32_t)S->mats.size()) {
+        delete r;
+        return fail(SPMV_EINVAL, "unknown matrix id %d", matrix_id);
+    }
+    const MatrixEntry &m = S->mats[matrix_id];
+    if (op != SRV_SPMV && op != SRV_CG) {
+        delete r;
+        return fail(SPMV_EINVAL, "unknown op %d", op);
+    }
+    if (op == SRV_SPMV && k < 1) {
+        delete r;
+        return fail(SPMV_EINVAL, "k = %d must be >= 1", k);
+    }
+    if (op == SRV_CG && (m.n_rows != m.n_cols || !(tol >= 0.0) || max_iter < 0)) {
+        delete r;
+        return fail(SPMV_EINVAL, "CG needs a square matrix, tol >= 0, max_iter >= 0");
+    }
+    if ((m.n_cols && !in) || (m.n_rows && !out)) {
+        delete r;
+        return fail(SPMV_EINVAL, "in or out is NULL");
+    }
+    r->ticket = S->next_ticket++;
+    r->mid = matrix_id;
+    r->op = op;
+    r->k = op == SRV_CG ? 1 : k;
+    r->in = in;
+    r->out = out;
+    r->tol = tol;
+    r->max_iter = max_iter;
+    r->t_submit = Clock::now();
+    r->extra = S->request_bytes(*r);
+    if (!S->any_submit) {
+        S->t_first = r->t_submit;
+        S->any_submit = true;
+    }
+    ++S->submitted;
+    S->all[r->ticket] = r;
+    S->incoming.push_back(r);
+    *ticket = r->ticket;
+    S->cv_sched.notify_all();
+    return SPMV_OK;
+}
+
+static void fill_result(const Request *r, srv_result *res) {
+    std::memset(res, 0, sizeof *res);
+    res->done = r->done ? 1 : 0;
+    res->status = r->status;
+    res->iterations = r->iterations;
+    res->op = r->op;
+    res->rel_residual = r->rel_residual;
+    if (r->done) {
+        res->latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+        res->queue_s = std::chrono::duration<double>(r->t_start - r->t_submit).count();
+        if (res->queue_s < 0) res->queue_s = 0;
+    }
+}
+
+extern "C" int srv_poll(spmv_server *srv, uint64_t ticket, srv_result *res) {
+    clear_error();
+    if (!srv || !res) return fail(SPMV_EINVAL, "NULL argument");
+    Server *S = srv->s;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(SPMV_EINVAL, "unknown ticket");
+    fill_result(it->second, res);
+    return SPMV_OK;
+}
+
+extern "C" int srv_wait(spmv_server *srv, uint64_t ticket, srv_result *res) {
+    clear_error();
+    if (!srv) return fail(SPMV_EINVAL, "NULL argument");
+    Server *S = srv->s;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(SPMV_EINVAL, "unknown ticket");
+    Request *r = it->second;
+    S->cv_done.wait(lk, [&] { return r->done; });
+    if (res) fill_result(r, res);
+    return SPMV_OK;
+}
+
+extern "C" int srv_drain(spmv_server *srv) {
+    clear_error();
+    if (!srv) return fail(SPMV_EINVAL, "NULL argument");
+    Server *S = srv->s;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted; });
+    return SPMV_OK;
+}
+
+extern "C" int srv_get_stats(spmv_server *srv, srv_stats *st) {
+    clear_error();
+    if (!srv || !st) return fail(SPMV_EINVAL, "NULL argument");
+    Server *S = srv->s;
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::memset(st, 0, sizeof *st);
+    st->submitted = S->submitted;
+    st->completed = S->completed;
+    st->failed = S->failed;
+    st->rounds = S->rounds;
+    st->uploads = S->policy.uploads();
+    st->evictions = S->policy.evictions();
+    st->used_bytes = (int64_t)S->policy.used();
+    st->peak_bytes = (int64_t)S->policy.peak();
+    std::vector<double> l = S->latencies;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (double)(l.size() - 1) + 0.5))]; };
+        st->p50_s = q(0.50);
+        st->p99_s = q(0.99);
+        st->max_s = l.back();
+        double sum = 0;
+        for (double v : l) sum += v;
+        st->mean_s = sum / (double)l.size();
+        st->wall_s = std::chrono::duration<double>(S->t_last - S->t_first).count();
+        st->throughput_rps = st->wall_s > 0 ? (double)S->completed / st->wall_s : 0.0;
+    }
+    return SPMV_OK;
+}
+
+extern "C" int srv_destroy(spmv_server *srv) {
+    clear_error();
+    if (!srv) return SPMV_OK;
+    Server *S = srv->s;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted; });
+        S->stop = true;
+    }
+    S->cv_sched.notify_all();
+    S->cv_slot.notify_all();
+    if (S->scheduler.joinable()) S->scheduler.join();
+    for (auto &sl : S->slots)
+        if (sl.th.joinable()) sl.th.join();
+    for (auto &m : S->mats)
+        if (m.dev) (void)spmv_destroy(m.dev);
+    for (auto &sl : S->slots) {
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+    }
+    if (S->items_host) (void)hipHostFree(S->items_host);
+    if (S->batch) (void)hipStreamDestroy(S->batch);
+    for (auto &kv : S->all) delete kv.second;
+    delete S;
+    delete srv;
+    return SPMV_OK;
+}
+
+extern "C" int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64_t *mat_bytes, int32_t n_ops,
+                                   const int32_t *op_kind, const int32_t *op_mat, const uint64_t *op_extra,
+                                   int32_t *verdict, int32_t *n_evicted, int32_t *uploaded, uint64_t *used) {
+    clear_error();
+    if (n_mats < 0 || n_ops < 0 || (n_mats && !mat_bytes) || (n_ops && (!op_kind || !op_mat || !op_extra)))
+        return fail(SPMV_EINVAL, "bad arguments");
+    BudgetLRU P(budget);
+    for (int i = 0; i < n_mats; ++i) P.add_matrix(mat_bytes[i]);
+    std::vector<int> ev;
+    for (int t = 0; t < n_ops; ++t) {
+        if (op_mat[t] < 0 || op_mat[t] >= n_mats) return fail(SPMV_EINVAL, "op %d: bad matrix", t);
+        int v = -1, ne = 0, up = 0;
+        if (op_kind[t] == 0) {
+            bool u = false;
+            v = P.admit(op_mat[t], op_extra[t], ev, u);
+            ne = (int)ev.size();
+            up = u ? 1 : 0;
+        } else {
+            if (P.pins(op_mat[t]) <= 0) return fail(SPMV_EINVAL, "op %d: release without admission", t);
+            P.release(op_mat[t], op_extra[t]);
+        }
+        if (verdict) verdict[t] = v;
+        if (n_evicted) n_evicted[t] = ne;
+        if (uploaded) uploaded[t] = up;
+        if (used) used[t] = P.used();
+    }
+    return SPMV_OK;
+}

@@ -1,0 +1,136 @@
+"""GPU tests of the continuous-batching server: results against the oracle,
+the same result alone and in the mix (bitwise), and the device-memory
+budget (eviction and rejection)."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+import oracle
+import paper_2107_12371_amd as spmv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    sizes = [1000, 4000, 9000, 30000, 70000, 150000]
+    return [mg.serving_matrix(n, seed=mg.seed_for(4) ^ (i + 1)) for i, n in enumerate(sizes)]
+
+
+def _requests(pool, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for t in range(n):
+        mid = int(rng.integers(len(pool)))
+        A = pool[mid]
+        if rng.random() < 0.5:
+            k = int(rng.integers(1, 9))
+            reqs.append(("spmv", mid, mg.uniform(k * A.n_cols, seed + t, 3).reshape(k, A.n_cols)))
+        else:
+            reqs.append(("cg", mid, mg.uniform(A.n_rows, seed + t, 4)))
+    return reqs
+
+
+def _submit(srv, r, tol=1e-8):
+    kind, mid, data = r
+    return srv.submit_spmv(mid, data) if kind == "spmv" else srv.submit_cg(mid, data, tol=tol)
+
+
+def test_results_match_the_oracle(pool):
+    reqs = _requests(pool, 24, 100)
+    with spmv.Server(n_slots=4) as srv:
+        ids = [srv.add_matrix(A) for A in pool]
+        assert ids == list(range(len(pool)))
+        tickets = [_submit(srv, r) for r in reqs]
+        for r, t in zip(reqs, tickets):
+            out, res = srv.wait(t)
+            assert res.done == 1 and res.status == 0
+            kind, mid, data = r
+            A = pool[mid]
+            if kind == "spmv":
+                for j in range(data.shape[0]):
+                    y_ref, bound = oracle.spmv(A, data[j])
+                    assert oracle.spmv_accept(out[j], y_ref, bound).all()
+            else:
+                Ax, _ = oracle.spmv(A, out)
+                assert np.linalg.norm(data - Ax) / np.linalg.norm(data) <= 1.05e-8
+                assert res.iterations > 0
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_alone_equals_mix_bitwise(pool):
+    reqs = _requests(pool, 30, 200)
+    with spmv.Server(n_slots=6) as srv:
+        for A in pool:
+            srv.add_matrix(A)
+        alone = []
+        for r in reqs:                      # one request at a time on an idle server
+            out, res = srv.wait(_submit(srv, r))
+            assert res.status == 0
+            alone.append(out.copy())
+        tickets = [_submit(srv, r) for r in reqs]   # everything at once
+        mixed = [srv.wait(t)[0] for t in tickets]
+        st = srv.stats()
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(a, m)
+    assert st["rounds"] < sum(1 for r in reqs if r[0] == "spmv") * 2   # SpMVs were batched
+
+
+def test_server_spmv_equals_direct_apply(pool):
+    A = pool[3]
+    X = mg.uniform(3 * A.n_cols, 7, 3).reshape(3, A.n_cols)
+    with spmv.Server() as srv:
+        srv.add_matrix(A)
+        out, _ = srv.wait(srv.submit_spmv(0, X))
+    with spmv.Matrix.from_csr(A, params={"tile_nnz": 1024, "kernel": 1, "window_mode": spmv.WINDOW_OFF}) as M:
+        for j in range(3):
+            y = M.apply(torch.as_tensor(X[j], device="cuda")).cpu().numpy()
+            assert np.array_equal(y, out[j])
+
+
+def test_budget_eviction_and_rejection(pool):
+    small = pool[:4]
+    est = lambda A: 12 * (A.nnz + 20) + 4 * (A.n_rows + 1) + 64 * (A.nnz // 512 + 16)
+    # the largest matrix plus a tenth, plus two request buffers: the four
+    # matrices together do not fit, so cycling over them must evict
+    budget = int(1.1 * est(small[3]) + 2 * 16 * small[3].n_rows)
+    assert sum(est(A) for A in small) > budget
+    reqs = [("spmv", i % 4, mg.uniform(small[i % 4].n_cols, i, 5)[None, :]) for i in range(12)]
+    with spmv.Server(hbm_budget_bytes=budget, n_slots=2) as srv:
+        for A in small:
+            srv.add_matrix(A)
+        outs = [srv.wait(_submit(srv, r)) for r in reqs]
+        st = srv.stats()
+        assert st["evictions"] > 0 and st["peak_bytes"] <= budget
+        for (kind, mid, X), (out, res) in zip(reqs, outs):
+            assert res.status == 0
+            y_ref, bound = oracle.spmv(small[mid], X[0])
+            assert oracle.spmv_accept(out[0], y_ref, bound).all()
+        big = pool[-1]
+        bid = srv.add_matrix(big)
+        _, res = srv.wait(srv.submit_spmv(bid, np.ones((1, big.n_cols))))
+        assert res.status == spmv.SPMV_EBUDGET
+
+
+def test_mixed_precision_cg_requests(pool):
+    A = pool[2]
+    b = mg.uniform(A.n_rows, 9, 4)
+    with spmv.Server(cg_mode=spmv.CG_MIXED_FP32) as srv:
+        srv.add_matrix(A)
+        x, res = srv.wait(srv.submit_cg(0, b, tol=1e-8))
+    assert res.status == 0
+    Ax, _ = oracle.spmv(A, x)
+    assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= 1.05e-8
+
+
+def test_bad_requests_are_rejected(pool):
+    with spmv.Server() as srv:
+        srv.add_matrix(pool[0])
+        with pytest.raises(spmv.SpmvError) as e:
+            srv.submit_spmv(5, np.ones((1, 3)))
+        assert e.value.code == spmv.SPMV_EINVAL
+        with pytest.raises(ValueError):
+            srv.submit_spmv(0, np.ones((1, pool[0].n_cols + 1)))

@@ -1,0 +1,56 @@
+"""The server's admission policy (device-memory budget + LRU eviction),
+replayed on the host through the library's test hook (no GPU)."""
+import paper_2107_12371_amd as spmv
+
+ADMIT, WAIT, NEVER = 0, 1, 2
+
+
+def test_admit_upload_reuse_and_release():
+    r = spmv.policy_simulate(100, [40, 30], [(0, 0, 10), (0, 0, 10), (1, 0, 10), (1, 0, 10)])
+    assert r[0] == (ADMIT, 0, 1, 50)      # upload 40 + 10 buffers
+    assert r[1] == (ADMIT, 0, 0, 60)      # resident already: only buffers
+    assert r[2][3] == 50 and r[3][3] == 40  # releases keep the matrix resident
+
+
+def test_lru_eviction_of_idle_matrices_only():
+    ops = [(0, 0, 0), (1, 0, 0),           # matrix 0 resident, idle (t=1)
+           (0, 1, 0), (1, 1, 0),           # matrix 1 resident, idle (t=2)
+           (0, 2, 0)]                      # needs 50: must evict the LRU idle one (matrix 0)
+    r = spmv.policy_simulate(100, [40, 40, 50], ops)
+    assert r[4] == (ADMIT, 1, 1, 90)
+    # pinned matrices are never evicted: with 0 and 1 in flight, 2 must wait
+    ops = [(0, 0, 0), (0, 1, 0), (0, 2, 0), (1, 0, 0), (0, 2, 0)]
+    r = spmv.policy_simulate(100, [40, 40, 50], ops)
+    assert r[2][0] == WAIT
+    assert r[4] == (ADMIT, 1, 1, 90)       # after 0 is released it is evicted
+
+
+def test_never_fits_and_buffers_count():
+    r = spmv.policy_simulate(100, [60], [(0, 0, 50)])
+    assert r[0][0] == NEVER
+    r = spmv.policy_simulate(100, [60], [(0, 0, 20), (0, 0, 20), (0, 0, 1)])
+    assert [v[0] for v in r] == [ADMIT, ADMIT, WAIT]
+
+
+def test_many_matrices_stay_within_budget():
+    import numpy as np
+    rng = np.random.default_rng(0)
+    sizes = rng.integers(1, 30, 40).tolist()
+    budget = 120
+    live, done_ops = [], []
+    for _ in range(300):
+        if live and rng.random() < 0.5:
+            m, e = live.pop(int(rng.integers(len(live))))
+            op = (1, m, e)
+        else:
+            op = (0, int(rng.integers(40)), int(rng.integers(0, 10)))
+        trial = spmv.policy_simulate(budget, sizes, done_ops + [op])
+        if op[0] == 0:
+            if trial[-1][0] != ADMIT:
+                continue
+            live.append(op[1:])
+        done_ops.append(op)
+        assert trial[-1][3] <= budget
+    # every in-flight request's matrix is resident: its bytes are counted
+    final = spmv.policy_simulate(budget, sizes, done_ops)
+    assert final[-1][3] >= sum(e for _, e in live) + sum(sizes[m] for m in {m for m, _ in live})
