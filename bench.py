@@ -197,6 +197,64 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     return out
 
 
+def config_lines(torch, log=log) -> dict:
+    """Per-configuration lines besides the headline (outside the timed region):
+    the 32^3 mesh with the LDS ring window vs direct gathers, the 126^3 kNN
+    matrix in RCM vs random order, and the 3x3 block-CSR operator with 1, 4, 8
+    right-hand sides in FP64 and FP32 storage."""
+    import meshgen as mg
+    import paper_2107_12371_amd as spmv
+    out = {}
+    A = mg.config0()
+    x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+    B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+    c0 = {}
+    for name, params in (("direct", {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 1024}),
+                         ("window_ring8192_block8", {"window_mode": spmv.WINDOW_FORCE, "tile_nnz": 1024,
+                                                     "ring_words": 8192, "window_block": 8}),
+                         ("window_ring8192_block32", {"window_mode": spmv.WINDOW_FORCE, "tile_nnz": 1024,
+                                                      "ring_words": 8192, "window_block": 32})):
+        with spmv.Matrix.from_csr(A, params=params) as M:
+            t = time_launches(lambda: M.apply(x, y), 200, 20, torch)
+            inf = M.info
+        c0[name] = {"us": round(t * 1e6, 2), "GBs_L2_resident": round(B / t / 1e9, 1),
+                    "window_tiles": inf["n_window_tiles"], "window_words": inf["window_words"]}
+    out["mesh32_352K_nnz"] = c0
+    log(f"32^3 mesh: {c0}")
+    c1 = {}
+    for ordering in ("rcm", "random"):
+        A = mg.config1(ordering)
+        x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+        y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+        B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+        with spmv.Matrix.from_csr(A) as M:
+            t = time_launches(lambda: M.apply(x, y), 100, 5, torch)
+        c1[ordering] = {"ms": round(t * 1e3, 4), "GBs": round(B / t / 1e9, 1), "rows": A.n_rows, "nnz": A.nnz}
+    c1["rcm_over_random"] = round(c1["random"]["ms"] / c1["rcm"]["ms"], 3)
+    out["knn126_2M_rows_100_spmv"] = c1
+    log(f"126^3 kNN: {c1}")
+    A = mg.config3()
+    c3 = {"block_rows": A.n_rows, "blocks": A.nnz}
+    with spmv.Matrix.from_csr(A, fp32=True) as M:
+        for k in (1, 4, 8):
+            X = torch.as_tensor(mg.uniform(3 * A.n_cols * k, 6, 1), device="cuda").view(3 * A.n_cols, k)
+            Y = torch.empty((3 * A.n_rows, k), dtype=torch.float64, device="cuda")
+            t = time_launches(lambda: M.spmm(X, Y), 20, 3, torch)
+            X32, Y32 = X.float(), Y.float()
+            t32 = time_launches(lambda: M.spmm_f32(X32, Y32), 20, 3, torch)
+            b64 = A.nnz * (72 + 4) + 4 * (A.n_rows + 1) + 8 * 3 * k * (A.n_cols + A.n_rows)
+            b32 = A.nnz * (36 + 4) + 4 * (A.n_rows + 1) + 4 * 3 * k * (A.n_cols + A.n_rows)
+            fl = 2 * 9 * A.nnz * k
+            c3[f"k{k}"] = {"fp64_ms": round(t * 1e3, 4), "fp64_GBs": round(b64 / t / 1e9, 1),
+                           "fp64_GFLOPs": round(fl / t / 1e9, 1), "fp32_ms": round(t32 * 1e3, 4),
+                           "fp32_GBs": round(b32 / t32 / 1e9, 1), "fp32_GFLOPs": round(fl / t32 / 1e9, 1)}
+            del X, Y, X32, Y32
+    out["bsr3x3_4M_cells"] = c3
+    log(f"3x3 block CSR: {c3}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,10 +353,13 @@ def main():
         torch.cuda.synchronize()
         del buf, dst
 
-    if not args.no_extras and not args.no_serve:
+    if not args.no_extras:
         M.close()
         del x, y
         torch.cuda.empty_cache()
+        extras["configs"] = config_lines(torch)
+        torch.cuda.empty_cache()
+    if not args.no_extras and not args.no_serve:
         extras["serving"] = serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64)
 
     cpu = None
