@@ -32,8 +32,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SpMV effective HBM GB/s (% of peak) FP64 vs mixed; CG solves/s + p99 latency"
 PEAK_HBM_GBS = 8000.0
-DOMINANT_KERNEL = "k_stream<double, double, double, double, 4096, 0>"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_fp64_hex27_16M_rcm_traffic.txt")
 KERNEL_SOURCES = ["paper_2107_12371_amd/csrc/spmv_kernels.hip", "paper_2107_12371_amd/csrc/tile.h",
                   "paper_2107_12371_amd/csrc/device.h", "paper_2107_12371_amd/csrc/launch.h"]
 
@@ -50,13 +48,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def read_traffic(hash_now: str):
+def dominant_kernel(info) -> tuple[str, str]:
+    """(kernel name, profile-summary stem) of the launch that does the work."""
+    if info["n_window_tiles"] > info["n_tiles"] // 2:
+        name = f"k_cwin<double, double, double, double, {info['tile_nnz']}, 0>"
+        return name, f"k_cwin{info['tile_nnz']}_fp64_hex27_16M_rcm"
+    name = f"k_stream<double, double, double, double, {info['tile_nnz']}, 0>"
+    return name, f"k_stream{info['tile_nnz']}_fp64_hex27_16M_rcm"
+
+
+def read_traffic(hash_now: str, stem: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on different kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", stem + "_traffic.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -211,10 +219,11 @@ def config_lines(torch, log=log) -> dict:
     B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
     c0 = {}
     for name, params in (("direct", {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 1024}),
-                         ("window_ring8192_block8", {"window_mode": spmv.WINDOW_FORCE, "tile_nnz": 1024,
-                                                     "ring_words": 8192, "window_block": 8}),
-                         ("window_ring8192_block32", {"window_mode": spmv.WINDOW_FORCE, "tile_nnz": 1024,
-                                                      "ring_words": 8192, "window_block": 32})):
+                         ("compact_windows", {"window_mode": spmv.WINDOW_AUTO, "tile_nnz": 1024}),
+                         ("ring_8192_block8", {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024,
+                                               "ring_words": 8192, "window_block": 8}),
+                         ("ring_8192_block32", {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024,
+                                                "ring_words": 8192, "window_block": 32})):
         with spmv.Matrix.from_csr(A, params=params) as M:
             t = time_launches(lambda: M.apply(x, y), 200, 20, torch)
             inf = M.info
@@ -263,6 +272,7 @@ def main():
     ap.add_argument("--m", type=int, default=252, help="lattice edge (252 -> 16,003,008 rows)")
     ap.add_argument("--ordering", default="rcm", choices=["rcm", "natural", "random"])
     ap.add_argument("--tile-nnz", type=int, default=0)
+    ap.add_argument("--window", type=int, default=0, help="window mode (0 auto/compact, 1 off, 2 ring)")
     ap.add_argument("--no-xcd-remap", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/CG/copy lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -292,7 +302,7 @@ def main():
     A = mg.config2(m=args.m, ordering=args.ordering)
     log(f"matrix n={A.n_rows} nnz={A.nnz} ({time.perf_counter() - t0:.1f} s)")
     x_h = mg.uniform(A.n_cols, mg.seed_for(2), 1)
-    params = {"tile_nnz": args.tile_nnz} if args.tile_nnz else None
+    params = {"tile_nnz": args.tile_nnz, "window_mode": args.window}
     M = spmv.Matrix.from_csr(A, fp32=not args.no_extras, params=params, xcd_remap=not args.no_xcd_remap)
     info = M.info
     log(f"resident: {info['device_bytes'] / 1e9:.2f} GB, tiles={info['n_tiles']} "
@@ -306,10 +316,20 @@ def main():
     gbs = B / t_step / 1e9
     log(f"FP64 SpMV: {t_step * 1e3:.4f} ms/step, {gbs:.1f} GB/s ({100 * gbs / PEAK_HBM_GBS:.1f}% of 8 TB/s)")
 
-    traffic = read_traffic(kernel_source_hash())
+    kname, stem = dominant_kernel(info)
+    traffic = read_traffic(kernel_source_hash(), stem)
+    # bytes the compact-window format itself moves: 8 B value + 2 B window
+    # position per entry, 8 B per run, 32 B per tile descriptor, row pointers,
+    # x once and y once (the CSR bytes B above are the algorithmic figure)
+    if info["n_window_tiles"]:
+        fmt = (A.nnz * 10 + 8 * info["n_runs"] + 32 * info["n_tiles"] + 4 * (A.n_rows + 1)
+               + 8 * A.n_cols + 8 * A.n_rows)
+    else:
+        fmt = B + 32 * info["n_tiles"]
     roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": DOMINANT_KERNEL, "alg_bytes_per_launch": B}
+                "kernel": kname, "alg_bytes_per_launch": B,
+                "format_bytes_per_launch": fmt, "format_GBs": round(fmt / t_step / 1e9, 2)}
 
     extras = {}
     if not args.no_extras:
@@ -377,6 +397,7 @@ def main():
         "config": {"workload": f"hex27-subset mesh {args.m}^3 ({A.n_rows} rows, {A.nnz} nnz), "
                                f"{args.ordering} order, FP64 CSR y=Ax",
                    "rows": A.n_rows, "nnz": A.nnz, "tile_nnz": info["tile_nnz"],
+                   "window_tiles": info["n_window_tiles"], "tiles": info["n_tiles"],
                    "xcd_remap": not args.no_xcd_remap},
         "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 2),
         "roofline": roofline,

@@ -56,25 +56,35 @@ typedef struct spmv_matrix spmv_matrix;
 #define SPMV_VALUES_BF16 0x2u   /* also keep a BF16 copy of the values */
 #define SPMV_NO_XCD_REMAP 0x4u  /* keep launch order = tile order (no XCD grouping) */
 
-/* Window policy for the LDS x-window path (the GPU counterpart of the
- * paper's circular vector cache, Sec. 5.1). */
-#define SPMV_WINDOW_AUTO 0  /* use the window where the staged words are few */
-#define SPMV_WINDOW_OFF 1   /* direct L2 gathers everywhere */
-#define SPMV_WINDOW_FORCE 2 /* window wherever it fits in the LDS ring */
+/* x-window policy.  The GPU counterparts of the paper's vector cache
+ * (Sec. 5.1): x words a tile needs are staged in LDS with contiguous loads
+ * and the tile's entries address them with 16-bit window-relative indices. */
+#define SPMV_WINDOW_AUTO 0 /* compact per-tile windows wherever they fit (default):
+                              the tile's distinct columns merged into at most 64
+                              runs, at most tile_nnz staged words; other tiles
+                              gather x directly.  With the default tile_nnz, AUTO
+                              builds windows only for matrices of at least 512 MB
+                              (smaller ones are served from cache), and only
+                              binary64 products use them */
+#define SPMV_WINDOW_OFF 1  /* direct L2 gathers everywhere */
+#define SPMV_WINDOW_RING 2 /* the paper's circular cache literally: one workgroup
+                              walks a block of adjacent tiles, staging only the
+                              words (colend_{i-1}, colend_i] into an LDS ring */
 
 /* Analysis parameters; zero fields take the defaults (shown). */
 typedef struct spmv_params {
     int32_t tile_nnz;      /* row-tile capacity: 1024, 2048 or 4096; a tile holds
-                              at most tile_nnz - 3 stored entries (0: chosen from
-                              nnz; longer rows take the long-row path) */
+                              at most tile_nnz - 3 stored entries; longer rows take
+                              the long-row path (0: chosen from nnz; with AUTO
+                              windows 2048 when windows cover most tiles) */
     int32_t tile_rows;     /* max rows per tile, <= 512 (0: 512) */
     int32_t window_mode;   /* SPMV_WINDOW_* (0: AUTO) */
-    int32_t ring_words;    /* LDS ring capacity in x words, a power of two in
-                              [256, 8192] (0: 4096) */
-    int32_t window_block;  /* adjacent tiles walked by one window workgroup
+    int32_t ring_words;    /* RING: LDS ring capacity in x words, a power of two
+                              in [256, 8192] (0: 4096) */
+    int32_t window_block;  /* RING: adjacent tiles walked by one workgroup
                               (0: chosen from the tile count) */
-    double window_ratio;   /* AUTO uses the window for a block when staged words
-                              <= window_ratio * stored entries (0: 0.25) */
+    int32_t window_gap;    /* AUTO: column gaps up to this many words are staged
+                              inside a run rather than starting a new run (0: 64) */
     int32_t kernel;        /* direct-gather kernel: 0 auto, 1 one workgroup per
                               tile, 2 pipelined persistent workgroups, 3 persistent
                               wavefront tiles (tile_nnz 1024, <= 128 rows) */
@@ -88,10 +98,11 @@ typedef struct spmv_info {
     int32_t n_tiles;        /* all row segments (stream tiles + long rows) */
     int32_t n_stream_tiles; /* tiles on the direct-gather path */
     int32_t n_long_rows;    /* rows longer than tile_nnz */
-    int32_t n_window_tiles; /* tiles on the LDS-window path */
-    int32_t n_window_blocks;
+    int32_t n_window_tiles; /* tiles on an LDS-window path (ring or compact) */
+    int32_t n_window_blocks; /* RING: blocks of adjacent tiles */
     int32_t ring_words;
     int64_t window_words;   /* x words staged into LDS per product */
+    int64_t n_runs;         /* compact windows: column runs over all tiles */
     int32_t has_fp32, has_bf16;
     int64_t device_bytes;   /* bytes of device memory held by the handle */
     int32_t block_size;     /* 1: scalar CSR, 3: 3x3 block CSR (n_rows/n_cols/nnz count blocks) */
@@ -292,18 +303,23 @@ const char *spmv_last_error(void);
 /*
  * spmv_plan_inspect: run the analysis plan on host arrays without touching
  * the GPU (for tests and tools).  Validates like spmv_create.  Outputs are
- * optional (NULL skips); pass arrays sized from a first call's *n_tiles_out:
+ * optional (NULL skips); size them from a first call's *n_tiles_out and
+ * info->n_runs:
  *   seg_bound   int32[n_tiles + 1] row boundaries of the tiles
- *   seg_kind    int32[n_tiles]: 0 direct-gather tile, 1 long row, 2 window tile
- *   win_off     int32[n_tiles]: first x word staged before the tile (window)
- *   win_cnt     int32[n_tiles]: number of x words staged (window), else 0
- *   win_block   int32[n_tiles]: window block id, -1 if not a window tile
+ *   seg_kind    int32[n_tiles]: 0 direct-gather tile, 1 long row,
+ *               2 ring-window tile, 3 compact-window tile
+ *   win_off     int32[n_tiles]: ring: first x word staged before the tile;
+ *               compact: index of the tile's first run
+ *   win_cnt     int32[n_tiles]: ring: x words staged; compact: number of runs
+ *   win_block   int32[n_tiles]: ring block id, -1 otherwise
+ *   runs        int32[2 * n_runs]: compact runs (first column, window position)
+ *   lidx        uint16[nnz]: compact tiles: each entry's window position
  *   info        plan summary (device_bytes is an estimate)
  */
 int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                       const int32_t *col_idx, const spmv_params *params, int32_t *n_tiles_out,
                       int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
-                      int32_t *win_block, spmv_info *info);
+                      int32_t *win_block, int32_t *runs, uint16_t *lidx, spmv_info *info);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libspmv_gfx950.so")
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE = 0, -1, -2, -3
 SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
 SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP = 0x1, 0x2, 0x4
-WINDOW_AUTO, WINDOW_OFF, WINDOW_FORCE = 0, 1, 2
+WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
 CG_FP64, CG_MIXED_FP32 = 0, 1
 
 EXPORTED = [
@@ -45,7 +45,7 @@ class SpmvError(RuntimeError):
 class spmv_params(ctypes.Structure):
     _fields_ = [("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
-                ("window_block", ctypes.c_int32), ("window_ratio", ctypes.c_double),
+                ("window_block", ctypes.c_int32), ("window_gap", ctypes.c_int32),
                 ("kernel", ctypes.c_int32)]
 
 
@@ -55,7 +55,7 @@ class spmv_info(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("n_stream_tiles", ctypes.c_int32),
                 ("n_long_rows", ctypes.c_int32), ("n_window_tiles", ctypes.c_int32),
                 ("n_window_blocks", ctypes.c_int32), ("ring_words", ctypes.c_int32),
-                ("window_words", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
+                ("window_words", ctypes.c_int64), ("n_runs", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("block_size", ctypes.c_int32)]
 
@@ -103,7 +103,7 @@ def lib():
         L.spmv_last_error.argtypes = []
         L.spmv_plan_inspect.restype = ctypes.c_int
         L.spmv_plan_inspect.argtypes = [i32, i32, i64, vp, vp, ctypes.POINTER(spmv_params),
-                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp,
+                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp,
                                         ctypes.POINTER(spmv_info)]
         _lib = L
     return _lib
@@ -141,23 +141,26 @@ def _info_dict(inf: spmv_info) -> dict:
 
 def plan_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, params: dict | None = None) -> dict:
     """Run the analysis plan on the host (no GPU).  Returns tile boundaries,
-    kinds (0 direct, 1 long row, 2 window), window offsets/counts/blocks and
-    the summary."""
+    kinds (0 direct, 1 long row, 2 ring window, 3 compact window), window
+    offsets/counts/blocks, compact runs (first column, window position),
+    window-relative indices and the summary."""
     rp, ci, _ = _host_csr(row_ptr, col_idx, None)
     L = lib()
     nt = ctypes.c_int32(0)
     inf = spmv_info()
     _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
-                               ctypes.byref(nt), None, None, None, None, None, ctypes.byref(inf)),
+                               ctypes.byref(nt), None, None, None, None, None, None, None, ctypes.byref(inf)),
            "spmv_plan_inspect")
     n = nt.value
     out = {k: np.zeros(n + (1 if k == "seg_bound" else 0), np.int32)
            for k in ("seg_bound", "seg_kind", "win_off", "win_cnt", "win_block")}
+    out["runs"] = np.zeros((inf.n_runs, 2), np.int32)
+    out["lidx"] = np.zeros(ci.shape[0] if inf.n_runs else 0, np.uint16)
     _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
                                ctypes.byref(nt), out["seg_bound"].ctypes.data,
                                out["seg_kind"].ctypes.data, out["win_off"].ctypes.data,
                                out["win_cnt"].ctypes.data, out["win_block"].ctypes.data,
-                               ctypes.byref(inf)), "spmv_plan_inspect")
+                               _ptr(out["runs"]), _ptr(out["lidx"]), ctypes.byref(inf)), "spmv_plan_inspect")
     out["info"] = _info_dict(inf)
     return out
 

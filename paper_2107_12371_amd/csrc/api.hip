@@ -149,6 +149,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         d.seg = sg;
         d.woff = P.win_off[sg];
         d.wcnt = P.win_cnt[sg];
+        d.width = P.cwin_width.empty() ? 0 : P.cwin_width[sg];
         return d;
     };
     auto upload_descs = [&](const std::vector<int32_t> &list, TileDesc **dst) {
@@ -165,6 +166,12 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     if (!rc && M.n_blk) {
         rc = upload_descs(P.win_list, &M.win_desc);
         if (!rc) rc = dev_upload(A, &M.win_blk_ptr, P.win_blk_ptr.data(), P.win_blk_ptr.size(), 0);
+    }
+    M.n_cwin = (int32_t)P.cwin_list.size();
+    if (!rc && M.n_cwin) {
+        rc = upload_descs(P.cwin_list, &M.cwin_desc);
+        if (!rc) rc = dev_upload(A, &M.runs, P.runs.data(), P.runs.size(), 0);
+        if (!rc) rc = dev_upload(A, &M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
     }
     if (!rc) prepare_launch_queries();
     if (!rc && M.n_blk) {
@@ -187,6 +194,8 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     I.n_stream_tiles = M.n_stream;
     I.n_long_rows = M.n_long;
     I.n_window_tiles = (int32_t)P.win_list.size();
+    for (int32_t sg : P.cwin_list) I.n_window_tiles += P.win_cnt[sg] > 0 ? 1 : 0;
+    I.n_runs = (int64_t)P.runs.size() / 2;
     I.n_window_blocks = M.n_blk;
     I.ring_words = P.ring_words;
     I.window_words = P.window_words;

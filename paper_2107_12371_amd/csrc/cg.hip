@@ -85,6 +85,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
     }
 }
 
+// First stage of a reduction over many partials: workgroup b sums the fixed
+// chunk [b*chunk, min(n, (b+1)*chunk)) in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restrict__ part, int n, int chunk,
+                                                         double *__restrict__ out, const CgState *st, int mode) {
+    __shared__ double sh[kBlock / kWave];
+    if ((mode == R_ALPHA || mode == R_BETA) && st->done) return;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double s = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 // After a failed true-residual check: continue from r = b - A x.
 __global__ void k_replace(CgState *st) {
     st->beta = st->rt2 / st->rho;
@@ -228,6 +241,7 @@ template <typename T, typename V> struct CgCore {
     int n;
     T *x, *r, *p, *q;
     double *part_seg, *part_vec;
+    double *part2;      // first-stage sums of a two-stage reduction
     CgState *st;        // device
     CgState *hst;       // pinned host mirror
     int n_wg, chunk, graph_iters;
@@ -245,13 +259,28 @@ template <typename T, typename V> struct CgCore {
         if (graph) (void)hipGraphDestroy(graph);
     }
 
+    // Deterministic reduction of n partials into the device scalars: one
+    // workgroup for up to 4096 partials, else a fixed-partition first stage
+    // over up to kStage1 workgroups and a one-workgroup second stage.
+    static constexpr int kStage1 = 256;
+    void reduce(const double *part, int n, int mode, hipStream_t t) {
+        if (n <= 4096) {
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part, n, st, mode);
+            return;
+        }
+        const int chunk = (n + kStage1 - 1) / kStage1;
+        const int nb = (n + chunk - 1) / chunk;
+        hipLaunchKernelGGL(k_reduce_stage, dim3(nb), dim3(kBlock), 0, t, part, n, chunk, part2, st, mode);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part2, nb, st, mode);
+    }
+
     hipError_t iteration(hipStream_t t) {
         const int *done = &st->done;
         hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part_seg, M.n_seg, st, (int)R_ALPHA);
+        reduce(part_seg, M.n_seg, R_ALPHA, t);
         hipLaunchKernelGGL((k_update_xr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_vec);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part_vec, n_wg, st, (int)R_BETA);
+        reduce(part_vec, n_wg, R_BETA, t);
         hipLaunchKernelGGL((k_update_p<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st);
         return hipGetLastError();
     }
@@ -281,7 +310,7 @@ template <typename T, typename V> struct CgCore {
     hipError_t true_residual(const T *b) {
         hipError_t e = launch_spmv<V, T, T, T>(M, val, x, r, EPI_RESID, b, part_seg, nullptr, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_seg, M.n_seg, st, (int)R_TRUE);
+        reduce(part_seg, M.n_seg, R_TRUE, s);
         return hipGetLastError();
     }
 
@@ -292,7 +321,7 @@ template <typename T, typename V> struct CgCore {
     int solve(const T *b, double tol, int max_iter, int *iters, int *replacements, bool confirm = true) {
         hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol, max_iter);
         HIP_TRY(true_residual(b));
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_seg, M.n_seg, st, (int)R_RHO0);
+        reduce(part_seg, M.n_seg, R_RHO0, s);
         hipLaunchKernelGGL((k_copy<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r);
         HIP_TRY(hipGetLastError());
         int rc = read_state();
@@ -350,6 +379,7 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
     HIP_TRY(B.alloc(&C.q, C.n));
     HIP_TRY(B.alloc(&C.part_seg, (size_t)std::max(C.M.n_seg, 1)));
     HIP_TRY(B.alloc(&C.part_vec, (size_t)C.n_wg));
+    HIP_TRY(B.alloc(&C.part2, (size_t)CgCore<T, V>::kStage1));
     HIP_TRY(B.alloc(&C.st, 1));
     return SPMV_OK;
 }

@@ -11,6 +11,7 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
 constexpr int kWave = 64;
 constexpr int kEntriesPerLane = 4; // stored entries a lane streams per pass
 constexpr int kPad = 16;           // padding entries after col/val arrays
+constexpr int kCwinMaxRunsDev = 64; // compact windows: runs per tile (plan limit)
 
 // Epilogues of the row-tile kernels.
 enum Epilogue : int {
@@ -24,9 +25,9 @@ struct TileDesc {
     int32_t r0, r1;   // rows [r0, r1)
     int32_t s, e;     // stored entries [s, e) = [row_ptr[r0], row_ptr[r1])
     int32_t seg;      // segment id (index of the tile's dot-product partial)
-    int32_t woff;     // window tiles: first x word staged before the tile
-    int32_t wcnt;     // window tiles: number of x words staged
-    int32_t pad;
+    int32_t woff;     // ring tiles: first x word staged; compact tiles: first run
+    int32_t wcnt;     // ring tiles: x words staged; compact tiles: number of runs
+    int32_t width;    // compact tiles: staged window words
 };
 
 // Kernel variants for the direct-gather tiles.
@@ -51,6 +52,10 @@ struct DevMatrix {
     int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_desc
     TileDesc *win_desc = nullptr;    // window tiles, grouped by block
     int32_t ring_words = 0;
+    int32_t n_cwin = 0;
+    TileDesc *cwin_desc = nullptr;   // compact-window tiles: woff = first run, wcnt = runs, pad = width
+    int32_t *runs = nullptr;         // (first column, window position) per run
+    uint16_t *lidx = nullptr;        // window-relative column per stored entry (+ padding)
     bool xcd_remap = true;
     int32_t kernel = KV_AUTO;        // direct-gather kernel variant
     int32_t block = 1;                // 1: scalar CSR, 3: 3x3 block CSR
@@ -85,6 +90,7 @@ template <> struct Val4<double> {
     }
     __device__ __forceinline__ void zero() { a = f64x2{0.0, 0.0}; b = a; }
     template <int J> __device__ __forceinline__ double get() const { return J < 2 ? a[J & 1] : b[J & 1]; }
+    __device__ __forceinline__ double get_dyn(int j) const { return j < 2 ? a[j & 1] : b[j & 1]; }
 };
 template <> struct Val4<float> {
     f32x4 a;
@@ -93,6 +99,7 @@ template <> struct Val4<float> {
     }
     __device__ __forceinline__ void zero() { a = f32x4{0.f, 0.f, 0.f, 0.f}; }
     template <int J> __device__ __forceinline__ float get() const { return a[J]; }
+    __device__ __forceinline__ float get_dyn(int j) const { return a[j]; }
 };
 template <> struct Val4<uint16_t> {  // bfloat16 bit patterns
     u32x2 a;
@@ -103,6 +110,11 @@ template <> struct Val4<uint16_t> {  // bfloat16 bit patterns
     template <int J> __device__ __forceinline__ float get() const {
         unsigned w = a[J >> 1];
         unsigned bits = (J & 1) ? (w & 0xffff0000u) : (w << 16);
+        return __uint_as_float(bits);
+    }
+    __device__ __forceinline__ float get_dyn(int j) const {
+        unsigned w = a[j >> 1];
+        unsigned bits = (j & 1) ? (w & 0xffff0000u) : (w << 16);
         return __uint_as_float(bits);
     }
 };

@@ -19,7 +19,14 @@ int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row
                  const int32_t *col_idx);
 
 // Segment kinds of the analysis plan.
-enum SegKind : int32_t { SEG_STREAM = 0, SEG_LONG = 1, SEG_WINDOW = 2 };
+enum SegKind : int32_t { SEG_STREAM = 0, SEG_LONG = 1, SEG_WINDOW = 2, SEG_CWIN = 3 };
+
+// The wavefront-tile kernel's number in spmv_params.kernel (its tiles are planned
+// differently: 1024-entry capacity, at most 128 rows).
+constexpr int KV_WAVE_PLAN = 3;
+
+// Compact per-tile windows: at most this many words and runs per tile.
+constexpr int kCwinMaxRuns = 64;  // must equal the kernels' kCwinMaxRunsDev
 
 // Analysis plan built once per matrix (the matrix is constant, so its
 // preprocessing is amortised -- paper Sec. 2).
@@ -28,7 +35,6 @@ struct Plan {
     int64_t nnz = 0;
     int32_t tile_nnz = 0, tile_rows = 0;
     int32_t window_mode = 0, ring_words = 0, window_block = 0, kernel = 0;
-    double window_ratio = 0.0;
     std::vector<int32_t> seg_bound;  // n_seg + 1 row boundaries
     std::vector<int32_t> seg_kind;   // SegKind per segment
     std::vector<int32_t> win_off;    // first staged x word (window segments)
@@ -39,6 +45,14 @@ struct Plan {
     std::vector<int32_t> win_list;     // window segment ids, grouped by block
     std::vector<int32_t> win_blk_ptr;  // n_blocks + 1 offsets into win_list
     int64_t window_words = 0;
+    // compact windows (SEG_CWIN): per tile, runs of columns staged in LDS;
+    // win_off/win_cnt hold the tile's first run and run count, cwin_width its
+    // staged words; runs are (first column, window position) pairs and lidx
+    // holds each stored entry's window position (16-bit, relative).
+    std::vector<int32_t> cwin_list;
+    std::vector<int32_t> cwin_width;   // per segment
+    std::vector<int32_t> runs;         // 2 per run
+    std::vector<uint16_t> lidx;        // per stored entry (compact tiles only)
     int32_t n_seg() const { return (int32_t)seg_kind.size(); }
 };
 

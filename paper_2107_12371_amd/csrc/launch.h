@@ -24,6 +24,8 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     const int *done;        // optional: non-zero makes the launch a no-op (CG)
     const int32_t *win_blk_ptr;
     int32_t ring_words;
+    const int32_t *runs;    // compact windows
+    const uint16_t *lidx;
 };
 
 constexpr int kBsrRows = 85;     // block rows per tile (3 lanes each)

@@ -148,6 +148,77 @@ __global__ __launch_bounds__(kBlock) void k_wave(SpmvArgs<V, X, Y> g) {
     }
 }
 
+// Compact windows (the paper's vector cache with short relative indices,
+// one tile at a time): the tile's x words -- its distinct columns merged into
+// runs -- are staged in LDS with contiguous loads, then every entry reads x
+// from LDS through its 16-bit window position.  The matrix stream shrinks
+// from 12 to 10 bytes per entry (FP64) and the scattered global gathers are
+// replaced by contiguous staging loads.  One LDS buffer holds the window and
+// then, after a barrier, the products (same row sums as k_stream, bitwise).
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+__global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
+    using Regs = WinTileRegs<V, NT>;
+    __shared__ A buf[Regs::kProd];
+    __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int b = blockIdx.x;
+    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    if (li >= g.n_list) return;
+    const TileDesc d = g.desc[li];
+    const X *__restrict__ x = g.x;
+    if (d.wcnt == 0) {
+        // a tile whose window does not fit: direct gathers, as in k_stream
+        TileRegs<V, NT> t;
+        t.load(g.col, g.val, d.s, d.e);
+        RowPre<Y, EPI> pre;
+        pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
+        A xv[TileRegs<V, NT>::kMaxPass][4];
+        t.gather([x](int c) { return x[c]; }, xv);
+        t.products(xv, buf);
+        __syncthreads();
+        tile_rows<Y, A, EPI>(pre, d.r0, d.r1, buf, g.y, g.part, d.seg, sh);
+        return;
+    }
+    Regs t;
+    t.load(g.lidx, g.val, d.s, d.e);
+    RowPre<Y, EPI> pre;
+    pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
+    const int nr = d.wcnt;
+    if ((int)threadIdx.x < nr) {
+        run_x[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x)];
+        run_p[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x) + 1];
+    }
+    if (threadIdx.x == 0) run_p[nr] = d.width;
+    __syncthreads();
+    // stage the window: position w lies in the run r with run_p[r] <= w < run_p[r+1]
+    constexpr int kStage = Regs::kProd / kBlock;
+    A xs[kStage];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+        const int w = min((int)threadIdx.x + i * kBlock, d.width - 1);
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (run_p[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
+    }
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+        const int w = (int)threadIdx.x + i * kBlock;
+        if (w < d.width) buf[w] = xs[i];
+    }
+    __syncthreads();
+    A pr[Regs::kMaxPass][4];
+    t.products(d.s, d.e, buf, pr);
+    __syncthreads();
+    t.store(pr, buf);
+    __syncthreads();
+    tile_rows<Y, A, EPI>(pre, d.r0, d.r1, buf, g.y, g.part, d.seg, sh);
+}
+
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
@@ -270,6 +341,27 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             }
             hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
+    }
+    if (M.n_cwin > 0) {
+        SpmvArgs<V, X, Y> a = g;
+        a.desc = M.cwin_desc;
+        a.n_list = M.n_cwin;
+        a.runs = M.runs;
+        a.lidx = M.lidx;
+        int grid = M.n_cwin;
+        a.per_xcd = 0;
+        if (M.xcd_remap && M.n_cwin >= 16) {
+            a.per_xcd = (M.n_cwin + 7) / 8;
+            grid = 8 * a.per_xcd;
+        }
+        // Binary64 values stream 10 instead of 12 bytes per entry through the
+        // window; with 4- or 2-byte values the window's extra barriers and LDS
+        // traffic outweigh the saving (measured), so those products treat the
+        // same tiles as direct-gather tiles.
+        if (sizeof(V) == 8)
+            hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
     }
     if (M.n_long > 0) {
         SpmvArgs<V, X, Y> a = g;

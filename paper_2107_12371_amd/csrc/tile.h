@@ -71,6 +71,62 @@ template <typename V, int NT, int LANES = kBlock> struct TileRegs {
     }
 };
 
+// A compact-window tile's stored entries: 16-bit window positions (8 bytes
+// per 4 entries) and values, streamed like TileRegs with clamped addresses.
+template <typename V, int NT> struct WinTileRegs {
+    static constexpr int kPass = kEntriesPerLane * kBlock;
+    static constexpr int kMaxPass = NT / kPass;
+    static constexpr int kProd = kMaxPass * kPass;
+    static_assert(NT % kPass == 0, "tile capacity must be a whole number of passes");
+    u32x2 w[kMaxPass];
+    Val4<V> v[kMaxPass];
+
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ lidx, const V *__restrict__ val, int s, int e) {
+        const int s4 = s & ~3;
+        const int last = e > s4 ? ((e - 1) & ~3) : s4;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p)
+            w[p] = stream_load<StreamNT<V>::value>(
+                reinterpret_cast<const u32x2 *>(lidx + min(s4 + p * kPass + lane0, last)));
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) v[p].load(val + min(s4 + p * kPass + lane0, last));
+    }
+
+    // products a_k * win[pos_k] (window in LDS) into registers.  Entries
+    // outside [s, e) belong to other tiles and read position 0 instead, so
+    // every LDS read stays inside this tile's window.
+    template <typename A>
+    __device__ __forceinline__ void products(int s, int e, const A *__restrict__ win,
+                                             A (&pr)[kMaxPass][4]) const {
+        const int s4 = s & ~3;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k = s4 + p * kPass + lane0;
+            const unsigned pos[4] = {w[p][0] & 0xffffu, w[p][0] >> 16, w[p][1] & 0xffffu, w[p][1] >> 16};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = k + j >= s && k + j < e;
+                pr[p][j] = to_acc<A>(v[p].get_dyn(j)) * win[in ? pos[j] : 0u];
+            }
+        }
+    }
+
+    template <typename A>
+    __device__ __forceinline__ void store(const A (&pr)[kMaxPass][4], A *__restrict__ prod) const {
+        const int lane0 = kEntriesPerLane * threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+            A *d = prod + p * kPass + lane0;
+            d[0] = pr[p][0];
+            d[1] = pr[p][1];
+            d[2] = pr[p][2];
+            d[3] = pr[p][3];
+        }
+    }
+};
+
 // Pass 2 inputs, loaded early (before the gathers and any prefetch, so
 // waiting for them never drains loads issued later): each lane's rows
 // r0 + lane and r0 + lane + 256 (tiles hold at most 512 rows), their entry

@@ -113,8 +113,27 @@ def check_plan(A, params=None):
             if hi_prev is not None and cnt and off == hi_prev + 1:
                 assert off + cnt - 1 == cols.max()   # loads exactly up to colend_i
             hi_prev = max(hi_prev if hi_prev is not None else -1, int(cols.max()))
+    # compact windows: every entry's 16-bit position maps back to its column
+    # through its tile's runs; windows fit the tile capacity, runs are ordered
+    cw = np.nonzero(kind == 3)[0]
+    runs = P["runs"]
+    for s in cw:
+        r0, nr = int(P["win_off"][s]), int(P["win_cnt"][s])
+        assert 0 <= nr <= 64
+        if nr == 0:
+            continue                  # direct-gather tile inside the window launch
+        rx, rpos = runs[r0:r0 + nr, 0].astype(np.int64), runs[r0:r0 + nr, 1].astype(np.int64)
+        assert rpos[0] == 0 and np.all(np.diff(rpos) > 0) and np.all(np.diff(rx) > 0)
+        a, b = rp[sb[s]], rp[sb[s + 1]]
+        pos = P["lidx"][a:b].astype(np.int64)
+        r = np.searchsorted(rpos, pos, side="right") - 1
+        assert np.array_equal(rx[r] + (pos - rpos[r]), A.col_idx[a:b])
+        cols = A.col_idx[a:b]
+        width = int(rpos[-1] + (cols[cols >= rx[-1]].max() - rx[-1] + 1))
+        assert width <= tnz
+        staged += width
     assert staged == info["window_words"]
-    assert info["n_window_tiles"] == win.size
+    assert info["n_window_tiles"] == win.size + int(np.sum(P["win_cnt"][cw] > 0))
     return P
 
 
@@ -140,7 +159,7 @@ def test_plan_invariants_edge_cases():
 @pytest.mark.parametrize("ring", [256, 1024, 4096])
 def test_plan_window_forced_ring_sizes(ring):
     A = mg.lattice(16, 16, 16, "faces", seed=3)         # bandwidth 256: many tiles fit
-    P = check_plan(A, {"tile_nnz": 1024, "window_mode": spmv.WINDOW_FORCE, "ring_words": ring,
+    P = check_plan(A, {"tile_nnz": 1024, "window_mode": spmv.WINDOW_RING, "ring_words": ring,
                        "window_block": 8})
     if ring >= 1024:
         assert P["info"]["n_window_tiles"] > 0
@@ -152,5 +171,20 @@ def test_plan_window_off_and_auto():
     A = mg.lattice(16, 16, 16, "faces", seed=3)
     P = check_plan(A, {"window_mode": spmv.WINDOW_OFF})
     assert P["info"]["n_window_tiles"] == 0
-    P = check_plan(A, {"window_mode": spmv.WINDOW_AUTO, "window_block": 16, "tile_nnz": 1024})
-    assert P["info"]["window_words"] <= 0.25 * A.nnz + 1
+    P = check_plan(A, {"window_mode": spmv.WINDOW_AUTO, "tile_nnz": 1024})
+    assert P["info"]["n_window_tiles"] == P["info"]["n_tiles"]          # every tile fits
+    assert P["info"]["window_words"] < A.nnz
+
+
+@pytest.mark.parametrize("gap", [1, 16, 256])
+def test_plan_compact_windows_mesh_and_scattered(gap):
+    A = mg.config0()
+    P = check_plan(A, {"tile_nnz": 4096, "window_gap": gap})
+    assert P["info"]["n_window_tiles"] > 0
+    # random order: columns scatter over the whole vector, windows do not fit
+    B = mg.config1("random", m=40)
+    P = check_plan(B, {"tile_nnz": 4096, "window_gap": gap})
+    assert P["info"]["n_window_tiles"] < P["info"]["n_tiles"]
+    C = mg.random_csr(5000, 5000, seed=9, mean_len=6.0, empty_frac=0.2, dense_rows=2, duplicates=True,
+                      unsorted=True)
+    check_plan(C, {"tile_nnz": 2048, "window_gap": gap})

@@ -98,7 +98,7 @@ def test_nan_inf_propagate_like_the_oracle():
     assert_parity(y, A, x)
 
 
-@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
+@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_RING, spmv.WINDOW_AUTO])
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
 @pytest.mark.parametrize("kernel,remap", [(1, True), (1, False), (2, True), (3, True)])
 def test_mesh_config0_paths(mode, tile, kernel, remap):
@@ -107,12 +107,12 @@ def test_mesh_config0_paths(mode, tile, kernel, remap):
     y, info = run64(A, x, xcd_remap=remap,
                     params={"tile_nnz": 1024 if kernel == 3 else tile, "window_mode": mode, "window_block": 8,
                             "ring_words": 8192, "kernel": kernel})
-    if mode == spmv.WINDOW_FORCE:
+    if mode != spmv.WINDOW_OFF:
         assert info["n_window_tiles"] > 0
     assert_parity(y, A, x)
 
 
-@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_FORCE])
+@pytest.mark.parametrize("mode", [spmv.WINDOW_OFF, spmv.WINDOW_RING, spmv.WINDOW_AUTO])
 def test_dyadic_bitwise(mode):
     for A in (mg.config0(dyadic=True), mg.config1("rcm", m=40, dyadic=True),
               mg.lattice(30, 30, 30, "stencil27", seed=5, dyadic=True)):
@@ -130,7 +130,7 @@ def test_ring_window_sizes_and_restarts():
     A = mg.lattice(32, 32, 40, "faces", seed=9)
     x = mg.uniform(A.n_cols, 13, 0)
     for ring in (1024, 2048, 4096, 8192):
-        y, info = run64(A, x, params={"window_mode": spmv.WINDOW_FORCE, "ring_words": ring,
+        y, info = run64(A, x, params={"window_mode": spmv.WINDOW_RING, "ring_words": ring,
                                       "window_block": 32, "tile_nnz": 1024})
         assert (info["n_window_tiles"] > 0) == (ring >= 4096)
         assert_parity(y, A, x)
@@ -140,7 +140,7 @@ def test_ring_window_sizes_and_restarts():
     perm = np.concatenate([np.arange(min(n, s + 2048) - 1, s - 1, -1) for s in range(0, n, 2048)])
     B = mg.permute(A, perm.astype(np.int32))
     P = spmv.plan_inspect(B.n_rows, B.n_cols, B.row_ptr, B.col_idx,
-                          {"window_mode": spmv.WINDOW_FORCE, "ring_words": 8192, "window_block": 32,
+                          {"window_mode": spmv.WINDOW_RING, "ring_words": 8192, "window_block": 32,
                            "tile_nnz": 1024})
     win = P["seg_kind"] == 2
     spans = np.array([B.col_idx[B.row_ptr[a]:B.row_ptr[b]].max() - B.col_idx[B.row_ptr[a]:B.row_ptr[b]].min() + 1
@@ -149,7 +149,7 @@ def test_ring_window_sizes_and_restarts():
     blocks = len(np.unique(P["win_block"][win]))
     assert restarts > blocks          # more full reloads than one per block
     xb = x[perm]
-    y, info = run64(B, xb, params={"window_mode": spmv.WINDOW_FORCE, "ring_words": 8192,
+    y, info = run64(B, xb, params={"window_mode": spmv.WINDOW_RING, "ring_words": 8192,
                                    "window_block": 32, "tile_nnz": 1024})
     assert info["n_window_tiles"] > 0
     assert_parity(y, B, xb)
@@ -189,6 +189,18 @@ def test_config1_full_size_and_permutation_equivariance(cfg1, ordering, kernel):
     x = mg.uniform(A.n_cols, 16, 0)
     y, _ = run64(A, x, params={"kernel": kernel})
     assert_parity(y, A, x)
+
+
+@pytest.mark.parametrize("gap", [0, 16, 64])
+def test_compact_windows_equal_direct_bitwise(cfg1, gap):
+    # staging x in LDS changes where x comes from, not the per-row sums
+    A = cfg1["rcm"]
+    x = mg.uniform(A.n_cols, 21, 0)
+    y_dir, _ = run64(A, x, params={"window_mode": spmv.WINDOW_OFF, "tile_nnz": 2048})
+    y_win, info = run64(A, x, params={"window_mode": spmv.WINDOW_AUTO, "window_gap": gap, "tile_nnz": 2048})
+    assert info["n_window_tiles"] > 0
+    assert np.array_equal(y_dir, y_win)
+    assert_parity(y_win, A, x)
 
 
 def test_kernel_variants_bitwise_identical(cfg1):
@@ -231,6 +243,27 @@ def test_fp32_paths_within_derived_bounds():
     assert np.all(np.abs(y16 - y_ref) <= 1.01 * (u16 + (m + 1) * u32) * bound)
     # the reduced-precision results are not just the binary64 result rounded
     assert np.max(np.abs(y32 - y_ref) / np.maximum(bound, 1e-300)) > 1e-9
+
+
+def test_reduced_precision_on_a_compact_window_handle(cfg1):
+    # FP32/BF16 products on a handle planned with compact windows run the
+    # direct kernel over the same tiles
+    A = cfg1["rcm"]
+    x = mg.uniform(A.n_cols, 22, 0)
+    y_ref, bound, m = _bounds(A, x)
+    with spmv.Matrix.from_csr(A) as M:
+        assert M.info["n_window_tiles"] == 0          # 165 MB matrix: served from cache, no windows
+    with spmv.Matrix.from_csr(A, fp32=True, bf16=True, params={"tile_nnz": 2048, "window_mode": 0}) as M:
+        assert M.info["n_window_tiles"] > 0
+        y64 = M.apply(to_dev(x)).cpu().numpy()
+        y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+        yv = M.apply_f32v(to_dev(x)).cpu().numpy()
+        y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    u32, u16 = 2.0 ** -24, 2.0 ** -8
+    assert oracle.spmv_accept(y64, y_ref, bound).all()
+    assert np.all(np.abs(y32 - y_ref) <= 1.01 * (m + 2) * u32 * bound)
+    assert np.all(np.abs(yv - y_ref) <= 1.01 * (u32 + m * 2.0 ** -53) * bound)
+    assert np.all(np.abs(y16 - y_ref) <= 1.01 * (u16 + (m + 1) * u32) * bound)
 
 
 def test_fp32_dyadic_bitwise():
