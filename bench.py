@@ -41,10 +41,15 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """sha256 of the SpMV kernel sources with // comments and blank lines
+    removed: a change of code invalidates stored counters, a comment does not."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -7,6 +7,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "bsr.h"
 #include "launch.h"
 #include "matrix.h"
 

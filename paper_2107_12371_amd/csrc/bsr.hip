@@ -5,76 +5,142 @@
 // holds cell i's neighbour blocks.  X and Y are row-major (3 n) x k, so the
 // k values of one scalar row sit contiguously and one gather brings all k.
 //
-// One workgroup per tile of up to 85 block rows and 512 stored blocks:
-// pass 1 stages the tile's block values (9 per block) and block columns in
-// LDS with coalesced streaming loads; pass 2 gives each (block row, scalar
-// row r) pair one lane, which walks the row's blocks in ascending order and
-// accumulates its k outputs:  Y[3i+r][j] += sum_c a_rc * X[3 col + c][j].
-// A block row with more than 512 blocks forms its own tile and reads its
-// values straight from global memory.  Tiles go to XCDs in contiguous runs
-// as in the scalar kernels.
+// One workgroup per tile of up to 85 block rows and 510 stored blocks (the
+// staged values of four tiles fill one CU's LDS).
+// Pass 1 stages the tile's block values (9 per block) and block columns in
+// LDS: every lane issues all of its 16-byte loads (fixed count, addresses
+// clamped to the tile) before the first LDS store, so the loads overlap.
+// Pass 2 gives each (scalar row, column group) one lane: JL lanes share a
+// scalar row 3i+r and each owns K/JL adjacent columns of Y, so the JL lanes
+// read one contiguous piece of each gathered X row.  A lane walks its row's
+// blocks U at a time: U column indices and 3U values from LDS, then all 3U
+// gathers of X, then the accumulation in ascending block order, so only
+// ceil(len/U) gather latencies are serial.  Out-of-row slots of the last
+// group re-read the row's last block (valid addresses) and are discarded
+// by a select, never by multiplying with zero, so Inf/NaN in X behave as
+// in the definition.  A block row with more than 510 blocks forms its own
+// tile and reads its values straight from global memory.  Tiles go to XCDs
+// in contiguous runs as in the scalar kernels.
+//
+// Per output the sum is sum over blocks (ascending) of a_r0 x0 + a_r1 x1 +
+// a_r2 x2, left to right, whatever K, JL and U are: a column of a k-column
+// product equals the one-column product of that column bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "bsr.h"
 #include "launch.h"
 
 namespace spmvlib {
 
-template <typename V, typename T, int K>
+template <typename V> struct BsrStage {
+    static constexpr int kVe = 16 / (int)sizeof(V);                           // values per 16-byte load
+    static constexpr int kVecs = (kBsrBlocks * 9 + kVe - 1) / kVe + 1;        // + 1: unaligned start
+    static constexpr int kTrips = (kVecs + kBlock - 1) / kBlock;
+    static constexpr int kColVecs = (kBsrBlocks + 3) / 4 + 1;                // + 1: unaligned start
+    static_assert(kColVecs <= kBlock, "one column load per lane");
+};
+
+// Pass-2 shapes (blocks per gather round U, lanes per scalar row JL) for
+// k = 1, 2, 4, 8 columns per launch.
+constexpr int kBsrU1 = 6, kBsrU2 = 4, kBsrU4 = 4, kBsrJL4 = 4, kBsrU8 = 4, kBsrJL8 = 4;
+
+// Pass 2 for lanes [t] of one tile; VP/CP point into LDS (staged) or global.
+template <typename V, typename T, int K, int JL, int U, typename VP, typename CP>
+__device__ __forceinline__ void bsr_rows(const BsrArgs<V, T> &g, int R0, int R1, int q0, VP vals, CP cols) {
+    constexpr int KC = K / JL;             // columns per lane
+    constexpr int kPairsPerPass = kBlock / JL;
+    const int t = (int)threadIdx.x;
+    const int jl = t % JL;
+    const int npairs = 3 * (R1 - R0);
+    for (int pr = t / JL; pr < npairs; pr += kPairsPerPass) {
+        const int br = R0 + pr / 3, r = pr % 3;
+        const int a = g.brow_ptr[br], z = g.brow_ptr[br + 1];
+        T acc[KC];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[j] = T(0);
+        const size_t xoff = (size_t)g.off + (size_t)jl * KC;
+        for (int q = a; q < z; q += U) {
+            int bc[U];
+            T v[U][3];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int qq = min(q + u, z - 1) - q0;
+                bc[u] = cols[qq];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[u][c] = static_cast<T>(vals[9 * (size_t)qq + 3 * r + c]);
+            }
+            T xv[U][3][KC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T *__restrict__ xr = g.X + (size_t)(3 * bc[u] + c) * g.ldx + xoff;
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) xv[u][c][j] = xr[j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in_row = q + u < z;
+#pragma unroll
+                for (int j = 0; j < KC; ++j) {
+                    T s = acc[j];
+                    s += v[u][0] * xv[u][0][j];
+                    s += v[u][1] * xv[u][1][j];
+                    s += v[u][2] * xv[u][2][j];
+                    acc[j] = in_row ? s : acc[j];
+                }
+            }
+        }
+        T *__restrict__ yr = g.Y + (size_t)(3 * br + r) * g.ldy + xoff;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) yr[j] = acc[j];
+    }
+}
+
+template <typename V, typename T, int K, int JL, int U>
 __global__ __launch_bounds__(kBlock) void k_bsr3(BsrArgs<V, T> g) {
-    __shared__ V sval[kBsrBlocks * 9];
-    __shared__ int32_t scol[kBsrBlocks];
+    using S = BsrStage<V>;
+    __shared__ i32x4 sval_raw[S::kTrips * kBlock];
+    __shared__ i32x4 scol_raw[S::kColVecs];
     const int b = blockIdx.x;
     const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
     if (li >= g.n_tiles) return;
+    const int t = (int)threadIdx.x;
     const int R0 = g.tiles[li], R1 = g.tiles[li + 1];
     const int q0 = g.brow_ptr[R0], q1 = g.brow_ptr[R1];
-    const bool staged = (q1 - q0) <= kBsrBlocks;
-    if (staged) {
-        const V *__restrict__ src = g.val + 9 * (size_t)q0;
-        const int nv = 9 * (q1 - q0);
-        for (int i = (int)threadIdx.x; i < nv; i += kBlock) sval[i] = __builtin_nontemporal_load(src + i);
-        for (int i = (int)threadIdx.x; i < q1 - q0; i += kBlock) scol[i] = __builtin_nontemporal_load(g.col + q0 + i);
+    if (q1 - q0 > kBsrBlocks) {  // one long block row: values from global memory
+        bsr_rows<V, T, K, JL, U>(g, R0, R1, q0, g.val + 9 * (size_t)q0, g.col + q0);
+        return;
     }
+    // Pass 1.  The arrays carry 16 elements of padding past the last block,
+    // so the rounded-up last vector stays inside the allocation; rounding
+    // the start down stays inside because allocations are 256-byte aligned.
+    const V *vbase = g.val + 9 * (size_t)q0;
+    const int vshift = (int)(((uintptr_t)vbase & 15) / sizeof(V));
+    const i32x4 *vsrc = reinterpret_cast<const i32x4 *>(vbase - vshift);
+    const int nvv = max((9 * (q1 - q0) + vshift + S::kVe - 1) / S::kVe, 1);
+    const int32_t *cbase = g.col + q0;
+    const int cshift = (int)(((uintptr_t)cbase & 15) / 4);
+    const i32x4 *csrc = reinterpret_cast<const i32x4 *>(cbase - cshift);
+    const int ncv = max((q1 - q0 + cshift + 3) / 4, 1);
+    i32x4 tv[S::kTrips];
+#pragma unroll
+    for (int i = 0; i < S::kTrips; ++i) tv[i] = __builtin_nontemporal_load(vsrc + min(t + i * kBlock, nvv - 1));
+    const i32x4 tc = __builtin_nontemporal_load(csrc + min(t, ncv - 1));
+#pragma unroll
+    for (int i = 0; i < S::kTrips; ++i) sval_raw[t + i * kBlock] = tv[i];
+    if (t < S::kColVecs) scol_raw[t] = tc;
     __syncthreads();
-    const int t = (int)threadIdx.x;
-    if (t >= 3 * (R1 - R0)) return;
-    const int br = R0 + t / 3, r = t % 3;
-    T acc[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = T(0);
-    const int a = g.brow_ptr[br], z = g.brow_ptr[br + 1];
-    for (int q = a; q < z; ++q) {
-        int bc;
-        T v[3];
-        if (staged) {
-            bc = scol[q - q0];
-            const V *s = sval + 9 * (q - q0) + 3 * r;
-            v[0] = static_cast<T>(s[0]);
-            v[1] = static_cast<T>(s[1]);
-            v[2] = static_cast<T>(s[2]);
-        } else {
-            bc = g.col[q];
-            const V *s = g.val + 9 * (size_t)q + 3 * r;
-            v[0] = static_cast<T>(s[0]);
-            v[1] = static_cast<T>(s[1]);
-            v[2] = static_cast<T>(s[2]);
-        }
-        const T *__restrict__ xr = g.X + (size_t)(3 * bc) * g.ldx + g.off;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int j = 0; j < K; ++j) acc[j] += v[c] * xr[(size_t)c * g.ldx + j];
-        }
-    }
-    T *__restrict__ yr = g.Y + (size_t)(3 * br + r) * g.ldy + g.off;
-#pragma unroll
-    for (int j = 0; j < K; ++j) yr[j] = acc[j];
+    const V *sval = reinterpret_cast<const V *>(sval_raw) + vshift;
+    const int32_t *scol = reinterpret_cast<const int32_t *>(scol_raw) + cshift;
+    bsr_rows<V, T, K, JL, U>(g, R0, R1, q0, sval, scol);
 }
 
-template <typename V, typename T, int K>
-static void launch_k(const DevMatrix &M, BsrArgs<V, T> g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_bsr3<V, T, K>), dim3(grid), dim3(kBlock), 0, st, g);
+template <typename V, typename T, int K, int JL, int U>
+static void launch_k(BsrArgs<V, T> g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_bsr3<V, T, K, JL, U>), dim3(grid), dim3(kBlock), 0, st, g);
 }
 
 template <typename V, typename T>
@@ -101,10 +167,10 @@ hipError_t launch_bsr3(const DevMatrix &M, const V *val, int k, const T *X, T *Y
     while (off < k) {
         const int rem = k - off;
         g.off = off;
-        if (rem >= 8) { launch_k<V, T, 8>(M, g, grid, st); off += 8; }
-        else if (rem >= 4) { launch_k<V, T, 4>(M, g, grid, st); off += 4; }
-        else if (rem >= 2) { launch_k<V, T, 2>(M, g, grid, st); off += 2; }
-        else { launch_k<V, T, 1>(M, g, grid, st); off += 1; }
+        if (rem >= 8) { launch_k<V, T, 8, kBsrJL8, kBsrU8>(g, grid, st); off += 8; }
+        else if (rem >= 4) { launch_k<V, T, 4, kBsrJL4, kBsrU4>(g, grid, st); off += 4; }
+        else if (rem >= 2) { launch_k<V, T, 2, 2, kBsrU2>(g, grid, st); off += 2; }
+        else { launch_k<V, T, 1, 1, kBsrU1>(g, grid, st); off += 1; }
     }
     return hipGetLastError();
 }

@@ -28,25 +28,6 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     const uint16_t *lidx;
 };
 
-constexpr int kBsrRows = 85;     // block rows per tile (3 lanes each)
-constexpr int kBsrBlocks = 512;  // stored 3x3 blocks staged in LDS per tile
-
-template <typename V, typename T> struct BsrArgs {
-    const int32_t *brow_ptr;
-    const int32_t *col;
-    const V *val;      // 9 values per block, row-major
-    const T *X;        // (3 n_cols) x ldx, row-major
-    T *Y;              // (3 n_rows) x ldy, row-major
-    const int32_t *tiles;  // n_tiles + 1 block-row boundaries
-    int32_t n_tiles;
-    int32_t per_xcd;
-    int32_t ldx, ldy, off;  // leading dimensions and first column of this launch
-};
-
-// Y = A X for a 3x3 block-CSR handle, k right-hand sides (row-major).
-template <typename V, typename T>
-hipError_t launch_bsr3(const DevMatrix &M, const V *val, int k, const T *X, T *Y, hipStream_t st);
-
 // y = A x over all segments of M (direct tiles, long rows, window blocks),
 // launched on `st`.  V: stored value type (double, float, uint16_t = bf16),
 // X/Y: vector types, A: accumulation type.  `part` must hold M.n_seg doubles

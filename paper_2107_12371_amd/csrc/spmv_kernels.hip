@@ -3,27 +3,37 @@
 // y_i = sum_{k in row i} a_k * x[c_k]   (paper Sec. 2 and 4.2: FP64 values,
 // 4-byte column indices; the column index must be read before the x
 // element it selects, Sec. 4.3).  The bandwidth-bound stream is the matrix
-// (12 bytes per stored entry in FP64); x is gathered through L2/MALL or,
-// on the window path, from an LDS ring that plays the part of the paper's
-// circular BRAM vector cache (Sec. 5.1).
+// (12 bytes per stored entry in FP64, 10 with 16-bit window positions); x is
+// gathered through L2/MALL or staged in LDS, which plays the part of the
+// paper's vector cache in BRAM (Sec. 5.1).
 //
-// Four kernels share one row-tile scheme:
-//  * k_pipe    (direct gathers, default): persistent workgroups, see below.
-//  * k_stream  (direct gathers): one workgroup per row tile.  Pass 1 streams
-//    the tile's values and column indices with 16-byte non-temporal loads,
-//    4 consecutive entries per lane, all passes issued before any gather
-//    so many loads are in flight; it gathers x and writes each product into
-//    LDS.  Pass 2 sums each row's products in ascending entry order (one
-//    lane per row) and writes y.  Tiles are assigned so that each XCD (its
-//    own L2) walks a contiguous range of rows, which keeps the band of x it
-//    needs resident in that L2.
+// All kernels share one row-tile scheme (tiles of whole rows, at most NT-3
+// stored entries and 512 rows; longer rows go to k_long):
+//  * k_stream  (direct gathers, default): one workgroup per row tile.  Pass 1
+//    streams the tile's column indices, then its values, with 16-byte loads,
+//    4 consecutive entries per lane, all passes issued before any gather so
+//    many loads are in flight; it gathers x and writes every product into
+//    LDS unconditionally.  Pass 2 sums each row's products in ascending
+//    entry order (one lane per row, inputs preloaded before the barrier)
+//    and writes y.  Tiles are assigned so that each XCD (its own L2) walks
+//    a contiguous range of rows, which keeps the band of x it needs resident
+//    in that L2.
+//  * k_cwin    compact windows: the tile's distinct columns, merged into at
+//    most 64 runs, are staged in LDS with contiguous loads and entries read
+//    x there through 16-bit window positions (default for large FP64
+//    products).  Tiles whose window does not fit run as in k_stream inside
+//    the same launch.
+//  * k_pipe, k_wave  persistent variants of k_stream (per workgroup and per
+//    wavefront) that prefetch the next tile's stream behind the current
+//    tile's gathers; selectable, measured slower on the mesh matrices.
 //  * k_long    one workgroup per row longer than a tile: strided partial sums
 //    per lane and a fixed-shape workgroup reduction.
-//  * k_window  one workgroup walks a block of adjacent tiles in order,
-//    staging into an LDS ring only the x words the previous tiles did not
-//    bring in, then gathers x from LDS.
+//  * k_window  the paper's circular cache taken literally: one workgroup
+//    walks a block of adjacent tiles in order, staging into an LDS ring only
+//    the x words the previous tiles did not bring in.
 // Every y_i is summed in an order fixed by the plan alone, so results are
-// bitwise reproducible and do not depend on what else runs on the GPU.
+// bitwise reproducible, the same for every kernel choice, and independent of
+// what else runs on the GPU.
 #include <hip/hip_runtime.h>
 
 #include "device.h"

@@ -337,6 +337,38 @@ def test_bsr3_fp32_storage_and_long_block_rows():
     _bsr_bound_check(Yb, B, Xb, 1e-12)
 
 
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 11])
+def test_bsr3_empty_rows_and_nonfinite_x(k):
+    # 300 block rows: a run of 120 empty rows (a whole tile without blocks),
+    # odd row lengths 0..13 so tiles start at odd block offsets, and one
+    # column of X holding NaN and another holding Inf
+    nbr, nbc = 300, 260
+    rng = np.random.default_rng(11)
+    lens = rng.integers(0, 14, nbr)
+    lens[100:220] = 0
+    lens[0] = 1
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(nbc, size=L, replace=False)) for L in lens]).astype(np.int32)
+    va = rng.uniform(-1, 1, (ci.shape[0], 3, 3))
+    B = mg.CSR(nbr, nbc, rp, ci, va, 3)
+    X = mg.uniform(3 * nbc * k, 40 + k, 0).reshape(3 * nbc, k)
+    X[3 * int(ci[0]) + 1, 0] = np.nan
+    X[3 * int(ci[-1]) + 2, k - 1] = np.inf
+    with spmv.Matrix.from_csr(B, fp32=True) as M:
+        assert M.info["n_tiles"] >= 3
+        Y = M.spmm(to_dev(X)).cpu().numpy()
+        Y32 = M.spmm_f32(to_dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+    Yr, Bd = oracle.bsr3_spmm(B, X)
+    assert np.isnan(Yr).any() and np.isinf(Yr).any()
+    assert oracle.spmv_accept(Y, Yr, Bd).all()
+    assert np.all(Y[3 * 100:3 * 220] == 0)
+    rt = np.broadcast_to(1.01 * (3 * np.repeat(lens, 3)[:, None] + 2) * 2.0 ** -24, Yr.shape)
+    fin = np.isfinite(Yr)
+    assert np.all(np.abs(Y32 - Yr)[fin] <= (rt * Bd)[fin])
+    assert np.array_equal(np.isnan(Y32), np.isnan(Yr))
+    assert np.array_equal(Y32[np.isinf(Yr)], Yr[np.isinf(Yr)])
+
+
 def test_bsr3_config3_shape_bitwise_dyadic():
     A = mg.bsr3(40, 40, 20, seed=7)
     # dyadic copy of the values: multiples of 2^-10 in [-2, 2]
