@@ -229,6 +229,87 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
     tile_rows<Y, A, EPI>(pre, d.r0, d.r1, buf, g.y, g.part, d.seg, sh);
 }
 
+// Persistent compact windows: the workgroups of an XCD walk its tile range
+// together (tile x*per_xcd + j, + W, + 2W, ...), and a workgroup issues the
+// next tile's matrix stream (window positions and values) right after its
+// current window's staging loads, so the stream stays in flight through the
+// products and row sums.  Same arithmetic as k_cwin, tile by tile.
+template <typename V, typename X, typename Y, typename A, int NT, int EPI>
+__global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
+    using Regs = WinTileRegs<V, NT>;
+    __shared__ A buf[Regs::kProd];
+    __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int end = min(g.n_list, (xcd + 1) * g.per_xcd);
+    const int W = g.wg_per_xcd;
+    int li = xcd * g.per_xcd + j;
+    if (li >= end) return;
+    const X *__restrict__ x = g.x;
+    TileDesc d = g.desc[li];
+    Regs cur;
+    cur.load(g.lidx, g.val, d.s, d.e);   // a direct tile ignores it
+    for (;;) {
+        const int ln = li + W;
+        const bool more = ln < end;
+        const TileDesc dn = g.desc[more ? ln : li];
+        RowPre<Y, EPI> pre;
+        pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
+        Regs nxt;
+        if (d.wcnt == 0) {
+            // a tile whose window does not fit: direct gathers, as in k_stream
+            TileRegs<V, NT> t;
+            t.load(g.col, g.val, d.s, d.e);
+            A xv[TileRegs<V, NT>::kMaxPass][4];
+            t.gather([x](int c) { return x[c]; }, xv);
+            nxt.load(g.lidx, g.val, dn.s, dn.e);
+            t.products(xv, buf);
+            __syncthreads();
+        } else {
+            const int nr = d.wcnt;
+            if ((int)threadIdx.x < nr) {
+                run_x[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x)];
+                run_p[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x) + 1];
+            }
+            if (threadIdx.x == 0) run_p[nr] = d.width;
+            __syncthreads();
+            constexpr int kStage = Regs::kProd / kBlock;
+            A xs[kStage];
+#pragma unroll
+            for (int i = 0; i < kStage; ++i) {
+                const int w = min((int)threadIdx.x + i * kBlock, d.width - 1);
+                int lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (run_p[mid] <= w) lo = mid;
+                    else hi = mid - 1;
+                }
+                xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
+            }
+            // next tile's stream (the last tile re-reads its own: L2 hits)
+            nxt.load(g.lidx, g.val, dn.s, dn.e);
+#pragma unroll
+            for (int i = 0; i < kStage; ++i) {
+                const int w = (int)threadIdx.x + i * kBlock;
+                if (w < d.width) buf[w] = xs[i];
+            }
+            __syncthreads();
+            A pr[Regs::kMaxPass][4];
+            cur.products(d.s, d.e, buf, pr);
+            __syncthreads();
+            cur.store(pr, buf);
+            __syncthreads();
+        }
+        tile_rows<Y, A, EPI>(pre, d.r0, d.r1, buf, g.y, g.part, d.seg, sh);
+        __syncthreads();
+        if (!more) break;
+        cur = nxt;
+        d = dn;
+        li = ln;
+    }
+}
+
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
@@ -292,6 +373,19 @@ template <typename V, typename X, typename Y, typename A, int NT, int EPI> stati
     if (occ == 0) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<V, X, Y, A, NT, EPI>, kBlock, 0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        occ = n;
+    }
+    return occ;
+}
+
+template <typename V, typename X, typename Y, typename A, int NT, int EPI> static int cwin_pipe_occupancy() {
+    static int occ = 0;
+    if (occ == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cwin_pipe<V, X, Y, A, NT, EPI>, kBlock, 0) !=
+                hipSuccess ||
             n < 1)
             n = 1;
         occ = n;
@@ -368,10 +462,19 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
         // window; with 4- or 2-byte values the window's extra barriers and LDS
         // traffic outweigh the saving (measured), so those products treat the
         // same tiles as direct-gather tiles.
-        if (sizeof(V) == 8)
-            hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
-        else
+        if constexpr (sizeof(V) == 8) {
+            if (M.kernel == KV_PIPELINED && M.n_cwin >= 64) {
+                a.per_xcd = (M.n_cwin + 7) / 8;
+                const int resident = cwin_pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
+                a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
+                hipLaunchKernelGGL((k_cwin_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st,
+                                   a);
+            } else {
+                hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
+            }
+        } else {
             hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
+        }
     }
     if (M.n_long > 0) {
         SpmvArgs<V, X, Y> a = g;
@@ -447,6 +550,13 @@ template <typename V, typename X, typename Y, typename A> static void warm_types
     pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
     pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
     pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
+    if constexpr (sizeof(V) == 8) {
+        cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_DOT>();
+        cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_RESID>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_PLAIN>();
+        cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
+        cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
+        cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
+    }
 }
 
 void prepare_launch_queries() {

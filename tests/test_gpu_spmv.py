@@ -200,6 +200,9 @@ def test_compact_windows_equal_direct_bitwise(cfg1, gap):
     y_win, info = run64(A, x, params={"window_mode": spmv.WINDOW_AUTO, "window_gap": gap, "tile_nnz": 2048})
     assert info["n_window_tiles"] > 0
     assert np.array_equal(y_dir, y_win)
+    y_pipe, _ = run64(A, x, params={"window_mode": spmv.WINDOW_AUTO, "window_gap": gap, "tile_nnz": 2048,
+                                    "kernel": 2})
+    assert np.array_equal(y_dir, y_pipe)
     assert_parity(y_win, A, x)
 
 
