@@ -314,12 +314,20 @@ const char *spmv_last_error(void);
  *   win_block   int32[n_tiles]: ring block id, -1 otherwise
  *   runs        int32[2 * n_runs]: compact runs (first column, window position)
  *   lidx        uint16[nnz]: compact tiles: each entry's window position
+ *   lidx12      uint32[768 * (number of tiles of kind 3)], filled only when
+ *               the tile capacity is 2048: the same positions as the device
+ *               reads them, 12 bits each; for the t-th compact tile (in row
+ *               order) lane l < 256 owns words 3*(256 t + l) .. +2 holding
+ *               entry s4 + 1024 p + 4 l + j (s4 = first entry rounded down
+ *               to a multiple of 4, p < 2, j < 4) in bits [12 m, 12 m + 12),
+ *               m = 4 p + j; entries outside the tile hold 0
  *   info        plan summary (device_bytes is an estimate)
  */
 int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                       const int32_t *col_idx, const spmv_params *params, int32_t *n_tiles_out,
                       int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
-                      int32_t *win_block, int32_t *runs, uint16_t *lidx, spmv_info *info);
+                      int32_t *win_block, int32_t *runs, uint16_t *lidx, uint32_t *lidx12,
+                      spmv_info *info);
 
 #ifdef __cplusplus
 }

@@ -103,7 +103,7 @@ def lib():
         L.spmv_last_error.argtypes = []
         L.spmv_plan_inspect.restype = ctypes.c_int
         L.spmv_plan_inspect.argtypes = [i32, i32, i64, vp, vp, ctypes.POINTER(spmv_params),
-                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp,
+                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp, vp,
                                         ctypes.POINTER(spmv_info)]
         _lib = L
     return _lib
@@ -143,13 +143,14 @@ def plan_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, params: dict | None
     """Run the analysis plan on the host (no GPU).  Returns tile boundaries,
     kinds (0 direct, 1 long row, 2 ring window, 3 compact window), window
     offsets/counts/blocks, compact runs (first column, window position),
-    window-relative indices and the summary."""
+    window-relative indices (16-bit per entry, and packed 12-bit per tile and
+    lane for 2048-entry tiles) and the summary."""
     rp, ci, _ = _host_csr(row_ptr, col_idx, None)
     L = lib()
     nt = ctypes.c_int32(0)
     inf = spmv_info()
     _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
-                               ctypes.byref(nt), None, None, None, None, None, None, None, ctypes.byref(inf)),
+                               ctypes.byref(nt), None, None, None, None, None, None, None, None, ctypes.byref(inf)),
            "spmv_plan_inspect")
     n = nt.value
     out = {k: np.zeros(n + (1 if k == "seg_bound" else 0), np.int32)
@@ -160,7 +161,15 @@ def plan_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, params: dict | None
                                ctypes.byref(nt), out["seg_bound"].ctypes.data,
                                out["seg_kind"].ctypes.data, out["win_off"].ctypes.data,
                                out["win_cnt"].ctypes.data, out["win_block"].ctypes.data,
-                               _ptr(out["runs"]), _ptr(out["lidx"]), ctypes.byref(inf)), "spmv_plan_inspect")
+                               _ptr(out["runs"]), _ptr(out["lidx"]), None, ctypes.byref(inf)),
+           "spmv_plan_inspect")
+    n_compact = int(np.sum(out["seg_kind"] == 3))
+    packed = inf.tile_nnz == 2048 and n_compact > 0 and inf.n_runs > 0
+    out["lidx12"] = np.zeros(768 * n_compact if packed else 0, np.uint32)
+    if packed:
+        _check(L.spmv_plan_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), _params(params),
+                                   ctypes.byref(nt), None, None, None, None, None, None, None,
+                                   _ptr(out["lidx12"]), ctypes.byref(inf)), "spmv_plan_inspect")
     out["info"] = _info_dict(inf)
     return out
 

@@ -172,7 +172,9 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     if (!rc && M.n_cwin) {
         rc = upload_descs(P.cwin_list, &M.cwin_desc);
         if (!rc) rc = dev_upload(A, &M.runs, P.runs.data(), P.runs.size(), 0);
-        if (!rc) rc = dev_upload(A, &M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
+        // 2048-entry tiles read packed 12-bit positions; other capacities 16-bit
+        if (!rc && !P.lidx12.empty()) rc = dev_upload(A, &M.lidx12, P.lidx12.data(), P.lidx12.size(), 0);
+        else if (!rc) rc = dev_upload(A, &M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
     }
     if (!rc) prepare_launch_queries();
     if (!rc && M.n_blk) {

@@ -56,6 +56,7 @@ struct DevMatrix {
     TileDesc *cwin_desc = nullptr;   // compact-window tiles: woff = first run, wcnt = runs, pad = width
     int32_t *runs = nullptr;         // (first column, window position) per run
     uint16_t *lidx = nullptr;        // window-relative column per stored entry (+ padding)
+    uint32_t *lidx12 = nullptr;      // 2048-entry tiles: packed 12-bit positions per tile and lane
     bool xcd_remap = true;
     int32_t kernel = KV_AUTO;        // direct-gather kernel variant
     int32_t block = 1;                // 1: scalar CSR, 3: 3x3 block CSR

@@ -53,8 +53,14 @@ struct Plan {
     std::vector<int32_t> cwin_width;   // per segment
     std::vector<int32_t> runs;         // 2 per run
     std::vector<uint16_t> lidx;        // per stored entry (compact tiles only)
+    // 2048-entry tiles: the same positions packed 12 bits each, per tile of
+    // cwin_list and per lane (256 lanes x 8 entries = 3 words per lane)
+    std::vector<uint32_t> lidx12;
     int32_t n_seg() const { return (int32_t)seg_kind.size(); }
 };
+
+constexpr int kPackTileNnz = 2048;  // tile capacity with packed 12-bit positions
+constexpr int kPackLanes = 256;     // lanes per workgroup; each lane owns 4 entries per 1024-entry pass
 
 // Tiles of consecutive block rows for the 3x3 block kernel: at most
 // max_rows block rows and max_blocks stored blocks per tile; a longer block

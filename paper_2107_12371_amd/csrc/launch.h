@@ -26,6 +26,7 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     int32_t ring_words;
     const int32_t *runs;    // compact windows
     const uint16_t *lidx;
+    const uint32_t *lidx12;
 };
 
 // y = A x over all segments of M (direct tiles, long rows, window blocks),

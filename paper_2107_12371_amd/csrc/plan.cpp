@@ -126,6 +126,40 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
     return rc;
 }
 
+// Window positions of 2048-entry tiles, 12 bits each, in the order the
+// window kernel's lanes own the entries: lane l covers entries
+// s4 + pass*1024 + 4l + j (s4 = tile start rounded down to a multiple of 4,
+// pass < 2, j < 4), entry m = 4*pass + j in bits [12m, 12m+12) of the lane's
+// three words.  Entries outside the tile keep position 0.
+static void pack_lidx12(const int32_t *row_ptr, Plan &P) {
+    const size_t nt = P.cwin_list.size();
+    P.lidx12.assign(nt * kPackLanes * 3, 0u);
+    const int nth = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    auto work = [&](int t) {
+        for (size_t i = t; i < nt; i += nth) {
+            const int32_t sg = P.cwin_list[i];
+            if (P.win_cnt[sg] == 0) continue;   // direct tile: no window
+            const int64_t s = row_ptr[P.seg_bound[sg]], e = row_ptr[P.seg_bound[sg + 1]];
+            const int64_t s4 = s & ~(int64_t)3;
+            for (int l = 0; l < kPackLanes; ++l) {
+                uint32_t *w = &P.lidx12[(i * kPackLanes + l) * 3];
+                for (int m = 0; m < 8; ++m) {
+                    const int64_t k = s4 + (m / 4) * (4 * kPackLanes) + 4 * l + (m % 4);
+                    if (k < s || k >= e) continue;
+                    const uint32_t v = P.lidx[k] & 0xfffu;
+                    const int bit = 12 * m, word = bit / 32, sh = bit % 32;
+                    w[word] |= v << sh;
+                    if (sh + 12 > 32) w[word + 1] |= v >> (32 - sh);
+                }
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+}
+
 static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                            const int32_t *col_idx, const spmv_params &p, int tnz, Plan &P) {
     if (tnz != 1024 && tnz != 2048 && tnz != 4096)
@@ -351,6 +385,7 @@ static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         if (P.seg_kind[s] == SEG_STREAM) P.stream_list.push_back(s);
         else if (P.seg_kind[s] == SEG_LONG) P.long_list.push_back(s);
     }
+    if (tnz == kPackTileNnz && !P.cwin_list.empty()) pack_lidx12(row_ptr, P);
     return SPMV_OK;
 }
 
@@ -361,7 +396,8 @@ extern "C" const char *spmv_last_error(void) { return spmvlib::last_error(); }
 extern "C" int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                                  const int32_t *col_idx, const spmv_params *params, int32_t *n_tiles_out,
                                  int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
-                                 int32_t *win_block, int32_t *runs, uint16_t *lidx, spmv_info *info) {
+                                 int32_t *win_block, int32_t *runs, uint16_t *lidx, uint32_t *lidx12,
+                                 spmv_info *info) {
     using namespace spmvlib;
     clear_error();
     int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
@@ -378,6 +414,7 @@ extern "C" int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, co
     if (win_block && ns) std::memcpy(win_block, P.win_block.data(), sizeof(int32_t) * ns);
     if (runs && !P.runs.empty()) std::memcpy(runs, P.runs.data(), sizeof(int32_t) * P.runs.size());
     if (lidx && !P.lidx.empty()) std::memcpy(lidx, P.lidx.data(), sizeof(uint16_t) * P.lidx.size());
+    if (lidx12 && !P.lidx12.empty()) std::memcpy(lidx12, P.lidx12.data(), sizeof(uint32_t) * P.lidx12.size());
     if (info) {
         std::memset(info, 0, sizeof *info);
         info->n_rows = n_rows; info->n_cols = n_cols; info->nnz = nnz;

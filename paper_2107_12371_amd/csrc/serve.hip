@@ -264,7 +264,7 @@ struct Server {
     }
 
     void solver_loop(int si) {
-        hipSetDevice(device);
+        const hipError_t dev_err = hipSetDevice(device);
         Slot &sl = slots[si];
         for (;;) {
             Request *r;
@@ -278,12 +278,14 @@ struct Server {
             const int n = A->M.n_rows;
             double *db = nullptr, *dx = nullptr;
             int rc = SPMV_OK;
-            hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&db), 8 * (size_t)std::max(n, 1), sl.stream);
+            hipError_t e = dev_err != hipSuccess ? dev_err : hipMallocAsync(reinterpret_cast<void **>(&db), 8 * (size_t)std::max(n, 1), sl.stream);
             if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&dx), 8 * (size_t)std::max(n, 1), sl.stream);
             if (e == hipSuccess) e = hipMemcpyAsync(db, r->in, 8 * (size_t)n, hipMemcpyHostToDevice, sl.stream);
             if (e == hipSuccess) e = hipMemsetAsync(dx, 0, 8 * (size_t)n, sl.stream);
             cg_info info{};
-            if (e != hipSuccess) {
+            if (dev_err != hipSuccess) {
+                rc = hip_fail(dev_err, "server solver thread: hipSetDevice");
+            } else if (e != hipSuccess) {
                 rc = hip_fail(e, "server solve buffers");
             } else {
                 rc = cg_run(A, db, dx, r->tol, r->max_iter, cfg.cg_mode, &info, sl.stream, sl.pinned);
@@ -313,7 +315,7 @@ struct Server {
     }
 
     void scheduler_loop() {
-        hipSetDevice(device);
+        const hipError_t dev_err = hipSetDevice(device);
         std::vector<int> evict;
         for (;;) {
             std::vector<Request *> round;
@@ -329,6 +331,11 @@ struct Server {
                 int64_t round_tiles = 0;
                 for (auto it = pending.begin(); it != pending.end();) {
                     Request *r = *it;
+                    if (dev_err != hipSuccess) {  // this thread cannot reach the device
+                        it = pending.erase(it);
+                        finish_locked(r, hip_fail(dev_err, "server scheduler thread: hipSetDevice"));
+                        continue;
+                    }
                     int slot = -1;
                     if (r->op == SRV_CG) {
                         slot = free_slot_locked();
@@ -407,7 +414,16 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     for (auto &sl : S->slots) {
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipHostMalloc(&sl.pinned, 256, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "server slot");
+        if (e != hipSuccess) {
+            const int rc = hip_fail(e, "server slot");
+            for (auto &t : S->slots) {
+                if (t.stream) (void)hipStreamDestroy(t.stream);
+                if (t.pinned) (void)hipHostFree(t.pinned);
+            }
+            (void)hipStreamDestroy(S->batch);
+            delete S;
+            return rc;
+        }
     }
     for (int i = 0; i < cfg.n_slots; ++i) S->slots[i].th = std::thread([S, i] { S->solver_loop(i); });
     S->scheduler = std::thread([S] { S->scheduler_loop(); });

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(SpmvArgs<V, X, Y> g) {
 // then, after a barrier, the products (same row sums as k_stream, bitwise).
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
-    using Regs = WinTileRegs<V, NT>;
+    using Regs = typename CwinRegsSel<V, NT>::type;
     __shared__ A buf[Regs::kProd];
     __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
     __shared__ double sh[kBlock / kWave];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
         return;
     }
     Regs t;
-    t.load(g.lidx, g.val, d.s, d.e);
+    t.load(g.lidx, g.lidx12, g.val, li, d.s, d.e);
     RowPre<Y, EPI> pre;
     pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
     const int nr = d.wcnt;
@@ -230,13 +230,15 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
 }
 
 // Persistent compact windows: the workgroups of an XCD walk its tile range
-// together (tile x*per_xcd + j, + W, + 2W, ...), and a workgroup issues the
-// next tile's matrix stream (window positions and values) right after its
-// current window's staging loads, so the stream stays in flight through the
-// products and row sums.  Same arithmetic as k_cwin, tile by tile.
+// together (tile x*per_xcd + j, + W, + 2W, ...).  As soon as a tile's
+// products are in registers, its stream registers are reloaded with the next
+// tile's stream (window positions and values), so that stream is in flight
+// through the product store, the row sums and the next tile's window
+// staging, without raising the register count (occupancy decides this
+// kernel's speed).  Same arithmetic as k_cwin, tile by tile.
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
-    using Regs = WinTileRegs<V, NT>;
+    using Regs = typename CwinRegsSel<V, NT>::type;
     __shared__ A buf[Regs::kProd];
     __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
     __shared__ double sh[kBlock / kWave];
@@ -249,22 +251,21 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
     const X *__restrict__ x = g.x;
     TileDesc d = g.desc[li];
     Regs cur;
-    cur.load(g.lidx, g.val, d.s, d.e);   // a direct tile ignores it
+    cur.load(g.lidx, g.lidx12, g.val, li, d.s, d.e);   // a direct tile ignores it
     for (;;) {
         const int ln = li + W;
         const bool more = ln < end;
-        const TileDesc dn = g.desc[more ? ln : li];
+        const TileDesc dn = g.desc[more ? ln : li];   // the last tile re-reads its own stream: L2 hits
         RowPre<Y, EPI> pre;
         pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
-        Regs nxt;
         if (d.wcnt == 0) {
             // a tile whose window does not fit: direct gathers, as in k_stream
             TileRegs<V, NT> t;
             t.load(g.col, g.val, d.s, d.e);
             A xv[TileRegs<V, NT>::kMaxPass][4];
             t.gather([x](int c) { return x[c]; }, xv);
-            nxt.load(g.lidx, g.val, dn.s, dn.e);
             t.products(xv, buf);
+            cur.load(g.lidx, g.lidx12, g.val, more ? ln : li, dn.s, dn.e);
             __syncthreads();
         } else {
             const int nr = d.wcnt;
@@ -287,8 +288,6 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
                 }
                 xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
             }
-            // next tile's stream (the last tile re-reads its own: L2 hits)
-            nxt.load(g.lidx, g.val, dn.s, dn.e);
 #pragma unroll
             for (int i = 0; i < kStage; ++i) {
                 const int w = (int)threadIdx.x + i * kBlock;
@@ -297,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
             __syncthreads();
             A pr[Regs::kMaxPass][4];
             cur.products(d.s, d.e, buf, pr);
+            cur.load(g.lidx, g.lidx12, g.val, more ? ln : li, dn.s, dn.e);
             __syncthreads();
             cur.store(pr, buf);
             __syncthreads();
@@ -304,7 +304,6 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
         tile_rows<Y, A, EPI>(pre, d.r0, d.r1, buf, g.y, g.part, d.seg, sh);
         __syncthreads();
         if (!more) break;
-        cur = nxt;
         d = dn;
         li = ln;
     }
@@ -452,6 +451,7 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
         a.n_list = M.n_cwin;
         a.runs = M.runs;
         a.lidx = M.lidx;
+        a.lidx12 = M.lidx12;
         int grid = M.n_cwin;
         a.per_xcd = 0;
         if (M.xcd_remap && M.n_cwin >= 16) {

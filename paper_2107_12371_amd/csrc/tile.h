@@ -81,7 +81,8 @@ template <typename V, int NT> struct WinTileRegs {
     u32x2 w[kMaxPass];
     Val4<V> v[kMaxPass];
 
-    __device__ __forceinline__ void load(const uint16_t *__restrict__ lidx, const V *__restrict__ val, int s, int e) {
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ lidx, const uint32_t *__restrict__ /*lidx12*/,
+                                         const V *__restrict__ val, int /*tile*/, int s, int e) {
         const int s4 = s & ~3;
         const int last = e > s4 ? ((e - 1) & ~3) : s4;
         const int lane0 = kEntriesPerLane * threadIdx.x;
@@ -126,6 +127,72 @@ template <typename V, int NT> struct WinTileRegs {
         }
     }
 };
+
+// Compact-window positions for 2048-entry tiles packed in 12 bits each (a
+// window holds at most 2048 words): lane l of the t-th window tile owns the
+// positions of its 8 entries (2 passes x 4) in the three 32-bit words at
+// lidx12[3 * (t * 256 + l)], entry m in bits [12m, 12m + 12) of the 96.
+// 1.5 instead of 2 bytes per entry; the layout is indexed by tile, not by
+// entry, so an entry outside the tile owns no bits and reads position 0.
+template <typename V> struct WinTileRegs12 {
+    static constexpr int kPass = kEntriesPerLane * kBlock;
+    static constexpr int kMaxPass = 2;
+    static constexpr int kProd = kMaxPass * kPass;
+    uint32_t w0, w1, w2;
+    Val4<V> v[kMaxPass];
+
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ /*lidx*/, const uint32_t *__restrict__ lidx12,
+                                         const V *__restrict__ val, int tile, int s, int e) {
+        const int s4 = s & ~3;
+        const int last = e > s4 ? ((e - 1) & ~3) : s4;
+        const int lane0 = kEntriesPerLane * threadIdx.x;
+        const uint32_t *q = lidx12 + 3 * ((size_t)tile * kBlock + threadIdx.x);
+        w0 = stream_load<StreamNT<V>::value>(q);
+        w1 = stream_load<StreamNT<V>::value>(q + 1);
+        w2 = stream_load<StreamNT<V>::value>(q + 2);
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) v[p].load(val + min(s4 + p * kPass + lane0, last));
+    }
+
+    template <int M> __device__ __forceinline__ unsigned pos() const {
+        if constexpr (M < 5) {
+            const uint64_t a = (uint64_t)w0 | ((uint64_t)w1 << 32);
+            return (unsigned)(a >> (12 * M)) & 0xfffu;
+        } else {
+            const uint64_t b = (uint64_t)w1 | ((uint64_t)w2 << 32);
+            return (unsigned)(b >> (12 * M - 32)) & 0xfffu;
+        }
+    }
+
+    template <typename A>
+    __device__ __forceinline__ void products(int s, int e, const A *__restrict__ win,
+                                             A (&pr)[kMaxPass][4]) const {
+        const unsigned ps[8] = {pos<0>(), pos<1>(), pos<2>(), pos<3>(), pos<4>(), pos<5>(), pos<6>(), pos<7>()};
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pr[p][j] = to_acc<A>(v[p].get_dyn(j)) * win[ps[4 * p + j]];
+        }
+    }
+
+    template <typename A>
+    __device__ __forceinline__ void store(const A (&pr)[kMaxPass][4], A *__restrict__ prod) const {
+        const int lane0 = kEntriesPerLane * threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+            A *d = prod + p * kPass + lane0;
+            d[0] = pr[p][0];
+            d[1] = pr[p][1];
+            d[2] = pr[p][2];
+            d[3] = pr[p][3];
+        }
+    }
+};
+
+// The compact-window register set of a tile capacity: packed 12-bit
+// positions for 2048-entry tiles, 16-bit positions otherwise.
+template <typename V, int NT> struct CwinRegsSel { using type = WinTileRegs<V, NT>; };
+template <typename V> struct CwinRegsSel<V, 2048> { using type = WinTileRegs12<V>; };
 
 // Pass 2 inputs, loaded early (before the gathers and any prefetch, so
 // waiting for them never drains loads issued later): each lane's rows

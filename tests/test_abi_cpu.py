@@ -134,6 +134,23 @@ def check_plan(A, params=None):
         staged += width
     assert staged == info["window_words"]
     assert info["n_window_tiles"] == win.size + int(np.sum(P["win_cnt"][cw] > 0))
+    # 2048-entry tiles: the packed 12-bit positions, decoded the way the
+    # kernel's lanes read them, are the 16-bit positions (0 outside the tile)
+    if tnz == 2048 and cw.size and P["runs"].size:
+        w = P["lidx12"].reshape(cw.size, 256, 3).astype(np.uint64)
+        lo = w[:, :, 0] | (w[:, :, 1] << np.uint64(32))
+        hi = w[:, :, 1] | (w[:, :, 2] << np.uint64(32))
+        lane = np.arange(256)
+        for t, sg in enumerate(cw):
+            a, b = rp[sb[sg]], rp[sb[sg + 1]]
+            for m in range(8):
+                k = (a & ~3) + (m // 4) * 1024 + 4 * lane + (m % 4)
+                got = ((lo[t] >> np.uint64(12 * m)) if m < 5 else (hi[t] >> np.uint64(12 * m - 32))) & np.uint64(0xfff)
+                inside = (k >= a) & (k < b)
+                want = np.zeros(256, np.uint64)
+                if P["win_cnt"][sg] > 0:
+                    want[inside] = P["lidx"][k[inside]]
+                assert np.array_equal(got, want), (t, m)
     return P
 
 
@@ -141,6 +158,13 @@ def check_plan(A, params=None):
 def test_plan_invariants_mesh(tile):
     A = mg.config0()
     check_plan(A, {"tile_nnz": tile})
+
+
+def test_plan_invariants_hex_mesh_packed_positions():
+    # the headline matrix family (hex 27-subset lattice, RCM) at 40^3
+    A = mg.config2(m=40)
+    P = check_plan(A, {"tile_nnz": 2048})
+    assert P["lidx12"].size == 768 * int(np.sum(P["seg_kind"] == 3)) > 0
 
 
 def test_plan_invariants_edge_cases():
