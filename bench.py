@@ -323,12 +323,20 @@ def main():
 
     kname, stem = dominant_kernel(info)
     traffic = read_traffic(kernel_source_hash(), stem)
-    # bytes the compact-window format itself moves: 8 B value + 2 B window
-    # position per entry, 8 B per run, 32 B per tile descriptor, row pointers,
-    # x once and y once (the CSR bytes B above are the algorithmic figure)
+    # bytes the compact-window format itself moves: 8 B value per entry, the
+    # window positions (2048-entry tiles: 12 bytes per lane and window tile,
+    # i.e. 1.5 B per entry; otherwise 2 B per entry), 8 B per run, 32 B per
+    # tile descriptor, row pointers, x once and y once; tiles without a
+    # window read 4 B column indices (counted as full tiles, an upper
+    # bound).  The CSR bytes B above are the algorithmic figure.
     if info["n_window_tiles"]:
-        fmt = (A.nnz * 10 + 8 * info["n_runs"] + 32 * info["n_tiles"] + 4 * (A.n_rows + 1)
-               + 8 * A.n_cols + 8 * A.n_rows)
+        n_direct = info["n_tiles"] - info["n_window_tiles"]
+        if info["tile_nnz"] == 2048:
+            pos = 3 * 4 * 256 * info["n_window_tiles"]
+        else:
+            pos = 2 * A.nnz
+        fmt = (A.nnz * 8 + pos + 4 * info["tile_nnz"] * n_direct + 8 * info["n_runs"] + 32 * info["n_tiles"]
+               + 4 * (A.n_rows + 1) + 8 * A.n_cols + 8 * A.n_rows)
     else:
         fmt = B + 32 * info["n_tiles"]
     roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
