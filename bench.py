@@ -86,6 +86,25 @@ def alg_bytes(n_rows, n_cols, nnz, val_bytes, x_bytes, y_bytes):
     return nnz * (val_bytes + 4) + 4 * (n_rows + 1) + x_bytes * n_cols + y_bytes * n_rows
 
 
+def time_cold(fn, reps, torch, scratch):
+    """Per-call seconds (p10, p50, p90) with caches cold: before every timed
+    call a 1 GiB scratch buffer is overwritten (not timed), evicting the
+    matrix and vectors from L2 and the 256 MB MALL.  Events on the current
+    stream bracket each call."""
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        scratch.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    q = np.quantile(np.array(ts), [0.1, 0.5, 0.9])
+    return float(q[0]), float(q[1]), float(q[2])
+
+
 def time_launches(fn, steps, warmup, torch):
     """Average seconds per call of fn() over `steps` calls, HIP events on the
     current stream (the stream every launch goes to)."""
@@ -113,9 +132,19 @@ def cpu_baseline(A, x, budget_s: float):
             break
     per = el / reps
     gbs = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8) / per / 1e9
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} full FP64 SpMVs of the same 16M-row matrix, single-threaded plain C "
-                      f"oracle, {per * 1e3:.1f} ms each"}
+                      f"oracle, {per * 1e3:.1f} ms each; host {cpu}, {os.cpu_count()} logical CPUs visible, "
+                      f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')} (the oracle uses one)"}
 
 
 def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=log):
@@ -214,10 +243,12 @@ def config_lines(torch, log=log) -> dict:
     """Per-configuration lines besides the headline (outside the timed region):
     the 32^3 mesh with the LDS ring window vs direct gathers, the 126^3 kNN
     matrix in RCM vs random order, and the 3x3 block-CSR operator with 1, 4, 8
-    right-hand sides in FP64 and FP32 storage."""
+    right-hand sides in FP64 and FP32 storage.  The two cache-resident sizes
+    are also timed cold (caches flushed before each call), with p10/p50/p90."""
     import meshgen as mg
     import paper_2107_12371_amd as spmv
     out = {}
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     A = mg.config0()
     x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
     y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
@@ -231,8 +262,11 @@ def config_lines(torch, log=log) -> dict:
                                                 "ring_words": 8192, "window_block": 32})):
         with spmv.Matrix.from_csr(A, params=params) as M:
             t = time_launches(lambda: M.apply(x, y), 200, 20, torch)
+            c10, c50, c90 = time_cold(lambda: M.apply(x, y), 50, torch, scratch)
             inf = M.info
         c0[name] = {"us": round(t * 1e6, 2), "GBs_L2_resident": round(B / t / 1e9, 1),
+                    "cold_us_p10_p50_p90": [round(c10 * 1e6, 2), round(c50 * 1e6, 2), round(c90 * 1e6, 2)],
+                    "GBs_cold_p50": round(B / c50 / 1e9, 1),
                     "window_tiles": inf["n_window_tiles"], "window_words": inf["window_words"]}
     out["mesh32_352K_nnz"] = c0
     log(f"32^3 mesh: {c0}")
@@ -244,9 +278,13 @@ def config_lines(torch, log=log) -> dict:
         B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
         with spmv.Matrix.from_csr(A) as M:
             t = time_launches(lambda: M.apply(x, y), 100, 5, torch)
-        c1[ordering] = {"ms": round(t * 1e3, 4), "GBs": round(B / t / 1e9, 1), "rows": A.n_rows, "nnz": A.nnz}
+            c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
+        c1[ordering] = {"ms": round(t * 1e3, 4), "GBs": round(B / t / 1e9, 1),
+                        "cold_ms_p10_p50_p90": [round(c10 * 1e3, 4), round(c50 * 1e3, 4), round(c90 * 1e3, 4)],
+                        "GBs_cold_p50": round(B / c50 / 1e9, 1), "rows": A.n_rows, "nnz": A.nnz}
     c1["rcm_over_random"] = round(c1["random"]["ms"] / c1["rcm"]["ms"], 3)
     out["knn126_2M_rows_100_spmv"] = c1
+    del scratch
     log(f"126^3 kNN: {c1}")
     A = mg.config3()
     c3 = {"block_rows": A.n_rows, "blocks": A.nnz}
