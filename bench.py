@@ -239,6 +239,27 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     return out
 
 
+def serving_in_child(args) -> dict:
+    """The serving stream in a child process of its own, so that whatever
+    happens there cannot take the headline measurement with it."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
+           "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=400)
+    except subprocess.TimeoutExpired:
+        log("serving: child timed out")
+        return {"failed": "timed out after 400 s"}
+    for line in r.stderr.splitlines():
+        if line.startswith("[bench]"):
+            print(line, file=sys.stderr, flush=True)
+    if r.returncode != 0:
+        log(f"serving: child exited with status {r.returncode}")
+        return {"failed": f"child exit status {r.returncode}"}
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    return json.loads(lines[-1]) if lines else {"failed": "no summary from the child"}
+
+
 def config_lines(torch, log=log) -> dict:
     """Per-configuration lines besides the headline (outside the timed region):
     the 32^3 mesh with the LDS ring window vs direct gathers, the 126^3 kNN
@@ -282,6 +303,12 @@ def config_lines(torch, log=log) -> dict:
         c1[ordering] = {"ms": round(t * 1e3, 4), "GBs": round(B / t / 1e9, 1),
                         "cold_ms_p10_p50_p90": [round(c10 * 1e3, 4), round(c50 * 1e3, 4), round(c90 * 1e3, 4)],
                         "GBs_cold_p50": round(B / c50 / 1e9, 1), "rows": A.n_rows, "nnz": A.nnz}
+        with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL}) as M:
+            t = time_launches(lambda: M.apply(x, y), 100, 5, torch)
+            pad = M.info["sell_entries"]
+        c1[ordering]["sell_ms"] = round(t * 1e3, 4)
+        c1[ordering]["sell_GBs"] = round(B / t / 1e9, 1)
+        c1[ordering]["sell_padding"] = round(pad / A.nnz - 1, 4)
     c1["rcm_over_random"] = round(c1["random"]["ms"] / c1["rcm"]["ms"], 3)
     out["knn126_2M_rows_100_spmv"] = c1
     del scratch
@@ -327,7 +354,16 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=32,
                     help="matrices in the serving pool (1024 in the full workload)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream and print its summary (the bench runs it this way "
+                         "in a child process)")
     args = ap.parse_args()
+    if args.serve_only:
+        import paper_2107_12371_amd as spmv
+        import meshgen as mg
+        print(json.dumps(serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64)),
+              flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "row partition with halo exchange is not built.", file=sys.stderr)
@@ -399,6 +435,17 @@ def main():
         tc = time_launches(lambda: dst.copy_(buf), 10, 2, torch)
         extras["copy_GBs_read_plus_write"] = round(2 * buf.numel() * 8 / tc / 1e9, 1)
         del buf, dst
+        # the same product in the other layouts: CSR row tiles with direct
+        # gathers, and sliced ELLPACK (SELL-C-sigma, sigma = 4096)
+        fm = {}
+        for name, prm in (("csr_direct", {"window_mode": spmv.WINDOW_OFF}), ("sell", {"format": spmv.FORMAT_SELL})):
+            with spmv.Matrix.from_csr(A, params=prm) as M2:
+                tf = time_launches(lambda: M2.apply(x, y), max(10, args.steps // 2), 3, torch)
+                fm[name] = {"ms": round(tf * 1e3, 4), "GBs": round(B / tf / 1e9, 1)}
+                if name == "sell":
+                    fm[name]["padding"] = round(M2.info["sell_entries"] / A.nnz - 1, 4)
+        extras["formats_16M"] = fm
+        log(f"formats: {fm}")
         b = torch.as_tensor(mg.uniform(A.n_rows, mg.seed_for(2), 2), device="cuda")
         for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32)):
             xs, ci = M.cg(b, tol=1e-10, max_iter=20000, mode=mode, raise_on_error=False)
@@ -431,7 +478,7 @@ def main():
         extras["configs"] = config_lines(torch)
         torch.cuda.empty_cache()
     if not args.no_extras and not args.no_serve:
-        extras["serving"] = serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64)
+        extras["serving"] = serving_in_child(args)
 
     cpu = None
     if not args.no_cpu:

@@ -88,7 +88,22 @@ typedef struct spmv_params {
     int32_t kernel;        /* direct-gather kernel: 0 auto, 1 one workgroup per
                               tile, 2 pipelined persistent workgroups, 3 persistent
                               wavefront tiles (tile_nnz 1024, <= 128 rows) */
+    int32_t format;        /* SPMV_FORMAT_* (0: CSR row tiles) */
+    int32_t sell_sigma;    /* SELL: rows are sorted by length inside windows of
+                              this many rows, a multiple of 64 (0: 4096; 64 keeps
+                              the row order) */
 } spmv_params;
+
+/* Storage formats of a scalar handle. */
+#define SPMV_FORMAT_CSR 0  /* CSR in row tiles, optional LDS windows (all of the above) */
+#define SPMV_FORMAT_SELL 1 /* sliced ELLPACK, SELL-C-sigma with C = 64 (the paper's
+                              sliced ELLPACK, Sec. 4.2, one wavefront lane per row):
+                              rows of at most 255 entries are sorted by length
+                              inside windows of sell_sigma rows and cut into slices
+                              of 64 rows stored column-major, padded to the slice's
+                              longest row; padding is masked, never multiplied.
+                              Longer rows take the long-row path.  The tile and
+                              window fields are ignored. */
 
 /* Summary of a handle's analysis plan and resident storage. */
 typedef struct spmv_info {
@@ -106,6 +121,9 @@ typedef struct spmv_info {
     int32_t has_fp32, has_bf16;
     int64_t device_bytes;   /* bytes of device memory held by the handle */
     int32_t block_size;     /* 1: scalar CSR, 3: 3x3 block CSR (n_rows/n_cols/nnz count blocks) */
+    int32_t format;         /* SPMV_FORMAT_* of a scalar handle */
+    int32_t n_slices;       /* SELL: slices of 64 rows */
+    int64_t sell_entries;   /* SELL: stored slots including padding (long rows excluded) */
 } spmv_info;
 
 /*
@@ -328,6 +346,27 @@ int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t
                       int32_t *seg_bound, int32_t *seg_kind, int32_t *win_off, int32_t *win_cnt,
                       int32_t *win_block, int32_t *runs, uint16_t *lidx, uint32_t *lidx12,
                       spmv_info *info);
+
+/*
+ * spmv_sell_inspect: the SELL-C-sigma layout spmv_create builds for
+ * SPMV_FORMAT_SELL, on host arrays and without the GPU (for tests and
+ * tools).  Validates like spmv_create.  Outputs are optional (NULL skips);
+ * size them from a first call's counts:
+ *   n_slices_out, n_entries_out (padded slice entries), n_long_out
+ *   perm       int32[64 * n_slices]: row of each slot (slice-major, lane-minor),
+ *              -1 for the empty slots of the last slice
+ *   len        uint8[64 * n_slices]: entries of each slot's row (0 if empty)
+ *   slice_ptr  int32[n_slices + 1]: first entry of each slice; a slice of width
+ *              w holds entry j of lane l at slice_ptr[s] + 64 j + l
+ *   col        int32[n_entries + entries of the long rows]: columns; padding
+ *              repeats the row's last column (0 for an empty row); the long
+ *              rows follow the slices in CSR order
+ *   long_rows  int32[n_long]: rows longer than 255 entries, ascending
+ */
+int spmv_sell_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                      const int32_t *col_idx, int32_t sigma, int32_t *n_slices_out, int64_t *n_entries_out,
+                      int32_t *n_long_out, int32_t *perm, uint8_t *len, int32_t *slice_ptr, int32_t *col,
+                      int32_t *long_rows);
 
 #ifdef __cplusplus
 }

@@ -27,12 +27,13 @@ SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE = 0, -1, -2, -3
 SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
 SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP = 0x1, 0x2, 0x4
 WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
+FORMAT_CSR, FORMAT_SELL = 0, 1
 CG_FP64, CG_MIXED_FP32 = 0, 1
 
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
     "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
-    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32",
+    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect",
 ]
 
 
@@ -46,7 +47,7 @@ class spmv_params(ctypes.Structure):
     _fields_ = [("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
                 ("window_block", ctypes.c_int32), ("window_gap", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("format", ctypes.c_int32), ("sell_sigma", ctypes.c_int32)]
 
 
 class spmv_info(ctypes.Structure):
@@ -57,7 +58,8 @@ class spmv_info(ctypes.Structure):
                 ("n_window_blocks", ctypes.c_int32), ("ring_words", ctypes.c_int32),
                 ("window_words", ctypes.c_int64), ("n_runs", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("block_size", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("format", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+                ("sell_entries", ctypes.c_int64)]
 
 
 class cg_info(ctypes.Structure):
@@ -105,6 +107,9 @@ def lib():
         L.spmv_plan_inspect.argtypes = [i32, i32, i64, vp, vp, ctypes.POINTER(spmv_params),
                                         ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp, vp,
                                         ctypes.POINTER(spmv_info)]
+        L.spmv_sell_inspect.restype = ctypes.c_int
+        L.spmv_sell_inspect.argtypes = [i32, i32, i64, vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i32), vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -119,7 +124,10 @@ def _params(p: dict | None):
     if not p:
         return None
     sp = spmv_params()
+    names = {f for f, _ in spmv_params._fields_}
     for k, v in p.items():
+        if k not in names:
+            raise ValueError(f"unknown spmv_params field {k!r}")
         setattr(sp, k, v)
     return ctypes.byref(sp)
 
@@ -171,6 +179,28 @@ def plan_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, params: dict | None
                                    ctypes.byref(nt), None, None, None, None, None, None, None,
                                    _ptr(out["lidx12"]), ctypes.byref(inf)), "spmv_plan_inspect")
     out["info"] = _info_dict(inf)
+    return out
+
+
+def sell_inspect(n_rows: int, n_cols: int, row_ptr, col_idx, sigma: int = 0) -> dict:
+    """The sliced-ELLPACK layout of SPMV_FORMAT_SELL on the host (no GPU):
+    slot rows (-1 empty), slot lengths, slice offsets, padded columns (long
+    rows appended after the slices) and the long rows."""
+    rp, ci, _ = _host_csr(row_ptr, col_idx, None)
+    L = lib()
+    ns, ne, nl = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(L.spmv_sell_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), sigma, ctypes.byref(ns),
+                               ctypes.byref(ne), ctypes.byref(nl), None, None, None, None, None), "spmv_sell_inspect")
+    lens = np.diff(rp.astype(np.int64))
+    n_long_entries = int(lens[lens > 255].sum())
+    out = {"perm": np.zeros(64 * ns.value, np.int32), "len": np.zeros(64 * ns.value, np.uint8),
+           "slice_ptr": np.zeros(ns.value + 1, np.int32), "col": np.zeros(ne.value + n_long_entries, np.int32),
+           "long_rows": np.zeros(nl.value, np.int32)}
+    _check(L.spmv_sell_inspect(n_rows, n_cols, ci.shape[0], _ptr(rp), _ptr(ci), sigma, ctypes.byref(ns),
+                               ctypes.byref(ne), ctypes.byref(nl), _ptr(out["perm"]), _ptr(out["len"]),
+                               out["slice_ptr"].ctypes.data, _ptr(out["col"]), _ptr(out["long_rows"])),
+           "spmv_sell_inspect")
+    out["n_slices"], out["n_entries"] = ns.value, ne.value
     return out
 
 

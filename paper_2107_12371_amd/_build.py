@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 OBJ_DIR = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["spmv_kernels.hip", "bsr.hip", "cg.hip", "api.hip", "serve.hip"]
-CXX_SOURCES = ["plan.cpp"]
+CXX_SOURCES = ["plan.cpp", "sell_plan.cpp"]
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 
 

@@ -92,6 +92,94 @@ static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, voi
     return SPMV_OK;
 }
 
+// A sliced-ELLPACK handle (SPMV_FORMAT_SELL): slices and long rows in one
+// column array and one array per value precision.
+static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                       const int32_t *col_idx, const double *values, uint32_t flags, const spmv_params &p,
+                       spmv_matrix **out) {
+    SellPlan S;
+    int rc = build_sell_plan(n_rows, row_ptr, p.sell_sigma, S);
+    if (rc) return rc;
+    auto *A = new (std::nothrow) spmv_matrix();
+    if (!A) return fail(SPMV_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) {
+        delete A;
+        return hip_fail(e, "hipGetDevice");
+    }
+    DevMatrix &M = A->M;
+    M.format = SPMV_FORMAT_SELL;
+    M.n_rows = n_rows;
+    M.n_cols = n_cols;
+    M.nnz = nnz;
+    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    int64_t total = S.n_entries;
+    for (size_t i = 0; i < S.long_rows.size(); ++i) total += row_ptr[S.long_rows[i] + 1] - row_ptr[S.long_rows[i]];
+    const size_t tot = (size_t)total, tot_pad = tot + kPad;
+    {
+        std::vector<int32_t> c(tot);
+        sell_fill_cols(S, row_ptr, col_idx, c.data());
+        rc = dev_upload(A, &M.col, c.data(), tot, tot_pad);
+    }
+    if (!rc) {
+        std::vector<double> v(tot);
+        sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return d; });
+        rc = dev_upload(A, &M.val64, v.data(), tot, tot_pad);
+    }
+    if (!rc && (flags & SPMV_VALUES_FP32)) {
+        std::vector<float> v(tot);
+        sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return (float)d; });
+        rc = dev_upload(A, &M.val32, v.data(), tot, tot_pad);
+    }
+    if (!rc && (flags & SPMV_VALUES_BF16)) {
+        std::vector<uint16_t> v(tot);
+        sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return to_bf16((float)d); });
+        rc = dev_upload(A, &M.val16, v.data(), tot, tot_pad);
+    }
+    M.n_slices = S.n_slices;
+    M.n_sell_wg = (S.n_slices + kBlock / kWave - 1) / (kBlock / kWave);
+    if (!rc) rc = dev_upload(A, &M.sell_perm, S.perm.data(), S.perm.size(), 0);
+    if (!rc) rc = dev_upload(A, &M.sell_len, S.len.data(), S.len.size(), 0);
+    if (!rc) rc = dev_upload(A, &M.sell_ptr, S.slice_ptr.data(), S.slice_ptr.size(), 0);
+    M.n_long = (int32_t)S.long_rows.size();
+    if (!rc && M.n_long) {
+        std::vector<TileDesc> d(M.n_long);
+        for (int32_t i = 0; i < M.n_long; ++i) {
+            const int32_t r = S.long_rows[i];
+            d[i] = TileDesc{};
+            d[i].r0 = r;
+            d[i].r1 = r + 1;
+            d[i].s = (int32_t)S.long_off[i];
+            d[i].e = (int32_t)(S.long_off[i] + (row_ptr[r + 1] - row_ptr[r]));
+            d[i].seg = M.n_sell_wg + i;
+        }
+        rc = dev_upload(A, &M.long_desc, d.data(), d.size(), 0);
+    }
+    M.n_seg = M.n_sell_wg + M.n_long;
+    if (!rc) prepare_launch_queries();
+    if (rc) {
+        for (void *q : A->allocs) (void)hipFree(q);
+        delete A;
+        return rc;
+    }
+    spmv_info &I = A->info;
+    std::memset(&I, 0, sizeof I);
+    I.n_rows = n_rows;
+    I.n_cols = n_cols;
+    I.nnz = nnz;
+    I.n_tiles = M.n_seg;
+    I.n_long_rows = M.n_long;
+    I.has_fp32 = M.val32 != nullptr;
+    I.has_bf16 = M.val16 != nullptr;
+    I.device_bytes = A->bytes;
+    I.block_size = 1;
+    I.format = SPMV_FORMAT_SELL;
+    I.n_slices = S.n_slices;
+    I.sell_entries = S.n_entries;
+    *out = A;
+    return SPMV_OK;
+}
+
 }  // namespace spmvlib
 
 using namespace spmvlib;
@@ -107,6 +195,10 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
     if (rc) return rc;
     if (nnz > 0 && !values) return fail(SPMV_EINVAL, "values is NULL with nnz > 0");
+    if (params && params->format != SPMV_FORMAT_CSR) {
+        if (params->format != SPMV_FORMAT_SELL) return fail(SPMV_EINVAL, "format = %d unknown", params->format);
+        return create_sell(n_rows, n_cols, nnz, row_ptr, col_idx, values, flags, *params, out);
+    }
     Plan P;
     rc = build_plan(n_rows, n_cols, nnz, row_ptr, col_idx, params, P);
     if (rc) return rc;

@@ -62,6 +62,13 @@ struct DevMatrix {
     int32_t block = 1;                // 1: scalar CSR, 3: 3x3 block CSR
     int32_t n_bsr_tiles = 0;
     int32_t *bsr_tiles = nullptr;     // block-row tile boundaries (block CSR)
+    // sliced ELLPACK handles: col / val* hold the slices (then the long rows)
+    int32_t format = 0;               // SPMV_FORMAT_CSR or SPMV_FORMAT_SELL
+    int32_t n_slices = 0;
+    int32_t n_sell_wg = 0;            // workgroups of 4 slices; long rows follow in n_seg
+    int32_t *sell_perm = nullptr;     // row per slot (-1: empty)
+    uint8_t *sell_len = nullptr;      // entries per slot
+    int32_t *sell_ptr = nullptr;      // n_slices + 1 entry offsets
 };
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));

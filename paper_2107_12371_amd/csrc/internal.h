@@ -62,6 +62,54 @@ struct Plan {
 constexpr int kPackTileNnz = 2048;  // tile capacity with packed 12-bit positions
 constexpr int kPackLanes = 256;     // lanes per workgroup; each lane owns 4 entries per 1024-entry pass
 
+// Sliced ELLPACK with sigma sorting (SELL-C-sigma; the paper's sliced
+// ELLPACK storage, Sec. 4.2, with C = 64 rows per slice, one per lane of a
+// wavefront).  Rows of at most kSellMaxLen entries are sorted by length
+// (descending, ties by row) within windows of sigma consecutive such rows and
+// cut into slices of 64; a slice stores its rows column-major, padded to its
+// longest row.  Longer rows are appended after the slices in CSR order and
+// take the long-row path.
+constexpr int kSellC = 64;
+constexpr int kSellMaxLen = 255;
+
+struct SellPlan {
+    int32_t sigma = 0;
+    int32_t n_slices = 0;
+    int64_t n_entries = 0;           // padded slice entries (64 * width per slice)
+    std::vector<int32_t> perm;       // 64 * n_slices slots: row, or -1 for an empty slot
+    std::vector<uint8_t> len;        // per slot: the row's stored entries (0 for empty)
+    std::vector<int32_t> slice_ptr;  // n_slices + 1 entry offsets
+    std::vector<int32_t> long_rows;  // rows longer than kSellMaxLen, ascending
+    std::vector<int64_t> long_off;   // their first entry, after the slices
+};
+
+int build_sell_plan(int32_t n_rows, const int32_t *row_ptr, int32_t sigma, SellPlan &S);
+
+// SELL columns from CSR (n_entries + long-row entries).  A padding slot
+// repeats its row's last column (column 0 for an empty row), so every
+// gather address is valid; kernels mask padding by row length.
+void sell_fill_cols(const SellPlan &S, const int32_t *row_ptr, const int32_t *col_idx, int32_t *col_out);
+
+// SELL values from CSR, converted by `cvt`; padding slots hold zero.
+template <typename O, typename F>
+void sell_fill_vals(const SellPlan &S, const int32_t *row_ptr, const double *val, O *out, F cvt) {
+    for (int32_t sl = 0; sl < S.n_slices; ++sl) {
+        const int64_t base = S.slice_ptr[sl];
+        const int width = (int)((S.slice_ptr[sl + 1] - base) / kSellC);
+        for (int lane = 0; lane < kSellC; ++lane) {
+            const int64_t slot = (int64_t)sl * kSellC + lane;
+            const int32_t r = S.perm[slot];
+            const int len = S.len[slot];
+            for (int j = 0; j < width; ++j)
+                out[base + (int64_t)j * kSellC + lane] = (r >= 0 && j < len) ? cvt(val[(int64_t)row_ptr[r] + j]) : cvt(0.0);
+        }
+    }
+    for (size_t i = 0; i < S.long_rows.size(); ++i) {
+        const int32_t r = S.long_rows[i];
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) out[S.long_off[i] + (k - row_ptr[r])] = cvt(val[k]);
+    }
+}
+
 // Tiles of consecutive block rows for the 3x3 block kernel: at most
 // max_rows block rows and max_blocks stored blocks per tile; a longer block
 // row forms a tile of its own.  Returns n_tiles + 1 boundaries.

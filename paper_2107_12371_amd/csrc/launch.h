@@ -27,6 +27,10 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     const int32_t *runs;    // compact windows
     const uint16_t *lidx;
     const uint32_t *lidx12;
+    const int32_t *sell_perm;  // sliced ELLPACK
+    const uint8_t *sell_len;
+    const int32_t *sell_ptr;
+    int32_t n_slices;
 };
 
 // y = A x over all segments of M (direct tiles, long rows, window blocks),

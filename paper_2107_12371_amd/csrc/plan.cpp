@@ -402,6 +402,8 @@ extern "C" int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, co
     clear_error();
     int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
     if (rc) return rc;
+    if (params && params->format != SPMV_FORMAT_CSR)
+        return fail(SPMV_EINVAL, "spmv_plan_inspect covers CSR row tiles; use spmv_sell_inspect");
     Plan P;
     rc = build_plan(n_rows, n_cols, nnz, row_ptr, col_idx, params, P);
     if (rc) return rc;

@@ -212,3 +212,77 @@ def test_plan_compact_windows_mesh_and_scattered(gap):
     C = mg.random_csr(5000, 5000, seed=9, mean_len=6.0, empty_frac=0.2, dense_rows=2, duplicates=True,
                       unsorted=True)
     check_plan(C, {"tile_nnz": 2048, "window_gap": gap})
+
+
+def check_sell(A, sigma):
+    """Invariants of the SELL-C-sigma layout against the CSR it came from."""
+    S = spmv.sell_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, sigma)
+    rp = A.row_ptr.astype(np.int64)
+    lens = np.diff(rp)
+    short = np.nonzero(lens <= 255)[0]
+    longr = np.nonzero(lens > 255)[0]
+    sig = sigma or 4096
+    perm, ln, sp, col = S["perm"], S["len"].astype(np.int64), S["slice_ptr"].astype(np.int64), S["col"]
+    ns = S["n_slices"]
+    assert ns == (short.size + 63) // 64 and perm.size == 64 * ns
+    # slots: the short rows, each once, sorted by length (descending, ties by
+    # row) inside each window of sigma short rows; empty slots only at the end
+    filled = perm[perm >= 0]
+    assert filled.size == short.size and np.all(perm[filled.size:] == -1)
+    for w0 in range(0, short.size, sig):
+        win = short[w0:w0 + sig]
+        want = sorted(win.tolist(), key=lambda r: (-lens[r], r))
+        assert filled[w0:w0 + sig].tolist() == want
+    assert np.array_equal(ln[perm >= 0], lens[filled]) and np.all(ln[perm < 0] == 0)
+    # slices: width = longest row, column-major entries, padding repeats the
+    # row's last column (0 for an empty row)
+    widths = np.diff(sp) // 64
+    assert np.all(np.diff(sp) % 64 == 0) and sp[0] == 0 and sp[-1] == S["n_entries"]
+    assert np.array_equal(widths, ln.reshape(ns, 64).max(axis=1) if ns else widths)
+    for sl in range(ns):
+        for lane in range(64):
+            r, L = perm[64 * sl + lane], ln[64 * sl + lane]
+            got = col[sp[sl] + 64 * np.arange(widths[sl]) + lane]
+            if r < 0:
+                assert np.all(got == 0)
+                continue
+            row = A.col_idx[rp[r]:rp[r + 1]]
+            pad = row[-1] if L else 0
+            assert np.array_equal(got[:L], row) and np.all(got[L:] == pad)
+    # long rows after the slices, in CSR order
+    assert np.array_equal(S["long_rows"], longr)
+    tail = np.concatenate([A.col_idx[rp[r]:rp[r + 1]] for r in longr]) if longr.size else np.zeros(0, np.int32)
+    assert np.array_equal(col[S["n_entries"]:], tail)
+    return S
+
+
+@pytest.mark.parametrize("sigma", [64, 512, 0])
+def test_sell_layout_mesh(sigma):
+    A = mg.config0()
+    S = check_sell(A, sigma)
+    # sorting inside windows cuts padding: the mesh rows vary from 7 to 23 entries
+    if sigma != 64:
+        assert S["n_entries"] <= 1.10 * A.nnz
+
+
+def test_sell_layout_edge_cases():
+    check_sell(mg.random_csr(1000, 700, seed=3, mean_len=4.0, empty_frac=0.3, dense_rows=2), 128)
+    check_sell(mg.random_csr(130, 130, seed=4, mean_len=0.0, empty_frac=1.0), 0)
+    n = 70
+    rows = [np.arange(300) if i in (5, 66) else np.arange(i % 7) for i in range(n)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    A = mg.CSR(n, 300, rp, np.concatenate(rows).astype(np.int32), np.ones(int(rp[-1])))
+    S = check_sell(A, 64)
+    assert S["long_rows"].tolist() == [5, 66]
+
+
+def test_sell_rejects_bad_sigma():
+    A = mg.config0()
+    for bad in (32, 100, -64):
+        with pytest.raises(spmv.SpmvError) as e:
+            spmv.sell_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, bad)
+        assert e.value.code == spmv.SPMV_EINVAL
+    with pytest.raises(spmv.SpmvError):
+        spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, {"format": spmv.FORMAT_SELL})
+    with pytest.raises(ValueError):
+        spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, {"tile_nzz": 1024})

@@ -54,15 +54,16 @@ def test_mesh16m_default_plan_sampled_rows(mesh16m):
 
 
 def test_mesh16m_kernels_and_plans_bitwise(mesh16m):
-    # compact windows (one workgroup per tile and persistent) and direct
-    # gathers give the same bits on every row
+    # compact windows (one workgroup per tile and persistent), direct
+    # gathers and sliced ELLPACK give the same bits on every row
     A = mesh16m
     x = torch.as_tensor(mg.uniform(A.n_cols, 102, 0), device=DEV)
     ys = []
-    for params in ({}, {"kernel": 2}, {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 2048}):
+    for params in ({}, {"kernel": 2}, {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 2048},
+                   {"format": spmv.FORMAT_SELL}):
         with spmv.Matrix.from_csr(A, params=params) as M:
             ys.append(M.apply(x).cpu())
-    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
+    assert all(torch.equal(ys[0], y) for y in ys[1:])
 
 
 @pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32])
