@@ -38,6 +38,7 @@
 
 #include "device.h"
 #include "launch.h"
+#include "sell.h"
 #include "spmv.h"
 #include "tile.h"
 
@@ -310,80 +311,6 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
     }
 }
 
-// Sliced ELLPACK (SELL-C-sigma, C = 64): one wavefront per slice and one
-// lane per row, the paper's column-wise slices (Sec. 4.2, 5.2) mapped onto a
-// wavefront instead of an FPGA pipeline.  Entry j of lane l sits at
-// slice_ptr[s] + 64 j + l, so every step of j is one coalesced 256-byte
-// column load and one 512-byte value load per wavefront.  A lane walks j in
-// groups of 8 with clamped addresses (all loads and gathers of a group in
-// flight together), and adds each product in ascending j only while
-// j < its row length: padding is masked, never multiplied, so Inf/NaN in x
-// behave as in the definition.  Products are rounded before they are added
-// (no fused multiply-add), the same arithmetic as the CSR row tiles, so a
-// SELL handle gives the same bits as a CSR handle.
-template <typename A> __device__ __forceinline__ A add_product(A sum, A a, A b) {
-#pragma clang fp contract(off)
-    const A p = a * b;
-    return sum + p;
-}
-
-template <typename V, typename X, typename Y, typename A, int EPI>
-__global__ __launch_bounds__(kBlock) void k_sell(SpmvArgs<V, X, Y> g) {
-    __shared__ double sh[kBlock / kWave];
-    if (g.done && *g.done) return;
-    const int b = blockIdx.x;
-    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
-    if (li >= g.n_list) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sl = li * (kBlock / kWave) + (int)threadIdx.x / kWave;
-    double dot = 0.0;
-    if (sl < g.n_slices) {
-        const int slot = sl * kWave + lane;
-        const int row = g.sell_perm[slot];
-        const int len = g.sell_len[slot];
-        const int base = g.sell_ptr[sl];
-        const int width = (g.sell_ptr[sl + 1] - base) / kWave;
-        const int rr = row >= 0 ? row : 0;
-        Y op = Y(0);
-        if (EPI == EPI_DOT) op = static_cast<Y>(g.x[rr]);
-        else if (EPI == EPI_RESID) op = g.b[rr];
-        A sum = A(0);
-        constexpr int U = 8;
-        for (int j = 0; j < width; j += U) {
-            int c[U];
-            V v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = base + min(j + u, width - 1) * kWave + lane;
-                c[u] = stream_load<StreamNT<V>::value>(g.col + k);
-                v[u] = stream_load<StreamNT<V>::value>(g.val + k);
-            }
-            A xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) xv[u] = static_cast<A>(g.x[c[u]]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const A t = add_product<A>(sum, to_acc<A>(v[u]), xv[u]);
-                sum = j + u < len ? t : sum;
-            }
-        }
-        if (row >= 0) {
-            if (EPI == EPI_RESID) {
-                const Y res = static_cast<Y>(op - static_cast<Y>(sum));
-                g.y[row] = res;
-                dot = static_cast<double>(res) * static_cast<double>(res);
-            } else {
-                g.y[row] = static_cast<Y>(sum);
-                if (EPI == EPI_DOT) dot = static_cast<double>(sum) * static_cast<double>(op);
-            }
-        }
-    }
-    if (EPI != EPI_PLAIN) {
-        const double t = block_sum(dot, sh);
-        if (threadIdx.x == 0) g.part[li] = t;
-    }
-}
-
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
@@ -570,21 +497,7 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
 
 template <typename V, typename X, typename Y, typename A, int EPI>
 static hipError_t launch_sell(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
-    if (M.n_sell_wg > 0) {
-        SpmvArgs<V, X, Y> a = g;
-        a.n_list = M.n_sell_wg;
-        a.sell_perm = M.sell_perm;
-        a.sell_len = M.sell_len;
-        a.sell_ptr = M.sell_ptr;
-        a.n_slices = M.n_slices;
-        int grid = M.n_sell_wg;
-        a.per_xcd = 0;
-        if (M.xcd_remap && M.n_sell_wg >= 16) {
-            a.per_xcd = (M.n_sell_wg + 7) / 8;
-            grid = 8 * a.per_xcd;
-        }
-        hipLaunchKernelGGL((k_sell<V, X, Y, A, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
-    }
+    if (M.n_sell_wg > 0) launch_sell_slices<V, X, Y, A>(M, g, EPI, st);
     if (M.n_long > 0) {
         SpmvArgs<V, X, Y> a = g;
         a.desc = M.long_desc;
