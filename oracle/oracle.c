@@ -35,6 +35,20 @@
  *                  linear solver" (Sec. 2); this is the textbook method with
  *                  x0 given, stopping on the recursive residual and confirming
  *                  with the true residual b - A x before returning.
+ *  oracle_pcg_bf16 conjugate gradients preconditioned with a polynomial in a
+ *                  bfloat16 copy of A (the scope's "BF16 for the preconditioner
+ *                  copy"): with D = diag(A), A~ = A's values rounded to
+ *                  binary32 and then to bfloat16 (8 significant bits, nearest,
+ *                  ties to even), the damped two-term Neumann series
+ *                      M^-1 r = w D^-1 (2 r - w A~ D^-1 r),
+ *                  i.e. w D^-1 sum_{k<2} (I - w A~ D^-1)^k, and the weight
+ *                  w = 1.9 / g with g = max_i sum_j |a~_ij| / sqrt(d_i d_j), a
+ *                  Gershgorin bound on the spectrum of D^-1/2 A~ D^-1/2, so M^-1
+ *                  is symmetric positive definite (M^-1 = 2w D^-1 - w^2
+ *                  D^-1 A~ D^-1, positive iff w * lambda_max < 2).  Standard
+ *                  preconditioned CG (e.g. Saad, Iterative Methods for Sparse
+ *                  Linear Systems, Alg. 9.1) on top, stopping and confirming as
+ *                  oracle_cg does.
  *
  * Pins (tests, independent of this code): exact rational brute force,
  * dyadic inputs whose results are exact in binary64, zero row sums of the
@@ -43,6 +57,7 @@
  * dense LAPACK solve.
  */
 #include <stdint.h>
+#include <stdlib.h>
 #include <math.h>
 
 /* y_i and bound_i for one row */
@@ -180,5 +195,115 @@ int oracle_cg(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const d
     }
     residual(n, row_ptr, col_idx, values, b, x, r);
     *rel_res = sqrt(dot(n, r, r)) / nb;
+    return status;
+}
+
+/* Nearest bfloat16 value (8 significant bits, ties to even) of a binary32
+ * value, from the definition: f = m 2^e with 1/2 <= |m| < 1, keep
+ * rint(m 2^8) 2^(e-8) (rint rounds to nearest even).  Finite normal inputs
+ * only, which is all the preconditioner sees. */
+static double bf16_round(float f) {
+    if (f == 0.0f || !isfinite(f)) return (double)f;
+    int e;
+    double m = frexp((double)f, &e);
+    return ldexp(rint(ldexp(m, 8)), e - 8);
+}
+
+/* z = w D^-1 (2 r - w A~ (D^-1 r)) */
+static void precond(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *vt,
+                    const double *dinv, double w, const double *r, double *t, double *z) {
+    for (int32_t i = 0; i < n; ++i) t[i] = dinv[i] * r[i];
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s = s + vt[k] * t[col_idx[k]];
+        z[i] = w * dinv[i] * (2.0 * r[i] - w * s);
+    }
+}
+
+/*
+ * Preconditioned CG with the bfloat16 polynomial preconditioner above.  Work
+ * arrays r, p, q, z, t (n each) are supplied by the caller; x holds x0 on
+ * entry.
+ *
+ *   r = b - A x;  z = M^-1 r;  p = z;  rho = r.z
+ *   repeat:  q = A p;  alpha = rho / (p.q)
+ *            x = x + alpha p;  r = r - alpha q
+ *            if ||r|| <= tol ||b||: confirm with the true residual; stop if
+ *               it passes, otherwise restart from r = b - A x (p = M^-1 r)
+ *            z = M^-1 r;  rho' = r.z;  beta = rho' / rho;  p = z + beta p
+ *
+ * Returns 0 when converged, 1 at max_iter, 2 on breakdown (p.q or r.z not
+ * positive and finite), 3 when a diagonal entry is not positive.  *weight
+ * receives w.
+ */
+int oracle_pcg_bf16(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+                    const double *b, double *x, double tol, int32_t max_iter,
+                    double *r, double *p, double *q, double *z, double *t,
+                    int32_t *iters, double *rel_res, double *weight) {
+    *iters = 0;
+    *rel_res = 0.0;
+    int64_t nnz = row_ptr[n];
+    double *vt = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *dinv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!vt || !dinv) { free(vt); free(dinv); return 3; }
+    for (int64_t k = 0; k < nnz; ++k) vt[k] = bf16_round((float)values[k]);
+    int status = 0;
+    for (int32_t i = 0; i < n && status == 0; ++i) {
+        double d = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col_idx[k] == i) d = d + values[k];
+        if (!(d > 0.0) || !isfinite(d)) status = 3;
+        else dinv[i] = 1.0 / d;
+    }
+    if (status != 0) { free(vt); free(dinv); return status; }
+    double g = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s = s + fabs(vt[k]) * sqrt(dinv[i] * dinv[col_idx[k]]);
+        if (s > g) g = s;
+    }
+    double w = g > 0.0 ? 1.9 / g : 1.0;
+    *weight = w;
+    double nb = sqrt(dot(n, b, b));
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        free(vt); free(dinv);
+        return 0;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    status = 1;
+    if (sqrt(dot(n, r, r)) <= tol * nb) status = 0;
+    precond(n, row_ptr, col_idx, vt, dinv, w, r, t, z);
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+    double rho = dot(n, r, z);
+    for (int32_t it = 1; it <= max_iter && status != 0; ++it) {
+        for (int32_t i = 0; i < n; ++i) {
+            double yi, bi;
+            row_sum(row_ptr, col_idx, values, p, i, &yi, &bi);
+            q[i] = yi;
+        }
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = 2; *iters = it - 1; break; }
+        double alpha = rho / pq;
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        *iters = it;
+        int restart = 0;
+        if (sqrt(dot(n, r, r)) <= tol * nb) {
+            residual(n, row_ptr, col_idx, values, b, x, r);
+            if (sqrt(dot(n, r, r)) <= tol * nb) { status = 0; break; }
+            restart = 1;
+        }
+        precond(n, row_ptr, col_idx, vt, dinv, w, r, t, z);
+        double rho_new = dot(n, r, z);
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) { status = 2; break; }
+        double beta = restart ? 0.0 : rho_new / rho;
+        for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    *rel_res = sqrt(dot(n, r, r)) / nb;
+    free(vt);
+    free(dinv);
     return status;
 }
