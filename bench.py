@@ -382,7 +382,8 @@ def main():
     log(f"matrix n={A.n_rows} nnz={A.nnz} ({time.perf_counter() - t0:.1f} s)")
     x_h = mg.uniform(A.n_cols, mg.seed_for(2), 1)
     params = {"tile_nnz": args.tile_nnz, "window_mode": args.window}
-    M = spmv.Matrix.from_csr(A, fp32=not args.no_extras, params=params, xcd_remap=not args.no_xcd_remap)
+    M = spmv.Matrix.from_csr(A, fp32=not args.no_extras, bf16=not args.no_extras, params=params,
+                             xcd_remap=not args.no_xcd_remap)
     info = M.info
     log(f"resident: {info['device_bytes'] / 1e9:.2f} GB, tiles={info['n_tiles']} "
         f"(tile_nnz={info['tile_nnz']}, window tiles={info['n_window_tiles']})")
@@ -447,7 +448,7 @@ def main():
         extras["formats_16M"] = fm
         log(f"formats: {fm}")
         b = torch.as_tensor(mg.uniform(A.n_rows, mg.seed_for(2), 2), device="cuda")
-        for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32)):
+        for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32), ("pcg_bf16", spmv.CG_PCG_BF16)):
             xs, ci = M.cg(b, tol=1e-10, max_iter=20000, mode=mode, raise_on_error=False)
             extras[f"cg_{name}_seconds"] = round(ci.seconds, 4)
             extras[f"cg_{name}_iterations"] = ci.iterations
@@ -458,11 +459,13 @@ def main():
             if name == "fp64":
                 x64 = xs.clone()
             else:
-                extras["cg_mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs - x64) / torch.linalg.norm(x64))
+                extras[f"cg_{name}_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs - x64) / torch.linalg.norm(x64))
             del xs
         extras["cg_solves_per_s_fp64"] = round(1.0 / extras["cg_fp64_seconds"], 4)
         extras["cg_solves_per_s_mixed"] = round(1.0 / extras["cg_mixed_seconds"], 4)
         extras["cg_mixed_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_mixed_seconds"], 3)
+        extras["cg_solves_per_s_pcg_bf16"] = round(1.0 / extras["cg_pcg_bf16_seconds"], 4)
+        extras["cg_pcg_bf16_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_pcg_bf16_seconds"], 3)
     if args.copy_calibration:
         buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(buf)

@@ -213,10 +213,19 @@ int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, voi
                            with binary64 values; inner CG with FP32 values,
                            FP32 vectors and FP32 SpMV accumulation, dots and
                            scalar recurrences in binary64 (needs SPMV_VALUES_FP32) */
+#define CG_PCG_BF16 2   /* CG preconditioned with a polynomial in the bfloat16
+                           copy A~ of A: M^-1 = w D^-1 (2I - w A~ D^-1), D =
+                           diag(A), w = 1.9 / max_i sum_j |a~_ij| / sqrt(d_i d_j)
+                           (M^-1 symmetric positive definite); binary64 iterate,
+                           residual, dots and scalars, one bfloat16 SpMV with
+                           FP32 vectors per iteration (needs SPMV_VALUES_BF16 and
+                           a CSR-format handle; SPMV_EBREAK if a diagonal entry is
+                           not positive) */
 
 typedef struct cg_info {
     int32_t iterations;        /* total CG iterations (inner iterations for MIXED) */
-    int32_t refinements;       /* outer refinement steps (MIXED), residual replacements (FP64) */
+    int32_t refinements;       /* outer refinement steps (MIXED), residual replacements (FP64),
+                                  restarts from the true residual (PCG) */
     double rel_residual;       /* true ||b - A x||_2 / ||b||_2 in binary64 at exit */
     double seconds;            /* wall time of the solve on the host clock */
 } cg_info;
@@ -228,7 +237,7 @@ typedef struct cg_info {
  *   x          device double[n], in: initial guess, out: last iterate
  *   tol        stop when ||b - A x||_2 <= tol * ||b||_2 (true residual)
  *   max_iter   iteration cap (total inner iterations for MIXED)
- *   mode       CG_FP64 or CG_MIXED_FP32
+ *   mode       CG_FP64, CG_MIXED_FP32 or CG_PCG_BF16
  *   info       optional, filled on return (also on ENOTCONV / EBREAK)
  * b = 0 gives x = 0 and 0 iterations.  Returns SPMV_ENOTCONV when the cap is
  * reached (x is the last iterate).  Blocks the host until done; work runs on

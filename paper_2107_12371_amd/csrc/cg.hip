@@ -17,6 +17,11 @@
 // synchronises once per replay.  Reductions are two-stage with a fixed
 // partition and a fixed order, so a solve is bitwise reproducible.
 //
+// Preconditioned (CG_PCG_BF16): standard preconditioned CG with the damped
+// Neumann polynomial M^-1 = w D^-1 (2I - w A~ D^-1) in the bfloat16 copy A~
+// of A (described with its kernels below); restarts from the true residual
+// when the recursive one drifts.
+//
 // Mixed precision (CG_MIXED_FP32): iterative refinement (Wilkinson; Moler
 // 1967).  The residual r = b - A x is formed with binary64 values and
 // vectors; the correction solve A d = r / ||r|| runs CG with the FP32 copy
@@ -38,15 +43,16 @@ namespace spmvlib {
 
 struct CgState {
     double rho, rho_new, pq, alpha, beta, bb, tol2, rt2;
+    double rr, omega;  // preconditioned CG: r.r of the iterate, polynomial weight
     int32_t iter, max_iter, done, flags;
 };
 
-enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4 };
-enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4 };
+enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
+enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7 };
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ part, int n, CgState *st, int mode) {
     __shared__ double sh[kBlock / kWave];
-    if ((mode == R_ALPHA || mode == R_BETA) && st->done) return;
+    if ((mode == R_ALPHA || mode == R_BETA || mode == R_RR || mode == R_RZ) && st->done) return;
     double s = 0.0;
     for (int i = (int)threadIdx.x; i < n; i += kBlock) s += part[i];
     const double t = block_sum(s, sh);
@@ -62,6 +68,41 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
                 st->done = 1;
             } else {
                 st->alpha = st->rho / t;
+            }
+            break;
+        case R_RR:  // preconditioned CG, after the x/r update: convergence on r.r
+            st->rr = t;
+            st->iter += 1;
+            if (!isfinite(t)) {
+                st->flags |= F_BREAKDOWN;
+                st->done = 1;
+            } else if (t <= st->tol2) {
+                st->flags |= F_CONVERGED;
+                st->done = 1;
+            }
+            break;
+        case R_RZ:  // preconditioned CG, after z = M^-1 r: beta from r.z
+            if (!(t > 0.0) || !isfinite(t)) {
+                st->flags |= F_BREAKDOWN;
+                st->done = 1;
+            } else {
+                st->beta = t / st->rho;
+                st->rho = t;
+                if (st->iter >= st->max_iter) {
+                    st->flags |= F_MAXITER;
+                    st->done = 1;
+                }
+            }
+            break;
+        case R_RZ0:  // preconditioned CG, (re)start: rho = r.z, p = z follows
+            st->rho = t;
+            st->beta = 0.0;
+            st->flags = 0;
+            st->done = st->iter >= st->max_iter ? 1 : 0;
+            if (st->done) st->flags = F_MAXITER;
+            if (!(t > 0.0) || !isfinite(t)) {
+                st->flags |= F_BREAKDOWN;
+                st->done = 1;
             }
             break;
         case R_BETA:
@@ -90,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
 __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restrict__ part, int n, int chunk,
                                                          double *__restrict__ out, const CgState *st, int mode) {
     __shared__ double sh[kBlock / kWave];
-    if ((mode == R_ALPHA || mode == R_BETA) && st->done) return;
+    if ((mode == R_ALPHA || mode == R_BETA || mode == R_RR || mode == R_RZ) && st->done) return;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double s = 0.0;
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) s += part[i];
@@ -185,6 +226,119 @@ __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *__rest
     const double sc = sqrt(st->rt2);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         x[i] = x[i] + sc * static_cast<double>(d[i]);
+}
+
+// ------------------------------------------- preconditioned CG (bfloat16)
+//
+// M^-1 r = w D^-1 (2 r - w A~ D^-1 r): a damped two-term Neumann polynomial
+// in A~, the bfloat16 copy of A, with D = diag(A) in binary64 and the weight
+// w = 1.9 / g, g = max_i sum_j |a~_ij| / sqrt(d_i d_j) (a Gershgorin bound on
+// the spectrum of D^-1/2 A~ D^-1/2), so M^-1 = 2w D^-1 - w^2 D^-1 A~ D^-1 is
+// symmetric positive definite.  One preconditioner application is one
+// bfloat16 SpMV (FP32 vectors and accumulation) between two vector passes.
+
+// dinv_i = 1 / a_ii (duplicates summed); NaN marks a diagonal that is not
+// positive and finite.
+__global__ __launch_bounds__(kBlock) void k_diag_inv(int n, const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val, double *__restrict__ dinv) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double d = 0.0;
+        for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) d += val[k];
+        dinv[i] = (d > 0.0 && isfinite(d)) ? 1.0 / d : __builtin_nan("");
+    }
+}
+
+// Per workgroup: max over its rows of sum_j |a~_ij| sqrt(dinv_i dinv_j)
+// (NaN if any row's is NaN).
+__global__ __launch_bounds__(kBlock) void k_gersh(int n, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const uint16_t *__restrict__ v16,
+                                                  const double *__restrict__ dinv, double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    double m = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double g = 0.0;
+        for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            g += fabs(static_cast<double>(__uint_as_float(static_cast<unsigned>(v16[k]) << 16))) *
+                 sqrt(dinv[i] * dinv[col[k]]);
+        m = (g > m || g != g) ? g : m;   // keeps NaN
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double u = __shfl_xor(m, o);
+        m = (u > m || u != u) ? u : m;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t = (sh[w] > t || sh[w] != sh[w]) ? sh[w] : t;
+        part[blockIdx.x] = t;
+    }
+}
+
+// g = max of the partials; w = 1.9 / g, or the bad-diagonal flag.
+__global__ __launch_bounds__(kBlock) void k_weight(const double *__restrict__ part, int n, CgState *st) {
+    if (threadIdx.x != 0) return;
+    double g = 0.0;
+    for (int i = 0; i < n; ++i) g = (part[i] > g || part[i] != part[i]) ? part[i] : g;
+    if (!(g > 0.0) || !isfinite(g)) {
+        st->flags |= F_BADDIAG;
+        st->done = 1;
+        st->omega = 0.0;
+    } else {
+        st->omega = 1.9 / g;
+    }
+}
+
+// t = D^-1 r in FP32 (the bfloat16 product's input)
+__global__ __launch_bounds__(kBlock) void k_dinv_f32(int n, float *__restrict__ t, const double *__restrict__ r,
+                                                     const double *__restrict__ dinv) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        t[i] = static_cast<float>(dinv[i] * r[i]);
+}
+
+// x += alpha p; r -= alpha q; t = D^-1 r (FP32); partial r.r
+__global__ __launch_bounds__(kBlock) void k_update_xr_pcg(int n, int chunk, double *__restrict__ x,
+                                                          double *__restrict__ r, const double *__restrict__ p,
+                                                          const double *__restrict__ q,
+                                                          const double *__restrict__ dinv, float *__restrict__ t,
+                                                          const CgState *st, double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->done) return;
+    const double a = st->alpha;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double d = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const double xi = x[i] + a * p[i];
+        const double ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        t[i] = static_cast<float>(dinv[i] * ri);
+        d += ri * ri;
+    }
+    const double tt = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tt;
+}
+
+// z = w D^-1 (2 r - w s) with s = A~ t; partial r.z
+__global__ __launch_bounds__(kBlock) void k_precond_z(int n, int chunk, const double *__restrict__ r,
+                                                      const float *__restrict__ s, const double *__restrict__ dinv,
+                                                      double *__restrict__ z, const CgState *st,
+                                                      double *__restrict__ part, int force) {
+    __shared__ double sh[kBlock / kWave];
+    if (!force && st->done) return;
+    const double w = st->omega;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double d = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const double zi = w * dinv[i] * (2.0 * r[i] - w * static_cast<double>(s[i]));
+        z[i] = zi;
+        d += r[i] * zi;
+    }
+    const double tt = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tt;
 }
 
 // ------------------------------------------------------------ host driver
@@ -286,11 +440,16 @@ template <typename T, typename V> struct CgCore {
     }
 
     int capture() {
+        return capture_with([this](hipStream_t t) { return iteration(t); });
+    }
+
+    // Captures graph_iters calls of iter(stream) into one replayable graph.
+    template <typename F> int capture_with(F &&iter) {
         hipStream_t cs;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int i = 0; i < graph_iters && e == hipSuccess; ++i) e = iteration(cs);
+            for (int i = 0; i < graph_iters && e == hipSuccess; ++i) e = iter(cs);
             hipError_t e2 = hipStreamEndCapture(cs, &graph);
             if (e == hipSuccess) e = e2;
         }
@@ -383,6 +542,108 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
     HIP_TRY(B.alloc(&C.st, 1));
     return SPMV_OK;
 }
+
+// Preconditioned CG with the bfloat16 polynomial preconditioner: CgCore's
+// buffers and reductions plus z, D^-1 and the FP32 vectors of the bfloat16
+// product.  One iteration is eight launches (SpMV + p.q, alpha, x/r update +
+// r.r + t = D^-1 r, convergence, bfloat16 SpMV, z + r.z, beta, p update).
+struct PcgCore : CgCore<double, double> {
+    double *z = nullptr, *dinv = nullptr;
+    float *t = nullptr, *sv = nullptr;
+
+    PcgCore(const DevMatrix &M_, int n_, hipStream_t s_) : CgCore<double, double>(M_, M_.val64, n_, s_) {}
+
+    hipError_t pcg_iteration(hipStream_t ts) {
+        const int *done = &st->done;
+        hipError_t e = launch_spmv<double, double, double, double>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, ts);
+        if (e != hipSuccess) return e;
+        reduce(part_seg, M.n_seg, R_ALPHA, ts);
+        hipLaunchKernelGGL(k_update_xr_pcg, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, t, st,
+                           part_vec);
+        reduce(part_vec, n_wg, R_RR, ts);
+        e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr, done, ts);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, r, sv, dinv, z, st, part_vec, 0);
+        reduce(part_vec, n_wg, R_RZ, ts);
+        hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+        return hipGetLastError();
+    }
+
+    // D^-1 and the polynomial weight (st->omega, or F_BADDIAG)
+    hipError_t setup() {
+        hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, M.row_ptr, M.col, M.val64, dinv);
+        hipLaunchKernelGGL(k_gersh, dim3(n_wg), dim3(kBlock), 0, s, n, M.row_ptr, M.col, M.val16, dinv, part_vec);
+        hipLaunchKernelGGL(k_weight, dim3(1), dim3(kWave), 0, s, part_vec, n_wg, st);
+        return hipGetLastError();
+    }
+
+    // From the current r: z = M^-1 r, rho = r.z, p = z (start and restarts)
+    hipError_t restart() {
+        hipLaunchKernelGGL(k_dinv_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, t, r, dinv);
+        hipError_t e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr,
+                                                                  nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, s, n, chunk, r, sv, dinv, z, st, part_vec, 1);
+        reduce(part_vec, n_wg, R_RZ0, s);
+        hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, z);
+        return hipGetLastError();
+    }
+
+    int pcg_solve(const double *b, double tol, int max_iter, int *iters, int *restarts) {
+        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol, max_iter);
+        HIP_TRY(setup());
+        int rc = read_state();
+        if (rc) return rc;
+        if (hst->flags & F_BADDIAG)
+            return fail(SPMV_EBREAK, "preconditioned CG needs a positive finite diagonal");
+        HIP_TRY(true_residual(b));
+        HIP_TRY(restart());
+        rc = read_state();
+        if (rc) return rc;
+        if (hst->rt2 <= hst->tol2) return SPMV_OK;
+        if (hst->flags & F_BREAKDOWN) return SPMV_EBREAK;
+        if (max_iter <= 0) return SPMV_ENOTCONV;
+        if (!exec) {
+            rc = capture_with([this](hipStream_t ts) { return pcg_iteration(ts); });
+            if (rc) return rc;
+        }
+        for (;;) {
+            HIP_TRY(hipGraphLaunch(exec, s));
+            rc = read_state();
+            if (rc) return rc;
+            if (hst->flags & F_BREAKDOWN) {
+                *iters = hst->iter;
+                return SPMV_EBREAK;
+            }
+            if (hst->flags & F_CONVERGED) {
+                HIP_TRY(true_residual(b));
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->rt2 <= hst->tol2) break;
+                // the recursive residual drifted: restart from r = b - A x
+                ++*restarts;
+                HIP_TRY(restart());
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->flags & F_BREAKDOWN) {
+                    *iters = hst->iter;
+                    return SPMV_EBREAK;
+                }
+                if (hst->flags & F_MAXITER) {
+                    *iters = hst->iter;
+                    return SPMV_ENOTCONV;
+                }
+                continue;
+            }
+            if ((hst->flags & F_MAXITER) || hst->iter >= max_iter) {
+                *iters = hst->iter;
+                return SPMV_ENOTCONV;
+            }
+        }
+        *iters = hst->iter;
+        return SPMV_OK;
+    }
+};
 
 }  // namespace
 
@@ -500,6 +761,52 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
 
 
 
+static int cg_pcg(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
+                  hipStream_t s, void *pinned) {
+    const DevMatrix &M = A->M;
+    const int n = M.n_rows;
+    Buffers B(s);
+    PcgCore C(M, n, s);
+    int rc = alloc_core(B, C);
+    if (rc) return rc;
+    HIP_TRY(B.alloc(&C.z, (size_t)n));
+    HIP_TRY(B.alloc(&C.dinv, (size_t)n));
+    HIP_TRY(B.alloc(&C.t, (size_t)n));
+    HIP_TRY(B.alloc(&C.sv, (size_t)n));
+    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
+    C.hst = static_cast<CgState *>(B.host);
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
+    HIP_TRY(hipGetLastError());
+    rc = C.read_state();
+    if (rc) return rc;
+    if (C.hst->bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    int iters = 0, restarts = 0;
+    rc = C.pcg_solve(b, tol, max_iter, &iters, &restarts);
+    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
+    const bool bad_diag = rc == SPMV_EBREAK && (C.hst->flags & F_BADDIAG);
+    int rc2;
+    HIP_TRY(C.true_residual(b));
+    if ((rc2 = C.read_state())) return rc2;
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, C.x);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->refinements = restarts;
+        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
+    }
+    if (rc == SPMV_ENOTCONV) return fail(rc, "PCG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (bad_diag) return fail(rc, "preconditioned CG needs a positive finite diagonal");
+    if (rc == SPMV_EBREAK) return fail(rc, "PCG breakdown (p.q or r.z <= 0 or not finite): matrix not SPD?");
+    return SPMV_OK;
+}
+
 int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter, int32_t mode,
            cg_info *info, hipStream_t s, void *pinned_state) {
     auto t0 = std::chrono::steady_clock::now();
@@ -508,9 +815,14 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     if (A->M.block != 1) return fail(SPMV_ENOTSUP, "cg_solve needs a scalar CSR handle");
     if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
     if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
-    if (mode != CG_FP64 && mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
+    if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16)
+        return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
     if (mode == CG_MIXED_FP32 && !A->M.val32)
         return fail(SPMV_ENOTSUP, "CG_MIXED_FP32 needs the FP32 copy (create with SPMV_VALUES_FP32)");
+    if (mode == CG_PCG_BF16 && !A->M.val16)
+        return fail(SPMV_ENOTSUP, "CG_PCG_BF16 needs the BF16 copy (create with SPMV_VALUES_BF16)");
+    if (mode == CG_PCG_BF16 && A->M.format != SPMV_FORMAT_CSR)
+        return fail(SPMV_ENOTSUP, "CG_PCG_BF16 needs a CSR handle (the diagonal is read from CSR rows)");
     const int n = A->M.n_rows;
     if (n == 0) return SPMV_OK;
     if (!b || !x) return fail(SPMV_EINVAL, "b or x is NULL");
@@ -523,6 +835,8 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     int rc;
     if (mode == CG_FP64) {
         rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);
+    } else if (mode == CG_PCG_BF16) {
+        rc = cg_pcg(A, b, x, tol, max_iter, info, s, pinned_state);
     } else {
         const char *env = std::getenv("SPMV_CG_INNER_TOL");
         double inner = env ? std::atof(env) : 1e-4;

@@ -118,3 +118,70 @@ def test_cg_breakdown_on_indefinite_matrix():
     with spmv.Matrix.from_csr(A) as M:
         _, info = M.cg(torch.as_tensor(b, device=DEV), raise_on_error=False)
     assert info.status == spmv.SPMV_EBREAK
+
+
+# ------------------------------------ preconditioned CG (bfloat16 copy)
+
+@pytest.fixture(scope="module")
+def pcg_ref(cfg0):
+    A, b, ref = cfg0
+    pref, w = oracle.pcg_bf16(A, b, tol=1e-10, max_iter=20000)
+    assert pref.status == 0
+    return pref
+
+
+def test_pcg_config0_against_oracle(cfg0, pcg_ref):
+    A, b, ref = cfg0
+    tol = 1e-10
+    with spmv.Matrix.from_csr(A, bf16=True) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=tol, mode=spmv.CG_PCG_BF16)
+    x = x.cpu().numpy()
+    assert info.status == 0
+    rr = true_rel_residual(A, x, b)
+    assert rr <= 1.05 * tol and abs(info.rel_residual - rr) <= 0.05 * tol
+    kappa = gershgorin_kappa(A, 1e-3)
+    assert np.linalg.norm(x - pcg_ref.x) / np.linalg.norm(pcg_ref.x) <= 2 * kappa * tol
+    # the GPU applies A~ to an FP32 vector with FP32 sums, the oracle in
+    # binary64, so the preconditioners differ in rounding: counts agree to 10%
+    assert abs(info.iterations - pcg_ref.iterations) <= 0.1 * pcg_ref.iterations
+    assert info.iterations < 0.8 * ref.iterations
+
+
+def test_pcg_diagonal_one_iteration_and_reproducible():
+    n = 4000
+    d = np.tile([1.0, 2.5, 4.0, 7.0, 0.375], n // 5)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = mg.uniform(n, 4, 0)
+    # M^-1 A is a multiple of I up to the FP32 rounding of the preconditioner's
+    # vectors (the oracle, all binary64, takes exactly one step): one step
+    # reaches 1e-6, a few reach 1e-12
+    with spmv.Matrix.from_csr(A, bf16=True) as M:
+        bt = torch.as_tensor(b, device=DEV)
+        kappa = d.max() / d.min()
+        rel = lambda v: np.linalg.norm(v.cpu().numpy() - b / d) / np.linalg.norm(b / d)
+        x, info = M.cg(bt, tol=1e-6, mode=spmv.CG_PCG_BF16)
+        assert info.iterations == 1 and rel(x) <= 2 * kappa * 1e-6
+        x, info = M.cg(bt, tol=1e-12, mode=spmv.CG_PCG_BF16)
+        x2, info2 = M.cg(bt, tol=1e-12, mode=spmv.CG_PCG_BF16)
+    assert info.iterations <= 3 and rel(x) <= 2 * kappa * 1e-12
+    assert torch.equal(x, x2) and info2.iterations == info.iterations
+
+
+def test_pcg_rejects_missing_copy_sell_and_bad_diagonal():
+    A = mg.config0()
+    b = torch.ones(A.n_rows, dtype=torch.float64, device=DEV)
+    with spmv.Matrix.from_csr(A) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(b, mode=spmv.CG_PCG_BF16)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+    with spmv.Matrix.from_csr(A, bf16=True, params={"format": spmv.FORMAT_SELL}) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(b, mode=spmv.CG_PCG_BF16)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+    n = 64
+    d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    B = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    with spmv.Matrix.from_csr(B, bf16=True) as M:
+        _, info = M.cg(torch.ones(n, dtype=torch.float64, device=DEV), mode=spmv.CG_PCG_BF16,
+                       raise_on_error=False)
+    assert info.status == spmv.SPMV_EBREAK
