@@ -58,7 +58,9 @@ typedef struct spmv_matrix spmv_matrix;
 
 /* x-window policy.  The GPU counterparts of the paper's vector cache
  * (Sec. 5.1): x words a tile needs are staged in LDS with contiguous loads
- * and the tile's entries address them with 16-bit window-relative indices. */
+ * and the tile's entries address them with short window-relative indices
+ * (12 bits packed per lane for 2048-entry tiles, 16 bits otherwise; the
+ * paper shortens its indices to 16 bits). */
 #define SPMV_WINDOW_AUTO 0 /* compact per-tile windows wherever they fit (default):
                               the tile's distinct columns merged into at most 64
                               runs, at most tile_nnz staged words; other tiles

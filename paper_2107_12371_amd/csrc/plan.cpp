@@ -99,10 +99,11 @@ int build_plan(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_p
     if (p.tile_nnz || p.kernel == KV_WAVE_PLAN || p.window_mode != SPMV_WINDOW_AUTO)
         return build_plan_once(n_rows, n_cols, nnz, row_ptr, col_idx, p, p.tile_nnz ? p.tile_nnz : default_tile_nnz(nnz), P);
     // AUTO with the default capacity: compact windows on 2048-entry tiles
-    // (measured fastest on the 16M-row mesh matrix: 0.691 ms vs 0.738 ms for
-    // the best direct-gather tiling), unless the windows cover under half of
-    // the tiles (scattered orderings), then direct gathers on the default
-    // capacity.
+    // (measured fastest on the 16M-row mesh matrix: 0.64 ms with packed
+    // 12-bit positions vs 0.738 ms for the best direct-gather tiling; 4096-
+    // and 1024-entry windows were slower), unless the windows cover under
+    // half of the tiles (scattered orderings), then direct gathers on the
+    // default capacity.
     // Compact windows pay only when the matrix streams from HBM: below about
     // twice the 256 MB last-level (MALL) cache the direct gathers hit cache
     // and the windows' staging is pure overhead (measured: 41.5 vs 30.4 us on a

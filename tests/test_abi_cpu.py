@@ -286,3 +286,12 @@ def test_sell_rejects_bad_sigma():
         spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, {"format": spmv.FORMAT_SELL})
     with pytest.raises(ValueError):
         spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, {"tile_nzz": 1024})
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__file__))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
