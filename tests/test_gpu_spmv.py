@@ -206,6 +206,34 @@ def test_compact_windows_equal_direct_bitwise(cfg1, gap):
     assert_parity(y_win, A, x)
 
 
+def test_compact_windows_nonfinite_empty_and_long_rows():
+    # 2048-entry compact tiles (packed positions) next to direct tiles inside
+    # the window launch, empty rows, rows longer than a tile, NaN/Inf in x
+    A = mg.config1("rcm", m=48)
+    n = A.n_rows
+    lens = np.diff(A.row_ptr).copy()
+    rows = [A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]] for i in range(n)]
+    vals = [A.values[A.row_ptr[i]:A.row_ptr[i + 1]] for i in range(n)]
+    rng = np.random.default_rng(5)
+    for i in rng.choice(n, 300, replace=False):
+        rows[i], vals[i] = rows[i][:0], vals[i][:0]          # empty rows
+    for i in (17, n // 2):
+        rows[i] = np.arange(0, n, 7, dtype=np.int32)[:5000]  # long rows
+        vals[i] = rng.uniform(-1, 1, rows[i].size)
+    rp = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int32)
+    B = mg.CSR(n, n, rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals))
+    x = mg.uniform(n, 23, 0)
+    x[[5, 999]] = np.nan
+    x[[77]] = np.inf
+    y_win, info = run64(B, x, params={"tile_nnz": 2048})
+    assert info["n_window_tiles"] > 0 and info["n_long_rows"] == 2
+    assert_parity(y_win, B, x)
+    y_dir, _ = run64(B, x, params={"tile_nnz": 2048, "window_mode": spmv.WINDOW_OFF})
+    assert np.array_equal(np.isnan(y_win), np.isnan(y_dir))
+    fin = ~np.isnan(y_dir)
+    assert np.array_equal(y_win[fin], y_dir[fin])
+
+
 def test_kernel_variants_bitwise_identical(cfg1):
     # the variants differ only in scheduling: every row's sum has the same order
     A = cfg1["rcm"]
