@@ -105,6 +105,21 @@ def time_cold(fn, reps, torch, scratch):
     return float(q[0]), float(q[1]), float(q[2])
 
 
+def time_each(fn, reps, torch):
+    """(p10, p50, p90) seconds of single calls, events around each call on
+    the current stream (back-to-back launches, warm caches)."""
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    ts = np.array([e0.elapsed_time(e1) / 1e3 for e0, e1 in ev])
+    q = np.quantile(ts, [0.1, 0.5, 0.9])
+    return float(q[0]), float(q[1]), float(q[2])
+
+
 def time_launches(fn, steps, warmup, torch):
     """Average seconds per call of fn() over `steps` calls, HIP events on the
     current stream (the stream every launch goes to)."""
@@ -398,6 +413,8 @@ def main():
     t_step = time_launches(lambda: M.apply(x, y), args.steps, args.warmup, torch)
     gbs = B / t_step / 1e9
     log(f"FP64 SpMV: {t_step * 1e3:.4f} ms/step, {gbs:.1f} GB/s ({100 * gbs / PEAK_HBM_GBS:.1f}% of 8 TB/s)")
+    # after the timed region: per-launch spread (events around each launch)
+    per = time_each(lambda: M.apply(x, y), args.steps, torch)
 
     kname, stem = dominant_kernel(info)
     traffic = read_traffic(kernel_source_hash(), stem)
@@ -420,7 +437,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": kname, "alg_bytes_per_launch": B,
-                "format_bytes_per_launch": fmt, "format_GBs": round(fmt / t_step / 1e9, 2)}
+                "format_bytes_per_launch": fmt, "format_GBs": round(fmt / t_step / 1e9, 2),
+                "launch_ms_p10_p50_p90": [round(v * 1e3, 4) for v in per]}
 
     extras = {}
     if not args.no_extras:
