@@ -214,7 +214,10 @@ int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, voi
 #define CG_MIXED_FP32 1 /* iterative refinement: binary64 residual r = b - A x
                            with binary64 values; inner CG with FP32 values,
                            FP32 vectors and FP32 SpMV accumulation, dots and
-                           scalar recurrences in binary64 (needs SPMV_VALUES_FP32) */
+                           scalar recurrences in binary64 (needs SPMV_VALUES_FP32).
+                           Each correction solve stops at a relative recursive
+                           residual of 1e-4, or of the value of the environment
+                           variable SPMV_CG_INNER_TOL when it is set */
 #define CG_PCG_BF16 2   /* CG preconditioned with a polynomial in the bfloat16
                            copy A~ of A: M^-1 = w D^-1 (2I - w A~ D^-1), D =
                            diag(A), w = 1.9 / max_i sum_j |a~_ij| / sqrt(d_i d_j)

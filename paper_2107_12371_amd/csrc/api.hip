@@ -16,11 +16,19 @@ namespace spmvlib {
 namespace {
 
 // Restores the caller's current device on scope exit.
+// Makes `dev` current for the guard's scope (and restores the caller's
+// device); err is the failure to switch, if any.
 struct DeviceGuard {
     int prev = -1;
+    hipError_t err = hipSuccess;
     explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-        else prev = -1;
+        err = hipGetDevice(&prev);
+        if (err != hipSuccess || prev == dev) {
+            prev = -1;
+            return;
+        }
+        err = hipSetDevice(dev);
+        if (err != hipSuccess) prev = -1;
     }
     ~DeviceGuard() {
         if (prev >= 0) (void)hipSetDevice(prev);
@@ -86,6 +94,7 @@ static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, voi
     if (rc) return rc;
     if (A->M.n_rows == 0) return SPMV_OK;
     DeviceGuard g(A->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
     hipError_t e = launch_spmv<V, X, Y, Acc>(A->M, val, x, y, EPI_PLAIN, nullptr, nullptr, nullptr,
                                              static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "spmv launch");
@@ -307,7 +316,8 @@ extern "C" int spmv_destroy(spmv_matrix *A) {
     if (!A) return SPMV_OK;
     int rc = SPMV_OK;
     {
-        DeviceGuard g(A->device);
+        DeviceGuard g(A->device);   // frees are attempted even if the switch failed
+        if (g.err != hipSuccess) rc = hip_fail(g.err, "making the matrix's device current");
         for (void *p : A->allocs) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess && rc == SPMV_OK) rc = hip_fail(e, "hipFree");
@@ -336,6 +346,7 @@ static int spmm_typed(const spmv_matrix *A, const V *val, int32_t k, const T *X,
     if (X && Y && overlaps(X, nx * sizeof(T), Y, ny * sizeof(T))) return fail(SPMV_EINVAL, "X and Y overlap");
     if (ny == 0) return SPMV_OK;
     DeviceGuard g(A->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
     hipError_t e = launch_bsr3<V, T>(A->M, val, k, X, Y, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "bsr3 launch");
     return SPMV_OK;

@@ -830,8 +830,16 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
         reinterpret_cast<uintptr_t>(x) < reinterpret_cast<uintptr_t>(b) + sizeof(double) * n)
         return fail(SPMV_EINVAL, "b and x overlap");
     int dev_prev = -1;
-    if (hipGetDevice(&dev_prev) == hipSuccess && dev_prev != A->device) (void)hipSetDevice(A->device);
-    else dev_prev = -1;
+    {
+        hipError_t e = hipGetDevice(&dev_prev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (dev_prev != A->device) {
+            e = hipSetDevice(A->device);
+            if (e != hipSuccess) return hip_fail(e, "making the matrix's device current");
+        } else {
+            dev_prev = -1;
+        }
+    }
     int rc;
     if (mode == CG_FP64) {
         rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);

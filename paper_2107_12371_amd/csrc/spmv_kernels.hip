@@ -43,6 +43,7 @@
 #include "tile.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace spmvlib {
 
@@ -370,50 +371,50 @@ __global__ __launch_bounds__(kBlock) void k_window(SpmvArgs<V, X, Y> g) {
 // Resident workgroups per CU of the pipelined kernel (queried once per
 // instantiation; every thread that races here computes the same value).
 template <typename V, typename X, typename Y, typename A, int NT, int EPI> static int pipe_occupancy() {
-    static int occ = 0;
-    if (occ == 0) {
+    static std::atomic<int> occ{0};
+    if (occ.load(std::memory_order_relaxed) == 0) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<V, X, Y, A, NT, EPI>, kBlock, 0) != hipSuccess ||
             n < 1)
             n = 1;
-        occ = n;
+        occ.store(n, std::memory_order_relaxed);
     }
-    return occ;
+    return occ.load(std::memory_order_relaxed);
 }
 
 template <typename V, typename X, typename Y, typename A, int NT, int EPI> static int cwin_pipe_occupancy() {
-    static int occ = 0;
-    if (occ == 0) {
+    static std::atomic<int> occ{0};
+    if (occ.load(std::memory_order_relaxed) == 0) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cwin_pipe<V, X, Y, A, NT, EPI>, kBlock, 0) !=
                 hipSuccess ||
             n < 1)
             n = 1;
-        occ = n;
+        occ.store(n, std::memory_order_relaxed);
     }
-    return occ;
+    return occ.load(std::memory_order_relaxed);
 }
 
 template <typename V, typename X, typename Y, typename A, int EPI> static int wave_occupancy() {
-    static int occ = 0;
-    if (occ == 0) {
+    static std::atomic<int> occ{0};
+    if (occ.load(std::memory_order_relaxed) == 0) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wave<V, X, Y, A, EPI>, kBlock, 0) != hipSuccess || n < 1)
             n = 1;
-        occ = n;
+        occ.store(n, std::memory_order_relaxed);
     }
-    return occ;
+    return occ.load(std::memory_order_relaxed);
 }
 
 static int cu_count() {
-    static int cus = 0;
-    if (cus == 0) {
+    static std::atomic<int> cus{0};
+    if (cus.load(std::memory_order_relaxed) == 0) {
         int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 8)
             n = 256;
-        cus = n;
+        cus.store(n, std::memory_order_relaxed);
     }
-    return cus;
+    return cus.load(std::memory_order_relaxed);
 }
 
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
