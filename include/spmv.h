@@ -284,6 +284,7 @@ typedef struct srv_result {
     double rel_residual;  /* CG: true relative residual */
     double latency_s;     /* submit -> result in the caller's buffer */
     double queue_s;       /* submit -> admission */
+    char message[160];    /* why the request failed; empty when status is SPMV_OK */
 } srv_result;
 
 typedef struct srv_stats {
@@ -320,9 +321,11 @@ int srv_destroy(spmv_server *srv);
  * srv_policy_simulate: replays the server's admission policy on the host
  * (no GPU), for tests.  Matrices need mat_bytes[i] when resident.  Op t is
  * an admission (op_kind 0) or a release (1) of a request on matrix op_mat[t]
- * holding op_extra[t] bytes of buffers.  Per op: verdict (0 admit, 1 wait,
- * 2 never; -1 for releases), number of evicted matrices, whether the matrix
- * is uploaded, and the bytes in use afterwards.
+ * holding op_extra[t] bytes of buffers, or (2) the release of the only
+ * request admitted on a matrix whose upload failed, which leaves the matrix
+ * not resident.  Per op: verdict (0 admit, 1 wait, 2 never; -1 for
+ * releases), number of evicted matrices, whether the matrix is uploaded, and
+ * the bytes in use afterwards.  Unknown kinds: SPMV_EINVAL.
  */
 int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64_t *mat_bytes, int32_t n_ops,
                         const int32_t *op_kind, const int32_t *op_mat, const uint64_t *op_extra,

@@ -386,7 +386,11 @@ class srv_config(ctypes.Structure):
 class srv_result(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("op", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("latency_s", ctypes.c_double),
-                ("queue_s", ctypes.c_double)]
+                ("queue_s", ctypes.c_double), ("_message", ctypes.c_char * 160)]
+
+    @property
+    def message(self) -> str:
+        return self._message.decode(errors="replace")
 
 
 class srv_stats(ctypes.Structure):

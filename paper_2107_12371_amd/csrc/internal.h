@@ -12,6 +12,7 @@ namespace spmvlib {
 // Thread-local error message; returns `code` for convenient `return fail(...)`.
 int fail(int code, const char *fmt, ...);
 void clear_error();
+const char *last_error();
 
 // Host-side CSR validation (paper Sec. 4.2 storage: int32 columns, row
 // pointers).  Returns SPMV_OK or SPMV_EINVAL with a message.

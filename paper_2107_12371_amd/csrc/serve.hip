@@ -21,6 +21,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -91,6 +92,7 @@ struct Request {
     Clock::time_point t_submit, t_start, t_done;
     bool done = false;
     int status = SPMV_OK;
+    char message[160] = {0};
     int iterations = 0;
     double rel_residual = 0.0;
 };
@@ -153,8 +155,11 @@ struct Server {
         return b;
     }
 
+    // Marks r done.  A failed request keeps the message of the error, which
+    // the calling thread has just recorded.
     void finish_locked(Request *r, int status) {
         r->status = status;
+        if (status != SPMV_OK) std::snprintf(r->message, sizeof r->message, "%s", last_error());
         r->t_done = Clock::now();
         r->done = true;
         if (status == SPMV_OK) {
@@ -274,8 +279,9 @@ struct Server {
                 if (sl.job == nullptr) return;
                 r = sl.job;
             }
+            clear_error();
             const spmv_matrix *A = r->A;
-            const int n = A->M.n_rows;
+            const int n = A ? A->M.n_rows : 0;
             double *db = nullptr, *dx = nullptr;
             int rc = SPMV_OK;
             hipError_t e = dev_err != hipSuccess ? dev_err : hipMallocAsync(reinterpret_cast<void **>(&db), 8 * (size_t)std::max(n, 1), sl.stream);
@@ -283,7 +289,9 @@ struct Server {
             if (e == hipSuccess) e = hipMemcpyAsync(db, r->in, 8 * (size_t)n, hipMemcpyHostToDevice, sl.stream);
             if (e == hipSuccess) e = hipMemsetAsync(dx, 0, 8 * (size_t)n, sl.stream);
             cg_info info{};
-            if (dev_err != hipSuccess) {
+            if (!A) {
+                rc = fail(SPMV_EDEVICE, "server: matrix %d is not resident", r->mid);
+            } else if (dev_err != hipSuccess) {
                 rc = hip_fail(dev_err, "server solver thread: hipSetDevice");
             } else if (e != hipSuccess) {
                 rc = hip_fail(e, "server solve buffers");
@@ -345,6 +353,7 @@ struct Server {
                         if (!round.empty() && round_tiles + est > cfg.max_round_tiles) { ++it; continue; }
                     }
                     bool upload = false;
+                    clear_error();
                     const auto v = policy.admit(r->mid, r->extra, evict, upload);
                     if (v == BudgetLRU::NEVER) {
                         it = pending.erase(it);
@@ -356,10 +365,14 @@ struct Server {
                         if (mats[m].dev) (void)spmv_destroy(mats[m].dev);
                         mats[m].dev = nullptr;
                     }
-                    if (upload) {
+                    if (upload || !mats[r->mid].dev) {
                         const int rc = upload_locked(r->mid);
                         if (rc != SPMV_OK) {
+                            // the matrix did not become resident: drop the
+                            // reservation so that a later request uploads it
                             policy.release(r->mid, r->extra);
+                            policy.unload(r->mid);
+                            mats[r->mid].dev = nullptr;
                             it = pending.erase(it);
                             finish_locked(r, rc);
                             continue;
@@ -510,6 +523,7 @@ static void fill_result(const Request *r, srv_result *res) {
     res->iterations = r->iterations;
     res->op = r->op;
     res->rel_residual = r->rel_residual;
+    std::memcpy(res->message, r->message, sizeof res->message);
     if (r->done) {
         res->latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
         res->queue_s = std::chrono::duration<double>(r->t_start - r->t_submit).count();
@@ -625,9 +639,15 @@ extern "C" int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64
             v = P.admit(op_mat[t], op_extra[t], ev, u);
             ne = (int)ev.size();
             up = u ? 1 : 0;
-        } else {
+        } else if (op_kind[t] == 1) {
             if (P.pins(op_mat[t]) <= 0) return fail(SPMV_EINVAL, "op %d: release without admission", t);
             P.release(op_mat[t], op_extra[t]);
+        } else if (op_kind[t] == 2) {  // the admitted request's upload failed
+            if (P.pins(op_mat[t]) != 1) return fail(SPMV_EINVAL, "op %d: failed upload needs one admission", t);
+            P.release(op_mat[t], op_extra[t]);
+            P.unload(op_mat[t]);
+        } else {
+            return fail(SPMV_EINVAL, "op %d: kind %d unknown", t, op_kind[t]);
         }
         if (verdict) verdict[t] = v;
         if (n_evicted) n_evicted[t] = ne;

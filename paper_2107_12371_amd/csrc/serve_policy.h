@@ -69,6 +69,14 @@ class BudgetLRU {
         used_ -= extra;
     }
 
+    // Matrix i could not be made resident after an admission that asked for
+    // its upload (and whose request has been released): it is not resident.
+    void unload(int i) {
+        if (!m_[i].resident) return;
+        m_[i].resident = false;
+        used_ -= m_[i].bytes;
+    }
+
     // Corrects the reservation of a matrix once its true size is known.
     void resize(int i, uint64_t bytes) {
         if (m_[i].resident) used_ = used_ - m_[i].bytes + bytes;

@@ -1,0 +1,139 @@
+// A host-only stand-in for the HIP runtime, linked with the library's objects
+// in place of the real runtime (kernels are registered but never run) so that the request
+// server's threads, admission, failure paths and clean-up run on the CPU
+// under AddressSanitizer.  Device memory is host memory, copies are memcpy,
+// kernel launches and graph replays do nothing.
+//
+// Two behaviours are scripted:
+//  * a 96-byte device-to-host copy is the CG solver reading its scalar state
+//    (10 doubles, 4 int32): it reads back a converged state, so every solve
+//    takes the capture -> replay -> confirm path and ends;
+//  * MOCK_FAIL_COPY_EVERY=N makes every N-th synchronous host-to-device copy
+//    fail.  Only matrix creation uses synchronous copies, so this makes
+//    uploads fail part-way through.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+
+namespace {
+thread_local int t_device = 0;
+std::atomic<long> n_sync_h2d{0};
+
+long fail_every() {
+    static const long v = [] {
+        const char *s = std::getenv("MOCK_FAIL_COPY_EVERY");
+        return s ? std::atol(s) : 0L;
+    }();
+    return v;
+}
+
+void copy_bytes(void *d, const void *s, size_t n) {
+    if (n) std::memcpy(d, s, n);
+}
+}  // namespace
+
+extern "C" {
+hipError_t hipMalloc(void **p, size_t n) {
+    *p = std::calloc(1, n ? n : 1);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipMallocAsync(void **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
+hipError_t hipFree(void *p) {
+    std::free(p);
+    return hipSuccess;
+}
+hipError_t hipFreeAsync(void *p, hipStream_t) { return hipFree(p); }
+hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { return hipMalloc(p, n); }
+hipError_t hipHostFree(void *p) { return hipFree(p); }
+
+hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k) {
+    const long every = fail_every();
+    if (every > 0 && k == hipMemcpyHostToDevice && ++n_sync_h2d % every == 0) return hipErrorOutOfMemory;
+    copy_bytes(d, s, n);
+    return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+    copy_bytes(d, s, n);
+    if (k == hipMemcpyDeviceToHost && n == 96) {  // the CG scalar state
+        double *v = static_cast<double *>(d);
+        v[0] = 1.0;  // rho
+        v[5] = 1.0;  // |b|^2
+        v[6] = 0.5;  // tol^2 |b|^2
+        v[7] = 0.1;  // true residual^2
+        int32_t *w = reinterpret_cast<int32_t *>(v + 10);
+        w[0] = 3;  // iterations
+        w[2] = 1;  // done
+        w[3] = 1;  // converged
+    }
+    return hipSuccess;
+}
+hipError_t hipMemset(void *d, int v, size_t n) {
+    std::memset(d, v, n);
+    return hipSuccess;
+}
+hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { return hipMemset(d, v, n); }
+
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned int) {
+    *s = reinterpret_cast<hipStream_t>(new int(1));
+    return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+    delete reinterpret_cast<int *>(s);
+    return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipGetDevice(int *d) {
+    *d = t_device;
+    return hipSuccess;
+}
+hipError_t hipSetDevice(int d) {
+    t_device = d;
+    return hipSuccess;
+}
+hipError_t hipGetLastError(void) { return hipSuccess; }
+const char *hipGetErrorString(hipError_t) { return "mock runtime error"; }
+hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) {
+    *v = 256;
+    return hipSuccess;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *, int, size_t) {
+    *n = 8;
+    return hipSuccess;
+}
+hipError_t hipFuncSetAttribute(const void *, hipFuncAttribute, int) { return hipSuccess; }
+hipError_t hipLaunchKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) { return hipSuccess; }
+
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+    *g = reinterpret_cast<hipGraph_t>(new int(2));
+    return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, hipGraphNode_t *, char *, size_t) {
+    *e = reinterpret_cast<hipGraphExec_t>(new int(3));
+    return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+    delete reinterpret_cast<int *>(e);
+    return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+    delete reinterpret_cast<int *>(g);
+    return hipSuccess;
+}
+
+// registration hooks that compiler-generated host code calls
+void **__hipRegisterFatBinary(const void *) {
+    static void *handle = nullptr;
+    return &handle;
+}
+void __hipRegisterFunction(void **, const void *, char *, const char *, unsigned int, void *, void *, dim3 *, dim3 *,
+                           int *) {}
+void __hipUnregisterFatBinary(void **) {}
+void __hipRegisterVar(void **, void *, char *, const char *, int, size_t, int, int) {}
+hipError_t __hipPushCallConfiguration(dim3, dim3, size_t, hipStream_t) { return hipSuccess; }
+hipError_t __hipPopCallConfiguration(dim3 *, dim3 *, size_t *, hipStream_t *) { return hipSuccess; }
+}

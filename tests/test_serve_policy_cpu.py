@@ -54,3 +54,24 @@ def test_many_matrices_stay_within_budget():
     # every in-flight request's matrix is resident: its bytes are counted
     final = spmv.policy_simulate(budget, sizes, done_ops)
     assert final[-1][3] >= sum(e for _, e in live) + sum(sizes[m] for m in {m for m, _ in live})
+
+
+def test_failed_upload_leaves_matrix_not_resident():
+    # admission asks for the upload of matrix 0; the upload fails (kind 2):
+    # nothing stays reserved, and the next request on matrix 0 uploads it again
+    r = spmv.policy_simulate(100, [40, 30], [(0, 0, 10), (2, 0, 10), (0, 0, 10), (1, 0, 10)])
+    assert r[0] == (ADMIT, 0, 1, 50)
+    assert r[1][3] == 0
+    assert r[2] == (ADMIT, 0, 1, 50)
+    assert r[3][3] == 40
+    # a failed upload frees room for others: matrix 1 fits without evicting
+    r = spmv.policy_simulate(60, [40, 50], [(0, 0, 0), (2, 0, 0), (0, 1, 5)])
+    assert r[2] == (ADMIT, 0, 1, 55)
+
+
+def test_simulator_rejects_bad_ops():
+    import pytest
+    with pytest.raises(spmv.SpmvError):
+        spmv.policy_simulate(100, [40], [(3, 0, 0)])
+    with pytest.raises(spmv.SpmvError):
+        spmv.policy_simulate(100, [40], [(2, 0, 0)])        # no admission to fail
