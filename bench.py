@@ -174,7 +174,11 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(1e3), np.log(1e6), pool_size)).astype(int)
     t0 = time.perf_counter()
-    pool = [mg.serving_matrix(int(n), seed ^ (i + 1)) for i, n in enumerate(sizes)]
+    pool = []
+    for i, n in enumerate(sizes):
+        pool.append(mg.serving_matrix(int(n), seed ^ (i + 1)))
+        if (i + 1) % 128 == 0:
+            log(f"serving pool: {i + 1} of {pool_size} matrices generated")
     log(f"serving pool: {pool_size} matrices, {sum(A.n_rows for A in pool)} rows "
         f"({time.perf_counter() - t0:.1f} s)")
 
@@ -224,11 +228,13 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     t1 = time.perf_counter()
     th.start()
     th.join()
-    lat, lat_cg, lat_spmv, iters, fails = [], [], [], [], 0
+    lat, lat_cg, lat_spmv, iters, fails, errors = [], [], [], [], 0, {}
     for r, t in zip(reqs, tickets):
         _, res = srv.wait(t)
         if res.status != 0:
             fails += 1
+            key = f"status {res.status}: {res.message}"
+            errors[key] = errors.get(key, 0) + 1
             continue
         lat.append(res.latency_s)
         (lat_cg if r[0] == "cg" else lat_spmv).append(res.latency_s)
@@ -247,7 +253,7 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
            "p99_spmv_ms": round(1e3 * q(lat_spmv, 0.99), 3) if lat_spmv else None,
            "throughput_rps": round(len(lat) / wall, 2), "cg_solves_per_s": round(len(lat_cg) / wall, 2),
            "mean_cg_iterations": round(float(np.mean(iters)), 1) if iters else None,
-           "failed": fails, "rounds": st["rounds"], "uploads": st["uploads"],
+           "failed": fails, "errors": errors, "rounds": st["rounds"], "uploads": st["uploads"],
            "evictions": st["evictions"], "peak_budget_bytes": st["peak_bytes"]}
     log(f"serving: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, {out['throughput_rps']} req/s "
         f"at {out['arrival_rate_rps']} req/s offered")
@@ -370,10 +376,7 @@ def main():
                     help="requests in the serving stream (the full workload is 4096)")
     ap.add_argument("--serve-pool", type=int, default=32,
                     help="matrices in the serving pool (1024 in the full workload)")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the serving stream (held by default: two runs ended in a host "
-                         "segmentation fault inside the server whose cause is not found yet)")
-    ap.add_argument("--no-serve", action="store_true", help="(default) skip the serving stream")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary (the bench runs it this way "
                          "in a child process)")
@@ -503,10 +506,8 @@ def main():
         torch.cuda.empty_cache()
         extras["configs"] = config_lines(torch)
         torch.cuda.empty_cache()
-    if not args.no_extras and args.serve and not args.no_serve:
+    if not args.no_extras and not args.no_serve:
         extras["serving"] = serving_in_child(args)
-    elif not args.no_extras:
-        extras["serving"] = {"held": "serving stream not run by default (see --serve)"}
 
     cpu = None
     if not args.no_cpu:

@@ -25,8 +25,18 @@
  *  - Matrix handles are immutable after creation: concurrent products with
  *    one handle on different streams are allowed.  spmv_destroy requires that
  *    no work using the handle is still in flight.
- *  - The library holds no global state besides the per-thread error message
- *    and per-device properties; it needs no init call.
+ *  - The library holds no global state besides the per-thread error message,
+ *    per-device properties and one process-wide lock; it needs no init call.
+ *    CG solves capture their iterations into HIP graphs.  HIP refuses some
+ *    runtime calls from other threads while a stream is being captured (work
+ *    on the legacy null stream, and with it some synchronous allocation,
+ *    free and copy calls), and the refused call also breaks the capture.  The
+ *    library's own such calls (matrix creation and destruction, pinned host
+ *    buffers, graph set-up and teardown) take the lock, as do its captures,
+ *    and its uploads never use the null stream, so library calls from any
+ *    number of threads do not collide.  A caller that submits null-stream
+ *    work from another thread during a CG solve can still make that solve
+ *    fail with SPMV_EDEVICE; give such work a stream of its own.
  */
 #ifndef PAPER_2107_12371_AMD_SPMV_H
 #define PAPER_2107_12371_AMD_SPMV_H

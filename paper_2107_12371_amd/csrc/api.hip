@@ -57,26 +57,53 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(e == hipErrorOutOfMemory ? SPMV_ENOMEM : SPMV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Allocates max(alloc_n, n, 1) elements, zero-fills the tail beyond n and
-// copies n elements from the host.
-template <typename T> static int dev_upload(spmv_matrix *A, T **dst, const T *src, size_t n, size_t alloc_n) {
-    if (alloc_n < n) alloc_n = n;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(T) * (alloc_n ? alloc_n : 1));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    A->allocs.push_back(p);
-    A->bytes += (int64_t)(sizeof(T) * (alloc_n ? alloc_n : 1));
-    if (alloc_n > n) {
-        e = hipMemset(static_cast<T *>(p) + n, 0, sizeof(T) * (alloc_n - n));
-        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+// The device side of one matrix creation.  It holds the capture gate for
+// its lifetime and copies through a private non-blocking stream, never the
+// legacy default stream (HIP refuses legacy-stream work while any stream is
+// being captured).
+struct Uploader {
+    spmv_matrix *A;
+    std::lock_guard<std::mutex> lock{capture_gate()};
+    hipStream_t s = nullptr;
+    hipError_t init = hipSuccess;
+
+    explicit Uploader(spmv_matrix *A_) : A(A_) { init = hipStreamCreateWithFlags(&s, hipStreamNonBlocking); }
+    ~Uploader() {
+        if (s) (void)hipStreamDestroy(s);
     }
-    if (n) {
-        e = hipMemcpy(p, src, sizeof(T) * n, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    Uploader(const Uploader &) = delete;
+    Uploader &operator=(const Uploader &) = delete;
+
+    // Allocates max(alloc_n, n, 1) elements, zero-fills the tail beyond n and
+    // copies n elements from the host; the copy has completed on return, so
+    // the host source may be released.
+    template <typename T> int put(T **dst, const T *src, size_t n, size_t alloc_n) {
+        if (alloc_n < n) alloc_n = n;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(T) * (alloc_n ? alloc_n : 1));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        A->allocs.push_back(p);
+        A->bytes += (int64_t)(sizeof(T) * (alloc_n ? alloc_n : 1));
+        if (alloc_n > n) {
+            e = hipMemsetAsync(static_cast<T *>(p) + n, 0, sizeof(T) * (alloc_n - n), s);
+            if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+        }
+        if (n) {
+            e = hipMemcpyAsync(p, src, sizeof(T) * n, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "upload");
+        *dst = static_cast<T *>(p);
+        return SPMV_OK;
     }
-    *dst = static_cast<T *>(p);
-    return SPMV_OK;
-}
+
+    // Releases what was allocated so far (failed creation).
+    void release_all() {
+        for (void *q : A->allocs) (void)hipFree(q);
+        A->allocs.clear();
+    }
+};
 
 static int check_apply(const spmv_matrix *A, const void *x, size_t xs, const void *y, size_t ys) {
     if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
@@ -116,6 +143,11 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
         delete A;
         return hip_fail(e, "hipGetDevice");
     }
+    Uploader U(A);
+    if (U.init != hipSuccess) {
+        delete A;
+        return hip_fail(U.init, "upload stream");
+    }
     DevMatrix &M = A->M;
     M.format = SPMV_FORMAT_SELL;
     M.n_rows = n_rows;
@@ -128,28 +160,28 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     {
         std::vector<int32_t> c(tot);
         sell_fill_cols(S, row_ptr, col_idx, c.data());
-        rc = dev_upload(A, &M.col, c.data(), tot, tot_pad);
+        rc = U.put(&M.col, c.data(), tot, tot_pad);
     }
     if (!rc) {
         std::vector<double> v(tot);
         sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return d; });
-        rc = dev_upload(A, &M.val64, v.data(), tot, tot_pad);
+        rc = U.put(&M.val64, v.data(), tot, tot_pad);
     }
     if (!rc && (flags & SPMV_VALUES_FP32)) {
         std::vector<float> v(tot);
         sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return (float)d; });
-        rc = dev_upload(A, &M.val32, v.data(), tot, tot_pad);
+        rc = U.put(&M.val32, v.data(), tot, tot_pad);
     }
     if (!rc && (flags & SPMV_VALUES_BF16)) {
         std::vector<uint16_t> v(tot);
         sell_fill_vals(S, row_ptr, values, v.data(), [](double d) { return to_bf16((float)d); });
-        rc = dev_upload(A, &M.val16, v.data(), tot, tot_pad);
+        rc = U.put(&M.val16, v.data(), tot, tot_pad);
     }
     M.n_slices = S.n_slices;
     M.n_sell_wg = (S.n_slices + kBlock / kWave - 1) / (kBlock / kWave);
-    if (!rc) rc = dev_upload(A, &M.sell_perm, S.perm.data(), S.perm.size(), 0);
-    if (!rc) rc = dev_upload(A, &M.sell_len, S.len.data(), S.len.size(), 0);
-    if (!rc) rc = dev_upload(A, &M.sell_ptr, S.slice_ptr.data(), S.slice_ptr.size(), 0);
+    if (!rc) rc = U.put(&M.sell_perm, S.perm.data(), S.perm.size(), 0);
+    if (!rc) rc = U.put(&M.sell_len, S.len.data(), S.len.size(), 0);
+    if (!rc) rc = U.put(&M.sell_ptr, S.slice_ptr.data(), S.slice_ptr.size(), 0);
     M.n_long = (int32_t)S.long_rows.size();
     if (!rc && M.n_long) {
         std::vector<TileDesc> d(M.n_long);
@@ -162,12 +194,12 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
             d[i].e = (int32_t)(S.long_off[i] + (row_ptr[r + 1] - row_ptr[r]));
             d[i].seg = M.n_sell_wg + i;
         }
-        rc = dev_upload(A, &M.long_desc, d.data(), d.size(), 0);
+        rc = U.put(&M.long_desc, d.data(), d.size(), 0);
     }
     M.n_seg = M.n_sell_wg + M.n_long;
     if (!rc) prepare_launch_queries();
     if (rc) {
-        for (void *q : A->allocs) (void)hipFree(q);
+        U.release_all();
         delete A;
         return rc;
     }
@@ -219,6 +251,11 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         delete A;
         return hip_fail(e, "hipGetDevice");
     }
+    Uploader U(A);
+    if (U.init != hipSuccess) {
+        delete A;
+        return hip_fail(U.init, "upload stream");
+    }
     DevMatrix &M = A->M;
     M.n_rows = n_rows;
     M.n_cols = n_cols;
@@ -227,18 +264,18 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     M.ring_words = P.ring_words;
     M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
     const size_t nz = (size_t)nnz, nz_pad = ((nz + 3) & ~(size_t)3) + kPad;
-    rc = dev_upload(A, &M.row_ptr, row_ptr, (size_t)n_rows + 1, (size_t)n_rows + 1);
-    if (!rc) rc = dev_upload(A, &M.col, col_idx, nz, nz_pad);
-    if (!rc) rc = dev_upload(A, &M.val64, values, nz, nz_pad);
+    rc = U.put(&M.row_ptr, row_ptr, (size_t)n_rows + 1, (size_t)n_rows + 1);
+    if (!rc) rc = U.put(&M.col, col_idx, nz, nz_pad);
+    if (!rc) rc = U.put(&M.val64, values, nz, nz_pad);
     if (!rc && (flags & SPMV_VALUES_FP32)) {
         std::vector<float> v32(nz);
         for (size_t k = 0; k < nz; ++k) v32[k] = (float)values[k];
-        rc = dev_upload(A, &M.val32, v32.data(), nz, nz_pad);
+        rc = U.put(&M.val32, v32.data(), nz, nz_pad);
     }
     if (!rc && (flags & SPMV_VALUES_BF16)) {
         std::vector<uint16_t> v16(nz);
         for (size_t k = 0; k < nz; ++k) v16[k] = to_bf16((float)values[k]);
-        rc = dev_upload(A, &M.val16, v16.data(), nz, nz_pad);
+        rc = U.put(&M.val16, v16.data(), nz, nz_pad);
     }
     M.n_seg = P.n_seg();
     M.kernel = P.kernel;
@@ -258,7 +295,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         std::vector<TileDesc> v;
         v.reserve(list.size());
         for (int32_t sg : list) v.push_back(desc_of(sg));
-        return dev_upload(A, dst, v.data(), v.size(), 0);
+        return U.put(dst, v.data(), v.size(), 0);
     };
     M.n_stream = (int32_t)P.stream_list.size();
     if (!rc && M.n_stream) rc = upload_descs(P.stream_list, &M.stream_desc);
@@ -267,15 +304,15 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     M.n_blk = P.win_blk_ptr.empty() ? 0 : (int32_t)P.win_blk_ptr.size() - 1;
     if (!rc && M.n_blk) {
         rc = upload_descs(P.win_list, &M.win_desc);
-        if (!rc) rc = dev_upload(A, &M.win_blk_ptr, P.win_blk_ptr.data(), P.win_blk_ptr.size(), 0);
+        if (!rc) rc = U.put(&M.win_blk_ptr, P.win_blk_ptr.data(), P.win_blk_ptr.size(), 0);
     }
     M.n_cwin = (int32_t)P.cwin_list.size();
     if (!rc && M.n_cwin) {
         rc = upload_descs(P.cwin_list, &M.cwin_desc);
-        if (!rc) rc = dev_upload(A, &M.runs, P.runs.data(), P.runs.size(), 0);
+        if (!rc) rc = U.put(&M.runs, P.runs.data(), P.runs.size(), 0);
         // 2048-entry tiles read packed 12-bit positions; other capacities 16-bit
-        if (!rc && !P.lidx12.empty()) rc = dev_upload(A, &M.lidx12, P.lidx12.data(), P.lidx12.size(), 0);
-        else if (!rc) rc = dev_upload(A, &M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
+        if (!rc && !P.lidx12.empty()) rc = U.put(&M.lidx12, P.lidx12.data(), P.lidx12.size(), 0);
+        else if (!rc) rc = U.put(&M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
     }
     if (!rc) prepare_launch_queries();
     if (!rc && M.n_blk) {
@@ -283,7 +320,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         if (e2 != hipSuccess) rc = hip_fail(e2, "window kernel LDS opt-in");
     }
     if (rc) {
-        for (void *p : A->allocs) (void)hipFree(p);
+        U.release_all();
         delete A;
         return rc;
     }
@@ -318,6 +355,7 @@ extern "C" int spmv_destroy(spmv_matrix *A) {
     {
         DeviceGuard g(A->device);   // frees are attempted even if the switch failed
         if (g.err != hipSuccess) rc = hip_fail(g.err, "making the matrix's device current");
+        std::lock_guard<std::mutex> lock(capture_gate());
         for (void *p : A->allocs) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess && rc == SPMV_OK) rc = hip_fail(e, "hipFree");
@@ -406,6 +444,11 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
         delete A;
         return hip_fail(e, "hipGetDevice");
     }
+    Uploader U(A);
+    if (U.init != hipSuccess) {
+        delete A;
+        return hip_fail(U.init, "upload stream");
+    }
     DevMatrix &M = A->M;
     M.block = 3;
     M.n_rows = n_block_rows;
@@ -413,18 +456,18 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     M.nnz = nnz_blocks;
     M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
     const size_t nb = (size_t)nnz_blocks;
-    rc = dev_upload(A, &M.row_ptr, brow_ptr, (size_t)n_block_rows + 1, 0);
-    if (!rc) rc = dev_upload(A, &M.col, bcol_idx, nb, nb + kPad);
-    if (!rc) rc = dev_upload(A, &M.val64, bvalues, 9 * nb, 9 * nb + kPad);
+    rc = U.put(&M.row_ptr, brow_ptr, (size_t)n_block_rows + 1, 0);
+    if (!rc) rc = U.put(&M.col, bcol_idx, nb, nb + kPad);
+    if (!rc) rc = U.put(&M.val64, bvalues, 9 * nb, 9 * nb + kPad);
     if (!rc && (flags & SPMV_VALUES_FP32)) {
         std::vector<float> v32(9 * nb);
         for (size_t k = 0; k < 9 * nb; ++k) v32[k] = (float)bvalues[k];
-        rc = dev_upload(A, &M.val32, v32.data(), 9 * nb, 9 * nb + kPad);
+        rc = U.put(&M.val32, v32.data(), 9 * nb, 9 * nb + kPad);
     }
     M.n_bsr_tiles = (int32_t)tiles.size() - 1;
-    if (!rc) rc = dev_upload(A, &M.bsr_tiles, tiles.data(), tiles.size(), 0);
+    if (!rc) rc = U.put(&M.bsr_tiles, tiles.data(), tiles.size(), 0);
     if (rc) {
-        for (void *p : A->allocs) (void)hipFree(p);
+        U.release_all();
         delete A;
         return rc;
     }

@@ -360,7 +360,10 @@ struct Buffers {
     explicit Buffers(hipStream_t s_) : s(s_) {}
     ~Buffers() {
         for (void *p : dev) (void)hipFreeAsync(p, s);
-        if (own_host && host) (void)hipHostFree(host);
+        if (own_host && host) {
+            std::lock_guard<std::mutex> lock(capture_gate());
+            (void)hipHostFree(host);
+        }
     }
     template <typename T> hipError_t alloc(T **p, size_t n) {
         void *q = nullptr;
@@ -377,6 +380,7 @@ struct Buffers {
             return hipSuccess;
         }
         own_host = true;
+        std::lock_guard<std::mutex> lock(capture_gate());
         return hipHostMalloc(&host, bytes, hipHostMallocDefault);
     }
 };
@@ -409,6 +413,8 @@ template <typename T, typename V> struct CgCore {
         graph_iters = n >= (1 << 20) ? 8 : (n >= (1 << 16) ? 16 : 32);
     }
     ~CgCore() {
+        if (!exec && !graph) return;
+        std::lock_guard<std::mutex> lock(capture_gate());
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -443,8 +449,11 @@ template <typename T, typename V> struct CgCore {
         return capture_with([this](hipStream_t t) { return iteration(t); });
     }
 
-    // Captures graph_iters calls of iter(stream) into one replayable graph.
+    // Captures graph_iters calls of iter(stream) into one replayable graph,
+    // with the capture gate held (one capture at a time in the process, and
+    // none during the library's synchronous runtime work).
     template <typename F> int capture_with(F &&iter) {
+        std::lock_guard<std::mutex> lock(capture_gate());
         hipStream_t cs;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,13 @@ namespace spmvlib {
 int fail(int code, const char *fmt, ...);
 void clear_error();
 const char *last_error();
+
+// Serialises the library's stream captures with its synchronous runtime
+// work (device and pinned allocations and frees, blocking copies, graph
+// teardown).  HIP rejects some of that work from other threads while a
+// stream of the device is being captured, and the rejected call also
+// invalidates the capture; holding this lock on both sides keeps them apart.
+std::mutex &capture_gate();
 
 // Host-side CSR validation (paper Sec. 4.2 storage: int32 columns, row
 // pointers).  Returns SPMV_OK or SPMV_EINVAL with a message.

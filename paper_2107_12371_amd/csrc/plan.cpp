@@ -43,6 +43,11 @@ void clear_error() { g_err[0] = 0; }
 
 const char *last_error() { return g_err; }
 
+std::mutex &capture_gate() {
+    static std::mutex m;
+    return m;
+}
+
 int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col_idx) {
     if (n_rows < 0 || n_cols < 0) return fail(SPMV_EINVAL, "negative dimension (%d x %d)", n_rows, n_cols);

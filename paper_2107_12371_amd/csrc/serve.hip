@@ -188,6 +188,8 @@ struct Server {
 
     // One round: every SpMV vector of the admitted requests in one launch.
     void run_round(std::vector<Request *> &round) {
+        clear_error();
+        (void)hipGetLastError();  // drop an error an earlier call of this thread left behind
         std::vector<MultiItem> items;
         std::vector<std::pair<Request *, std::pair<double *, double *>>> bufs;
         int total = 0;
@@ -219,6 +221,7 @@ struct Server {
         }
         if (err == SPMV_OK && !items.empty()) {
             if (items.size() > items_cap) {
+                std::lock_guard<std::mutex> gate(capture_gate());
                 if (items_host) (void)hipHostFree(items_host);
                 items_cap = std::max<size_t>(items.size(), 2 * items_cap);
                 hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&items_host), items_cap * sizeof(MultiItem),
@@ -280,6 +283,7 @@ struct Server {
                 r = sl.job;
             }
             clear_error();
+            (void)hipGetLastError();  // drop an error an earlier call of this thread left behind
             const spmv_matrix *A = r->A;
             const int n = A ? A->M.n_rows : 0;
             double *db = nullptr, *dx = nullptr;
@@ -424,6 +428,7 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
         return hip_fail(e, "server stream");
     }
     S->slots.resize(cfg.n_slots);
+    std::unique_lock<std::mutex> gate(capture_gate());
     for (auto &sl : S->slots) {
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipHostMalloc(&sl.pinned, 256, hipHostMallocDefault);
@@ -438,6 +443,7 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
             return rc;
         }
     }
+    gate.unlock();
     for (int i = 0; i < cfg.n_slots; ++i) S->slots[i].th = std::thread([S, i] { S->solver_loop(i); });
     S->scheduler = std::thread([S] { S->scheduler_loop(); });
     *out = new spmv_server{S};
@@ -610,6 +616,7 @@ extern "C" int srv_destroy(spmv_server *srv) {
         if (sl.th.joinable()) sl.th.join();
     for (auto &m : S->mats)
         if (m.dev) (void)spmv_destroy(m.dev);
+    std::lock_guard<std::mutex> gate(capture_gate());
     for (auto &sl : S->slots) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
