@@ -284,6 +284,8 @@ typedef struct srv_config {
     int32_t n_slots;           /* concurrent CG solves, <= 64 (0: 8) */
     int32_t cg_mode;           /* CG_FP64 or CG_MIXED_FP32 for solve requests */
     int32_t max_round_tiles;   /* cap on workgroups per SpMV round (0: 2^20) */
+    int32_t preload;           /* 1: upload each matrix in the background as it is added, while it
+                                  fits in the free budget without evicting (0: on first request) */
 } srv_config;
 
 typedef struct srv_result {
@@ -307,8 +309,11 @@ typedef struct srv_stats {
 
 /* Creates the server on the current device (cfg NULL: defaults). */
 int srv_create(const srv_config *cfg, spmv_server **out);
-/* Registers a host CSR matrix (copied; uploaded on first use).  *matrix_id is
- * its handle for srv_submit.  Validation as in spmv_create. */
+/* Registers a host CSR matrix (copied).  It is uploaded by the server's
+ * upload thread, on its first request or, with cfg.preload, at once if it
+ * fits.  *matrix_id is its handle for srv_submit.  Validation as in
+ * spmv_create.  A failed upload fails the requests that waited for it, with
+ * its message; the next request on the matrix tries again. */
 int srv_add_matrix(spmv_server *srv, int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                    const int32_t *col_idx, const double *values, int32_t *matrix_id);
 /* Submits a request.  in/out are HOST buffers (SRV_SPMV: k*n_cols in,
@@ -321,7 +326,7 @@ int srv_submit(spmv_server *srv, int32_t matrix_id, int32_t op, int32_t k, const
 int srv_poll(spmv_server *srv, uint64_t ticket, srv_result *res);
 /* Blocks until the ticket is done (res may be NULL). */
 int srv_wait(spmv_server *srv, uint64_t ticket, srv_result *res);
-/* Blocks until every submitted request is done. */
+/* Blocks until every submitted request is done and no upload is running. */
 int srv_drain(spmv_server *srv);
 int srv_get_stats(spmv_server *srv, srv_stats *st);
 /* Drains, stops the threads and frees everything. */
@@ -331,11 +336,13 @@ int srv_destroy(spmv_server *srv);
  * srv_policy_simulate: replays the server's admission policy on the host
  * (no GPU), for tests.  Matrices need mat_bytes[i] when resident.  Op t is
  * an admission (op_kind 0) or a release (1) of a request on matrix op_mat[t]
- * holding op_extra[t] bytes of buffers, or (2) the release of the only
- * request admitted on a matrix whose upload failed, which leaves the matrix
- * not resident.  Per op: verdict (0 admit, 1 wait, 2 never; -1 for
- * releases), number of evicted matrices, whether the matrix is uploaded, and
- * the bytes in use afterwards.  Unknown kinds: SPMV_EINVAL.
+ * holding op_extra[t] bytes of buffers, (2) a failed upload of a resident
+ * matrix, which leaves it not resident (its requests are released with 1),
+ * or (3) a preload, which makes the matrix resident only if it fits in the
+ * free budget (verdict 0) and otherwise does nothing (verdict 1).  Per op:
+ * verdict (0 admit, 1 wait, 2 never; -1 for releases and failed uploads),
+ * number of evicted matrices, whether the matrix is uploaded, and the bytes
+ * in use afterwards.  Unknown kinds: SPMV_EINVAL.
  */
 int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64_t *mat_bytes, int32_t n_ops,
                         const int32_t *op_kind, const int32_t *op_mat, const uint64_t *op_extra,

@@ -380,7 +380,7 @@ SRV_SPMV, SRV_CG = 0, 1
 
 class srv_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
-                ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32)]
+                ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32), ("preload", ctypes.c_int32)]
 
 
 class srv_result(ctypes.Structure):
@@ -453,9 +453,9 @@ class Server:
     kept alive until their request is reported done."""
 
     def __init__(self, hbm_budget_bytes: int = 0, n_slots: int = 0, cg_mode: int = CG_FP64,
-                 max_round_tiles: int = 0):
+                 max_round_tiles: int = 0, preload: bool = False):
         L = _serve_lib()
-        cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles)
+        cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles, 1 if preload else 0)
         h = ctypes.c_void_p()
         _check(L.srv_create(ctypes.byref(cfg), ctypes.byref(h)), "srv_create")
         self._h = h

@@ -84,7 +84,8 @@ using Clock = std::chrono::steady_clock;
 struct Request {
     uint64_t ticket = 0;
     int32_t mid = 0, op = 0, k = 1, max_iter = 0;
-    const spmv_matrix *A = nullptr;  // resident handle, set at admission (pinned until done)
+    const spmv_matrix *A = nullptr;  // resident handle, set at dispatch (pinned from admission until done)
+    uint32_t gen = 0;                // upload attempt of its matrix that it waits for
     const double *in = nullptr;
     double *out = nullptr;
     double tol = 0.0;
@@ -99,9 +100,15 @@ struct Request {
 
 struct MatrixEntry {
     int32_t n_rows = 0, n_cols = 0;
-    std::vector<int32_t> row_ptr, col_idx;
+    std::vector<int32_t> row_ptr, col_idx;  // host copy, immutable once added
     std::vector<double> values;
+    // device state, under the server's mutex: a matrix is ready when dev is
+    // set and no upload is running; an upload attempt that fails records its
+    // generation and message for the requests that waited on it
     spmv_matrix *dev = nullptr;
+    bool uploading = false;
+    uint32_t gen = 0, failed_gen = 0;
+    char error[160] = {0};
 };
 
 struct Slot {
@@ -119,13 +126,17 @@ struct Server {
     srv_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_sched, cv_done, cv_slot;
+    std::condition_variable cv_sched, cv_done, cv_slot, cv_upload, cv_ready;
     std::deque<Request *> incoming, pending;
+    std::vector<Request *> waiting_spmv;  // admitted SpMV requests not yet in a round
+    std::deque<int> upload_queue;         // matrices for the upload thread
+    int uploads_in_flight = 0;
+    bool wake = false;                    // something the scheduler waits for changed
     std::unordered_map<uint64_t, Request *> all;
     std::deque<MatrixEntry> mats;  // stable element addresses; read under `mu`
     BudgetLRU policy;
     std::vector<Slot> slots;
-    std::thread scheduler;
+    std::thread scheduler, uploader;
     hipStream_t batch = nullptr;
     MultiItem *items_host = nullptr;
     size_t items_cap = 0;
@@ -155,11 +166,11 @@ struct Server {
         return b;
     }
 
-    // Marks r done.  A failed request keeps the message of the error, which
-    // the calling thread has just recorded.
-    void finish_locked(Request *r, int status) {
+    // Marks r done.  A failed request keeps `msg`, else the message of the
+    // error the calling thread has just recorded.
+    void finish_locked(Request *r, int status, const char *msg = nullptr) {
         r->status = status;
-        if (status != SPMV_OK) std::snprintf(r->message, sizeof r->message, "%s", last_error());
+        if (status != SPMV_OK) std::snprintf(r->message, sizeof r->message, "%s", msg ? msg : last_error());
         r->t_done = Clock::now();
         r->done = true;
         if (status == SPMV_OK) {
@@ -169,21 +180,72 @@ struct Server {
             ++failed;
         }
         t_last = r->t_done;
+        wake = true;
         cv_done.notify_all();
     }
 
-    int upload_locked(int mid) {
-        MatrixEntry &m = mats[mid];
+    // The device handle of a server matrix (FP32 copy for mixed-precision
+    // solves).  Reads only the entry's immutable host arrays.
+    int create_handle(const MatrixEntry &m, spmv_matrix **out) const {
         spmv_params p{};
         p.tile_nnz = kServeTile;
         p.window_mode = SPMV_WINDOW_OFF;
         p.kernel = KV_ONE_TILE;
         const uint32_t flags = cfg.cg_mode == CG_MIXED_FP32 ? SPMV_VALUES_FP32 : 0u;
-        int rc = spmv_create(m.n_rows, m.n_cols, (int64_t)m.col_idx.size(), m.row_ptr.data(),
-                             m.col_idx.empty() ? nullptr : m.col_idx.data(),
-                             m.values.empty() ? nullptr : m.values.data(), flags, &p, &m.dev);
-        if (rc == SPMV_OK) policy.resize(mid, (uint64_t)m.dev->bytes);
-        return rc;
+        return spmv_create(m.n_rows, m.n_cols, (int64_t)m.col_idx.size(), m.row_ptr.data(),
+                           m.col_idx.empty() ? nullptr : m.col_idx.data(),
+                           m.values.empty() ? nullptr : m.values.data(), flags, &p, out);
+    }
+
+    // Queues matrix mid for the upload thread; the policy already counts it
+    // resident.  The upload holds its own pin until it ends.
+    void start_upload_locked(int mid) {
+        MatrixEntry &m = mats[mid];
+        m.uploading = true;
+        ++m.gen;
+        policy.pin(mid);
+        ++uploads_in_flight;
+        upload_queue.push_back(mid);
+        cv_upload.notify_one();
+    }
+
+    // Uploads run here, off the scheduler, so that rounds and admissions go
+    // on while a large matrix is copied.
+    void uploader_loop() {
+        const hipError_t dev_err = hipSetDevice(device);
+        for (;;) {
+            int mid;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_upload.wait(lk, [&] { return stop || !upload_queue.empty(); });
+                if (upload_queue.empty()) return;
+                mid = upload_queue.front();
+                upload_queue.pop_front();
+            }
+            const MatrixEntry &m = mats[mid];  // deque elements never move
+            clear_error();
+            (void)hipGetLastError();
+            spmv_matrix *h = nullptr;
+            const int rc = dev_err != hipSuccess ? hip_fail(dev_err, "server upload thread: hipSetDevice")
+                                                 : create_handle(m, &h);
+            std::lock_guard<std::mutex> lk(mu);
+            MatrixEntry &e = mats[mid];
+            e.uploading = false;
+            if (rc == SPMV_OK) {
+                e.dev = h;
+                policy.resize(mid, (uint64_t)h->bytes);
+            } else {
+                e.failed_gen = e.gen;
+                std::snprintf(e.error, sizeof e.error, "%s", last_error());
+                policy.unload(mid);  // waiting requests fail; a later request uploads again
+            }
+            policy.release(mid, 0);
+            --uploads_in_flight;
+            wake = true;
+            cv_ready.notify_all();
+            cv_sched.notify_all();
+            cv_done.notify_all();
+        }
     }
 
     // One round: every SpMV vector of the admitted requests in one launch.
@@ -268,7 +330,6 @@ struct Server {
             --in_flight_spmv;
             finish_locked(r, err);
         }
-        cv_sched.notify_all();
     }
 
     void solver_loop(int si) {
@@ -281,6 +342,16 @@ struct Server {
                 cv_slot.wait(lk, [&] { return stop || sl.job != nullptr; });
                 if (sl.job == nullptr) return;
                 r = sl.job;
+                MatrixEntry &m = mats[r->mid];
+                cv_ready.wait(lk, [&] { return !m.uploading && (m.dev || m.failed_gen >= r->gen); });
+                if (!m.dev) {  // the upload this request waited for failed
+                    policy.release(r->mid, r->extra);
+                    sl.job = nullptr;
+                    finish_locked(r, SPMV_EDEVICE, m.error);
+                    cv_sched.notify_all();
+                    continue;
+                }
+                r->A = m.dev;
             }
             clear_error();
             (void)hipGetLastError();  // drop an error an earlier call of this thread left behind
@@ -331,16 +402,18 @@ struct Server {
         std::vector<int> evict;
         for (;;) {
             std::vector<Request *> round;
+            std::vector<spmv_matrix *> evicted;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_sched.wait_for(lk, std::chrono::microseconds(500),
-                                  [&] { return stop || !incoming.empty() || !pending.empty(); });
-                if (stop && incoming.empty() && pending.empty()) return;
+                cv_sched.wait_for(lk, std::chrono::microseconds(500), [&] { return stop || wake; });
+                wake = false;
+                if (stop && incoming.empty() && pending.empty() && waiting_spmv.empty()) return;
                 while (!incoming.empty()) {
                     pending.push_back(incoming.front());
                     incoming.pop_front();
                 }
-                int64_t round_tiles = 0;
+                // admission: reserve memory (evicting idle matrices), start
+                // uploads, give each CG request a slot
                 for (auto it = pending.begin(); it != pending.end();) {
                     Request *r = *it;
                     if (dev_err != hipSuccess) {  // this thread cannot reach the device
@@ -352,9 +425,6 @@ struct Server {
                     if (r->op == SRV_CG) {
                         slot = free_slot_locked();
                         if (slot < 0) { ++it; continue; }
-                    } else {
-                        const int64_t est = (int64_t)r->k * (int64_t)(mats[r->mid].col_idx.size() / kServeTile + 1);
-                        if (!round.empty() && round_tiles + est > cfg.max_round_tiles) { ++it; continue; }
                     }
                     bool upload = false;
                     clear_error();
@@ -365,36 +435,46 @@ struct Server {
                         continue;
                     }
                     if (v == BudgetLRU::WAIT) { ++it; continue; }
-                    for (int m : evict) {
-                        if (mats[m].dev) (void)spmv_destroy(mats[m].dev);
+                    for (int m : evict) {  // idle and resident: never uploading
+                        if (mats[m].dev) evicted.push_back(mats[m].dev);
                         mats[m].dev = nullptr;
                     }
-                    if (upload || !mats[r->mid].dev) {
-                        const int rc = upload_locked(r->mid);
-                        if (rc != SPMV_OK) {
-                            // the matrix did not become resident: drop the
-                            // reservation so that a later request uploads it
-                            policy.release(r->mid, r->extra);
-                            policy.unload(r->mid);
-                            mats[r->mid].dev = nullptr;
-                            it = pending.erase(it);
-                            finish_locked(r, rc);
-                            continue;
-                        }
-                    }
+                    MatrixEntry &m = mats[r->mid];
+                    if (upload || (!m.dev && !m.uploading)) start_upload_locked(r->mid);
+                    r->gen = m.gen;
                     it = pending.erase(it);
                     r->t_start = Clock::now();
-                    r->A = mats[r->mid].dev;
                     if (r->op == SRV_CG) {
                         slots[slot].job = r;
                         cv_slot.notify_all();
                     } else {
-                        round.push_back(r);
+                        waiting_spmv.push_back(r);
                         ++in_flight_spmv;
-                        round_tiles += (int64_t)r->k * r->A->M.n_stream;
                     }
                 }
+                // dispatch: the next round takes admitted SpMV requests whose
+                // matrix is ready, up to the round's workgroup cap
+                int64_t round_tiles = 0;
+                for (auto it = waiting_spmv.begin(); it != waiting_spmv.end();) {
+                    Request *r = *it;
+                    MatrixEntry &m = mats[r->mid];
+                    if (m.uploading || (!m.dev && m.failed_gen < r->gen)) { ++it; continue; }
+                    if (!m.dev) {  // the upload this request waited for failed
+                        it = waiting_spmv.erase(it);
+                        policy.release(r->mid, r->extra);
+                        --in_flight_spmv;
+                        finish_locked(r, SPMV_EDEVICE, m.error);
+                        continue;
+                    }
+                    const int64_t est = (int64_t)r->k * m.dev->M.n_stream;
+                    if (!round.empty() && round_tiles + est > cfg.max_round_tiles) { ++it; continue; }
+                    r->A = m.dev;
+                    round.push_back(r);
+                    round_tiles += est;
+                    it = waiting_spmv.erase(it);
+                }
             }
+            for (spmv_matrix *d : evicted) (void)spmv_destroy(d);
             if (!round.empty()) run_round(round);
         }
     }
@@ -446,6 +526,7 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     gate.unlock();
     for (int i = 0; i < cfg.n_slots; ++i) S->slots[i].th = std::thread([S, i] { S->solver_loop(i); });
     S->scheduler = std::thread([S] { S->scheduler_loop(); });
+    S->uploader = std::thread([S] { S->uploader_loop(); });
     *out = new spmv_server{S};
     return SPMV_OK;
 }
@@ -468,6 +549,7 @@ extern "C" int srv_add_matrix(spmv_server *srv, int32_t n_rows, int32_t n_cols, 
     const uint64_t bytes = S->matrix_bytes(m);
     S->mats.push_back(std::move(m));
     *matrix_id = S->policy.add_matrix(bytes);
+    if (S->cfg.preload && S->policy.preload(*matrix_id)) S->start_upload_locked(*matrix_id);
     return SPMV_OK;
 }
 
@@ -518,6 +600,7 @@ extern "C" int srv_submit(spmv_server *srv, int32_t matrix_id, int32_t op, int32
     S->all[r->ticket] = r;
     S->incoming.push_back(r);
     *ticket = r->ticket;
+    S->wake = true;
     S->cv_sched.notify_all();
     return SPMV_OK;
 }
@@ -566,7 +649,7 @@ extern "C" int srv_drain(spmv_server *srv) {
     if (!srv) return fail(SPMV_EINVAL, "NULL argument");
     Server *S = srv->s;
     std::unique_lock<std::mutex> lk(S->mu);
-    S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted; });
+    S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted && S->uploads_in_flight == 0; });
     return SPMV_OK;
 }
 
@@ -606,12 +689,14 @@ extern "C" int srv_destroy(spmv_server *srv) {
     Server *S = srv->s;
     {
         std::unique_lock<std::mutex> lk(S->mu);
-        S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted; });
+        S->cv_done.wait(lk, [&] { return S->completed + S->failed == S->submitted && S->uploads_in_flight == 0; });
         S->stop = true;
     }
     S->cv_sched.notify_all();
     S->cv_slot.notify_all();
+    S->cv_upload.notify_all();
     if (S->scheduler.joinable()) S->scheduler.join();
+    if (S->uploader.joinable()) S->uploader.join();
     for (auto &sl : S->slots)
         if (sl.th.joinable()) sl.th.join();
     for (auto &m : S->mats)
@@ -649,10 +734,13 @@ extern "C" int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64
         } else if (op_kind[t] == 1) {
             if (P.pins(op_mat[t]) <= 0) return fail(SPMV_EINVAL, "op %d: release without admission", t);
             P.release(op_mat[t], op_extra[t]);
-        } else if (op_kind[t] == 2) {  // the admitted request's upload failed
-            if (P.pins(op_mat[t]) != 1) return fail(SPMV_EINVAL, "op %d: failed upload needs one admission", t);
-            P.release(op_mat[t], op_extra[t]);
+        } else if (op_kind[t] == 2) {  // the matrix's upload failed
+            if (!P.resident(op_mat[t])) return fail(SPMV_EINVAL, "op %d: failed upload of a matrix not resident", t);
             P.unload(op_mat[t]);
+        } else if (op_kind[t] == 3) {  // preload
+            const bool made = P.preload(op_mat[t]);
+            v = made ? 0 : 1;
+            up = made ? 1 : 0;
         } else {
             return fail(SPMV_EINVAL, "op %d: kind %d unknown", t, op_kind[t]);
         }

@@ -63,6 +63,23 @@ class BudgetLRU {
         return ADMIT;
     }
 
+    // Uploads matrix i ahead of any request if it fits in the free budget
+    // without evicting anything; returns whether it was made resident.
+    bool preload(int i) {
+        Ent &e = m_[i];
+        if (e.resident || used_ + e.bytes > budget_) return false;
+        e.resident = true;
+        used_ += e.bytes;
+        e.last = ++clock_;
+        ++uploads_;
+        if (used_ > peak_) peak_ = used_;
+        return true;
+    }
+
+    // Holds matrix i against eviction without reserving buffers (an upload
+    // in progress); undone by release(i, 0).
+    void pin(int i) { m_[i].pins += 1; }
+
     // A request on matrix i that reserved `extra` bytes has finished.
     void release(int i, uint64_t extra) {
         m_[i].pins -= 1;

@@ -8,9 +8,9 @@
 //  * a 96-byte device-to-host copy is the CG solver reading its scalar state
 //    (10 doubles, 4 int32): it reads back a converged state, so every solve
 //    takes the capture -> replay -> confirm path and ends;
-//  * MOCK_FAIL_COPY_EVERY=N makes every N-th synchronous host-to-device copy
-//    fail.  Only matrix creation uses synchronous copies, so this makes
-//    uploads fail part-way through.
+//  * MOCK_FAIL_COPY_EVERY=N makes every N-th host-to-device copy fail
+//    (matrix uploads, request inputs), so that uploads fail part-way through
+//    and requests fail while buffers are being filled.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -20,7 +20,7 @@
 
 namespace {
 thread_local int t_device = 0;
-std::atomic<long> n_sync_h2d{0};
+std::atomic<long> n_h2d{0};
 
 long fail_every() {
     static const long v = [] {
@@ -49,13 +49,18 @@ hipError_t hipFreeAsync(void *p, hipStream_t) { return hipFree(p); }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { return hipMalloc(p, n); }
 hipError_t hipHostFree(void *p) { return hipFree(p); }
 
-hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k) {
+static bool injected_failure(hipMemcpyKind k) {
     const long every = fail_every();
-    if (every > 0 && k == hipMemcpyHostToDevice && ++n_sync_h2d % every == 0) return hipErrorOutOfMemory;
+    return every > 0 && k == hipMemcpyHostToDevice && ++n_h2d % every == 0;
+}
+
+hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k) {
+    if (injected_failure(k)) return hipErrorOutOfMemory;
     copy_bytes(d, s, n);
     return hipSuccess;
 }
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+    if (injected_failure(k)) return hipErrorOutOfMemory;
     copy_bytes(d, s, n);
     if (k == hipMemcpyDeviceToHost && n == 96) {  // the CG scalar state
         double *v = static_cast<double *>(d);

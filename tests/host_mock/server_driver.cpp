@@ -1,10 +1,12 @@
 // Drives the request server (srv_*) over six banded matrices with mixes of
-// SpMV and CG requests (several slot counts, both CG modes, and a small
-// device budget that forces evictions and rejections), then checks the
+// SpMV and CG requests (several slot counts, both CG modes, uploads on first
+// request or preloaded, and a small device budget that forces evictions and
+// rejections), then checks the
 // outcome of every request: it is reported done, and a failed one carries a
 // message.  Prints one summary line; exits 0 when every check holds.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <random>
 #include <thread>
 #include <vector>
@@ -40,12 +42,13 @@ int main(int argc, char **argv) {
     std::mt19937_64 rng(7);
     std::vector<Banded> pool;
     for (int n : {1000, 4000, 9000, 30000, 70000, 150000}) pool.push_back(banded(n));
-    long completed = 0, failed = 0, without_message = 0, not_done = 0, bad_stats = 0;
+    long completed = 0, failed = 0, without_message = 0, not_done = 0, bad_stats = 0, upload_failed = 0;
     for (int rep = 0; rep < reps; ++rep) {
         srv_config cfg{};
         cfg.n_slots = 2 + rep % 5;
         cfg.cg_mode = rep % 3 == 2 ? CG_MIXED_FP32 : CG_FP64;
         if (rep % 4 == 3) cfg.hbm_budget_bytes = 6000000;
+        cfg.preload = rep % 2;
         spmv_server *S = nullptr;
         if (srv_create(&cfg, &S) != SPMV_OK) {
             std::printf("srv_create failed: %s\n", spmv_last_error());
@@ -59,6 +62,7 @@ int main(int argc, char **argv) {
                 return 2;
             }
         }
+        if (rep % 3 == 1) (void)srv_drain(S);  // preloads (if any) finish first
         const int n_req = 24 + rep % 13;
         std::vector<std::vector<double>> in(n_req), out(n_req);
         std::vector<uint64_t> ticket(n_req);
@@ -92,6 +96,7 @@ int main(int argc, char **argv) {
             } else {
                 ++failed;
                 if (!r.message[0]) ++without_message;
+                if (std::strncmp(r.message, "hipMemcpyAsync", 14) == 0) ++upload_failed;  // a matrix upload
             }
         }
         srv_stats st;
@@ -99,7 +104,7 @@ int main(int argc, char **argv) {
         if (st.completed + st.failed != st.submitted || st.submitted != n_req) ++bad_stats;
         (void)srv_destroy(S);
     }
-    std::printf("summary completed=%ld failed=%ld without_message=%ld not_done=%ld bad_stats=%ld\n", completed, failed,
-                without_message, not_done, bad_stats);
+    std::printf("summary completed=%ld failed=%ld upload_failed=%ld without_message=%ld not_done=%ld bad_stats=%ld\n",
+                completed, failed, upload_failed, without_message, not_done, bad_stats);
     return (without_message || not_done || bad_stats) ? 3 : 0;
 }

@@ -129,6 +129,54 @@ def test_budget_eviction_and_rejection(pool):
         assert res.status == spmv.SPMV_EBUDGET and "budget" in res.message
 
 
+def _check(pool, r, out, res):
+    _ok(res)
+    kind, mid, data = r
+    A = pool[mid]
+    if kind == "spmv":
+        for j in range(data.shape[0]):
+            y_ref, bound = oracle.spmv(A, data[j])
+            assert oracle.spmv_accept(out[j], y_ref, bound).all()
+    else:
+        Ax, _ = oracle.spmv(A, out)
+        assert np.linalg.norm(data - Ax) / np.linalg.norm(data) <= 1.05e-8
+
+
+def test_preload_uploads_at_registration(pool):
+    reqs = _requests(pool, 16, 300)
+    with spmv.Server(n_slots=4, preload=True) as srv:
+        for A in pool:
+            srv.add_matrix(A)
+        srv.drain()                                   # waits for the background uploads
+        assert srv.stats()["uploads"] == len(pool)
+        tickets = [_submit(srv, r) for r in reqs]
+        for r, t in zip(reqs, tickets):
+            out, res = srv.wait(t)
+            _check(pool, r, out, res)
+        assert srv.stats()["uploads"] == len(pool)   # no upload on the request path
+
+
+def test_preload_within_budget_then_on_demand(pool):
+    small = pool[:4]
+    est = lambda A: 12 * (A.nnz + 20) + 4 * (A.n_rows + 1) + 64 * (A.nnz // 512 + 16)
+    # room for matrices 0-2 preloaded in order but not for matrix 3 as well;
+    # requests on matrix 3 then evict idle preloaded ones
+    budget = int(est(small[0]) + est(small[1]) + est(small[3]) + 32 * small[3].n_rows)
+    assert sum(est(A) for A in small) > budget
+    reqs = [("spmv", i % 4, mg.uniform(small[i % 4].n_cols, 40 + i, 5)[None, :]) for i in range(8)]
+    with spmv.Server(hbm_budget_bytes=budget, n_slots=2, preload=True) as srv:
+        for A in small:
+            srv.add_matrix(A)
+        srv.drain()
+        st = srv.stats()
+        assert st["uploads"] == 3 and st["peak_bytes"] <= budget
+        for r in reqs:
+            out, res = srv.wait(_submit(srv, r))
+            _check(small, r, out, res)
+        st = srv.stats()
+        assert st["evictions"] > 0 and st["peak_bytes"] <= budget
+
+
 def test_mixed_precision_cg_requests(pool):
     A = pool[2]
     b = mg.uniform(A.n_rows, 9, 4)

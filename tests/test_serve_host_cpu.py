@@ -6,7 +6,8 @@ The regression case: when a matrix upload fails, the request reports the
 error and the matrix must not stay marked resident without a device handle
 (that state made the next request on the matrix dereference a null handle in
 a server thread).  Uploads are made to fail by the mock's
-MOCK_FAIL_COPY_EVERY knob."""
+MOCK_FAIL_COPY_EVERY knob; the driver counts the requests that failed with an
+upload's message."""
 import os
 import re
 import shutil
@@ -61,14 +62,14 @@ def run(exe, reps, fail_every=None):
     r = subprocess.run([exe, str(reps)], capture_output=True, text=True, env=env, timeout=300)
     assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, f"rc={r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
-    m = re.search(r"summary completed=(\d+) failed=(\d+)", r.stdout)
+    m = re.search(r"summary completed=(\d+) failed=(\d+) upload_failed=(\d+)", r.stdout)
     assert m, r.stdout
-    return int(m.group(1)), int(m.group(2))
+    return int(m.group(1)), int(m.group(2)), int(m.group(3))
 
 
 def test_server_threads_clean_under_asan(driver):
-    completed, failed = run(driver, 8)
-    assert completed > 0
+    completed, failed, upload_failed = run(driver, 8)
+    assert completed > 0 and upload_failed == 0
 
 
 @pytest.mark.parametrize("every", [3, 5, 7, 11])
@@ -76,7 +77,7 @@ def test_failed_uploads_report_errors_and_do_not_crash(driver, every):
     # every 3rd copy failing fails every upload (a matrix takes several
     # copies); with rarer failures, a matrix whose upload failed is uploaded
     # again by a later request, which then succeeds
-    completed, failed = run(driver, 8, every)
-    assert failed > 0
+    completed, failed, upload_failed = run(driver, 8, every)
+    assert upload_failed > 0
     if every >= 7:
         assert completed > 0

@@ -57,21 +57,33 @@ def test_many_matrices_stay_within_budget():
 
 
 def test_failed_upload_leaves_matrix_not_resident():
-    # admission asks for the upload of matrix 0; the upload fails (kind 2):
-    # nothing stays reserved, and the next request on matrix 0 uploads it again
-    r = spmv.policy_simulate(100, [40, 30], [(0, 0, 10), (2, 0, 10), (0, 0, 10), (1, 0, 10)])
+    # admission asks for the upload of matrix 0; the upload fails (kind 2) and
+    # the request is released: nothing stays reserved, and the next request
+    # on matrix 0 uploads it again
+    r = spmv.policy_simulate(100, [40, 30], [(0, 0, 10), (2, 0, 0), (1, 0, 10), (0, 0, 10), (1, 0, 10)])
     assert r[0] == (ADMIT, 0, 1, 50)
-    assert r[1][3] == 0
-    assert r[2] == (ADMIT, 0, 1, 50)
-    assert r[3][3] == 40
+    assert r[1][3] == 10 and r[2][3] == 0
+    assert r[3] == (ADMIT, 0, 1, 50)
+    assert r[4][3] == 40
     # a failed upload frees room for others: matrix 1 fits without evicting
-    r = spmv.policy_simulate(60, [40, 50], [(0, 0, 0), (2, 0, 0), (0, 1, 5)])
-    assert r[2] == (ADMIT, 0, 1, 55)
+    r = spmv.policy_simulate(60, [40, 50], [(0, 0, 0), (2, 0, 0), (1, 0, 0), (0, 1, 5)])
+    assert r[3] == (ADMIT, 0, 1, 55)
+
+
+def test_preload_only_into_free_budget():
+    r = spmv.policy_simulate(100, [40, 30, 50], [(3, 0, 0), (3, 1, 0), (3, 2, 0), (3, 0, 0)])
+    assert [x[0] for x in r] == [ADMIT, ADMIT, WAIT, WAIT]     # 2 does not fit; 0 is already resident
+    assert [x[2] for x in r] == [1, 1, 0, 0] and r[-1][3] == 70
+    # a preloaded matrix serves requests without another upload and, idle,
+    # can be evicted like any other
+    r = spmv.policy_simulate(80, [40, 30, 50], [(3, 0, 0), (0, 0, 10), (1, 0, 10), (0, 2, 0)])
+    assert r[1] == (ADMIT, 0, 0, 50)
+    assert r[3] == (ADMIT, 1, 1, 50)
 
 
 def test_simulator_rejects_bad_ops():
     import pytest
     with pytest.raises(spmv.SpmvError):
-        spmv.policy_simulate(100, [40], [(3, 0, 0)])
+        spmv.policy_simulate(100, [40], [(5, 0, 0)])
     with pytest.raises(spmv.SpmvError):
-        spmv.policy_simulate(100, [40], [(2, 0, 0)])        # no admission to fail
+        spmv.policy_simulate(100, [40], [(2, 0, 0)])        # not resident: no upload to fail
