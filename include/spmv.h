@@ -286,6 +286,7 @@ typedef struct srv_config {
     int32_t max_round_tiles;   /* cap on workgroups per SpMV round (0: 2^20) */
     int32_t preload;           /* 1: upload each matrix in the background as it is added, while it
                                   fits in the free budget without evicting (0: on first request) */
+    int32_t n_lanes;           /* SpMV rounds in flight at once, each on its own stream, <= 16 (0: 4) */
 } srv_config;
 
 typedef struct srv_result {

@@ -380,7 +380,8 @@ SRV_SPMV, SRV_CG = 0, 1
 
 class srv_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
-                ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32), ("preload", ctypes.c_int32)]
+                ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32), ("preload", ctypes.c_int32),
+                ("n_lanes", ctypes.c_int32)]
 
 
 class srv_result(ctypes.Structure):
@@ -453,9 +454,9 @@ class Server:
     kept alive until their request is reported done."""
 
     def __init__(self, hbm_budget_bytes: int = 0, n_slots: int = 0, cg_mode: int = CG_FP64,
-                 max_round_tiles: int = 0, preload: bool = False):
+                 max_round_tiles: int = 0, preload: bool = False, n_lanes: int = 0):
         L = _serve_lib()
-        cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles, 1 if preload else 0)
+        cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles, 1 if preload else 0, n_lanes)
         h = ctypes.c_void_p()
         _check(L.srv_create(ctypes.byref(cfg), ctypes.byref(h)), "srv_create")
         self._h = h

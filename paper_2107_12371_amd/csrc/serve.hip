@@ -3,11 +3,16 @@
 // Requests (k SpMVs, or a CG solve) arrive at any time through srv_submit.
 // A scheduler thread admits them as device memory and solver slots free up
 // (BudgetLRU: resident matrices + request buffers within an HBM budget,
-// least-recently-used idle matrices evicted), and runs rounds:
-//  * every admitted SpMV request joins the next round, and one launch of the
-//    multi-matrix kernel k_multi covers the tiles of all of the round's
-//    vectors, whatever matrix each belongs to (a workgroup finds its item by
-//    binary search over the round's tile offsets);
+// least-recently-used idle matrices evicted) and hands out work:
+//  * matrices are uploaded by an upload thread, on first request or ahead of
+//    time (preloading), so a large upload never stalls the scheduler;
+//  * admitted SpMV requests whose matrix is resident form rounds, and a free
+//    SpMV lane (a worker thread with its own stream) runs each round: the
+//    vectors in, one launch of the multi-matrix kernel k_multi over the
+//    tiles of all of the round's vectors, whatever matrix each belongs to (a
+//    workgroup finds its item by binary search over the round's tile
+//    offsets), the results out.  Requests that move many vector words over
+//    the host link get rounds of their own, so small ones keep batching;
 //  * each admitted CG request runs on a solver slot: a worker thread with
 //    its own stream drives the graph-captured CG iterations, overlapping
 //    with the rounds and with the other slots.
@@ -118,6 +123,22 @@ struct Slot {
     Request *job = nullptr;
 };
 
+// An SpMV lane: a worker thread with its own stream that runs one round at a
+// time (copies in, one k_multi launch, copies out), so that a round moving a
+// large request's vectors over the host link does not hold up the others.
+struct Lane {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    MultiItem *items_host = nullptr;  // pinned staging of the round's item table
+    size_t items_cap = 0;
+    std::vector<Request *> job;
+    bool busy = false;
+};
+
+// Requests moving at least this many vector words between host and device
+// get rounds of their own.
+constexpr int64_t kLargeRequestWords = int64_t(1) << 22;
+
 double seconds(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
 
 }  // namespace
@@ -126,7 +147,7 @@ struct Server {
     srv_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_sched, cv_done, cv_slot, cv_upload, cv_ready;
+    std::condition_variable cv_sched, cv_done, cv_slot, cv_upload, cv_ready, cv_lane;
     std::deque<Request *> incoming, pending;
     std::vector<Request *> waiting_spmv;  // admitted SpMV requests not yet in a round
     std::deque<int> upload_queue;         // matrices for the upload thread
@@ -136,10 +157,8 @@ struct Server {
     std::deque<MatrixEntry> mats;  // stable element addresses; read under `mu`
     BudgetLRU policy;
     std::vector<Slot> slots;
+    std::vector<Lane> lanes;
     std::thread scheduler, uploader;
-    hipStream_t batch = nullptr;
-    MultiItem *items_host = nullptr;
-    size_t items_cap = 0;
     uint64_t next_ticket = 1;
     int64_t submitted = 0, completed = 0, failed = 0, rounds = 0;
     int in_flight_spmv = 0;
@@ -248,8 +267,10 @@ struct Server {
         }
     }
 
-    // One round: every SpMV vector of the admitted requests in one launch.
-    void run_round(std::vector<Request *> &round) {
+    // One round on lane ln: every SpMV vector of the round's requests in one
+    // launch.  Frees the lane when done.
+    void run_round(std::vector<Request *> &round, Lane &ln) {
+        const hipStream_t batch = ln.stream;
         clear_error();
         (void)hipGetLastError();  // drop an error an earlier call of this thread left behind
         std::vector<MultiItem> items;
@@ -282,24 +303,25 @@ struct Server {
             }
         }
         if (err == SPMV_OK && !items.empty()) {
-            if (items.size() > items_cap) {
+            if (items.size() > ln.items_cap) {
                 std::lock_guard<std::mutex> gate(capture_gate());
-                if (items_host) (void)hipHostFree(items_host);
-                items_cap = std::max<size_t>(items.size(), 2 * items_cap);
-                hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&items_host), items_cap * sizeof(MultiItem),
-                                             hipHostMallocDefault);
+                if (ln.items_host) (void)hipHostFree(ln.items_host);
+                ln.items_cap = std::max<size_t>(items.size(), 2 * ln.items_cap);
+                hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ln.items_host),
+                                             ln.items_cap * sizeof(MultiItem), hipHostMallocDefault);
                 if (e != hipSuccess) {
-                    items_host = nullptr;
-                    items_cap = 0;
+                    ln.items_host = nullptr;
+                    ln.items_cap = 0;
                     err = hip_fail(e, "server item staging");
                 }
             }
             if (err == SPMV_OK) {
-                std::memcpy(items_host, items.data(), items.size() * sizeof(MultiItem));
+                std::memcpy(ln.items_host, items.data(), items.size() * sizeof(MultiItem));
                 MultiItem *ditems = nullptr;
                 hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&ditems), items.size() * sizeof(MultiItem), batch);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(ditems, items_host, items.size() * sizeof(MultiItem), hipMemcpyHostToDevice, batch);
+                    e = hipMemcpyAsync(ditems, ln.items_host, items.size() * sizeof(MultiItem), hipMemcpyHostToDevice,
+                                       batch);
                 if (e == hipSuccess) {
                     hipLaunchKernelGGL((k_multi<kServeTile>), dim3(total), dim3(kBlock), 0, batch, ditems,
                                        (int)items.size(), total);
@@ -330,6 +352,37 @@ struct Server {
             --in_flight_spmv;
             finish_locked(r, err);
         }
+        round.clear();
+        ln.busy = false;
+    }
+
+    void lane_loop(int li) {
+        const hipError_t dev_err = hipSetDevice(device);
+        Lane &ln = lanes[li];
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_lane.wait(lk, [&] { return stop || ln.busy; });
+                if (!ln.busy) return;
+                if (dev_err != hipSuccess) {
+                    for (Request *r : ln.job) {
+                        policy.release(r->mid, r->extra);
+                        --in_flight_spmv;
+                        finish_locked(r, hip_fail(dev_err, "server lane thread: hipSetDevice"));
+                    }
+                    ln.job.clear();
+                    ln.busy = false;
+                    continue;
+                }
+            }
+            run_round(ln.job, ln);
+        }
+    }
+
+    int free_lane_locked() const {
+        for (size_t i = 0; i < lanes.size(); ++i)
+            if (!lanes[i].busy) return (int)i;
+        return -1;
     }
 
     void solver_loop(int si) {
@@ -401,7 +454,6 @@ struct Server {
         const hipError_t dev_err = hipSetDevice(device);
         std::vector<int> evict;
         for (;;) {
-            std::vector<Request *> round;
             std::vector<spmv_matrix *> evicted;
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -452,30 +504,39 @@ struct Server {
                         ++in_flight_spmv;
                     }
                 }
-                // dispatch: the next round takes admitted SpMV requests whose
-                // matrix is ready, up to the round's workgroup cap
-                int64_t round_tiles = 0;
-                for (auto it = waiting_spmv.begin(); it != waiting_spmv.end();) {
-                    Request *r = *it;
-                    MatrixEntry &m = mats[r->mid];
-                    if (m.uploading || (!m.dev && m.failed_gen < r->gen)) { ++it; continue; }
-                    if (!m.dev) {  // the upload this request waited for failed
+                // dispatch: each free lane takes a round of admitted SpMV
+                // requests whose matrix is ready, up to the round's workgroup
+                // cap; a large request goes alone
+                for (int li = free_lane_locked(); li >= 0; li = free_lane_locked()) {
+                    std::vector<Request *> &round = lanes[li].job;
+                    int64_t round_tiles = 0;
+                    bool alone = false;
+                    for (auto it = waiting_spmv.begin(); it != waiting_spmv.end() && !alone;) {
+                        Request *r = *it;
+                        MatrixEntry &m = mats[r->mid];
+                        if (m.uploading || (!m.dev && m.failed_gen < r->gen)) { ++it; continue; }
+                        if (!m.dev) {  // the upload this request waited for failed
+                            it = waiting_spmv.erase(it);
+                            policy.release(r->mid, r->extra);
+                            --in_flight_spmv;
+                            finish_locked(r, SPMV_EDEVICE, m.error);
+                            continue;
+                        }
+                        const bool large = (int64_t)r->k * (m.n_rows + m.n_cols) >= kLargeRequestWords;
+                        const int64_t est = (int64_t)r->k * m.dev->M.n_stream;
+                        if (!round.empty() && (large || round_tiles + est > cfg.max_round_tiles)) { ++it; continue; }
+                        r->A = m.dev;
+                        round.push_back(r);
+                        round_tiles += est;
+                        alone = large;
                         it = waiting_spmv.erase(it);
-                        policy.release(r->mid, r->extra);
-                        --in_flight_spmv;
-                        finish_locked(r, SPMV_EDEVICE, m.error);
-                        continue;
                     }
-                    const int64_t est = (int64_t)r->k * m.dev->M.n_stream;
-                    if (!round.empty() && round_tiles + est > cfg.max_round_tiles) { ++it; continue; }
-                    r->A = m.dev;
-                    round.push_back(r);
-                    round_tiles += est;
-                    it = waiting_spmv.erase(it);
+                    if (round.empty()) break;
+                    lanes[li].busy = true;
+                    cv_lane.notify_all();
                 }
             }
             for (spmv_matrix *d : evicted) (void)spmv_destroy(d);
-            if (!round.empty()) run_round(round);
         }
     }
 };
@@ -498,33 +559,40 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     if (cfg.n_slots <= 0) cfg.n_slots = 8;
     if (cfg.n_slots > 64) return fail(SPMV_EINVAL, "n_slots = %d exceeds 64", cfg.n_slots);
     if (cfg.max_round_tiles <= 0) cfg.max_round_tiles = 1 << 20;
+    if (cfg.n_lanes <= 0) cfg.n_lanes = 4;
+    if (cfg.n_lanes > 16) return fail(SPMV_EINVAL, "n_lanes = %d exceeds 16", cfg.n_lanes);
     if (cfg.cg_mode != CG_FP64 && cfg.cg_mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown cg_mode");
     auto *S = new (std::nothrow) Server(cfg);
     if (!S) return fail(SPMV_ENOMEM, "host allocation failed");
     hipError_t e = hipGetDevice(&S->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->batch, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete S;
-        return hip_fail(e, "server stream");
+        return hip_fail(e, "hipGetDevice");
     }
     S->slots.resize(cfg.n_slots);
+    S->lanes.resize(cfg.n_lanes);
     std::unique_lock<std::mutex> gate(capture_gate());
     for (auto &sl : S->slots) {
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipHostMalloc(&sl.pinned, 256, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            const int rc = hip_fail(e, "server slot");
-            for (auto &t : S->slots) {
-                if (t.stream) (void)hipStreamDestroy(t.stream);
-                if (t.pinned) (void)hipHostFree(t.pinned);
-            }
-            (void)hipStreamDestroy(S->batch);
-            delete S;
-            return rc;
+        if (e != hipSuccess) break;
+    }
+    for (size_t i = 0; i < S->lanes.size() && e == hipSuccess; ++i)
+        e = hipStreamCreateWithFlags(&S->lanes[i].stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        const int rc = hip_fail(e, "server streams");
+        for (auto &t : S->slots) {
+            if (t.stream) (void)hipStreamDestroy(t.stream);
+            if (t.pinned) (void)hipHostFree(t.pinned);
         }
+        for (auto &ln : S->lanes)
+            if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        delete S;
+        return rc;
     }
     gate.unlock();
     for (int i = 0; i < cfg.n_slots; ++i) S->slots[i].th = std::thread([S, i] { S->solver_loop(i); });
+    for (int i = 0; i < cfg.n_lanes; ++i) S->lanes[i].th = std::thread([S, i] { S->lane_loop(i); });
     S->scheduler = std::thread([S] { S->scheduler_loop(); });
     S->uploader = std::thread([S] { S->uploader_loop(); });
     *out = new spmv_server{S};
@@ -695,10 +763,13 @@ extern "C" int srv_destroy(spmv_server *srv) {
     S->cv_sched.notify_all();
     S->cv_slot.notify_all();
     S->cv_upload.notify_all();
+    S->cv_lane.notify_all();
     if (S->scheduler.joinable()) S->scheduler.join();
     if (S->uploader.joinable()) S->uploader.join();
     for (auto &sl : S->slots)
         if (sl.th.joinable()) sl.th.join();
+    for (auto &ln : S->lanes)
+        if (ln.th.joinable()) ln.th.join();
     for (auto &m : S->mats)
         if (m.dev) (void)spmv_destroy(m.dev);
     std::lock_guard<std::mutex> gate(capture_gate());
@@ -706,8 +777,10 @@ extern "C" int srv_destroy(spmv_server *srv) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
-    if (S->items_host) (void)hipHostFree(S->items_host);
-    if (S->batch) (void)hipStreamDestroy(S->batch);
+    for (auto &ln : S->lanes) {
+        if (ln.items_host) (void)hipHostFree(ln.items_host);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+    }
     for (auto &kv : S->all) delete kv.second;
     delete S;
     delete srv;
