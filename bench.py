@@ -162,12 +162,13 @@ def cpu_baseline(A, x, budget_s: float):
                       f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')} (the oracle uses one)"}
 
 
-def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=log):
+def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, preload: bool = False, log=log):
     """Request stream: a pool of 32^3-style mesh matrices with log-uniform
     10^3..10^6 rows; each request picks a matrix uniformly and asks for
-    k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  The pool is made
-    resident before the stream (preloading).  Arrivals are Poisson at 0.7x the
-    closed-loop capacity measured on a burst."""
+    k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is uploaded
+    on its first request (that request pays for it), or, with `preload`, while
+    the pool is registered.  Arrivals are Poisson at 0.7x the closed-loop
+    capacity measured on a burst of requests."""
     import threading
 
     import meshgen as mg
@@ -192,20 +193,20 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
             return ("spmv", mid, r.uniform(-1, 1, (k, A.n_cols)))
         return ("cg", mid, r.uniform(-1, 1, A.n_rows))
 
-    # the pool is registered with preloading: matrices are uploaded in the
-    # background as they are added and stay resident (they fit the budget)
-    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=True)
+    # the pool fits the budget, so matrices stay resident once uploaded
+    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=preload)
     t0 = time.perf_counter()
     for A in pool:
         srv.add_matrix(A)
     srv.drain()
-    log(f"serving pool resident: {srv.stats()['uploads']} uploads ({time.perf_counter() - t0:.1f} s)")
+    log(f"serving pool registered: {srv.stats()['uploads']} uploaded ahead ({time.perf_counter() - t0:.1f} s)")
 
     def submit(r):
         kind, mid, data = r
         return srv.submit_spmv(mid, data) if kind == "spmv" else srv.submit_cg(mid, data, tol=1e-8)
 
-    # closed-loop capacity: two bursts, the second one timed
+    # closed-loop capacity: two bursts of requests on matrices drawn as in the
+    # stream, the second one timed
     burst = [make(-1 - i) for i in range(min(64, n_requests))]
     tb = time.perf_counter()
     for t in [submit(r) for r in burst]:
@@ -252,6 +253,7 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     q = lambda a, f: float(np.quantile(np.array(a), f)) if a else None
     out = {"requests": n_requests, "pool": pool_size, "arrival_rate_rps": round(lam, 2),
            "closed_loop_capacity_rps": round(cap, 2), "cg_mode": "mixed" if cg_mode else "fp64",
+           "preload": preload,
            "p50_ms": round(1e3 * q(lat, 0.5), 3), "p99_ms": round(1e3 * q(lat, 0.99), 3),
            "p50_cg_ms": round(1e3 * q(lat_cg, 0.5), 3) if lat_cg else None,
            "p99_cg_ms": round(1e3 * q(lat_cg, 0.99), 3) if lat_cg else None,
@@ -266,12 +268,14 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, log=lo
     return out
 
 
-def serving_in_child(args) -> dict:
+def serving_in_child(args, preload: bool = False) -> dict:
     """The serving stream in a child process of its own, so that whatever
     happens there cannot take the headline measurement with it."""
     import subprocess
     cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
            "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool)]
+    if preload:
+        cmd.append("--serve-preload")
     try:
         r = subprocess.run(cmd, capture_output=True, text=True, timeout=400)
     except subprocess.TimeoutExpired:
@@ -383,6 +387,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=32,
                     help="matrices in the serving pool (1024 in the full workload)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-preload", action="store_true",
+                    help="serving: upload the pool while registering it instead of on first request")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary (the bench runs it this way "
                          "in a child process)")
@@ -390,8 +396,8 @@ def main():
     if args.serve_only:
         import paper_2107_12371_amd as spmv
         import meshgen as mg
-        print(json.dumps(serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64)),
-              flush=True)
+        print(json.dumps(serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64,
+                                     preload=args.serve_preload)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -513,7 +519,8 @@ def main():
         extras["configs"] = config_lines(torch)
         torch.cuda.empty_cache()
     if not args.no_extras and not args.no_serve:
-        extras["serving"] = serving_in_child(args)
+        extras["serving"] = serving_in_child(args)                       # uploads on first touch
+        extras["serving_preloaded"] = serving_in_child(args, preload=True)
 
     cpu = None
     if not args.no_cpu:

@@ -12,8 +12,9 @@ independent implementation, never by re-running the oracle's own formula.
   coefficients, paper Sec. 4.1);
 * linearity; scipy's CSR product and numpy's dense product (independent code);
 * CG: one-step closed form on A 1 = s 1, termination in d steps for d
-  distinct eigenvalues, a dense LAPACK solve, Ritz values from the alpha/beta
-  recurrences;
+  distinct eigenvalues, rational-arithmetic CG that ends with the exact
+  solution within n steps, a dense LAPACK solve, Ritz values from the
+  alpha/beta recurrences;
 * planted mistakes (dropped term, wrong sign, transposed operand, shifted
   column) are caught by the pins above.
 """
@@ -239,6 +240,59 @@ def test_cg_terminates_in_d_steps_for_d_eigenvalues():
 def _dense(A):
     S = sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols))
     return S.toarray()
+
+
+def _exact_cg(D, b):
+    """Conjugate gradients in rational arithmetic; returns (x, steps)."""
+    n = len(b)
+    A = [[Fraction(v) for v in row] for row in D]
+    mv = lambda v: [sum(A[i][j] * v[j] for j in range(n)) for i in range(n)]
+    dt = lambda u, v: sum(a * c for a, c in zip(u, v))
+    x = [Fraction(0)] * n
+    r = [Fraction(v) for v in b]
+    p = list(r)
+    rho = dt(r, r)
+    steps = 0
+    while rho != 0:
+        q = mv(p)
+        alpha = rho / dt(p, q)
+        x = [xi + alpha * pi for xi, pi in zip(x, p)]
+        r = [ri - alpha * qi for ri, qi in zip(r, q)]
+        steps += 1
+        rho_new = dt(r, r)
+        if rho_new == 0:
+            break
+        p = [ri + (rho_new / rho) * pi for ri, pi in zip(r, p)]
+        rho = rho_new
+        assert steps <= n, "exact CG must end within n steps"
+    return x, steps
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_cg_exact_arithmetic_finite_termination(n):
+    # a small SPD mesh-style matrix with dyadic entries: exact CG reaches A x = b
+    # exactly in at most n steps; the oracle's binary64 CG lands within
+    # kappa * tol of that exact solution
+    rng = np.random.default_rng(100 + n)
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if j == i + 1 or rng.random() < 0.3:
+                D[i, j] = D[j, i] = -float(rng.integers(4, 13)) / 8.0
+    np.fill_diagonal(D, -D.sum(axis=1) + 0.25)
+    b = rng.integers(-8, 9, n).astype(float) / 4.0
+    b[0] = 1.0
+    x_exact, steps = _exact_cg(D, b)
+    assert steps <= n
+    A_f = [[Fraction(v) for v in row] for row in D]
+    assert [sum(A_f[i][j] * x_exact[j] for j in range(n)) for i in range(n)] == [Fraction(v) for v in b]
+    S = sp.csr_matrix(D)
+    A = mg.CSR(n, n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64))
+    tol = 1e-12
+    r = oracle.cg(A, b, tol=tol, max_iter=10 * n)
+    xe = np.array([float(v) for v in x_exact])
+    assert r.status == 0
+    assert np.linalg.norm(r.x - xe) / np.linalg.norm(xe) <= 2 * np.linalg.cond(D) * tol
 
 
 def test_cg_against_dense_lapack_solve():
