@@ -82,6 +82,10 @@ def read_traffic(hash_now: str, stem: str):
         return None
 
 
+# untimed settling time before each extra (non-headline) measurement
+WARM_S = 0.05
+
+
 def alg_bytes(n_rows, n_cols, nnz, val_bytes, x_bytes, y_bytes):
     return nnz * (val_bytes + 4) + 4 * (n_rows + 1) + x_bytes * n_cols + y_bytes * n_rows
 
@@ -120,12 +124,21 @@ def time_each(fn, reps, torch):
     return float(q[0]), float(q[1]), float(q[2])
 
 
-def time_launches(fn, steps, warmup, torch):
+def time_launches(fn, steps, warmup, torch, min_warm_s=0.0):
     """Average seconds per call of fn() over `steps` calls, HIP events on the
-    current stream (the stream every launch goes to)."""
+    current stream (the stream every launch goes to), after `warmup` untimed
+    calls and, when min_warm_s > 0, further untimed calls until that much
+    time has passed (the part's clocks settle only under sustained load, and
+    drop while the host prepares the next input)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if min_warm_s > 0:
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < min_warm_s:
+            for _ in range(10):
+                fn()
+            torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
@@ -313,7 +326,7 @@ def config_lines(torch, log=log) -> dict:
                          ("ring_8192_block32", {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024,
                                                 "ring_words": 8192, "window_block": 32})):
         with spmv.Matrix.from_csr(A, params=params) as M:
-            t = time_launches(lambda: M.apply(x, y), 200, 20, torch)
+            t = time_launches(lambda: M.apply(x, y), 200, 20, torch, WARM_S)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 50, torch, scratch)
             inf = M.info
         c0[name] = {"us": round(t * 1e6, 2), "GBs_L2_resident": round(B / t / 1e9, 1),
@@ -329,13 +342,13 @@ def config_lines(torch, log=log) -> dict:
         y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
         B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
         with spmv.Matrix.from_csr(A) as M:
-            t = time_launches(lambda: M.apply(x, y), 100, 5, torch)
+            t = time_launches(lambda: M.apply(x, y), 100, 5, torch, WARM_S)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
         c1[ordering] = {"ms": round(t * 1e3, 4), "GBs": round(B / t / 1e9, 1),
                         "cold_ms_p10_p50_p90": [round(c10 * 1e3, 4), round(c50 * 1e3, 4), round(c90 * 1e3, 4)],
                         "GBs_cold_p50": round(B / c50 / 1e9, 1), "rows": A.n_rows, "nnz": A.nnz}
         with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL}) as M:
-            t = time_launches(lambda: M.apply(x, y), 100, 5, torch)
+            t = time_launches(lambda: M.apply(x, y), 100, 5, torch, WARM_S)
             pad = M.info["sell_entries"]
         c1[ordering]["sell_ms"] = round(t * 1e3, 4)
         c1[ordering]["sell_GBs"] = round(B / t / 1e9, 1)
@@ -350,9 +363,9 @@ def config_lines(torch, log=log) -> dict:
         for k in (1, 4, 8):
             X = torch.as_tensor(mg.uniform(3 * A.n_cols * k, 6, 1), device="cuda").view(3 * A.n_cols, k)
             Y = torch.empty((3 * A.n_rows, k), dtype=torch.float64, device="cuda")
-            t = time_launches(lambda: M.spmm(X, Y), 20, 3, torch)
+            t = time_launches(lambda: M.spmm(X, Y), 20, 3, torch, WARM_S)
             X32, Y32 = X.float(), Y.float()
-            t32 = time_launches(lambda: M.spmm_f32(X32, Y32), 20, 3, torch)
+            t32 = time_launches(lambda: M.spmm_f32(X32, Y32), 20, 3, torch, WARM_S)
             b64 = A.nnz * (72 + 4) + 4 * (A.n_rows + 1) + 8 * 3 * k * (A.n_cols + A.n_rows)
             b32 = A.nnz * (36 + 4) + 4 * (A.n_rows + 1) + 4 * 3 * k * (A.n_cols + A.n_rows)
             fl = 2 * 9 * A.nnz * k
@@ -461,7 +474,7 @@ def main():
     if not args.no_extras:
         x32 = x.float()
         y32 = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
-        t32 = time_launches(lambda: M.apply_f32(x32, y32), max(10, args.steps // 2), 3, torch)
+        t32 = time_launches(lambda: M.apply_f32(x32, y32), max(10, args.steps // 2), 3, torch, WARM_S)
         B32 = alg_bytes(A.n_rows, A.n_cols, A.nnz, 4, 4, 4)
         extras["fp32_spmv_GBs"] = round(B32 / t32 / 1e9, 2)
         extras["fp32_spmv_ms"] = round(t32 * 1e3, 4)
@@ -471,7 +484,7 @@ def main():
         # HBM ceiling of a plain device copy (1 GiB each way)
         buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(buf)
-        tc = time_launches(lambda: dst.copy_(buf), 10, 2, torch)
+        tc = time_launches(lambda: dst.copy_(buf), 10, 2, torch, WARM_S)
         extras["copy_GBs_read_plus_write"] = round(2 * buf.numel() * 8 / tc / 1e9, 1)
         del buf, dst
         # the same product in the other layouts: CSR row tiles with direct
@@ -479,7 +492,7 @@ def main():
         fm = {}
         for name, prm in (("csr_direct", {"window_mode": spmv.WINDOW_OFF}), ("sell", {"format": spmv.FORMAT_SELL})):
             with spmv.Matrix.from_csr(A, params=prm) as M2:
-                tf = time_launches(lambda: M2.apply(x, y), max(10, args.steps // 2), 3, torch)
+                tf = time_launches(lambda: M2.apply(x, y), max(10, args.steps // 2), 3, torch, WARM_S)
                 fm[name] = {"ms": round(tf * 1e3, 4), "GBs": round(B / tf / 1e9, 1)}
                 if name == "sell":
                     fm[name]["padding"] = round(M2.info["sell_entries"] / A.nnz - 1, 4)
