@@ -196,3 +196,21 @@ def test_bad_requests_are_rejected(pool):
         assert e.value.code == spmv.SPMV_EINVAL
         with pytest.raises(ValueError):
             srv.submit_spmv(0, np.ones((1, pool[0].n_cols + 1)))
+    for bad in ({"n_lanes": 17}, {"n_slots": 65}, {"cg_mode": 7}):
+        with pytest.raises(spmv.SpmvError) as e:
+            spmv.Server(**bad)
+        assert e.value.code == spmv.SPMV_EINVAL
+
+
+def test_one_lane_and_small_rounds(pool):
+    # a single SpMV lane and a tiny round cap: rounds serialize and split, and
+    # results are still the oracle's
+    reqs = [r for r in _requests(pool, 12, 500) if r[0] == "spmv"]
+    with spmv.Server(n_lanes=1, max_round_tiles=8) as srv:
+        for A in pool:
+            srv.add_matrix(A)
+        tickets = [_submit(srv, r) for r in reqs]
+        for r, t in zip(reqs, tickets):
+            out, res = srv.wait(t)
+            _check(pool, r, out, res)
+        assert srv.stats()["rounds"] >= len(reqs)
