@@ -27,6 +27,8 @@
 // vectors; the correction solve A d = r / ||r|| runs CG with the FP32 copy
 // of A, FP32 vectors and FP32 SpMV accumulation, while its dot products and
 // scalar recurrences stay in binary64; x += ||r|| d in binary64.
+// CG_MIXED_FP32V is the same refinement whose correction solve keeps binary64
+// vectors and accumulation and reads only the values in FP32.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -214,14 +216,16 @@ template <typename T> __global__ __launch_bounds__(kBlock) void k_zero(int n, T 
 }
 
 // r32 = r64 / sqrt(rt2)   (unit-norm right-hand side of the correction solve)
-__global__ __launch_bounds__(kBlock) void k_scale_to_f32(int n, float *__restrict__ d, const double *__restrict__ s,
-                                                         const CgState *st) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_residual(int n, T *__restrict__ d, const double *__restrict__ s,
+                                                           const CgState *st) {
     const double inv = 1.0 / sqrt(st->rt2);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = static_cast<float>(s[i] * inv);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = static_cast<T>(s[i] * inv);
 }
 
-// x64 += sqrt(rt2) * d32
-__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *__restrict__ x, const float *__restrict__ d,
+// x64 += sqrt(rt2) * d
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *__restrict__ x, const T *__restrict__ d,
                                                            const CgState *st) {
     const double sc = sqrt(st->rt2);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
@@ -697,6 +701,10 @@ static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol,
     return SPMV_OK;
 }
 
+// Iterative refinement whose correction solves read the FP32 values; T is
+// the correction solve's vector and accumulation type (float, or double for
+// products that round only the stored values).
+template <typename T>
 static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
                     hipStream_t s, double inner_tol, void *pinned) {
     const DevMatrix &M = A->M;
@@ -704,7 +712,7 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
     Buffers B(s);
     // outer (binary64) residual machinery reuses a CgCore for its buffers
     CgCore<double, double> O(M, M.val64, n, s);
-    CgCore<float, float> I(M, M.val32, n, s);
+    CgCore<T, float> I(M, M.val32, n, s);
     int rc = alloc_core(B, O);
     if (!rc) rc = alloc_core(B, I);
     if (rc) return rc;
@@ -724,7 +732,7 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
         if (info) info->rel_residual = 0.0;
         return SPMV_OK;
     }
-    float *rhs = nullptr;  // the correction solve's right-hand side (kept intact)
+    T *rhs = nullptr;  // the correction solve's right-hand side (kept intact)
     HIP_TRY(B.alloc(&rhs, (size_t)n));
     int iters = 0, outer = 0, repl = 0;
     int status = SPMV_ENOTCONV;
@@ -738,12 +746,12 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
         }
         if (iters >= max_iter || outer >= 200) break;
         // correction solve A32 d = r / ||r|| from d = 0; its "b" is I.r after scaling
-        hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.q, O.r, O.st);
-        hipLaunchKernelGGL((k_zero<float>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.x);
-        hipLaunchKernelGGL((k_dot_part<float>), dim3(I.n_wg), dim3(kBlock), 0, s, n, I.chunk, I.q, I.q, I.part_vec);
+        hipLaunchKernelGGL((k_scale_residual<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.q, O.r, O.st);
+        hipLaunchKernelGGL((k_zero<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, I.x);
+        hipLaunchKernelGGL((k_dot_part<T>), dim3(I.n_wg), dim3(kBlock), 0, s, n, I.chunk, I.q, I.q, I.part_vec);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, I.part_vec, I.n_wg, I.st, (int)R_BB);
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_copy<float, float>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, rhs, I.q);
+        hipLaunchKernelGGL((k_copy<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, rhs, I.q);
         int it_inner = 0;
         rc = I.solve(rhs, inner_tol, max_iter - iters, &it_inner, &repl, false);
         iters += it_inner;
@@ -752,7 +760,7 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
             break;
         }
         if (rc != SPMV_OK && rc != SPMV_ENOTCONV) return rc;
-        hipLaunchKernelGGL(k_add_correction, dim3(grid_for(n)), dim3(kBlock), 0, s, n, O.x, I.x, O.st);
+        hipLaunchKernelGGL((k_add_correction<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, O.x, I.x, O.st);
         HIP_TRY(hipGetLastError());
         ++outer;
     }
@@ -764,7 +772,7 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
         info->rel_residual = std::sqrt(O.hst->rt2 / bb);
     }
     if (status == SPMV_ENOTCONV) return fail(status, "mixed CG did not reach tol = %g within %d iterations", tol, max_iter);
-    if (status == SPMV_EBREAK) return fail(status, "CG breakdown in the FP32 correction solve");
+    if (status == SPMV_EBREAK) return fail(status, "CG breakdown in the correction solve");
     return SPMV_OK;
 }
 
@@ -824,10 +832,10 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     if (A->M.block != 1) return fail(SPMV_ENOTSUP, "cg_solve needs a scalar CSR handle");
     if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
     if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
-    if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16)
+    if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16 && mode != CG_MIXED_FP32V)
         return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
-    if (mode == CG_MIXED_FP32 && !A->M.val32)
-        return fail(SPMV_ENOTSUP, "CG_MIXED_FP32 needs the FP32 copy (create with SPMV_VALUES_FP32)");
+    if ((mode == CG_MIXED_FP32 || mode == CG_MIXED_FP32V) && !A->M.val32)
+        return fail(SPMV_ENOTSUP, "mixed-precision CG needs the FP32 copy (create with SPMV_VALUES_FP32)");
     if (mode == CG_PCG_BF16 && !A->M.val16)
         return fail(SPMV_ENOTSUP, "CG_PCG_BF16 needs the BF16 copy (create with SPMV_VALUES_BF16)");
     if (mode == CG_PCG_BF16 && A->M.format != SPMV_FORMAT_CSR)
@@ -857,7 +865,8 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     } else {
         const char *env = std::getenv("SPMV_CG_INNER_TOL");
         double inner = env ? std::atof(env) : 1e-4;
-        rc = cg_mixed(A, b, x, tol, max_iter, info, s, inner, pinned_state);
+        rc = mode == CG_MIXED_FP32 ? cg_mixed<float>(A, b, x, tol, max_iter, info, s, inner, pinned_state)
+                                   : cg_mixed<double>(A, b, x, tol, max_iter, info, s, inner, pinned_state);
     }
     if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
     if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

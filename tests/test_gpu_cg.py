@@ -42,7 +42,7 @@ def cfg0():
     return A, b, ref
 
 
-@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32])
+@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32, spmv.CG_MIXED_FP32V])
 def test_cg_config0_against_oracle(cfg0, mode):
     A, b, ref = cfg0
     tol = 1e-10
@@ -107,6 +107,12 @@ def test_cg_rejects_bad_input():
         with pytest.raises(spmv.SpmvError) as e:
             M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_MIXED_FP32)
         assert e.value.code == spmv.SPMV_ENOTSUP
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_MIXED_FP32V)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=4)
+        assert e.value.code == spmv.SPMV_EINVAL
 
 
 def test_cg_breakdown_on_indefinite_matrix():

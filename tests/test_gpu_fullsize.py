@@ -66,11 +66,12 @@ def test_mesh16m_kernels_and_plans_bitwise(mesh16m):
     assert all(torch.equal(ys[0], y) for y in ys[1:])
 
 
-@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32, spmv.CG_PCG_BF16])
+@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32, spmv.CG_PCG_BF16, spmv.CG_MIXED_FP32V])
 def test_mesh16m_cg_to_1e10(mesh16m, mode):
     A = mesh16m
     b = mg.uniform(A.n_rows, 103, 4)
-    with spmv.Matrix.from_csr(A, fp32=(mode == spmv.CG_MIXED_FP32), bf16=(mode == spmv.CG_PCG_BF16)) as M:
+    fp32 = mode in (spmv.CG_MIXED_FP32, spmv.CG_MIXED_FP32V)
+    with spmv.Matrix.from_csr(A, fp32=fp32, bf16=(mode == spmv.CG_PCG_BF16)) as M:
         x, info = M.cg(torch.as_tensor(b, device=DEV), tol=1e-10, max_iter=5000, mode=mode)
         x = x.cpu().numpy()
     assert info.iterations > 0
