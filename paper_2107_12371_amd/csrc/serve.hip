@@ -154,7 +154,7 @@ struct Server {
     int uploads_in_flight = 0;
     bool wake = false;                    // something the scheduler waits for changed
     std::unordered_map<uint64_t, Request *> all;
-    std::deque<MatrixEntry> mats;  // stable element addresses; read under `mu`
+    std::deque<MatrixEntry> mats;  // stable element addresses; indexed under `mu` only
     BudgetLRU policy;
     std::vector<Slot> slots;
     std::vector<Lane> lanes;
@@ -234,21 +234,25 @@ struct Server {
         const hipError_t dev_err = hipSetDevice(device);
         for (;;) {
             int mid;
+            MatrixEntry *m;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_upload.wait(lk, [&] { return stop || !upload_queue.empty(); });
                 if (upload_queue.empty()) return;
                 mid = upload_queue.front();
                 upload_queue.pop_front();
+                // the element's address is taken under the lock (indexing
+                // reads the deque's block map, which srv_add_matrix may
+                // reallocate); the element itself never moves
+                m = &mats[mid];
             }
-            const MatrixEntry &m = mats[mid];  // deque elements never move
             clear_error();
             (void)hipGetLastError();
             spmv_matrix *h = nullptr;
             const int rc = dev_err != hipSuccess ? hip_fail(dev_err, "server upload thread: hipSetDevice")
-                                                 : create_handle(m, &h);
+                                                 : create_handle(*m, &h);
             std::lock_guard<std::mutex> lk(mu);
-            MatrixEntry &e = mats[mid];
+            MatrixEntry &e = *m;
             e.uploading = false;
             if (rc == SPMV_OK) {
                 e.dev = h;

@@ -14,6 +14,8 @@
 #include "spmv.h"
 
 namespace {
+constexpr int kCopies = 8;
+
 struct Banded {
     int n = 0;
     std::vector<int32_t> row_ptr, col;
@@ -54,12 +56,16 @@ int main(int argc, char **argv) {
             std::printf("srv_create failed: %s\n", spmv_last_error());
             return 2;
         }
-        for (const Banded &m : pool) {
-            int32_t id = -1;
-            if (srv_add_matrix(S, m.n, m.n, (int64_t)m.col.size(), m.row_ptr.data(), m.col.data(), m.val.data(),
-                               &id) != SPMV_OK) {
-                std::printf("srv_add_matrix failed: %s\n", spmv_last_error());
-                return 2;
+        // each matrix is registered kCopies times (matrix id = copy * 6 + i),
+        // so registration goes on while preloads of earlier ids run
+        for (int copy = 0; copy < kCopies; ++copy) {
+            for (const Banded &m : pool) {
+                int32_t id = -1;
+                if (srv_add_matrix(S, m.n, m.n, (int64_t)m.col.size(), m.row_ptr.data(), m.col.data(), m.val.data(),
+                                   &id) != SPMV_OK) {
+                    std::printf("srv_add_matrix failed: %s\n", spmv_last_error());
+                    return 2;
+                }
             }
         }
         if (rep % 3 == 1) (void)srv_drain(S);  // preloads (if any) finish first
@@ -67,8 +73,8 @@ int main(int argc, char **argv) {
         std::vector<std::vector<double>> in(n_req), out(n_req);
         std::vector<uint64_t> ticket(n_req);
         for (int t = 0; t < n_req; ++t) {
-            const int mid = (int)(rng() % (rep % 4 == 3 ? 4 : pool.size()));
-            const int n = pool[mid].n;
+            const int mid = (int)(rng() % (rep % 4 == 3 ? 4 : kCopies * pool.size()));
+            const int n = pool[mid % pool.size()].n;
             int rc;
             if (rng() % 2) {
                 const int k = 1 + (int)(rng() % 8);

@@ -1,6 +1,7 @@
 """The request server's host code on the CPU: the library's objects linked
 against a mock HIP runtime (tests/host_mock/mock_hip.cpp) under
-AddressSanitizer, driven with the serving tests' request mixes.
+AddressSanitizer and ThreadSanitizer, driven with the serving tests' request
+mixes.
 
 The regression case: when a matrix upload fails, the request reports the
 error and the matrix must not stay marked resident without a device handle
@@ -22,24 +23,23 @@ HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-@pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def _build(tmp_path_factory, sanitizer):
     if not (os.path.exists(HIPCC) and os.path.exists(CLANG)):
         pytest.skip("ROCm compilers not found")
-    out = tmp_path_factory.mktemp("host_mock")
+    out = tmp_path_factory.mktemp("host_mock_" + sanitizer)
     inc = [f"-I{ROOT}/include", f"-I{CSRC}"]
     jobs = []
     for f in ("serve", "cg", "api", "spmv_kernels", "sell", "bsr"):
         jobs.append([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", *inc, "--offload-arch=gfx950",
                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                     "-Xarch_host", "-fsanitize=address", "-c", os.path.join(CSRC, f + ".hip"),
+                     "-Xarch_host", f"-fsanitize={sanitizer}", "-c", os.path.join(CSRC, f + ".hip"),
                      "-o", str(out / (f + ".o"))])
-    jobs.append([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", "-Xarch_host", "-fsanitize=address", "-c",
+    jobs.append([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", "-Xarch_host", f"-fsanitize={sanitizer}", "-c",
                  os.path.join(MOCK, "mock_hip.cpp"), "-o", str(out / "mock_hip.o")])
     for f in ("plan", "sell_plan"):
-        jobs.append([CLANG, "-O1", "-g", "-std=c++17", "-fPIC", "-fsanitize=address", *inc, "-c",
+        jobs.append([CLANG, "-O1", "-g", "-std=c++17", "-fPIC", f"-fsanitize={sanitizer}", *inc, "-c",
                      os.path.join(CSRC, f + ".cpp"), "-o", str(out / (f + ".o"))])
-    jobs.append([CLANG, "-O1", "-g", "-std=c++17", "-fsanitize=address", *inc, "-c",
+    jobs.append([CLANG, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizer}", *inc, "-c",
                  os.path.join(MOCK, "server_driver.cpp"), "-o", str(out / "server_driver.o")])
     procs = [subprocess.Popen(j, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True) for j in jobs]
     for j, p in zip(jobs, procs):
@@ -47,20 +47,33 @@ def driver(tmp_path_factory):
         assert p.returncode == 0, f"{' '.join(j)}\n{log}"
     objs = sorted(str(p) for p in out.glob("*.o"))
     exe = str(out / "server_driver")
-    r = subprocess.run([CLANG, "-fsanitize=address", "-g", "-o", exe, *objs, "-lpthread"],
+    r = subprocess.run([CLANG, f"-fsanitize={sanitizer}", "-g", "-o", exe, *objs, "-lpthread"],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
+    return exe, out
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    exe, out = _build(tmp_path_factory, "address")
+    yield exe
+    shutil.rmtree(out, ignore_errors=True)
+
+
+@pytest.fixture(scope="module")
+def driver_tsan(tmp_path_factory):
+    exe, out = _build(tmp_path_factory, "thread")
     yield exe
     shutil.rmtree(out, ignore_errors=True)
 
 
 def run(exe, reps, fail_every=None):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", TSAN_OPTIONS="halt_on_error=1")
     env.pop("MOCK_FAIL_COPY_EVERY", None)
     if fail_every:
         env["MOCK_FAIL_COPY_EVERY"] = str(fail_every)
     r = subprocess.run([exe, str(reps)], capture_output=True, text=True, env=env, timeout=300)
-    assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "AddressSanitizer" not in r.stderr and "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, f"rc={r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
     m = re.search(r"summary completed=(\d+) failed=(\d+) upload_failed=(\d+)", r.stdout)
     assert m, r.stdout
@@ -81,3 +94,12 @@ def test_failed_uploads_report_errors_and_do_not_crash(driver, every):
     assert upload_failed > 0
     if every >= 7:
         assert completed > 0
+
+
+@pytest.mark.parametrize("every", [None, 7])
+def test_server_threads_race_free(driver_tsan, every):
+    # ThreadSanitizer over the same mixes, matrices registered while earlier
+    # ones are preloaded (the registration list grows under the upload thread)
+    completed, failed, upload_failed = run(driver_tsan, 6, every)
+    assert completed > 0
+    assert (upload_failed > 0) == (every is not None)
