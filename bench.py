@@ -498,6 +498,17 @@ def main():
                     fm[name]["padding"] = round(M2.info["sell_entries"] / A.nnz - 1, 4)
         extras["formats_16M"] = fm
         log(f"formats: {fm}")
+        # k = 8 right-hand sides in one product (values read once) vs 8 products
+        k = 8
+        Xk = torch.as_tensor(mg.uniform(A.n_cols * k, mg.seed_for(2), 5), device="cuda").view(A.n_cols, k)
+        Yk = torch.empty((A.n_rows, k), dtype=torch.float64, device="cuda")
+        tk = time_launches(lambda: M.spmm(Xk, Yk), 20, 3, torch, WARM_S)
+        Bk = A.nnz * 12 + 4 * (A.n_rows + 1) + 8 * k * (A.n_cols + A.n_rows)
+        extras["spmm_k8"] = {"ms": round(tk * 1e3, 4), "GBs": round(Bk / tk / 1e9, 1),
+                             "GFLOPs": round(2 * k * A.nnz / tk / 1e9, 1),
+                             "vs_8_single_products": round(8 * t_step / tk, 3)}
+        log(f"SpMM k=8: {extras['spmm_k8']}")
+        del Xk, Yk
         b = torch.as_tensor(mg.uniform(A.n_rows, mg.seed_for(2), 2), device="cuda")
         for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32), ("pcg_bf16", spmv.CG_PCG_BF16),
                            ("mixed_f32v", spmv.CG_MIXED_FP32V)):

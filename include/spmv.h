@@ -204,6 +204,20 @@ int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int64_t nnz_blo
                      uint32_t flags, spmv_matrix **out);
 
 /*
+ * spmv_spmm: Y = A X for a scalar CSR handle with k >= 1 right-hand sides
+ * (paper Sec. 2: the product of the solver, here applied to k vectors at
+ * once, e.g. the k vectors of one serving request).
+ *   X  device double[n_cols * k], row-major (the k values of one row of X
+ *      are contiguous)
+ *   Y  device double[n_rows * k], row-major, fully overwritten
+ * The values are read once for all k columns.  Every output is summed as
+ * spmv_apply sums a row, so column j of Y equals spmv_apply of column j of
+ * X bit for bit.  X and Y must not overlap (SPMV_EINVAL), k >= 1.
+ * SPMV_ENOTSUP on block-CSR handles (bsr3_spmm) and SELL-format handles.
+ */
+int spmv_spmm(const spmv_matrix *A, int32_t k, const double *X, double *Y, void *stream);
+
+/*
  * bsr3_spmm: Y = A X for a block-CSR handle with k >= 1 right-hand sides.
  *   X  device double[(3 n_block_cols) * k], row-major (the k values of one
  *      scalar row are contiguous)

@@ -33,7 +33,7 @@ CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V = 0, 1, 2, 3
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
     "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
-    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect",
+    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect", "spmv_spmm",
 ]
 
 
@@ -96,7 +96,7 @@ def lib():
             getattr(L, f).argtypes = [vp, vp, vp, vp]
         L.spmv_create_bsr3.restype = ctypes.c_int
         L.spmv_create_bsr3.argtypes = [i32, i32, i64, vp, vp, vp, u32, ctypes.POINTER(vp)]
-        for f in ("bsr3_spmm", "bsr3_spmm_f32"):
+        for f in ("bsr3_spmm", "bsr3_spmm_f32", "spmv_spmm"):
             getattr(L, f).restype = ctypes.c_int
             getattr(L, f).argtypes = [vp, i32, vp, vp, vp]
         L.cg_solve.restype = ctypes.c_int
@@ -280,9 +280,12 @@ class Matrix:
         return self
 
     def spmm(self, X, Y=None, stream=None):
-        """Y = A X for a block-CSR handle, X of shape (3 n_block_cols, k) (``bsr3_spmm``)."""
+        """Y = A X with k right-hand sides, X of shape (n_cols, k) row-major:
+        ``bsr3_spmm`` for block-CSR handles (n_cols = 3 n_block_cols),
+        ``spmv_spmm`` for scalar CSR handles."""
         torch = _torch()
-        return self._spmm("bsr3_spmm", X, Y, torch.float64, stream)
+        fn = "bsr3_spmm" if self.info["block_size"] == 3 else "spmv_spmm"
+        return self._spmm(fn, X, Y, torch.float64, stream)
 
     def spmm_f32(self, X, Y=None, stream=None):
         torch = _torch()

@@ -1,6 +1,7 @@
 // C ABI: matrix handles (create / destroy / info) and the product entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -10,6 +11,7 @@
 #include "bsr.h"
 #include "launch.h"
 #include "matrix.h"
+#include "spmm.h"
 
 namespace spmvlib {
 
@@ -314,6 +316,11 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         if (!rc && !P.lidx12.empty()) rc = U.put(&M.lidx12, P.lidx12.data(), P.lidx12.size(), 0);
         else if (!rc) rc = U.put(&M.lidx, P.lidx.data(), P.lidx.size(), nz_pad);
     }
+    A->n_win_tiles = (int32_t)P.win_list.size();
+    for (int32_t sg = 0; sg < P.n_seg(); ++sg)
+        if (P.seg_kind[sg] != SEG_LONG)
+            A->max_tile_entries = std::max(A->max_tile_entries,
+                                           row_ptr[P.seg_bound[sg + 1]] - row_ptr[P.seg_bound[sg]]);
     if (!rc) prepare_launch_queries();
     if (!rc && M.n_blk) {
         hipError_t e2 = prepare_window_kernels();
@@ -363,6 +370,27 @@ extern "C" int spmv_destroy(spmv_matrix *A) {
     }
     delete A;
     return rc;
+}
+
+extern "C" int spmv_spmm(const spmv_matrix *A, int32_t k, const double *X, double *Y, void *stream) {
+    clear_error();
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (A->M.block != 1) return fail(SPMV_ENOTSUP, "spmv_spmm needs a scalar CSR handle (use bsr3_spmm)");
+    if (A->M.format != SPMV_FORMAT_CSR) return fail(SPMV_ENOTSUP, "spmv_spmm needs a CSR-format handle");
+    if (k < 1) return fail(SPMV_EINVAL, "k = %d must be >= 1", k);
+    if ((int64_t)A->max_tile_entries * 12 > 65536)
+        return fail(SPMV_ENOTSUP, "tiles of %d entries exceed the product's LDS staging", A->max_tile_entries);
+    if (A->M.n_rows == 0) return SPMV_OK;
+    if (!Y) return fail(SPMV_EINVAL, "Y is NULL");
+    if (A->M.nnz > 0 && !X) return fail(SPMV_EINVAL, "X is NULL");
+    if (X && overlaps(X, sizeof(double) * (size_t)k * (size_t)A->M.n_cols, Y,
+                      sizeof(double) * (size_t)k * (size_t)A->M.n_rows))
+        return fail(SPMV_EINVAL, "X and Y overlap");
+    DeviceGuard g(A->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
+    const hipError_t e = launch_spmm(A, X, Y, k, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "spmm launch");
+    return SPMV_OK;
 }
 
 extern "C" int spmv_get_info(const spmv_matrix *A, spmv_info *info) {

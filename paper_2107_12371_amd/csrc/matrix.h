@@ -14,6 +14,8 @@ struct spmv_matrix {
     int device = 0;
     int64_t bytes = 0;
     std::vector<void *> allocs;
+    int32_t n_win_tiles = 0;       // ring-window tiles (all blocks)
+    int32_t max_tile_entries = 0;  // stored entries of the largest row tile
 };
 
 namespace spmvlib {

@@ -1,0 +1,120 @@
+// Y = A X for a scalar CSR handle with k right-hand sides, X and Y row-major
+// (the k values of one row contiguous), so one gather of X's row c brings
+// all the columns a lane works on.
+//
+// One workgroup per row tile of the handle's plan (direct, compact-window
+// and ring tiles alike; only the tile's rows and stored entries are used).
+// The tile's values and column indices are staged in LDS with coalesced
+// loads; then the lanes take (row, column group) tasks: a lane walks its
+// row's entries in ascending order, gathers KC adjacent values of row c of
+// X, and adds the rounded products one by one starting from zero, exactly
+// as the single-vector product sums a row, so column j of Y equals the
+// single-vector product of column j of X bit for bit.  A row longer than a
+// tile gets one workgroup per (row, column) with the lane-strided partial
+// sums and the fixed-shape reduction of the single-vector long-row kernel.
+// The values are read once for all k columns, which is what the batched
+// requests of a serving workload need.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+#include "spmm.h"
+
+namespace spmvlib {
+
+__device__ __forceinline__ double add_rounded_product(double sum, double a, double b) {
+#pragma clang fp contract(off)
+    const double p = a * b;
+    return sum + p;
+}
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_spmm_tiles(const TileDesc *__restrict__ desc, int n_list, int per_xcd,
+                                                       const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val, const double *__restrict__ X,
+                                                       double *__restrict__ Y, int k, int cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sv = reinterpret_cast<double *>(smem);
+    int32_t *sc = reinterpret_cast<int32_t *>(sv + cap);
+    const int b = blockIdx.x;
+    const int li = per_xcd ? (b & 7) * per_xcd + (b >> 3) : b;
+    if (li >= n_list) return;
+    const TileDesc d = desc[li];
+    const int n = min(d.e - d.s, cap);  // the host sizes cap to the largest tile
+    for (int i = (int)threadIdx.x; i < n; i += kBlock) {
+        sv[i] = val[d.s + i];
+        sc[i] = col[d.s + i];
+    }
+    __syncthreads();
+    const int groups = (k + KC - 1) / KC;
+    const int tasks = (d.r1 - d.r0) * groups;
+    for (int t = (int)threadIdx.x; t < tasks; t += kBlock) {
+        const int r = d.r0 + t / groups;
+        const int j0 = (t % groups) * KC;
+        const int a = row_ptr[r] - d.s, z = min(row_ptr[r + 1] - d.s, n);
+        double acc[KC];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[j] = 0.0;
+        for (int q = a; q < z; ++q) {
+            const double v = sv[q];
+            const double *__restrict__ xr = X + (size_t)sc[q] * k + j0;
+#pragma unroll
+            for (int j = 0; j < KC; ++j)
+                if (j0 + j < k) acc[j] = add_rounded_product(acc[j], v, xr[j]);
+        }
+        double *__restrict__ yr = Y + (size_t)r * k + j0;
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+            if (j0 + j < k) yr[j] = acc[j];
+    }
+}
+
+// Row d.r0 (longer than a tile), column blockIdx.y.
+__global__ __launch_bounds__(kBlock) void k_spmm_long(const TileDesc *__restrict__ desc,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val, const double *__restrict__ X,
+                                                      double *__restrict__ Y, int k) {
+    __shared__ double sh[kBlock / kWave];
+    const TileDesc d = desc[blockIdx.x];
+    const int j = (int)blockIdx.y;
+    double acc = 0.0;
+    for (int q = d.s + (int)threadIdx.x; q < d.e; q += kBlock) acc += val[q] * X[(size_t)col[q] * k + j];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) Y[(size_t)d.r0 * k + j] = t;
+}
+
+template <int KC>
+static void launch_tiles(const TileDesc *desc, int n, bool remap, const DevMatrix &M, const double *X, double *Y,
+                         int k, int cap, hipStream_t st) {
+    int grid = n, per_xcd = 0;
+    if (remap && n >= 16) {
+        per_xcd = (n + 7) / 8;
+        grid = 8 * per_xcd;
+    }
+    const size_t lds = (size_t)cap * (sizeof(double) + sizeof(int32_t));
+    hipLaunchKernelGGL((k_spmm_tiles<KC>), dim3(grid), dim3(kBlock), lds, st, desc, n, per_xcd, M.row_ptr, M.col,
+                       M.val64, X, Y, k, cap);
+}
+
+hipError_t launch_spmm(const spmv_matrix *A, const double *X, double *Y, int k, hipStream_t st) {
+    const DevMatrix &M = A->M;
+    const int cap = std::max(A->max_tile_entries, 1);
+    const struct {
+        const TileDesc *desc;
+        int n;
+    } lists[3] = {{M.stream_desc, M.n_stream}, {M.cwin_desc, M.n_cwin}, {M.win_desc, A->n_win_tiles}};
+    for (const auto &l : lists) {
+        if (l.n <= 0) continue;
+        if (k >= 8) launch_tiles<8>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
+        else if (k >= 4) launch_tiles<4>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
+        else if (k >= 2) launch_tiles<2>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
+        else launch_tiles<1>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
+    }
+    if (M.n_long > 0)
+        hipLaunchKernelGGL(k_spmm_long, dim3(M.n_long, k), dim3(kBlock), 0, st, M.long_desc, M.col, M.val64, X, Y, k);
+    return hipGetLastError();
+}
+
+}  // namespace spmvlib

@@ -10,6 +10,8 @@ derived from their arithmetic:
   BF16 values, FP32 x/acc:       (2^-8 + (m + 1) * 2^-24) * bound
 with m the row length and a 1% slack for the second-order terms.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -422,3 +424,71 @@ def test_bsr3_rejects_misuse():
         with pytest.raises(spmv.SpmvError) as e:
             M.spmm(torch.ones((C.n_cols, 1), dtype=torch.float64, device=DEV))
         assert e.value.code == spmv.SPMV_ENOTSUP
+
+
+SPMM_PLANS = {
+    "auto": {},
+    "direct1024": {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 1024},
+    "ring1024": {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024},
+    "tiles4096": {"tile_nnz": 4096},
+}
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 13])
+@pytest.mark.parametrize("plan", list(SPMM_PLANS))
+def test_spmm_columns_equal_spmv_bitwise(plan, k):
+    # irregular CSR with empty rows, rows longer than any tile, duplicates,
+    # unsorted columns and NaN/Inf in X: every column of the k-column product
+    # equals the single-vector product bit for bit and meets the oracle bound
+    A = mg.random_csr(3000, 2500, seed=61, mean_len=9.0, empty_frac=0.1, dense_rows=3, duplicates=True,
+                      unsorted=True)
+    X = mg.uniform(A.n_cols * k, 62 + k, 0).reshape(A.n_cols, k)
+    X[5, 0] = np.nan
+    X[77, k - 1] = np.inf
+    with spmv.Matrix.from_csr(A, params=SPMM_PLANS[plan]) as M:
+        Xd = torch.as_tensor(X, device=DEV)
+        Y = M.spmm(Xd).cpu().numpy()
+        for j in range(k):
+            y = M.apply(torch.as_tensor(np.ascontiguousarray(X[:, j]), device=DEV)).cpu().numpy()
+            assert np.array_equal(Y[:, j], y, equal_nan=True), (plan, k, j)
+            y_ref, bound = oracle.spmv(A, X[:, j])
+            assert oracle.spmv_accept(Y[:, j], y_ref, bound).all()
+
+
+def test_spmm_mesh_compact_windows_and_ring():
+    A = mg.config0()
+    k = 8
+    X = mg.uniform(A.n_cols * k, 63, 0).reshape(A.n_cols, k)
+    for params in ({"tile_nnz": 2048}, {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024}):
+        with spmv.Matrix.from_csr(A, params=params) as M:
+            assert M.info["n_window_tiles"] > 0
+            Y = M.spmm(torch.as_tensor(X, device=DEV)).cpu().numpy()
+            for j in range(k):
+                y = M.apply(torch.as_tensor(np.ascontiguousarray(X[:, j]), device=DEV)).cpu().numpy()
+                assert np.array_equal(Y[:, j], y)
+    Ad = mg.config0(dyadic=True)
+    Xd = np.stack([mg.dyadic_x(Ad.n_cols, seed=70 + j) for j in range(4)], axis=1)
+    with spmv.Matrix.from_csr(Ad) as M:
+        Y = M.spmm(torch.as_tensor(Xd, device=DEV)).cpu().numpy()
+    for j in range(4):
+        assert np.array_equal(Y[:, j], oracle.spmv(Ad, Xd[:, j])[0])
+
+
+def test_spmm_rejects_misuse():
+    A = mg.config0()
+    L = spmv.lib()
+    X = torch.ones((A.n_cols, 2), dtype=torch.float64, device=DEV)
+    Y = torch.empty((A.n_rows, 2), dtype=torch.float64, device=DEV)
+    with spmv.Matrix.from_csr(A) as M:
+        assert L.spmv_spmm(M.handle, 0, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), None) == \
+            spmv.SPMV_EINVAL
+        assert L.spmv_spmm(M.handle, 2, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), None) == \
+            spmv.SPMV_EINVAL
+    with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL}) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.spmm(X)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+    B = mg.config3(nx=6, ny=5, nz=4)
+    with spmv.Matrix.from_csr(B) as M:
+        assert L.spmv_spmm(M.handle, 2, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), None) == \
+            spmv.SPMV_ENOTSUP

@@ -14,7 +14,12 @@ import re
 import shutil
 import subprocess
 
+import importlib
+
 import pytest
+
+# the library's source lists
+LIB_SOURCES = importlib.import_module("paper_2107_12371_amd._build")
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2107_12371_amd", "csrc")
@@ -29,14 +34,14 @@ def _build(tmp_path_factory, sanitizer):
     out = tmp_path_factory.mktemp("host_mock_" + sanitizer)
     inc = [f"-I{ROOT}/include", f"-I{CSRC}"]
     jobs = []
-    for f in ("serve", "cg", "api", "spmv_kernels", "sell", "bsr"):
+    for f in (os.path.splitext(src)[0] for src in LIB_SOURCES.HIP_SOURCES):
         jobs.append([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", *inc, "--offload-arch=gfx950",
                      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                      "-Xarch_host", f"-fsanitize={sanitizer}", "-c", os.path.join(CSRC, f + ".hip"),
                      "-o", str(out / (f + ".o"))])
     jobs.append([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", "-Xarch_host", f"-fsanitize={sanitizer}", "-c",
                  os.path.join(MOCK, "mock_hip.cpp"), "-o", str(out / "mock_hip.o")])
-    for f in ("plan", "sell_plan"):
+    for f in (os.path.splitext(src)[0] for src in LIB_SOURCES.CXX_SOURCES):
         jobs.append([CLANG, "-O1", "-g", "-std=c++17", "-fPIC", f"-fsanitize={sanitizer}", *inc, "-c",
                      os.path.join(CSRC, f + ".cpp"), "-o", str(out / (f + ".o"))])
     jobs.append([CLANG, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizer}", *inc, "-c",
