@@ -65,6 +65,12 @@ typedef struct spmv_matrix spmv_matrix;
 #define SPMV_VALUES_FP32 0x1u   /* also keep an FP32 copy of the values */
 #define SPMV_VALUES_BF16 0x2u   /* also keep a BF16 copy of the values */
 #define SPMV_NO_XCD_REMAP 0x4u  /* keep launch order = tile order (no XCD grouping) */
+#define SPMV_DEVICE_PTRS 0x8u   /* row_ptr, col_idx and values are device (or managed)
+                                   arrays of the current device, holding n_rows + 1, nnz
+                                   and nnz elements (9 nnz_blocks values for block CSR);
+                                   they are copied to the host for the plan, then
+                                   uploaded as host arrays are.  A pointer the runtime
+                                   does not know as device memory is SPMV_EINVAL */
 
 /* x-window policy.  The GPU counterparts of the paper's vector cache
  * (Sec. 5.1): x words a tile needs are staged in LDS with contiguous loads
@@ -143,12 +149,14 @@ typedef struct spmv_info {
  * everything the products need to device memory.
  *   n_rows, n_cols  >= 0
  *   nnz             stored entries, 0 <= nnz <= 2^31 - 64
- *   row_ptr         host int32[n_rows + 1]: row_ptr[0] = 0, non-decreasing,
+ *   row_ptr         int32[n_rows + 1]: row_ptr[0] = 0, non-decreasing,
  *                   row_ptr[n_rows] = nnz
- *   col_idx         host int32[nnz], each in [0, n_cols); unsorted columns and
+ *   col_idx         int32[nnz], each in [0, n_cols); unsorted columns and
  *                   duplicate (row, col) entries are accepted (all are summed)
- *   values          host double[nnz] (any values, including NaN/Inf)
- *   flags           SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP
+ *   values          double[nnz] (any values, including NaN/Inf)
+ *                   (host arrays, or device arrays with SPMV_DEVICE_PTRS)
+ *   flags           SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP |
+ *                   SPMV_DEVICE_PTRS
  *   params          NULL for defaults
  *   out             receives the new handle (NULL on failure)
  * The caller keeps ownership of its arrays.  The device is the current HIP
@@ -191,10 +199,12 @@ int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream
  * produced by coupled three-component operators on a mesh (velocity u, v, w
  * per cell; paper Sec. 2: row i = cell i, its blocks = neighbour cells).
  *   n_block_rows, n_block_cols >= 0; nnz_blocks stored blocks
- *   brow_ptr   host int32[n_block_rows + 1] (same rules as CSR row_ptr)
- *   bcol_idx   host int32[nnz_blocks] in [0, n_block_cols)
- *   bvalues    host double[9 * nnz_blocks], each block row-major
- *   flags      SPMV_VALUES_FP32 keeps an FP32 copy; SPMV_NO_XCD_REMAP
+ *   brow_ptr   int32[n_block_rows + 1] (same rules as CSR row_ptr)
+ *   bcol_idx   int32[nnz_blocks] in [0, n_block_cols)
+ *   bvalues    double[9 * nnz_blocks], each block row-major
+ *              (host arrays, or device arrays with SPMV_DEVICE_PTRS)
+ *   flags      SPMV_VALUES_FP32 keeps an FP32 copy; SPMV_NO_XCD_REMAP;
+ *              SPMV_DEVICE_PTRS
  * The scalar matrix is (3 n_block_rows) x (3 n_block_cols).  spmv_apply and
  * spmv_apply_f32 on such a handle compute the k = 1 product; cg_solve,
  * spmv_apply_f32v and spmv_apply_bf16 return SPMV_ENOTSUP.

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libspmv_gfx950.so")
 
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE = 0, -1, -2, -3
 SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
-SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP = 0x1, 0x2, 0x4
+SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP, SPMV_DEVICE_PTRS = 0x1, 0x2, 0x4, 0x8
 WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
 FORMAT_CSR, FORMAT_SELL = 0, 1
 CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V = 0, 1, 2, 3
@@ -254,6 +254,33 @@ class Matrix:
                              _params(params), ctypes.byref(h)), "spmv_create")
         self._h = h
         self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, int(ci.shape[0])
+
+    @classmethod
+    def from_device_csr(cls, n_rows: int, n_cols: int, row_ptr, col_idx, values, *,
+                        fp32: bool = False, bf16: bool = False, xcd_remap: bool = True,
+                        params: dict | None = None) -> "Matrix":
+        """A resident CSR matrix from device tensors (int32 row_ptr and col_idx,
+        float64 values, contiguous, on the current device) via
+        ``SPMV_DEVICE_PTRS``."""
+        torch = _torch()
+        for t, dt, name in ((row_ptr, torch.int32, "row_ptr"), (col_idx, torch.int32, "col_idx"),
+                            (values, torch.float64, "values")):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+        if row_ptr.numel() != n_rows + 1 or values.numel() != col_idx.numel():
+            raise ValueError("row_ptr needs n_rows + 1 entries and values one per column index")
+        nnz = int(col_idx.numel())
+        flags = SPMV_DEVICE_PTRS | (SPMV_VALUES_FP32 if fp32 else 0) | (SPMV_VALUES_BF16 if bf16 else 0)
+        flags |= 0 if xcd_remap else SPMV_NO_XCD_REMAP
+        h = ctypes.c_void_p()
+        _check(lib().spmv_create(n_rows, n_cols, nnz, ctypes.c_void_p(row_ptr.data_ptr()),
+                                 ctypes.c_void_p(col_idx.data_ptr() if nnz else None),
+                                 ctypes.c_void_p(values.data_ptr() if nnz else None), flags,
+                                 _params(params), ctypes.byref(h)), "spmv_create")
+        self = cls.__new__(cls)
+        self._h = h
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
+        return self
 
     @classmethod
     def from_csr(cls, A, **kw) -> "Matrix":

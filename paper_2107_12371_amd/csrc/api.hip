@@ -130,6 +130,29 @@ static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, voi
     return SPMV_OK;
 }
 
+// SPMV_DEVICE_PTRS: copies n elements of a caller's device array into a
+// host vector (the plan is built on the host).  A pointer that the runtime
+// does not know as device or managed memory is SPMV_EINVAL.
+template <typename T> static int fetch_device(const T *src, size_t n, std::vector<T> &dst, const char *what) {
+    dst.resize(n);
+    if (n == 0) return SPMV_OK;
+    if (!src) return fail(SPMV_EINVAL, "%s is NULL", what);
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, src) != hipSuccess ||
+        (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        return fail(SPMV_EINVAL, "%s is not device memory (SPMV_DEVICE_PTRS)", what);
+    }
+    std::lock_guard<std::mutex> lock(capture_gate());
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (s) (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return SPMV_OK;
+}
+
 // A sliced-ELLPACK handle (SPMV_FORMAT_SELL): slices and long rows in one
 // column array and one array per value precision.
 static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
@@ -233,8 +256,19 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     clear_error();
     if (!out) return fail(SPMV_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags & ~(SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP))
+    if (flags & ~(SPMV_VALUES_FP32 | SPMV_VALUES_BF16 | SPMV_NO_XCD_REMAP | SPMV_DEVICE_PTRS))
         return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & SPMV_DEVICE_PTRS) {
+        if (n_rows < 0 || nnz < 0) return fail(SPMV_EINVAL, "n_rows = %d, nnz = %lld", n_rows, (long long)nnz);
+        std::vector<int32_t> rp, ci;
+        std::vector<double> va;
+        int rc = fetch_device(row_ptr, (size_t)n_rows + 1, rp, "row_ptr");
+        if (!rc) rc = fetch_device(col_idx, (size_t)nnz, ci, "col_idx");
+        if (!rc) rc = fetch_device(values, (size_t)nnz, va, "values");
+        if (rc) return rc;
+        return spmv_create(n_rows, n_cols, nnz, rp.data(), nnz ? ci.data() : nullptr, nnz ? va.data() : nullptr,
+                           flags & ~SPMV_DEVICE_PTRS, params, out);
+    }
     int rc = validate_csr(n_rows, n_cols, nnz, row_ptr, col_idx);
     if (rc) return rc;
     if (nnz > 0 && !values) return fail(SPMV_EINVAL, "values is NULL with nnz > 0");
@@ -457,8 +491,21 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     clear_error();
     if (!out) return fail(SPMV_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP)) return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP | SPMV_DEVICE_PTRS))
+        return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
     if (nnz_blocks > (int64_t)(INT32_MAX / 9) - 64) return fail(SPMV_EINVAL, "too many blocks");
+    if (flags & SPMV_DEVICE_PTRS) {
+        if (n_block_rows < 0 || nnz_blocks < 0)
+            return fail(SPMV_EINVAL, "n_block_rows = %d, nnz_blocks = %lld", n_block_rows, (long long)nnz_blocks);
+        std::vector<int32_t> rp, ci;
+        std::vector<double> va;
+        int rc = fetch_device(brow_ptr, (size_t)n_block_rows + 1, rp, "brow_ptr");
+        if (!rc) rc = fetch_device(bcol_idx, (size_t)nnz_blocks, ci, "bcol_idx");
+        if (!rc) rc = fetch_device(bvalues, 9 * (size_t)nnz_blocks, va, "bvalues");
+        if (rc) return rc;
+        return spmv_create_bsr3(n_block_rows, n_block_cols, nnz_blocks, rp.data(), nnz_blocks ? ci.data() : nullptr,
+                                nnz_blocks ? va.data() : nullptr, flags & ~SPMV_DEVICE_PTRS, out);
+    }
     int rc = validate_csr(n_block_rows, n_block_cols, nnz_blocks, brow_ptr, bcol_idx);
     if (rc) return rc;
     if ((int64_t)n_block_rows * 3 > INT32_MAX || (int64_t)n_block_cols * 3 > INT32_MAX)

@@ -493,3 +493,56 @@ def test_spmm_rejects_misuse():
     with spmv.Matrix.from_csr(B) as M:
         assert L.spmv_spmm(M.handle, 2, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), None) == \
             spmv.SPMV_ENOTSUP
+
+
+def test_create_from_device_arrays():
+    # a handle made from device arrays (SPMV_DEVICE_PTRS) is the handle made
+    # from the same host arrays: bitwise equal products and the same plan
+    A = mg.random_csr(4000, 3500, seed=81, mean_len=8.0, empty_frac=0.1, dense_rows=2, duplicates=True,
+                      unsorted=True)
+    x = torch.as_tensor(mg.uniform(A.n_cols, 82, 0), device=DEV)
+    rp = torch.as_tensor(A.row_ptr, device=DEV)
+    ci = torch.as_tensor(A.col_idx, device=DEV)
+    va = torch.as_tensor(A.values, device=DEV)
+    with spmv.Matrix.from_csr(A, fp32=True) as H, \
+            spmv.Matrix.from_device_csr(A.n_rows, A.n_cols, rp, ci, va, fp32=True) as D:
+        assert np.array_equal(H.apply(x).cpu().numpy(), D.apply(x).cpu().numpy())
+        assert np.array_equal(H.apply_f32(x.float()).cpu().numpy(), D.apply_f32(x.float()).cpu().numpy())
+        assert {k: v for k, v in H.info.items() if k != "device_bytes"} == \
+            {k: v for k, v in D.info.items() if k != "device_bytes"}
+    B = mg.config3(nx=6, ny=5, nz=4)
+    Xb = torch.as_tensor(mg.uniform(B.n_cols * 3 * 2, 83, 0), device=DEV).view(3 * B.n_cols, 2)
+    L = spmv.lib()
+    h = ctypes.c_void_p()
+    brp, bci = torch.as_tensor(B.row_ptr, device=DEV), torch.as_tensor(B.col_idx, device=DEV)
+    bva = torch.as_tensor(np.ascontiguousarray(B.values).reshape(-1), device=DEV)
+    assert L.spmv_create_bsr3(B.n_rows, B.n_cols, B.nnz, ctypes.c_void_p(brp.data_ptr()),
+                              ctypes.c_void_p(bci.data_ptr()), ctypes.c_void_p(bva.data_ptr()),
+                              spmv.SPMV_DEVICE_PTRS, ctypes.byref(h)) == spmv.SPMV_OK
+    try:
+        Yd = torch.empty((3 * B.n_rows, 2), dtype=torch.float64, device=DEV)
+        assert L.bsr3_spmm(h, 2, ctypes.c_void_p(Xb.data_ptr()), ctypes.c_void_p(Yd.data_ptr()), None) == 0
+        with spmv.Matrix.from_csr(B) as M:
+            assert np.array_equal(M.spmm(Xb).cpu().numpy(), Yd.cpu().numpy())
+    finally:
+        L.spmv_destroy(h)
+
+
+def test_create_from_device_arrays_rejects_host_pointers():
+    A = mg.config0()
+    L = spmv.lib()
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(A.row_ptr)
+    ci = torch.as_tensor(A.col_idx, device=DEV)
+    va = torch.as_tensor(A.values, device=DEV)
+    rc = L.spmv_create(A.n_rows, A.n_cols, A.nnz, rp.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ci.data_ptr()),
+                       ctypes.c_void_p(va.data_ptr()), spmv.SPMV_DEVICE_PTRS, None, ctypes.byref(h))
+    assert rc == spmv.SPMV_EINVAL and not h.value
+    assert b"not device memory" in L.spmv_last_error()
+    # the device arrays are validated like host ones
+    bad = torch.as_tensor(A.col_idx, device=DEV).clone()
+    bad[7] = A.n_cols
+    rc = L.spmv_create(A.n_rows, A.n_cols, A.nnz, ctypes.c_void_p(torch.as_tensor(A.row_ptr, device=DEV).data_ptr()),
+                       ctypes.c_void_p(bad.data_ptr()), ctypes.c_void_p(va.data_ptr()), spmv.SPMV_DEVICE_PTRS, None,
+                       ctypes.byref(h))
+    assert rc == spmv.SPMV_EINVAL
