@@ -99,6 +99,12 @@ hipError_t hipSetDevice(int d) {
     return hipSuccess;
 }
 hipError_t hipGetLastError(void) { return hipSuccess; }
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t *a, const void *p) {  // all memory is "device" here
+    *a = hipPointerAttribute_t{};
+    a->type = hipMemoryTypeDevice;
+    a->devicePointer = const_cast<void *>(p);
+    return hipSuccess;
+}
 const char *hipGetErrorString(hipError_t) { return "mock runtime error"; }
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) {
     *v = 256;
