@@ -472,6 +472,18 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # the read ceiling of this part: a plain streaming read of 4 GiB (far
+        # beyond L2 and the 256 MB MALL) at several grid sizes, the best kept
+        buf = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+        best = 0.0
+        for wg_per_cu in (4, 8, 16, 32):
+            part = torch.empty(256 * wg_per_cu, dtype=torch.float64, device="cuda")
+            tr = time_launches(lambda: spmv.calibrate_read(buf, part), 20, 3, torch, WARM_S)
+            best = max(best, buf.numel() * 8 / tr / 1e9)
+        del buf, part
+        roofline["read_ceiling_GBs"] = round(best, 1)
+        roofline["frac_of_read_ceiling"] = round(gbs / best, 4)
+        log(f"read ceiling (streaming read of 4 GiB): {best:.1f} GB/s; headline {100 * gbs / best:.1f}% of it")
         x32 = x.float()
         y32 = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
         t32 = time_launches(lambda: M.apply_f32(x32, y32), max(10, args.steps // 2), 3, torch, WARM_S)

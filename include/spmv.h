@@ -376,6 +376,17 @@ int srv_policy_simulate(uint64_t budget, int32_t n_mats, const uint64_t *mat_byt
                         const int32_t *op_kind, const int32_t *op_mat, const uint64_t *op_extra,
                         int32_t *verdict, int32_t *n_evicted, int32_t *uploaded, uint64_t *used);
 
+/*
+ * spmv_calibrate_read: reads buf (device double[n], 16-byte aligned, n even)
+ * once with a plain streaming kernel of n_blocks workgroups of 256 lanes,
+ * storing each workgroup's sum of the values in partials (device
+ * double[n_blocks]).  Timing it over a buffer far larger than the caches
+ * gives the HBM read rate a streaming kernel reaches on this part, the
+ * practical ceiling against which the products are also reported.
+ * Asynchronous on `stream`.  SPMV_EINVAL for bad sizes, alignment or NULL.
+ */
+int spmv_calibrate_read(const double *buf, int64_t n, double *partials, int32_t n_blocks, void *stream);
+
 /* Thread-local message describing the calling thread's last failure ("" if none). */
 const char *spmv_last_error(void);
 

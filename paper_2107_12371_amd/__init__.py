@@ -33,7 +33,7 @@ CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V = 0, 1, 2, 3
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
     "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
-    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect", "spmv_spmm",
+    "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect", "spmv_spmm", "spmv_calibrate_read",
 ]
 
 
@@ -101,6 +101,8 @@ def lib():
             getattr(L, f).argtypes = [vp, i32, vp, vp, vp]
         L.cg_solve.restype = ctypes.c_int
         L.cg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(cg_info), vp]
+        L.spmv_calibrate_read.restype = ctypes.c_int
+        L.spmv_calibrate_read.argtypes = [vp, i64, vp, i32, vp]
         L.spmv_last_error.restype = ctypes.c_char_p
         L.spmv_last_error.argtypes = []
         L.spmv_plan_inspect.restype = ctypes.c_int
@@ -460,6 +462,18 @@ def _serve_lib():
         L.srv_policy_simulate.argtypes = [u64, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L._serve_ready = True
     return L
+
+
+def calibrate_read(buf, partials, stream=None) -> None:
+    """One streaming read of the float64 device tensor ``buf`` (16-byte
+    aligned, even length) into one sum per workgroup in ``partials``
+    (``spmv_calibrate_read``; grid = partials.numel() workgroups)."""
+    torch = _torch()
+    _check_vec(buf, torch.float64, buf.numel(), "buf")
+    _check_vec(partials, torch.float64, partials.numel(), "partials")
+    _check(lib().spmv_calibrate_read(ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                     ctypes.c_void_p(partials.data_ptr()), partials.numel(),
+                                     _stream_ptr(stream)), "spmv_calibrate_read")
 
 
 def policy_simulate(budget: int, mat_bytes, ops) -> list[tuple[int, int, int, int]]:

@@ -19,7 +19,7 @@ LIB_NAME = "libspmv_gfx950.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 OBJ_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["spmv_kernels.hip", "sell.hip", "bsr.hip", "spmm.hip", "cg.hip", "api.hip", "serve.hip"]
+HIP_SOURCES = ["spmv_kernels.hip", "sell.hip", "bsr.hip", "spmm.hip", "calib.hip", "cg.hip", "api.hip", "serve.hip"]
 CXX_SOURCES = ["plan.cpp", "sell_plan.cpp"]
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 

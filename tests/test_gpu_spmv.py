@@ -546,3 +546,18 @@ def test_create_from_device_arrays_rejects_host_pointers():
                        ctypes.c_void_p(bad.data_ptr()), ctypes.c_void_p(va.data_ptr()), spmv.SPMV_DEVICE_PTRS, None,
                        ctypes.byref(h))
     assert rc == spmv.SPMV_EINVAL
+
+
+def test_read_calibration_sums_and_rejects_misuse():
+    buf = torch.as_tensor(mg.uniform(1 << 20, 91, 0), device=DEV)
+    part = torch.empty(64, dtype=torch.float64, device=DEV)
+    spmv.calibrate_read(buf, part)
+    assert abs(part.sum().item() - buf.sum().item()) <= 1e-9 * buf.abs().sum().item()
+    L = spmv.lib()
+    odd = torch.ones(5, dtype=torch.float64, device=DEV)
+    assert L.spmv_calibrate_read(ctypes.c_void_p(odd.data_ptr()), 5, ctypes.c_void_p(part.data_ptr()), 64,
+                                 None) == spmv.SPMV_EINVAL
+    assert L.spmv_calibrate_read(ctypes.c_void_p(buf.data_ptr() + 8), 2, ctypes.c_void_p(part.data_ptr()), 64,
+                                 None) == spmv.SPMV_EINVAL
+    assert L.spmv_calibrate_read(ctypes.c_void_p(buf.data_ptr()), 2, ctypes.c_void_p(part.data_ptr()), 0,
+                                 None) == spmv.SPMV_EINVAL
