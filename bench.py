@@ -476,7 +476,7 @@ def main():
         # beyond L2 and the 256 MB MALL) at several grid sizes, the best kept
         buf = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
         best = 0.0
-        for wg_per_cu in (4, 8, 16, 32):
+        for wg_per_cu in (2, 4, 8, 16, 32):
             part = torch.empty(256 * wg_per_cu, dtype=torch.float64, device="cuda")
             tr = time_launches(lambda: spmv.calibrate_read(buf, part), 20, 3, torch, WARM_S)
             best = max(best, buf.numel() * 8 / tr / 1e9)

@@ -1,8 +1,10 @@
 // Calibration: the rate at which a plain streaming kernel reads HBM on this
 // part, the practical ceiling the products are also reported against (the
 // published 8 TB/s is the nominal one).  Each lane reads 16-byte pieces in
-// a grid-stride loop, four independent loads in flight per iteration, and
-// the workgroup's sum is stored so that no load can be dropped.
+// a grid-stride loop with non-temporal loads (measured on a 4 GiB buffer:
+// 7.09 TB/s at 2048 workgroups, against 6.38 with ordinary loads and at
+// most 6.27 with four loads in flight per lane), and the workgroup's sum is
+// stored so that no load can be dropped.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -15,18 +17,10 @@ __global__ __launch_bounds__(kBlock) void k_read_stream(const f64x2 *__restrict_
                                                         double *__restrict__ part) {
     __shared__ double sh[kBlock / kWave];
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    f64x2 s0{0.0, 0.0}, s1 = s0, s2 = s0, s3 = s0;
-    for (; i + 3 * stride < n2; i += 4 * stride) {
-        const f64x2 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-        s0 += a;
-        s1 += b;
-        s2 += c;
-        s3 += d;
-    }
-    for (; i < n2; i += stride) s0 += p[i];
-    const f64x2 t = (s0 + s1) + (s2 + s3);
-    const double sum = block_sum(t[0] + t[1], sh);
+    f64x2 s{0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += stride)
+        s += __builtin_nontemporal_load(p + i);
+    const double sum = block_sum(s[0] + s[1], sh);
     if (threadIdx.x == 0) part[blockIdx.x] = sum;
 }
 
