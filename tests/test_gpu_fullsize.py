@@ -53,6 +53,26 @@ def test_mesh16m_default_plan_sampled_rows(mesh16m):
     assert np.isfinite(y).all()
 
 
+def test_mesh16m_spmm_k8_sampled_rows(mesh16m):
+    # the k = 8 product the bench times: sampled rows of every column against
+    # the oracle, two whole columns bitwise against the single-vector product
+    A = mesh16m
+    k = 8
+    X = mg.uniform(A.n_cols * k, 104, 5).reshape(A.n_cols, k)
+    with spmv.Matrix.from_csr(A) as M:
+        info = M.info
+        Xd = torch.as_tensor(X, device=DEV)
+        Y = M.spmm(Xd)
+        for j in (0, k - 1):
+            y = M.apply(Xd[:, j].contiguous())
+            assert torch.equal(Y[:, j], y), j
+        Y = Y.cpu().numpy()
+    rows = _sample_rows(A, info, 8)
+    for j in range(k):
+        y_ref, bound = oracle.spmv_rows(A, np.ascontiguousarray(X[:, j]), rows)
+        assert oracle.spmv_accept(Y[rows, j], y_ref, bound).all(), j
+
+
 def test_mesh16m_kernels_and_plans_bitwise(mesh16m):
     # compact windows (one workgroup per tile and persistent), direct
     # gathers and sliced ELLPACK give the same bits on every row
