@@ -461,11 +461,11 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             a.per_xcd = (M.n_cwin + 7) / 8;
             grid = 8 * a.per_xcd;
         }
-        // Binary64 values stream 10 instead of 12 bytes per entry through the
-        // window; with 4- or 2-byte values the window's extra barriers and LDS
-        // traffic outweigh the saving (measured), so those products treat the
-        // same tiles as direct-gather tiles.
-        if constexpr (sizeof(V) == 8) {
+        // 8- and 4-byte values go through the windows (16M-row mesh matrix:
+        // FP64 0.60 vs 0.73 ms direct, FP32 0.42 vs 0.48, FP32 values with
+        // FP64 x 0.50 vs 0.56); bfloat16 products gain nothing from them
+        // (0.404 either way), so they treat the same tiles as direct tiles.
+        if constexpr (sizeof(V) >= 4) {
             if (M.kernel == KV_PIPELINED && M.n_cwin >= 64) {
                 a.per_xcd = (M.n_cwin + 7) / 8;
                 const int resident = cwin_pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
