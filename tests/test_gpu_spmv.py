@@ -270,12 +270,6 @@ def test_fp32_paths_within_derived_bounds():
         y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
         yv = M.apply_f32v(to_dev(x)).cpu().numpy()
         y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
-    with spmv.Matrix.from_csr(A, fp32=True, bf16=True, params={"tile_nnz": 2048, "window_mode": spmv.WINDOW_OFF}) as D:
-        assert D.info["n_window_tiles"] == 0
-        assert np.array_equal(D.apply(to_dev(x)).cpu().numpy(), y64)
-        assert np.array_equal(D.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64), y32)
-        assert np.array_equal(D.apply_f32v(to_dev(x)).cpu().numpy(), yv)
-        assert np.array_equal(D.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64), y16)
     u32, u16 = 2.0 ** -24, 2.0 ** -8
     assert np.all(np.abs(y32 - y_ref) <= 1.01 * (m + 2) * u32 * bound)
     assert np.all(np.abs(yv - y_ref) <= 1.01 * (u32 + m * 2.0 ** -53) * bound)
@@ -299,6 +293,12 @@ def test_reduced_precision_on_a_compact_window_handle(cfg1):
         y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
         yv = M.apply_f32v(to_dev(x)).cpu().numpy()
         y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    with spmv.Matrix.from_csr(A, fp32=True, bf16=True, params={"tile_nnz": 2048, "window_mode": spmv.WINDOW_OFF}) as D:
+        assert D.info["n_window_tiles"] == 0
+        assert np.array_equal(D.apply(to_dev(x)).cpu().numpy(), y64)
+        assert np.array_equal(D.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64), y32)
+        assert np.array_equal(D.apply_f32v(to_dev(x)).cpu().numpy(), yv)
+        assert np.array_equal(D.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64), y16)
     u32, u16 = 2.0 ** -24, 2.0 ** -8
     assert oracle.spmv_accept(y64, y_ref, bound).all()
     assert np.all(np.abs(y32 - y_ref) <= 1.01 * (m + 2) * u32 * bound)
