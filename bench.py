@@ -19,6 +19,7 @@ Progress goes to stderr; stdout gets exactly one JSON line.
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -375,6 +376,29 @@ def config_lines(torch, log=log) -> dict:
             del X, Y, X32, Y32
     out["bsr3x3_4M_cells"] = c3
     log(f"3x3 block CSR: {c3}")
+    # context at the paper's own sizes (Table 1): tet-like stand-ins with its
+    # row counts, warm (back-to-back) and cold; the paper's FPGA times of the
+    # cached design (Table 2, units not stated: read as seconds) beside them
+    paper = {}
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "fpga_timings.csv")
+    with open(gold) as f:
+        for row in csv.DictReader(line for line in f if not line.startswith("#")):
+            paper[row["name"]] = float(row["cached"])
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    t1 = {}
+    for name in mg.TABLE1_ROWS:
+        A = mg.table1_matrix(name)
+        x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+        y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+        B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+        with spmv.Matrix.from_csr(A) as M:
+            t = time_launches(lambda: M.apply(x, y), 200, 20, torch, WARM_S)
+            c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
+        t1[name] = {"rows": A.n_rows, "nnz": A.nnz, "us": round(t * 1e6, 2), "cold_us_p50": round(c50 * 1e6, 2),
+                    "GBs_cold_p50": round(B / c50 / 1e9, 1), "paper_fpga_cached_s": paper.get(name)}
+    del scratch
+    out["table1_sizes_tet_like"] = t1
+    log(f"Table 1 sizes: {t1}")
     return out
 
 

@@ -23,6 +23,8 @@ for them):
   edge/vertex neighbour pair kept with probability 1/2 (7-27 nnz per row), RCM.
 * ``config3``  200x200x100 lattice, 3x3 block-CSR, 7-11 blocks per block row.
 * ``serving_matrix``  config0-style lattices of any size for request streams.
+* ``tet_like`` / ``table1_matrix``  stand-ins for the paper's tetrahedral
+  matrices (Table 1 row counts, at most four neighbours per cell), RCM.
 
 Off-diagonals are -w with one w ~ U[0.5, 1.5) per undirected edge, and the
 diagonal is sum(w) + shift (shift = 1e-3), so A is symmetric, strictly
@@ -86,6 +88,8 @@ def _L():
         lib.mg_rcm.argtypes = [vp, vp]
         lib.mg_random_perm.restype = None
         lib.mg_random_perm.argtypes = [i32, u64, vp]
+        lib.mg_degree_capped.restype = i64
+        lib.mg_degree_capped.argtypes = [i64, vp, vp, i64, i32, vp]
         lib.mg_uniform.restype = None
         lib.mg_uniform.argtypes = [i64, u64, u64, dbl, dbl, vp]
         for f in ("mg_n_rows", "mg_n_cols", "mg_block"):
@@ -295,6 +299,52 @@ def config3(nx: int = 200, ny: int = 200, nz: int = 100, seed: int | None = None
     """3x3 block CSR on 200x200x100 cells (4,000,000 block rows), natural order."""
     s = seed_for(3) if seed is None else seed
     return bsr3(nx, ny, nz, s)
+
+
+# the paper's Table 1 matrices (rows); nnz/rows is 4.93-4.97 there
+TABLE1_ROWS = {"C50K": 49336, "C100K": 97521, "C200K": 187078, "C400K": 398000, "C800K": 775058}
+
+
+def tet_like(n: int, seed: int | None = None, shift: float = 1e-3) -> CSR:
+    """Stand-in for the paper's tetrahedral-mesh matrices (Table 1, Sec. 2: a
+    cell of a tetrahedral mesh has at most four face neighbours, so a row has
+    at most five non-zeros).  n cells on a jittered lattice (+-0.35 per
+    axis); candidate pairs are each cell's 16 nearest cells, taken by
+    increasing distance (ties by index) and kept while both cells have fewer
+    than four neighbours.  Weights, diagonal and RCM order as in the other
+    meshes; row lengths 1-5."""
+    import scipy.sparse as sp
+    from scipy.spatial import cKDTree
+    s = seed_for(5) if seed is None else seed
+    m = int(np.ceil(n ** (1.0 / 3.0)))
+    idx = np.arange(n, dtype=np.int64)
+    pts = np.stack([idx % m, (idx // m) % m, idx // (m * m)], axis=1).astype(np.float64)
+    pts += 0.35 * uniform(3 * n, s, 11).reshape(n, 3)
+    dist, nb = cKDTree(pts).query(pts, k=17)
+    i = np.repeat(idx, 16)
+    j = nb[:, 1:].reshape(-1).astype(np.int64)
+    d = dist[:, 1:].reshape(-1)
+    key = np.minimum(i, j) * n + np.maximum(i, j)
+    ukey, first = np.unique(key, return_index=True)          # each pair once (same distance both ways)
+    ukey = ukey[np.lexsort((ukey, d[first]))]                 # by distance, ties by index
+    pa, pb = ukey // n, ukey % n
+    keep = np.empty(len(ukey), np.uint8)
+    if _L().mg_degree_capped(len(ukey), pa.ctypes.data, pb.ctypes.data, n, 4, keep.ctypes.data) < 0:
+        raise MemoryError("meshgen: degree-capped fill failed")
+    ea, eb = pa[keep == 1], pb[keep == 1]
+    w = 1.0 + 0.5 * uniform(len(ea), s, 12)                     # U[0.5, 1.5) per undirected edge
+    diag = np.bincount(ea, w, n) + np.bincount(eb, w, n) + shift
+    S = sp.coo_matrix((np.concatenate([-w, -w, diag]),
+                       (np.concatenate([ea, eb, idx]), np.concatenate([eb, ea, idx]))), shape=(n, n)).tocsr()
+    S.sort_indices()
+    A = CSR(n, n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64))
+    return reorder(A, "rcm", s)
+
+
+def table1_matrix(name: str) -> CSR:
+    """The tet-like stand-in with the row count of the paper's matrix ``name``."""
+    n = TABLE1_ROWS[name]
+    return _cached(f"table1_{name}", lambda: tet_like(n))
 
 
 def serving_matrix(n_target: int, seed: int) -> CSR:

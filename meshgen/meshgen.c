@@ -618,3 +618,31 @@ mg_csr *mg_from_arrays(int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t bloc
     }
     return A;
 }
+
+/* Walks the pairs (a[p], b[p]) of vertices in [0, n) in the given order and
+ * keeps a pair while both of its vertices have fewer than `cap` kept pairs
+ * (the degree-capped greedy fill of the tetrahedral stand-in).  keep[p] is
+ * set to 1 or 0.  Returns the number of pairs kept, or -1 if a vertex is out
+ * of range or memory runs out. */
+int64_t mg_degree_capped(int64_t n_pairs, const int64_t *a, const int64_t *b, int64_t n, int32_t cap,
+                         uint8_t *keep) {
+    int32_t *deg = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    if (!deg) return -1;
+    int64_t kept = 0;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int64_t u = a[p], v = b[p];
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            free(deg);
+            return -1;
+        }
+        keep[p] = 0;
+        if (deg[u] < cap && deg[v] < cap) {
+            ++deg[u];
+            ++deg[v];
+            keep[p] = 1;
+            ++kept;
+        }
+    }
+    free(deg);
+    return kept;
+}

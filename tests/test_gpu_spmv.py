@@ -568,3 +568,15 @@ def test_read_calibration_sums_and_rejects_misuse():
                                  None) == spmv.SPMV_EINVAL
     assert L.spmv_calibrate_read(ctypes.c_void_p(buf.data_ptr()), 2, ctypes.c_void_p(part.data_ptr()), 0,
                                  None) == spmv.SPMV_EINVAL
+
+
+@pytest.mark.parametrize("name", ["C50K", "C800K"])
+def test_table1_sized_tet_stand_ins(name):
+    # the paper's matrix sizes (Table 1), tet-like stand-ins: every row against
+    # the oracle on the default plan and on the ring window (the paper's cache)
+    A = mg.table1_matrix(name)
+    x = mg.uniform(A.n_cols, 93, 0)
+    for params in ({}, {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024, "ring_words": 8192,
+                        "window_block": 8}):
+        y, info = run64(A, x, params=params)
+        assert_parity(y, A, x)

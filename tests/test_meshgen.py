@@ -137,3 +137,27 @@ def test_dyadic_values():
     assert np.all(A.values * 1024 == np.round(A.values * 1024))
     x = mg.dyadic_x(1000, 2)
     assert len(np.unique(x)) == 1000 and np.all(x * 2 ** 20 == np.round(x * 2 ** 20))
+
+
+def test_tet_like_stand_in_matches_table1_shape():
+    """The tetrahedral stand-in at the paper's C50K size: at most four
+    neighbours per cell (five non-zeros per row, Sec. 2), symmetric pattern
+    and values, full diagonal, strictly dominant, nnz/rows as in Table 1,
+    deterministic."""
+    with open(os.path.join(GOLDEN, "table1_matrices.csv")) as f:
+        rows = {r["name"]: r for r in csv.DictReader(line for line in f if not line.startswith("#"))}
+    assert mg.TABLE1_ROWS == {k: int(v["rows"]) for k, v in rows.items()}
+    A = mg.tet_like(mg.TABLE1_ROWS["C50K"])
+    n = A.n_rows
+    L = np.diff(A.row_ptr)
+    assert n == 49336 and L.max() <= 5 and L.min() >= 1
+    assert (A.nnz - n) % 2 == 0
+    paper = int(rows["C50K"]["nnz"]) / n
+    assert abs(A.nnz / n - paper) < 0.02
+    S = sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(n, n))
+    assert abs(S - S.T).max() == 0
+    d = S.diagonal()
+    off = np.asarray(abs(S).sum(axis=1)).ravel() - np.abs(d)
+    assert np.all(d > 0) and np.all(d - off > 0.9e-3)
+    B = mg.tet_like(mg.TABLE1_ROWS["C50K"])
+    assert np.array_equal(A.col_idx, B.col_idx) and np.array_equal(A.values, B.values)
