@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests skip cleanly when no GPU is present (e.g. CPU-only CI); the
-    # GPU machine selects them with -m gpu.
+    # machine with a GPU selects them with -m gpu.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
