@@ -110,6 +110,25 @@ def time_cold(fn, reps, torch, scratch):
     return float(q[0]), float(q[1]), float(q[2])
 
 
+def time_graph(fn, calls, replays, torch):
+    """Seconds per call of fn() with the host out of the way: `calls` calls
+    recorded once into a HIP graph (stream capture), replayed `replays`
+    times back to back between HIP events after 50 ms of untimed replays."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            fn()
+    t = time_launches(g.replay, replays, 3, torch, WARM_S)
+    del g
+    return t / calls
+
+
 def time_each(fn, reps, torch):
     """(p10, p50, p90) seconds of single calls, events around each call on
     the current stream (back-to-back launches, warm caches)."""
@@ -393,8 +412,10 @@ def config_lines(torch, log=log) -> dict:
         B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
         with spmv.Matrix.from_csr(A) as M:
             t = time_launches(lambda: M.apply(x, y), 200, 20, torch, WARM_S)
+            tg = time_graph(lambda: M.apply(x, y), 100, 10, torch)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
-        t1[name] = {"rows": A.n_rows, "nnz": A.nnz, "us": round(t * 1e6, 2), "cold_us_p50": round(c50 * 1e6, 2),
+        t1[name] = {"rows": A.n_rows, "nnz": A.nnz, "us": round(t * 1e6, 2), "graph_us": round(tg * 1e6, 2),
+                    "GBs_graph": round(B / tg / 1e9, 1), "cold_us_p50": round(c50 * 1e6, 2),
                     "GBs_cold_p50": round(B / c50 / 1e9, 1), "paper_fpga_cached_s": paper.get(name)}
     del scratch
     out["table1_sizes_tet_like"] = t1

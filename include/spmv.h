@@ -178,6 +178,10 @@ int spmv_get_info(const spmv_matrix *A, spmv_info *info);
  * order that depends only on the handle, so results are bitwise reproducible
  * and independent of concurrent work.  Per row the result meets
  * |y_i - exact_i| <= gamma_m * sum_k |a_ik||x_k| (m = row length).
+ * The call only enqueues kernels on `stream` (no allocation, copy, memset or
+ * synchronisation), so a caller may record it into a HIP graph by stream
+ * capture and replay it; the same holds for the other spmv_apply_* calls
+ * and spmv_spmm / bsr3_spmm.
  */
 int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
 

@@ -580,3 +580,54 @@ def test_table1_sized_tet_stand_ins(name):
                         "window_block": 8}):
         y, info = run64(A, x, params=params)
         assert_parity(y, A, x)
+
+
+@pytest.mark.parametrize("params", [{}, {"tile_nnz": 2048}, {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024}])
+def test_apply_and_spmm_replay_from_a_hip_graph(params):
+    # the apply calls only enqueue kernels, so a caller may record them into a
+    # HIP graph: three chained products y1 = A x, y2 = A y1, y3 = A y2 and one
+    # three-column product, captured once, replayed with a new x each time
+    # (eager copies and synchronisations between replays), every replay equal
+    # bit for bit to the same calls made eagerly
+    A = mg.config0()
+    k = 3
+    with spmv.Matrix.from_csr(A, params=params) as M:
+        if params:
+            assert M.info["n_window_tiles"] > 0
+        x = torch.zeros(A.n_cols, dtype=torch.float64, device=DEV)
+        X = torch.zeros((A.n_cols, k), dtype=torch.float64, device=DEV)
+        ys = [torch.empty(A.n_rows, dtype=torch.float64, device=DEV) for _ in range(3)]
+        Y = torch.empty((A.n_rows, k), dtype=torch.float64, device=DEV)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            M.apply(x, ys[0])
+            M.spmm(X, Y)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            M.apply(x, ys[0])
+            M.apply(ys[0], ys[1])
+            M.apply(ys[1], ys[2])
+            M.spmm(X, Y)
+        for rep in range(4):
+            xr = mg.uniform(A.n_cols, 94, rep)
+            Xr = mg.uniform(A.n_cols * k, 95, rep).reshape(A.n_cols, k)
+            x.copy_(to_dev(xr))
+            X.copy_(to_dev(Xr))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = [y.cpu().numpy() for y in ys]
+            got_Y = Y.cpu().numpy()
+            e = [M.apply(to_dev(xr))]
+            e.append(M.apply(e[0]))
+            e.append(M.apply(e[1]))
+            eY = M.spmm(to_dev(Xr), torch.empty_like(Y))
+            torch.cuda.synchronize()
+            for a, b in zip(got, e):
+                assert np.array_equal(a, b.cpu().numpy()), f"replay {rep}"
+            assert np.array_equal(got_Y, eY.cpu().numpy()), f"replay {rep}"
+            assert_parity(got[0], A, xr)
+        del g
