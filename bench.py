@@ -396,8 +396,10 @@ def config_lines(torch, log=log) -> dict:
     out["bsr3x3_4M_cells"] = c3
     log(f"3x3 block CSR: {c3}")
     # context at the paper's own sizes (Table 1): tet-like stand-ins with its
-    # row counts, warm (back-to-back) and cold; the paper's FPGA times of the
-    # cached design (Table 2, units not stated: read as seconds) beside them
+    # row counts, SpMV warm (called back to back, and replayed from a graph)
+    # and cold, and CG to 1e-10 (the solver the paper's SpMV serves); the
+    # paper's FPGA times of the cached design (Table 2, units not stated:
+    # read as seconds) beside them
     paper = {}
     gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "fpga_timings.csv")
     with open(gold) as f:
@@ -410,13 +412,23 @@ def config_lines(torch, log=log) -> dict:
         x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
         y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
         B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
-        with spmv.Matrix.from_csr(A) as M:
+        b = torch.as_tensor(mg.uniform(A.n_rows, 7, 1), device="cuda")
+        with spmv.Matrix.from_csr(A, bf16=True) as M:
             t = time_launches(lambda: M.apply(x, y), 200, 20, torch, WARM_S)
             tg = time_graph(lambda: M.apply(x, y), 100, 10, torch)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
+            cg = {}
+            for mode_name, mode in (("fp64", spmv.CG_FP64), ("pcg_bf16", spmv.CG_PCG_BF16)):
+                best = None
+                for _ in range(3):
+                    _, info = M.cg(b, tol=1e-10, mode=mode)
+                    best = info if best is None or info.seconds < best.seconds else best
+                cg[mode_name] = {"ms": round(best.seconds * 1e3, 3), "it": best.iterations,
+                                 "us_per_it": round(best.seconds * 1e6 / max(best.iterations, 1), 2)}
         t1[name] = {"rows": A.n_rows, "nnz": A.nnz, "us": round(t * 1e6, 2), "graph_us": round(tg * 1e6, 2),
                     "GBs_graph": round(B / tg / 1e9, 1), "cold_us_p50": round(c50 * 1e6, 2),
-                    "GBs_cold_p50": round(B / c50 / 1e9, 1), "paper_fpga_cached_s": paper.get(name)}
+                    "GBs_cold_p50": round(B / c50 / 1e9, 1), "cg_1e-10": cg,
+                    "paper_fpga_cached_s": paper.get(name)}
     del scratch
     out["table1_sizes_tet_like"] = t1
     log(f"Table 1 sizes: {t1}")

@@ -8,10 +8,11 @@
 //               stop if it passes, else continue from r = b - A x
 //            beta = rho' / rho;  p = r + beta p;  rho = rho'
 //
-// One iteration is five launches: the SpMV with the p.q partial fused into
-// its epilogue, a one-workgroup reduction that forms alpha on the device,
-// the fused x/r update with the r.r partial, a reduction that forms beta and
-// the convergence flag, and the p update.  All scalars live on the device;
+// One iteration is four launches: the SpMV with the p.q partial fused into
+// its epilogue; the x/r update with the r.r partial, whose workgroups each
+// form alpha from the SpMV's partials (above 1,024 partials alpha takes a
+// reduction launch of its own); a one-workgroup reduction that forms beta
+// and the convergence flag; and the p update.  All scalars live on the device;
 // every kernel returns at once when the device flag `done` is set, so a
 // captured graph of several iterations can be replayed blindly and the host
 // synchronises once per replay.  Reductions are two-stage with a fixed
@@ -53,13 +54,21 @@ struct CgState {
 enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
 enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7 };
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ part, int n, CgState *st, int mode) {
-    __shared__ double sh[kBlock / kWave];
-    if ((mode == R_ALPHA || mode == R_BETA || mode == R_RR || mode == R_RZ) && st->done) return;
+// Sum of part[0..n) in the one fixed order every reduction of the solver
+// uses (lane l adds l, l + kBlock, ...; then block_sum); the result is in
+// thread 0.  The loops over a workgroup's elements here and below are
+// unrolled by 4 so that a lane's loads are in flight together (one memory
+// round trip instead of four on small systems); the order of the additions
+// is unchanged.
+__device__ __forceinline__ double sum_partials(const double *part, int n, double *sh) {
     double s = 0.0;
+#pragma unroll 4
     for (int i = (int)threadIdx.x; i < n; i += kBlock) s += part[i];
-    const double t = block_sum(s, sh);
-    if (threadIdx.x != 0) return;
+    return block_sum(s, sh);
+}
+
+// Applies the finished sum t of reduction `mode` to the solver state.
+__device__ void apply_reduction(CgState *st, int mode, double t) {
     switch (mode) {
         case R_BB: st->bb = t; break;
         case R_RHO0: st->rho = t; break;
@@ -129,6 +138,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ part, int n, CgState *st, int mode) {
+    __shared__ double sh[kBlock / kWave];
+    if ((mode == R_ALPHA || mode == R_BETA || mode == R_RR || mode == R_RZ) && st->done) return;
+    const double t = sum_partials(part, n, sh);
+    if (threadIdx.x == 0) apply_reduction(st, mode, t);
+}
+
 // First stage of a reduction over many partials: workgroup b sums the fixed
 // chunk [b*chunk, min(n, (b+1)*chunk)) in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restrict__ part, int n, int chunk,
@@ -137,6 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restric
     if ((mode == R_ALPHA || mode == R_BETA || mode == R_RR || mode == R_RZ) && st->done) return;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double s = 0.0;
+#pragma unroll 4
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) s += part[i];
     const double t = block_sum(s, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = t;
@@ -160,15 +177,44 @@ __global__ void k_init_state(CgState *st, double tol, int max_iter) {
     st->alpha = st->beta = st->pq = st->rho_new = 0.0;
 }
 
+// x += alpha p, r -= alpha q and the r.r partial of each workgroup.  With
+// n_pq >= 0 every workgroup forms p.q from the SpMV's n_pq partials itself
+// (few partials: cheaper than a reduction launch) and alpha = rho / p.q
+// from it; with n_pq < 0 alpha was formed by a reduction launch.  The sum is
+// sum_partials over the same partials as that launch, so the iterates are
+// bit for bit the same.  The state's done flag is read once at entry; within
+// a launch only workgroup 0 sets it, on a p.q breakdown, which every
+// workgroup detects alike.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_xr(int n, int chunk, T *__restrict__ x, T *__restrict__ r,
                                                       const T *__restrict__ p, const T *__restrict__ q,
-                                                      const CgState *st, double *__restrict__ part) {
+                                                      CgState *st, const double *__restrict__ part_pq, int n_pq,
+                                                      double *__restrict__ part) {
     __shared__ double sh[kBlock / kWave];
+    __shared__ double pq_all;
     if (st->done) return;
-    const T a = static_cast<T>(st->alpha);
+    double alpha;
+    if (n_pq >= 0) {
+        const double t = sum_partials(part_pq, n_pq, sh);
+        if (threadIdx.x == 0) pq_all = t;
+        __syncthreads();
+        const double pq = pq_all;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_ALPHA, pq);
+            return;
+        }
+        alpha = st->rho / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->alpha = alpha;
+        }
+    } else {
+        alpha = st->alpha;
+    }
+    const T a = static_cast<T>(alpha);
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
+#pragma unroll 4
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
         const T xi = x[i] + a * p[i];
         const T ri = r[i] - a * q[i];
@@ -202,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_part(int n, int chunk, const T *
     __shared__ double sh[kBlock / kWave];
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
+#pragma unroll 4
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) d += static_cast<double>(a[i]) * static_cast<double>(b[i]);
     const double t = block_sum(d, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -315,6 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_pcg(int n, int chunk, doub
     const double a = st->alpha;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
+#pragma unroll 4
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
         const double xi = x[i] + a * p[i];
         const double ri = r[i] - a * q[i];
@@ -337,6 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_precond_z(int n, int chunk, const do
     const double w = st->omega;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
+#pragma unroll 4
     for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
         const double zi = w * dinv[i] * (2.0 * r[i] - w * static_cast<double>(s[i]));
         z[i] = zi;
@@ -428,6 +477,9 @@ template <typename T, typename V> struct CgCore {
     // workgroup for up to 4096 partials, else a fixed-partition first stage
     // over up to kStage1 workgroups and a one-workgroup second stage.
     static constexpr int kStage1 = 256;
+    // Up to this many SpMV partials every workgroup of the x/r update sums
+    // them itself instead of waiting for a reduction launch.
+    static constexpr int kFoldAlpha = 1024;
     void reduce(const double *part, int n, int mode, hipStream_t t) {
         if (n <= 4096) {
             hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part, n, st, mode);
@@ -443,8 +495,10 @@ template <typename T, typename V> struct CgCore {
         const int *done = &st->done;
         hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t);
         if (e != hipSuccess) return e;
-        reduce(part_seg, M.n_seg, R_ALPHA, t);
-        hipLaunchKernelGGL((k_update_xr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_vec);
+        const bool fold_alpha = M.n_seg <= kFoldAlpha;
+        if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, t);
+        hipLaunchKernelGGL((k_update_xr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_seg,
+                           fold_alpha ? M.n_seg : -1, part_vec);
         reduce(part_vec, n_wg, R_BETA, t);
         hipLaunchKernelGGL((k_update_p<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st);
         return hipGetLastError();
