@@ -49,6 +49,10 @@
  *                  preconditioned CG (e.g. Saad, Iterative Methods for Sparse
  *                  Linear Systems, Alg. 9.1) on top, stopping and confirming as
  *                  oracle_cg does.
+ *  oracle_pcg_jacobi the same preconditioned CG with the Jacobi
+ *                  preconditioner M = D = diag(A) (duplicates summed), i.e.
+ *                  z = D^-1 r: the first preconditioner of the scope's
+ *                  preconditioned-CG step, in binary64.
  *
  * Pins (tests, independent of this code): exact rational brute force,
  * dyadic inputs whose results are exact in binary64, zero row sums of the
@@ -304,6 +308,71 @@ int oracle_pcg_bf16(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, c
     residual(n, row_ptr, col_idx, values, b, x, r);
     *rel_res = sqrt(dot(n, r, r)) / nb;
     free(vt);
+    free(dinv);
+    return status;
+}
+
+/*
+ * Preconditioned CG with M = D = diag(A): the recurrences, stopping rule and
+ * restarts of oracle_pcg_bf16 with z = D^-1 r.  Work arrays r, p, q, z (n
+ * each) are supplied by the caller; x holds x0 on entry.  Returns 0 when
+ * converged, 1 at max_iter, 2 on breakdown (p.q or r.z not positive and
+ * finite), 3 when a diagonal entry is not positive and finite.
+ */
+int oracle_pcg_jacobi(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+                      const double *b, double *x, double tol, int32_t max_iter,
+                      double *r, double *p, double *q, double *z,
+                      int32_t *iters, double *rel_res) {
+    *iters = 0;
+    *rel_res = 0.0;
+    double *dinv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!dinv) return 3;
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col_idx[k] == i) d = d + values[k];
+        if (!(d > 0.0) || !isfinite(d)) { free(dinv); return 3; }
+        dinv[i] = 1.0 / d;
+    }
+    double nb = sqrt(dot(n, b, b));
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        free(dinv);
+        return 0;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    int status = 1;
+    if (sqrt(dot(n, r, r)) <= tol * nb) status = 0;
+    for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+    double rho = dot(n, r, z);
+    for (int32_t it = 1; it <= max_iter && status != 0; ++it) {
+        for (int32_t i = 0; i < n; ++i) {
+            double yi, bi;
+            row_sum(row_ptr, col_idx, values, p, i, &yi, &bi);
+            q[i] = yi;
+        }
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = 2; *iters = it - 1; break; }
+        double alpha = rho / pq;
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        *iters = it;
+        int restart = 0;
+        if (sqrt(dot(n, r, r)) <= tol * nb) {
+            residual(n, row_ptr, col_idx, values, b, x, r);
+            if (sqrt(dot(n, r, r)) <= tol * nb) { status = 0; break; }
+            restart = 1;
+        }
+        for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        double rho_new = dot(n, r, z);
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) { status = 2; break; }
+        double beta = restart ? 0.0 : rho_new / rho;
+        for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    *rel_res = sqrt(dot(n, r, r)) / nb;
     free(dinv);
     return status;
 }

@@ -412,6 +412,71 @@ def test_pcg_zero_rhs_and_bad_diagonal():
     assert r.status == 3
 
 
+# ------------------------------------- preconditioned CG (Jacobi)
+
+def _badly_scaled(seed):
+    """S A S for an SPD mesh matrix A and S = diag(s), s log-uniform in
+    [1, 100]: still SPD, with a diagonal spread over four decades."""
+    A = mg.lattice(6, 6, 5, "stencil27", seed=seed)
+    s = np.exp(np.random.default_rng(seed).uniform(0.0, np.log(100.0), A.n_rows))
+    S = sp.diags(s) @ sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols)) @ sp.diags(s)
+    S = S.tocsr()
+    S.sort_indices()
+    return mg.CSR(A.n_rows, A.n_cols, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+
+
+def test_pcg_jacobi_diagonal_system_one_iteration():
+    # A = D: z = D^-1 b is the solution and alpha = 1, so one step solves it
+    n = 37
+    d = np.random.default_rng(5).uniform(0.5, 50.0, n)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = mg.uniform(n, 4, 1)
+    r = oracle.pcg_jacobi(A, b, tol=1e-12, max_iter=20)
+    assert r.status == 0 and r.iterations == 1
+    assert np.allclose(r.x, b / d, rtol=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_pcg_jacobi_is_cg_on_the_symmetrically_scaled_system(k):
+    # with M = D, the PCG iterates are x_k = D^-1/2 y_k, y_k the CG iterates
+    # for D^-1/2 A D^-1/2 y = D^-1/2 b (both from zero); the scaled system is
+    # formed here with scipy and solved by the plain CG oracle
+    A = _badly_scaled(61)
+    Ad = _dense(A)
+    dh = 1.0 / np.sqrt(np.diag(Ad))
+    Sc = sp.csr_matrix(dh[:, None] * Ad * dh[None, :])
+    As = mg.CSR(A.n_rows, A.n_cols, Sc.indptr.astype(np.int32), Sc.indices.astype(np.int32), Sc.data)
+    b = mg.uniform(A.n_rows, 61, 1)
+    y = oracle.cg(As, dh * b, tol=0.0, max_iter=k)
+    x = oracle.pcg_jacobi(A, b, tol=0.0, max_iter=k)
+    assert x.status == 1 and y.status == 1 and x.iterations == y.iterations == k
+    assert np.linalg.norm(x.x - dh * y.x) <= 1e-11 * np.linalg.norm(x.x)
+
+
+def test_pcg_jacobi_helps_on_a_badly_scaled_diagonal_and_matches_lapack():
+    A = _badly_scaled(62)
+    Ad = _dense(A)
+    b = mg.uniform(A.n_rows, 62, 1)
+    tol = 1e-10
+    r_cg = oracle.cg(A, b, tol=tol, max_iter=20000)
+    r = oracle.pcg_jacobi(A, b, tol=tol, max_iter=20000)
+    assert r.status == 0 and r_cg.status == 0
+    assert r.iterations < 0.5 * r_cg.iterations
+    xs = np.linalg.solve(Ad, b)
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) <= 2 * np.linalg.cond(Ad) * tol
+    assert np.linalg.norm(b - Ad @ r.x) / np.linalg.norm(b) <= tol * 1.01
+
+
+def test_pcg_jacobi_zero_rhs_bad_diagonal_and_max_iter():
+    A = mg.config0()
+    r = oracle.pcg_jacobi(A, np.zeros(A.n_rows), tol=1e-10)
+    assert r.status == 0 and r.iterations == 0 and np.all(r.x == 0)
+    B = mg.CSR(2, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    assert oracle.pcg_jacobi(B, np.ones(2), tol=1e-10).status == 3
+    r = oracle.pcg_jacobi(A, mg.uniform(A.n_rows, 3, 0), tol=1e-14, max_iter=4)
+    assert r.status == 1 and r.iterations == 4
+
+
 # -------------------------------------------------- planted mistakes
 
 def _mutant_dropped_term(A):
