@@ -418,7 +418,8 @@ def config_lines(torch, log=log) -> dict:
             tg = time_graph(lambda: M.apply(x, y), 100, 10, torch)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
             cg = {}
-            for mode_name, mode in (("fp64", spmv.CG_FP64), ("pcg_bf16", spmv.CG_PCG_BF16)):
+            for mode_name, mode in (("fp64", spmv.CG_FP64), ("pcg_bf16", spmv.CG_PCG_BF16),
+                                    ("pcg_jacobi", spmv.CG_PCG_JACOBI)):
                 best = None
                 for _ in range(3):
                     _, info = M.cg(b, tol=1e-10, mode=mode)
@@ -580,7 +581,7 @@ def main():
         del Xk, Yk
         b = torch.as_tensor(mg.uniform(A.n_rows, mg.seed_for(2), 2), device="cuda")
         for name, mode in (("fp64", spmv.CG_FP64), ("mixed", spmv.CG_MIXED_FP32), ("pcg_bf16", spmv.CG_PCG_BF16),
-                           ("mixed_f32v", spmv.CG_MIXED_FP32V)):
+                           ("mixed_f32v", spmv.CG_MIXED_FP32V), ("pcg_jacobi", spmv.CG_PCG_JACOBI)):
             xs, ci = M.cg(b, tol=1e-10, max_iter=20000, mode=mode, raise_on_error=False)
             extras[f"cg_{name}_seconds"] = round(ci.seconds, 4)
             extras[f"cg_{name}_iterations"] = ci.iterations
@@ -600,6 +601,8 @@ def main():
         extras["cg_pcg_bf16_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_pcg_bf16_seconds"], 3)
         extras["cg_solves_per_s_mixed_f32v"] = round(1.0 / extras["cg_mixed_f32v_seconds"], 4)
         extras["cg_mixed_f32v_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_mixed_f32v_seconds"], 3)
+        extras["cg_solves_per_s_pcg_jacobi"] = round(1.0 / extras["cg_pcg_jacobi_seconds"], 4)
+        extras["cg_pcg_jacobi_speedup"] = round(extras["cg_fp64_seconds"] / extras["cg_pcg_jacobi_seconds"], 3)
     if args.copy_calibration:
         buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(buf)

@@ -269,6 +269,10 @@ int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, voi
 #define CG_MIXED_FP32V 3 /* the refinement of CG_MIXED_FP32 with an inner CG that
                            reads the FP32 values but keeps binary64 vectors and
                            binary64 SpMV accumulation (needs SPMV_VALUES_FP32) */
+#define CG_PCG_JACOBI 4  /* CG preconditioned with M = D = diag(A) (duplicates
+                           summed), all in binary64 (needs a CSR-format handle;
+                           SPMV_EBREAK if a diagonal entry is not positive and
+                           finite) */
 
 typedef struct cg_info {
     int32_t iterations;        /* total CG iterations (inner iterations for MIXED) */
@@ -285,7 +289,7 @@ typedef struct cg_info {
  *   x          device double[n], in: initial guess, out: last iterate
  *   tol        stop when ||b - A x||_2 <= tol * ||b||_2 (true residual)
  *   max_iter   iteration cap (total inner iterations for MIXED)
- *   mode       CG_FP64, CG_MIXED_FP32, CG_PCG_BF16 or CG_MIXED_FP32V
+ *   mode       CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V or CG_PCG_JACOBI
  *   info       optional, filled on return (also on ENOTCONV / EBREAK)
  * b = 0 gives x = 0 and 0 iterations.  Returns SPMV_ENOTCONV when the cap is
  * reached (x is the last iterate).  Blocks the host until done; work runs on

@@ -28,7 +28,7 @@ SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
 SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP, SPMV_DEVICE_PTRS = 0x1, 0x2, 0x4, 0x8
 WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
 FORMAT_CSR, FORMAT_SELL = 0, 1
-CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V = 0, 1, 2, 3
+CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V, CG_PCG_JACOBI = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",

@@ -23,6 +23,9 @@
 // of A (described with its kernels below); restarts from the true residual
 // when the recursive one drifts.
 //
+// Jacobi-preconditioned (CG_PCG_JACOBI): the same preconditioned CG with
+// M = diag(A).
+//
 // Mixed precision (CG_MIXED_FP32): iterative refinement (Wilkinson; Moler
 // 1967).  The residual r = b - A x is formed with binary64 values and
 // vectors; the correction solve A d = r / ||r|| runs CG with the FP32 copy
@@ -52,7 +55,7 @@ struct CgState {
 };
 
 enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
-enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7 };
+enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7, R_DIAG = 8 };
 
 // Sum of part[0..n) in the one fixed order every reduction of the solver
 // uses (lane l adds l, l + kBlock, ...; then block_sum); the result is in
@@ -117,6 +120,12 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
                 st->done = 1;
             }
             break;
+        case R_DIAG:  // Jacobi preconditioner: t counts diagonals that are not positive and finite
+            if (t != 0.0) {
+                st->flags |= F_BADDIAG;
+                st->done = 1;
+            }
+            break;
         case R_BETA:
             st->rho_new = t;
             st->iter += 1;
@@ -177,14 +186,37 @@ __global__ void k_init_state(CgState *st, double tol, int max_iter) {
     st->alpha = st->beta = st->pq = st->rho_new = 0.0;
 }
 
-// x += alpha p, r -= alpha q and the r.r partial of each workgroup.  With
-// n_pq >= 0 every workgroup forms p.q from the SpMV's n_pq partials itself
-// (few partials: cheaper than a reduction launch) and alpha = rho / p.q
-// from it; with n_pq < 0 alpha was formed by a reduction launch.  The sum is
-// sum_partials over the same partials as that launch, so the iterates are
-// bit for bit the same.  The state's done flag is read once at entry; within
-// a launch only workgroup 0 sets it, on a p.q breakdown, which every
-// workgroup detects alike.
+// alpha for the x/r update.  With n_pq >= 0 every workgroup forms p.q from
+// the SpMV's n_pq partials itself (few partials: cheaper than a reduction
+// launch) and alpha = rho / p.q from it; with n_pq < 0 alpha was formed by a
+// reduction launch.  The sum is sum_partials over the same partials as that
+// launch, so the iterates are bit for bit the same.  Returns false on a p.q
+// breakdown, which every workgroup detects alike and workgroup 0 records;
+// the state's done flag is read once at kernel entry, and within a launch
+// only that record sets it.
+__device__ __forceinline__ bool form_alpha(CgState *st, const double *__restrict__ part_pq, int n_pq, double *sh,
+                                           double *pq_all, double &alpha) {
+    if (n_pq < 0) {
+        alpha = st->alpha;
+        return true;
+    }
+    const double t = sum_partials(part_pq, n_pq, sh);
+    if (threadIdx.x == 0) *pq_all = t;
+    __syncthreads();
+    const double pq = *pq_all;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_ALPHA, pq);
+        return false;
+    }
+    alpha = st->rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+    }
+    return true;
+}
+
+// x += alpha p, r -= alpha q and the r.r partial of each workgroup
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_xr(int n, int chunk, T *__restrict__ x, T *__restrict__ r,
                                                       const T *__restrict__ p, const T *__restrict__ q,
@@ -194,23 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int n, int chunk, T *__res
     __shared__ double pq_all;
     if (st->done) return;
     double alpha;
-    if (n_pq >= 0) {
-        const double t = sum_partials(part_pq, n_pq, sh);
-        if (threadIdx.x == 0) pq_all = t;
-        __syncthreads();
-        const double pq = pq_all;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_ALPHA, pq);
-            return;
-        }
-        alpha = st->rho / pq;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->pq = pq;
-            st->alpha = alpha;
-        }
-    } else {
-        alpha = st->alpha;
-    }
+    if (!form_alpha(st, part_pq, n_pq, sh, &pq_all, alpha)) return;
     const T a = static_cast<T>(alpha);
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
@@ -393,6 +409,90 @@ __global__ __launch_bounds__(kBlock) void k_precond_z(int n, int chunk, const do
     }
     const double tt = block_sum(d, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = tt;
+}
+
+// ------------------------------------------- preconditioned CG (Jacobi)
+//
+// M = D = diag(A): z = D^-1 r is fused into the x/r update, and r.r and r.z
+// are reduced in one launch, so an iteration is four launches like plain CG
+// (SpMV + p.q; x/r/z update, with alpha formed in it on small systems; the
+// r.r / r.z reduction that forms the convergence flag and beta; p update).
+
+// Per workgroup: how many entries of v are NaN (k_diag_inv marks a diagonal
+// that is not positive and finite so).
+__global__ __launch_bounds__(kBlock) void k_count_nan(int n, int chunk, const double *__restrict__ v,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double c = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) c += v[i] != v[i] ? 1.0 : 0.0;
+    const double t = block_sum(c, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r; partials r.r and r.z
+__global__ __launch_bounds__(kBlock) void k_update_xr_jacobi(int n, int chunk, double *__restrict__ x,
+                                                             double *__restrict__ r, const double *__restrict__ p,
+                                                             const double *__restrict__ q,
+                                                             const double *__restrict__ dinv,
+                                                             double *__restrict__ z, CgState *st,
+                                                             const double *__restrict__ part_pq, int n_pq,
+                                                             double *__restrict__ part_rr,
+                                                             double *__restrict__ part_rz) {
+    __shared__ double sh[kBlock / kWave], sh2[kBlock / kWave];
+    __shared__ double pq_all;
+    if (st->done) return;
+    double a;
+    if (!form_alpha(st, part_pq, n_pq, sh, &pq_all, a)) return;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double drr = 0.0, drz = 0.0;
+#pragma unroll 4
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const double xi = x[i] + a * p[i];
+        const double ri = r[i] - a * q[i];
+        const double zi = dinv[i] * ri;
+        x[i] = xi;
+        r[i] = ri;
+        z[i] = zi;
+        drr += ri * ri;
+        drz += ri * zi;
+    }
+    const double trr = block_sum(drr, sh);
+    const double trz = block_sum(drz, sh2);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = trr;
+        part_rz[blockIdx.x] = trz;
+    }
+}
+
+// z = D^-1 r and the r.z partial, whatever the done flag (start, restarts)
+__global__ __launch_bounds__(kBlock) void k_precond_jacobi(int n, int chunk, const double *__restrict__ r,
+                                                           const double *__restrict__ dinv, double *__restrict__ z,
+                                                           double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double d = 0.0;
+#pragma unroll 4
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const double zi = dinv[i] * r[i];
+        z[i] = zi;
+        d += r[i] * zi;
+    }
+    const double t = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// The convergence test on r.r, then (unless it stopped) beta from r.z: the
+// two reductions k_reduce makes with R_RR and R_RZ, in one launch.
+__global__ __launch_bounds__(kBlock) void k_reduce_rr_rz(const double *__restrict__ part_rr,
+                                                         const double *__restrict__ part_rz, int n, CgState *st) {
+    __shared__ double sh[kBlock / kWave], sh2[kBlock / kWave];
+    if (st->done) return;
+    const double trr = sum_partials(part_rr, n, sh);
+    const double trz = sum_partials(part_rz, n, sh2);
+    if (threadIdx.x != 0) return;
+    apply_reduction(st, R_RR, trr);
+    if (!st->done) apply_reduction(st, R_RZ, trz);
 }
 
 // ------------------------------------------------------------ host driver
@@ -611,20 +711,32 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
     return SPMV_OK;
 }
 
-// Preconditioned CG with the bfloat16 polynomial preconditioner: CgCore's
-// buffers and reductions plus z, D^-1 and the FP32 vectors of the bfloat16
-// product.  One iteration is eight launches (SpMV + p.q, alpha, x/r update +
-// r.r + t = D^-1 r, convergence, bfloat16 SpMV, z + r.z, beta, p update).
+// Preconditioned CG: CgCore's buffers and reductions plus z and D^-1, and
+// for the bfloat16 polynomial preconditioner the FP32 vectors of its
+// product.  Polynomial: eight launches per iteration (SpMV + p.q, alpha, x/r
+// update + r.r + t = D^-1 r, convergence, bfloat16 SpMV, z + r.z, beta, p
+// update).  Jacobi: four (see its kernels).
 struct PcgCore : CgCore<double, double> {
-    double *z = nullptr, *dinv = nullptr;
+    double *z = nullptr, *dinv = nullptr, *part_rz = nullptr;
     float *t = nullptr, *sv = nullptr;
+    bool jacobi;
 
-    PcgCore(const DevMatrix &M_, int n_, hipStream_t s_) : CgCore<double, double>(M_, M_.val64, n_, s_) {}
+    PcgCore(const DevMatrix &M_, int n_, hipStream_t s_, bool jacobi_)
+        : CgCore<double, double>(M_, M_.val64, n_, s_), jacobi(jacobi_) {}
 
     hipError_t pcg_iteration(hipStream_t ts) {
         const int *done = &st->done;
         hipError_t e = launch_spmv<double, double, double, double>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, ts);
         if (e != hipSuccess) return e;
+        if (jacobi) {
+            const bool fold_alpha = M.n_seg <= kFoldAlpha;
+            if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, ts);
+            hipLaunchKernelGGL(k_update_xr_jacobi, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, z,
+                               st, part_seg, fold_alpha ? M.n_seg : -1, part_vec, part_rz);
+            hipLaunchKernelGGL(k_reduce_rr_rz, dim3(1), dim3(kBlock), 0, ts, part_vec, part_rz, n_wg, st);
+            hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+            return hipGetLastError();
+        }
         reduce(part_seg, M.n_seg, R_ALPHA, ts);
         hipLaunchKernelGGL(k_update_xr_pcg, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, t, st,
                            part_vec);
@@ -637,9 +749,14 @@ struct PcgCore : CgCore<double, double> {
         return hipGetLastError();
     }
 
-    // D^-1 and the polynomial weight (st->omega, or F_BADDIAG)
+    // D^-1 and the polynomial weight (st->omega), or F_BADDIAG
     hipError_t setup() {
         hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, M.row_ptr, M.col, M.val64, dinv);
+        if (jacobi) {
+            hipLaunchKernelGGL(k_count_nan, dim3(n_wg), dim3(kBlock), 0, s, n, chunk, dinv, part_vec);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_vec, n_wg, st, (int)R_DIAG);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_gersh, dim3(n_wg), dim3(kBlock), 0, s, n, M.row_ptr, M.col, M.val16, dinv, part_vec);
         hipLaunchKernelGGL(k_weight, dim3(1), dim3(kWave), 0, s, part_vec, n_wg, st);
         return hipGetLastError();
@@ -647,6 +764,12 @@ struct PcgCore : CgCore<double, double> {
 
     // From the current r: z = M^-1 r, rho = r.z, p = z (start and restarts)
     hipError_t restart() {
+        if (jacobi) {
+            hipLaunchKernelGGL(k_precond_jacobi, dim3(n_wg), dim3(kBlock), 0, s, n, chunk, r, dinv, z, part_vec);
+            reduce(part_vec, n_wg, R_RZ0, s);
+            hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, z);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_dinv_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, t, r, dinv);
         hipError_t e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr,
                                                                   nullptr, s);
@@ -834,17 +957,21 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
 
 
 static int cg_pcg(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
-                  hipStream_t s, void *pinned) {
+                  hipStream_t s, void *pinned, bool jacobi) {
     const DevMatrix &M = A->M;
     const int n = M.n_rows;
     Buffers B(s);
-    PcgCore C(M, n, s);
+    PcgCore C(M, n, s, jacobi);
     int rc = alloc_core(B, C);
     if (rc) return rc;
     HIP_TRY(B.alloc(&C.z, (size_t)n));
     HIP_TRY(B.alloc(&C.dinv, (size_t)n));
-    HIP_TRY(B.alloc(&C.t, (size_t)n));
-    HIP_TRY(B.alloc(&C.sv, (size_t)n));
+    if (jacobi) {
+        HIP_TRY(B.alloc(&C.part_rz, (size_t)C.n_wg));
+    } else {
+        HIP_TRY(B.alloc(&C.t, (size_t)n));
+        HIP_TRY(B.alloc(&C.sv, (size_t)n));
+    }
     HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
     C.hst = static_cast<CgState *>(B.host);
     hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
@@ -887,14 +1014,15 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     if (A->M.block != 1) return fail(SPMV_ENOTSUP, "cg_solve needs a scalar CSR handle");
     if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
     if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
-    if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16 && mode != CG_MIXED_FP32V)
+    if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16 && mode != CG_MIXED_FP32V &&
+        mode != CG_PCG_JACOBI)
         return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
     if ((mode == CG_MIXED_FP32 || mode == CG_MIXED_FP32V) && !A->M.val32)
         return fail(SPMV_ENOTSUP, "mixed-precision CG needs the FP32 copy (create with SPMV_VALUES_FP32)");
     if (mode == CG_PCG_BF16 && !A->M.val16)
         return fail(SPMV_ENOTSUP, "CG_PCG_BF16 needs the BF16 copy (create with SPMV_VALUES_BF16)");
-    if (mode == CG_PCG_BF16 && A->M.format != SPMV_FORMAT_CSR)
-        return fail(SPMV_ENOTSUP, "CG_PCG_BF16 needs a CSR handle (the diagonal is read from CSR rows)");
+    if ((mode == CG_PCG_BF16 || mode == CG_PCG_JACOBI) && A->M.format != SPMV_FORMAT_CSR)
+        return fail(SPMV_ENOTSUP, "preconditioned CG needs a CSR handle (the diagonal is read from CSR rows)");
     const int n = A->M.n_rows;
     if (n == 0) return SPMV_OK;
     if (!b || !x) return fail(SPMV_EINVAL, "b or x is NULL");
@@ -915,8 +1043,8 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     int rc;
     if (mode == CG_FP64) {
         rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);
-    } else if (mode == CG_PCG_BF16) {
-        rc = cg_pcg(A, b, x, tol, max_iter, info, s, pinned_state);
+    } else if (mode == CG_PCG_BF16 || mode == CG_PCG_JACOBI) {
+        rc = cg_pcg(A, b, x, tol, max_iter, info, s, pinned_state, mode == CG_PCG_JACOBI);
     } else {
         // each correction solve reduces the residual by the inner tolerance,
         // so r = ceil(log tol / log 1e-4) refinements of 0.6 tol^(1/r) reach

@@ -111,7 +111,7 @@ def test_cg_rejects_bad_input():
             M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_MIXED_FP32V)
         assert e.value.code == spmv.SPMV_ENOTSUP
         with pytest.raises(spmv.SpmvError) as e:
-            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=4)
+            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=5)
         assert e.value.code == spmv.SPMV_EINVAL
 
 
@@ -191,3 +191,90 @@ def test_pcg_rejects_missing_copy_sell_and_bad_diagonal():
         _, info = M.cg(torch.ones(n, dtype=torch.float64, device=DEV), mode=spmv.CG_PCG_BF16,
                        raise_on_error=False)
     assert info.status == spmv.SPMV_EBREAK
+
+
+def _badly_scaled(nx, seed):
+    # S A S for an SPD mesh matrix A, S = diag(s) with s log-uniform in
+    # [1, 100]: SPD with a diagonal spread over four decades
+    import scipy.sparse as sp
+    A = mg.lattice(nx, nx, nx, "stencil27", seed=seed)
+    s = np.exp(np.random.default_rng(seed).uniform(0.0, np.log(100.0), A.n_rows))
+    S = (sp.diags(s) @ sp.csr_matrix((A.values, A.col_idx, A.row_ptr), shape=(A.n_rows, A.n_cols))
+         @ sp.diags(s)).tocsr()
+    S.sort_indices()
+    return mg.CSR(A.n_rows, A.n_cols, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+
+
+def _check_jacobi(A, b, tol, kappa):
+    ref = oracle.pcg_jacobi(A, b, tol=tol, max_iter=20000)
+    assert ref.status == 0
+    with spmv.Matrix.from_csr(A) as M:
+        bt = torch.as_tensor(b, device=DEV)
+        x, info = M.cg(bt, tol=tol, mode=spmv.CG_PCG_JACOBI)
+        x2, info2 = M.cg(bt, tol=tol, mode=spmv.CG_PCG_JACOBI)
+    assert torch.equal(x, x2) and info2.iterations == info.iterations
+    x = x.cpu().numpy()
+    assert info.status == 0
+    rr = true_rel_residual(A, x, b)
+    assert rr <= 1.05 * tol and abs(info.rel_residual - rr) <= 0.05 * tol
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 2 * kappa * tol
+    # both sides in binary64: the counts differ only by rounding order
+    assert abs(info.iterations - ref.iterations) <= 0.1 * ref.iterations
+    return info
+
+
+def test_pcg_jacobi_badly_scaled_against_oracle():
+    A = _badly_scaled(12, 71)
+    b = mg.uniform(A.n_rows, 71, 1)
+    tol = 1e-10
+    D = np.zeros((A.n_rows, A.n_cols))
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    np.add.at(D, (rows, A.col_idx), A.values)
+    info = _check_jacobi(A, b, tol, np.linalg.cond(D))
+    with spmv.Matrix.from_csr(A) as M:
+        _, plain = M.cg(torch.as_tensor(b, device=DEV), tol=tol, mode=spmv.CG_FP64)
+    assert info.iterations < 0.5 * plain.iterations
+
+
+@pytest.mark.parametrize("name", ["config0", "C400K"])
+def test_pcg_jacobi_mesh_against_oracle(name):
+    # config0: the SpMV leaves few partials (alpha formed inside the update);
+    # the Table 1 sized C400K stand-in: a separate reduction forms alpha
+    A = mg.config0() if name == "config0" else mg.table1_matrix(name)
+    b = mg.uniform(A.n_rows, 72, 1)
+    with spmv.Matrix.from_csr(A) as M:
+        n_seg = M.info["n_tiles"]
+    assert (n_seg <= 1024) == (name == "config0")
+    _check_jacobi(A, b, 1e-10, gershgorin_kappa(A, 1e-3))
+
+
+def test_pcg_jacobi_diagonal_one_iteration():
+    n = 4000
+    d = np.random.default_rng(5).uniform(0.5, 50.0, n)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = mg.uniform(n, 4, 1)
+    with spmv.Matrix.from_csr(A) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=1e-12, mode=spmv.CG_PCG_JACOBI)
+    assert info.status == 0 and info.iterations == 1
+    assert np.allclose(x.cpu().numpy(), b / d, rtol=1e-14)
+
+
+def test_pcg_jacobi_rejects_sell_and_bad_diagonal():
+    A = mg.config0()
+    b = torch.ones(A.n_rows, dtype=torch.float64, device=DEV)
+    with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL}) as M:
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(b, mode=spmv.CG_PCG_JACOBI)
+        assert e.value.code == spmv.SPMV_ENOTSUP
+    n = 64
+    for bad in (-1.0, 0.0, float("nan")):
+        d = np.ones(n)
+        d[n // 2] = bad
+        B = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+        with spmv.Matrix.from_csr(B) as M:
+            _, info = M.cg(torch.ones(n, dtype=torch.float64, device=DEV), mode=spmv.CG_PCG_JACOBI,
+                           raise_on_error=False)
+        assert info.status == spmv.SPMV_EBREAK
+        with spmv.Matrix.from_csr(B) as M:
+            with pytest.raises(spmv.SpmvError, match="positive finite diagonal"):
+                M.cg(torch.ones(n, dtype=torch.float64, device=DEV), mode=spmv.CG_PCG_JACOBI)

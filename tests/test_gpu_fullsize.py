@@ -86,7 +86,8 @@ def test_mesh16m_kernels_and_plans_bitwise(mesh16m):
     assert all(torch.equal(ys[0], y) for y in ys[1:])
 
 
-@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32, spmv.CG_PCG_BF16, spmv.CG_MIXED_FP32V])
+@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_MIXED_FP32, spmv.CG_PCG_BF16, spmv.CG_MIXED_FP32V,
+                                  spmv.CG_PCG_JACOBI])
 def test_mesh16m_cg_to_1e10(mesh16m, mode):
     A = mesh16m
     b = mg.uniform(A.n_rows, 103, 4)
