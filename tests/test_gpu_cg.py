@@ -126,6 +126,29 @@ def test_cg_breakdown_on_indefinite_matrix():
     assert info.status == spmv.SPMV_EBREAK
 
 
+@pytest.mark.parametrize("n,neg,first", [(200, 3, False), (2_000_000, 0, True)])
+def test_cg_breakdown_step_matches_oracle(n, neg, first):
+    # a p.q breakdown is reported at the oracle's step: after two iterations on
+    # a small indefinite diagonal system (few SpMV partials: alpha is formed
+    # inside the x/r update), and at once on a 2M-row one (many partials:
+    # alpha from a reduction launch)
+    if first:
+        d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+        b = np.zeros(n)
+        b[0], b[1] = 1.0, 1.0
+    else:
+        d = np.linspace(1.0, 10.0, n)
+        d[-neg:] = -np.linspace(0.5, 5.0, neg)
+        b = np.ones(n)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    ref = oracle.cg(A, b, tol=1e-10, max_iter=1000)
+    assert ref.status == 2 and ref.iterations == (0 if first else 2)
+    with spmv.Matrix.from_csr(A) as M:
+        assert (M.info["n_tiles"] > 1024) == first
+        _, info = M.cg(torch.as_tensor(b, device=DEV), tol=1e-10, max_iter=1000, raise_on_error=False)
+    assert info.status == spmv.SPMV_EBREAK and info.iterations == ref.iterations
+
+
 # ------------------------------------ preconditioned CG (bfloat16 copy)
 
 @pytest.fixture(scope="module")
