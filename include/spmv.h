@@ -257,7 +257,8 @@ int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, voi
                            residual of 0.6 tol^(1/r), r = ceil(log tol / log 1e-4)
                            the number of refinements it plans for (2.8e-4 at
                            tol = 1e-10), or at the value of the environment
-                           variable SPMV_CG_INNER_TOL when it is set */
+                           variable SPMV_CG_INNER_TOL when it is set to a
+                           number in (0, 1) (other values are ignored) */
 #define CG_PCG_BF16 2   /* CG preconditioned with a polynomial in the bfloat16
                            copy A~ of A: M^-1 = w D^-1 (2I - w A~ D^-1), D =
                            diag(A), w = 1.9 / max_i sum_j |a~_ij| / sqrt(d_i d_j)

@@ -1051,9 +1051,10 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
         // tol without overshooting it (2.8e-4 at tol = 1e-10: 0.875 s against
         // 0.903 s with 1e-4 on the 16M-row mesh matrix, three refinements each)
         const char *env = std::getenv("SPMV_CG_INNER_TOL");
+        const double env_tol = env ? std::strtod(env, nullptr) : 0.0;
         double inner = 1e-4;
-        if (env) {
-            inner = std::atof(env);
+        if (env_tol > 0.0 && env_tol < 1.0) {
+            inner = env_tol;
         } else if (tol > 0.0 && tol < 1.0) {
             const double r = std::max(1.0, std::ceil(std::log(tol) / std::log(1e-4)));
             inner = 0.6 * std::pow(tol, 1.0 / r);
