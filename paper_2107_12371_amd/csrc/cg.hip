@@ -8,11 +8,13 @@
 //               stop if it passes, else continue from r = b - A x
 //            beta = rho' / rho;  p = r + beta p;  rho = rho'
 //
-// One iteration is four launches: the SpMV with the p.q partial fused into
-// its epilogue; the x/r update with the r.r partial, whose workgroups each
-// form alpha from the SpMV's partials (above 1,024 partials alpha takes a
-// reduction launch of its own); a one-workgroup reduction that forms beta
-// and the convergence flag; and the p update.  All scalars live on the device;
+// One iteration is three launches on small systems: the SpMV with the p.q
+// partial fused into its epilogue; the x/r update with the r.r partial,
+// whose workgroups each form alpha from the SpMV's partials; and the p
+// update, whose workgroups each form beta (and workgroup 0 the convergence
+// flag) from the r.r partials.  With more than 1,024 partials of either
+// kind that scalar takes a reduction launch of its own (five launches on
+// the largest systems).  All scalars live on the device;
 // every kernel returns at once when the device flag `done` is set, so a
 // captured graph of several iterations can be replayed blindly and the host
 // synchronises once per replay.  Reductions are two-stage with a fixed
@@ -48,6 +50,9 @@
 
 namespace spmvlib {
 
+// rho_new is the rho the next alpha step divides by; that step also copies
+// it to rho.  Every step that sets rho sets rho_new too, except the p update
+// with beta formed in it (R_BETA_DEFER), whose workgroups all read rho.
 struct CgState {
     double rho, rho_new, pq, alpha, beta, bb, tol2, rt2;
     double rr, omega;  // preconditioned CG: r.r of the iterate, polynomial weight
@@ -55,7 +60,10 @@ struct CgState {
 };
 
 enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
-enum : int { R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7, R_DIAG = 8 };
+enum : int {
+    R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7, R_DIAG = 8,
+    R_BETA_DEFER = 9
+};
 
 // Sum of part[0..n) in the one fixed order every reduction of the solver
 // uses (lane l adds l, l + kBlock, ...; then block_sum); the result is in
@@ -74,7 +82,10 @@ __device__ __forceinline__ double sum_partials(const double *part, int n, double
 __device__ void apply_reduction(CgState *st, int mode, double t) {
     switch (mode) {
         case R_BB: st->bb = t; break;
-        case R_RHO0: st->rho = t; break;
+        case R_RHO0:
+            st->rho = t;
+            st->rho_new = t;
+            break;
         case R_TRUE: st->rt2 = t; break;
         case R_ALPHA:
             st->pq = t;
@@ -82,7 +93,8 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
                 st->flags |= F_BREAKDOWN;
                 st->done = 1;
             } else {
-                st->alpha = st->rho / t;
+                st->alpha = st->rho_new / t;
+                st->rho = st->rho_new;
             }
             break;
         case R_RR:  // preconditioned CG, after the x/r update: convergence on r.r
@@ -103,6 +115,7 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
             } else {
                 st->beta = t / st->rho;
                 st->rho = t;
+                st->rho_new = t;
                 if (st->iter >= st->max_iter) {
                     st->flags |= F_MAXITER;
                     st->done = 1;
@@ -111,6 +124,7 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
             break;
         case R_RZ0:  // preconditioned CG, (re)start: rho = r.z, p = z follows
             st->rho = t;
+            st->rho_new = t;
             st->beta = 0.0;
             st->flags = 0;
             st->done = st->iter >= st->max_iter ? 1 : 0;
@@ -127,6 +141,7 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
             }
             break;
         case R_BETA:
+        case R_BETA_DEFER:  // as R_BETA; rho is left to the next alpha step
             st->rho_new = t;
             st->iter += 1;
             if (!isfinite(t)) {
@@ -137,7 +152,7 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
                 st->done = 1;
             } else {
                 st->beta = t / st->rho;
-                st->rho = t;
+                if (mode == R_BETA) st->rho = t;
                 if (st->iter >= st->max_iter) {
                     st->flags |= F_MAXITER;
                     st->done = 1;
@@ -172,6 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restric
 __global__ void k_replace(CgState *st) {
     st->beta = st->rt2 / st->rho;
     st->rho = st->rt2;
+    st->rho_new = st->rt2;
     st->flags = 0;
     st->done = st->iter >= st->max_iter ? 1 : 0;
     if (st->done) st->flags = F_MAXITER;
@@ -208,10 +224,11 @@ __device__ __forceinline__ bool form_alpha(CgState *st, const double *__restrict
         if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_ALPHA, pq);
         return false;
     }
-    alpha = st->rho / pq;
+    alpha = st->rho_new / pq;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pq = pq;
         st->alpha = alpha;
+        st->rho = st->rho_new;
     }
     return true;
 }
@@ -247,6 +264,33 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int n, T *__restrict__ p, c
                                                      const CgState *st) {
     if (st->done) return;
     const T b = static_cast<T>(st->beta);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = r[i] + b * p[i];
+}
+
+// p = r + beta p with beta formed in the same launch: when the x/r update
+// left few r.r partials, every workgroup sums them itself (sum_partials, the
+// order of the reduction launch) and takes beta = r.r / rho from the rho of
+// this iteration, which no workgroup writes here.  Workgroup 0 records the
+// step (R_BETA_DEFER: iteration count, convergence, beta, rho_new); the next
+// alpha step copies rho_new to rho.  The done flag is read at entry and set
+// here only where no workgroup updates p (converged, breakdown) or where p
+// is no longer read (the iteration cap).  Same beta, bit for bit, as the
+// reduction launch followed by k_update_p.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_p_fold(int n, T *__restrict__ p, const T *__restrict__ r,
+                                                          CgState *st, const double *__restrict__ part,
+                                                          int n_part) {
+    __shared__ double sh[kBlock / kWave];
+    __shared__ double rr_all;
+    if (st->done) return;
+    const double t0 = sum_partials(part, n_part, sh);
+    if (threadIdx.x == 0) rr_all = t0;
+    __syncthreads();
+    const double t = rr_all;
+    const double rho = st->rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_BETA_DEFER, t);
+    if (!isfinite(t) || t <= st->tol2) return;
+    const T b = static_cast<T>(t / rho);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = r[i] + b * p[i];
 }
 
@@ -580,6 +624,10 @@ template <typename T, typename V> struct CgCore {
     // Up to this many SpMV partials every workgroup of the x/r update sums
     // them itself instead of waiting for a reduction launch.
     static constexpr int kFoldAlpha = 1024;
+    // Up to this many r.r partials (systems up to 1,048,576 rows) every
+    // workgroup of the p update forms beta itself (measured: -7% per
+    // iteration at 398,000 rows, -1.5% at 775,058).
+    static constexpr int kFoldBeta = 1024;
     void reduce(const double *part, int n, int mode, hipStream_t t) {
         if (n <= 4096) {
             hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part, n, st, mode);
@@ -599,8 +647,13 @@ template <typename T, typename V> struct CgCore {
         if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, t);
         hipLaunchKernelGGL((k_update_xr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_seg,
                            fold_alpha ? M.n_seg : -1, part_vec);
-        reduce(part_vec, n_wg, R_BETA, t);
-        hipLaunchKernelGGL((k_update_p<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st);
+        if (n_wg <= kFoldBeta) {
+            hipLaunchKernelGGL((k_update_p_fold<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st, part_vec,
+                               n_wg);
+        } else {
+            reduce(part_vec, n_wg, R_BETA, t);
+            hipLaunchKernelGGL((k_update_p<T>), dim3(grid_for(n)), dim3(kBlock), 0, t, n, p, r, st);
+        }
         return hipGetLastError();
     }
 
