@@ -62,7 +62,7 @@ struct CgState {
 enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
 enum : int {
     R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7, R_DIAG = 8,
-    R_BETA_DEFER = 9
+    R_BETA_DEFER = 9, R_RZ_DEFER = 10
 };
 
 // Sum of part[0..n) in the one fixed order every reduction of the solver
@@ -109,12 +109,13 @@ __device__ void apply_reduction(CgState *st, int mode, double t) {
             }
             break;
         case R_RZ:  // preconditioned CG, after z = M^-1 r: beta from r.z
+        case R_RZ_DEFER:  // as R_RZ; rho is left to the next alpha step
             if (!(t > 0.0) || !isfinite(t)) {
                 st->flags |= F_BREAKDOWN;
                 st->done = 1;
             } else {
                 st->beta = t / st->rho;
-                st->rho = t;
+                if (mode == R_RZ) st->rho = t;
                 st->rho_new = t;
                 if (st->iter >= st->max_iter) {
                     st->flags |= F_MAXITER;
@@ -458,9 +459,10 @@ __global__ __launch_bounds__(kBlock) void k_precond_z(int n, int chunk, const do
 // ------------------------------------------- preconditioned CG (Jacobi)
 //
 // M = D = diag(A): z = D^-1 r is fused into the x/r update, and r.r and r.z
-// are reduced in one launch, so an iteration is four launches like plain CG
+// are reduced together, so an iteration takes the launches of plain CG
 // (SpMV + p.q; x/r/z update, with alpha formed in it on small systems; the
-// r.r / r.z reduction that forms the convergence flag and beta; p update).
+// r.r / r.z reduction that forms the convergence flag and beta, folded into
+// the p update on small systems; p update).
 
 // Per workgroup: how many entries of v are NaN (k_diag_inv marks a diagonal
 // that is not positive and finite so).
@@ -507,6 +509,36 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_jacobi(int n, int chunk, d
         part_rr[blockIdx.x] = trr;
         part_rz[blockIdx.x] = trz;
     }
+}
+
+// p = z + beta p with the convergence test and beta formed in the same
+// launch, as k_update_p_fold does for plain CG: every workgroup sums the r.r
+// and r.z partials itself (the order of k_reduce_rr_rz) and workgroup 0
+// records the step (R_RR, then R_RZ_DEFER), so no workgroup reads a field
+// another writes here.
+__global__ __launch_bounds__(kBlock) void k_update_p_jacobi(int n, double *__restrict__ p,
+                                                            const double *__restrict__ z, CgState *st,
+                                                            const double *__restrict__ part_rr,
+                                                            const double *__restrict__ part_rz, int n_part) {
+    __shared__ double sh[kBlock / kWave], sh2[kBlock / kWave];
+    __shared__ double rr_all, rz_all;
+    if (st->done) return;
+    const double a0 = sum_partials(part_rr, n_part, sh);
+    const double b0 = sum_partials(part_rz, n_part, sh2);
+    if (threadIdx.x == 0) {
+        rr_all = a0;
+        rz_all = b0;
+    }
+    __syncthreads();
+    const double rr = rr_all, rz = rz_all;
+    const double rho = st->rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        apply_reduction(st, R_RR, rr);
+        if (!st->done) apply_reduction(st, R_RZ_DEFER, rz);
+    }
+    if (!isfinite(rr) || rr <= st->tol2 || !(rz > 0.0) || !isfinite(rz)) return;
+    const double b = rz / rho;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + b * p[i];
 }
 
 // z = D^-1 r and the r.z partial, whatever the done flag (start, restarts)
@@ -768,7 +800,7 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
 // for the bfloat16 polynomial preconditioner the FP32 vectors of its
 // product.  Polynomial: eight launches per iteration (SpMV + p.q, alpha, x/r
 // update + r.r + t = D^-1 r, convergence, bfloat16 SpMV, z + r.z, beta, p
-// update).  Jacobi: four (see its kernels).
+// update).  Jacobi: three to five (see its kernels).
 struct PcgCore : CgCore<double, double> {
     double *z = nullptr, *dinv = nullptr, *part_rz = nullptr;
     float *t = nullptr, *sv = nullptr;
@@ -786,8 +818,13 @@ struct PcgCore : CgCore<double, double> {
             if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, ts);
             hipLaunchKernelGGL(k_update_xr_jacobi, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, z,
                                st, part_seg, fold_alpha ? M.n_seg : -1, part_vec, part_rz);
-            hipLaunchKernelGGL(k_reduce_rr_rz, dim3(1), dim3(kBlock), 0, ts, part_vec, part_rz, n_wg, st);
-            hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+            if (n_wg <= kFoldBeta) {
+                hipLaunchKernelGGL(k_update_p_jacobi, dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st, part_vec,
+                                   part_rz, n_wg);
+            } else {
+                hipLaunchKernelGGL(k_reduce_rr_rz, dim3(1), dim3(kBlock), 0, ts, part_vec, part_rz, n_wg, st);
+                hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+            }
             return hipGetLastError();
         }
         reduce(part_seg, M.n_seg, R_ALPHA, ts);
