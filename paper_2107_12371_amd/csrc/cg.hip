@@ -412,15 +412,19 @@ __global__ __launch_bounds__(kBlock) void k_dinv_f32(int n, float *__restrict__ 
         t[i] = static_cast<float>(dinv[i] * r[i]);
 }
 
-// x += alpha p; r -= alpha q; t = D^-1 r (FP32); partial r.r
+// x += alpha p; r -= alpha q; t = D^-1 r (FP32); partial r.r (alpha formed
+// here on small systems, as in k_update_xr)
 __global__ __launch_bounds__(kBlock) void k_update_xr_pcg(int n, int chunk, double *__restrict__ x,
                                                           double *__restrict__ r, const double *__restrict__ p,
                                                           const double *__restrict__ q,
                                                           const double *__restrict__ dinv, float *__restrict__ t,
-                                                          const CgState *st, double *__restrict__ part) {
+                                                          CgState *st, const double *__restrict__ part_pq,
+                                                          int n_pq, double *__restrict__ part) {
     __shared__ double sh[kBlock / kWave];
+    __shared__ double pq_all;
     if (st->done) return;
-    const double a = st->alpha;
+    double a;
+    if (!form_alpha(st, part_pq, n_pq, sh, &pq_all, a)) return;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double d = 0.0;
 #pragma unroll 4
@@ -511,12 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_jacobi(int n, int chunk, d
     }
 }
 
-// p = z + beta p with the convergence test and beta formed in the same
-// launch, as k_update_p_fold does for plain CG: every workgroup sums the r.r
-// and r.z partials itself (the order of k_reduce_rr_rz) and workgroup 0
-// records the step (R_RR, then R_RZ_DEFER), so no workgroup reads a field
-// another writes here.
-__global__ __launch_bounds__(kBlock) void k_update_p_jacobi(int n, double *__restrict__ p,
+// Preconditioned CG: p = z + beta p with the convergence test and beta
+// formed in the same launch, as k_update_p_fold does for plain CG: every
+// workgroup sums the r.r and r.z partials itself (the order of the
+// reduction launches) and workgroup 0 records the step (R_RR, then
+// R_RZ_DEFER), so no workgroup reads a field another writes here.
+__global__ __launch_bounds__(kBlock) void k_update_p_pcg(int n, double *__restrict__ p,
                                                             const double *__restrict__ z, CgState *st,
                                                             const double *__restrict__ part_rr,
                                                             const double *__restrict__ part_rz, int n_part) {
@@ -798,9 +802,11 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
 
 // Preconditioned CG: CgCore's buffers and reductions plus z and D^-1, and
 // for the bfloat16 polynomial preconditioner the FP32 vectors of its
-// product.  Polynomial: eight launches per iteration (SpMV + p.q, alpha, x/r
-// update + r.r + t = D^-1 r, convergence, bfloat16 SpMV, z + r.z, beta, p
-// update).  Jacobi: three to five (see its kernels).
+// product.  Polynomial: eight launches per iteration on the largest systems
+// (SpMV + p.q, alpha, x/r update + r.r + t = D^-1 r, convergence, bfloat16
+// SpMV, z + r.z, beta, p update), five on small ones, where alpha is formed
+// in the x/r update and the convergence test and beta in the p update.
+// Jacobi: three to five (see its kernels).
 struct PcgCore : CgCore<double, double> {
     double *z = nullptr, *dinv = nullptr, *part_rz = nullptr;
     float *t = nullptr, *sv = nullptr;
@@ -819,7 +825,7 @@ struct PcgCore : CgCore<double, double> {
             hipLaunchKernelGGL(k_update_xr_jacobi, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, z,
                                st, part_seg, fold_alpha ? M.n_seg : -1, part_vec, part_rz);
             if (n_wg <= kFoldBeta) {
-                hipLaunchKernelGGL(k_update_p_jacobi, dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st, part_vec,
+                hipLaunchKernelGGL(k_update_p_pcg, dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st, part_vec,
                                    part_rz, n_wg);
             } else {
                 hipLaunchKernelGGL(k_reduce_rr_rz, dim3(1), dim3(kBlock), 0, ts, part_vec, part_rz, n_wg, st);
@@ -827,15 +833,24 @@ struct PcgCore : CgCore<double, double> {
             }
             return hipGetLastError();
         }
-        reduce(part_seg, M.n_seg, R_ALPHA, ts);
+        const bool fold_alpha = M.n_seg <= kFoldAlpha, fold_beta = n_wg <= kFoldBeta;
+        if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, ts);
         hipLaunchKernelGGL(k_update_xr_pcg, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, x, r, p, q, dinv, t, st,
-                           part_vec);
-        reduce(part_vec, n_wg, R_RR, ts);
+                           part_seg, fold_alpha ? M.n_seg : -1, part_vec);
+        // folded: the convergence test waits for the p update, so on the last
+        // iteration the preconditioner runs once more (it writes neither x nor r)
+        if (!fold_beta) reduce(part_vec, n_wg, R_RR, ts);
         e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr, done, ts);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, r, sv, dinv, z, st, part_vec, 0);
-        reduce(part_vec, n_wg, R_RZ, ts);
-        hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+        double *rz = fold_beta ? part_rz : part_vec;
+        hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, r, sv, dinv, z, st, rz, 0);
+        if (fold_beta) {
+            hipLaunchKernelGGL(k_update_p_pcg, dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st, part_vec,
+                               part_rz, n_wg);
+        } else {
+            reduce(part_vec, n_wg, R_RZ, ts);
+            hipLaunchKernelGGL((k_update_p<double>), dim3(grid_for(n)), dim3(kBlock), 0, ts, n, p, z, st);
+        }
         return hipGetLastError();
     }
 
@@ -1056,9 +1071,8 @@ static int cg_pcg(const spmv_matrix *A, const double *b, double *x, double tol, 
     if (rc) return rc;
     HIP_TRY(B.alloc(&C.z, (size_t)n));
     HIP_TRY(B.alloc(&C.dinv, (size_t)n));
-    if (jacobi) {
-        HIP_TRY(B.alloc(&C.part_rz, (size_t)C.n_wg));
-    } else {
+    HIP_TRY(B.alloc(&C.part_rz, (size_t)C.n_wg));
+    if (!jacobi) {
         HIP_TRY(B.alloc(&C.t, (size_t)n));
         HIP_TRY(B.alloc(&C.sv, (size_t)n));
     }
