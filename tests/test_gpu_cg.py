@@ -301,3 +301,28 @@ def test_pcg_jacobi_rejects_sell_and_bad_diagonal():
         with spmv.Matrix.from_csr(B) as M:
             with pytest.raises(spmv.SpmvError, match="positive finite diagonal"):
                 M.cg(torch.ones(n, dtype=torch.float64, device=DEV), mode=spmv.CG_PCG_JACOBI)
+
+
+@pytest.mark.parametrize("mode", [spmv.CG_FP64, spmv.CG_PCG_BF16])
+def test_table1_c400k_against_oracle(mode):
+    # 398,000 rows: the SpMV leaves more than 1,024 p.q partials (alpha from a
+    # reduction launch) and the x/r update at most 1,024 r.r partials (the
+    # convergence test and beta formed inside the p update)
+    A = mg.table1_matrix("C400K")
+    b = mg.uniform(A.n_rows, 73, 1)
+    tol = 1e-10
+    if mode == spmv.CG_FP64:
+        ref = oracle.cg(A, b, tol=tol, max_iter=20000)
+    else:
+        ref, _ = oracle.pcg_bf16(A, b, tol=tol, max_iter=20000)
+    assert ref.status == 0
+    with spmv.Matrix.from_csr(A, bf16=(mode == spmv.CG_PCG_BF16)) as M:
+        assert M.info["n_tiles"] > 1024 and (A.n_rows + 1023) // 1024 <= 1024
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=tol, mode=mode)
+    x = x.cpu().numpy()
+    assert info.status == 0
+    rr = true_rel_residual(A, x, b)
+    assert rr <= 1.05 * tol and abs(info.rel_residual - rr) <= 0.05 * tol
+    kappa = gershgorin_kappa(A, 1e-3)
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 2 * kappa * tol
+    assert abs(info.iterations - ref.iterations) <= 0.1 * ref.iterations
