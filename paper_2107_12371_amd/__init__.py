@@ -213,8 +213,15 @@ def _torch():
 
 def _stream_ptr(stream):
     torch = _torch()
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is None:
+        # the current stream's raw handle without building a Stream object
+        # (2.5 us per call, a third of a small product's host cost); the same
+        # stream torch.cuda.current_stream() names, capture streams included
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return ctypes.c_void_p(raw(torch.cuda.current_device()))
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _check_vec(t, dtype, n: int, name: str):
