@@ -172,7 +172,9 @@ template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
     using Regs = typename CwinRegsSel<V, NT>::type;
     __shared__ A buf[Regs::kProd];
+    constexpr int kMapWords = Regs::kProd / 32;
     __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
+    __shared__ uint2 run_map[kMapWords];  // per 32 window positions: run-start bits, starts before them
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
     const int b = blockIdx.x;
@@ -198,24 +200,43 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
     RowPre<Y, EPI> pre;
     pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
     const int nr = d.wcnt;
-    if ((int)threadIdx.x < nr) {
-        run_x[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x)];
-        run_p[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x) + 1];
+    if ((int)threadIdx.x < kWave) {
+        // wave 0 (nr <= 64 runs): the runs, and a bitmap of the positions
+        // where runs start with, per 32 positions, the number of starts
+        // before them, so that a position's run is one popcount away.  The
+        // steps are LDS operations of one wave, which complete in order.
+        const int lane = threadIdx.x;
+        for (int j = lane; j < kMapWords; j += kWave) run_map[j].x = 0u;
+        if (lane < nr) {
+            const int rp = g.runs[2 * (d.woff + lane) + 1];
+            run_x[lane] = g.runs[2 * (d.woff + lane)];
+            run_p[lane] = rp;
+            atomicOr(&run_map[rp >> 5].x, 1u << (rp & 31));
+        }
+        if (lane == 0) run_p[nr] = d.width;
+        int before = 0;
+        for (int j0 = 0; j0 < kMapWords; j0 += kWave) {
+            const int j = j0 + lane;
+            const int c = j < kMapWords ? __popc(run_map[j].x) : 0;
+            int incl = c;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            if (j < kMapWords) run_map[j].y = (uint32_t)(before + incl - c);
+            before += __shfl(incl, kWave - 1);
+        }
     }
-    if (threadIdx.x == 0) run_p[nr] = d.width;
     __syncthreads();
-    // stage the window: position w lies in the run r with run_p[r] <= w < run_p[r+1]
+    // stage the window: position w lies in the run r with run_p[r] <= w <
+    // run_p[r+1], r = (run starts at positions <= w) - 1 (run_p[0] = 0)
     constexpr int kStage = Regs::kProd / kBlock;
     A xs[kStage];
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
         const int w = min((int)threadIdx.x + i * kBlock, d.width - 1);
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (run_p[mid] <= w) lo = mid;
-            else hi = mid - 1;
-        }
+        const uint2 m = run_map[w >> 5];
+        const int lo = (int)m.y + __popc(m.x & ((2u << (w & 31)) - 1u)) - 1;
         xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
     }
 #pragma unroll
