@@ -161,6 +161,47 @@ __global__ __launch_bounds__(kBlock) void k_wave(SpmvArgs<V, X, Y> g) {
     }
 }
 
+// Wave 0 (a tile has at most 64 runs) loads the tile's runs and builds, over
+// the window's positions, a bitmap of the positions where runs start with,
+// per 32 positions, the number of starts before them, so that a position's
+// run is one popcount away (cwin_run_of).  The steps are LDS operations of
+// one wave, which complete in order; the caller synchronises the workgroup
+// before the map is read.
+template <int kMapWords>
+__device__ __forceinline__ void cwin_load_runs(const int32_t *__restrict__ runs, const TileDesc &d, int32_t *run_x,
+                                               int32_t *run_p, uint2 *run_map) {
+    if ((int)threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x, nr = d.wcnt;
+    for (int j = lane; j < kMapWords; j += kWave) run_map[j].x = 0u;
+    if (lane < nr) {
+        const int rp = runs[2 * (d.woff + lane) + 1];
+        run_x[lane] = runs[2 * (d.woff + lane)];
+        run_p[lane] = rp;
+        atomicOr(&run_map[rp >> 5].x, 1u << (rp & 31));
+    }
+    if (lane == 0) run_p[nr] = d.width;
+    int before = 0;
+    for (int j0 = 0; j0 < kMapWords; j0 += kWave) {
+        const int j = j0 + lane;
+        const int c = j < kMapWords ? __popc(run_map[j].x) : 0;
+        int incl = c;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        if (j < kMapWords) run_map[j].y = (uint32_t)(before + incl - c);
+        before += __shfl(incl, kWave - 1);
+    }
+}
+
+// The run r holding window position w, run_p[r] <= w < run_p[r + 1]: the
+// number of run starts at positions <= w, minus one (run_p[0] = 0).  The
+// same index as a binary search over run_p; no loop.
+__device__ __forceinline__ int cwin_run_of(const uint2 *run_map, int w) {
+    const uint2 m = run_map[w >> 5];
+    return (int)m.y + __popc(m.x & ((2u << (w & 31)) - 1u)) - 1;
+}
+
 // Compact windows (the paper's vector cache with short relative indices,
 // one tile at a time): the tile's x words -- its distinct columns merged into
 // runs -- are staged in LDS with contiguous loads, then every entry reads x
@@ -199,44 +240,15 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
     t.load(g.lidx, g.lidx12, g.val, li, d.s, d.e);
     RowPre<Y, EPI> pre;
     pre.load(g.row_ptr, g.x, g.b, d.r0, d.r1, d.s & ~3);
-    const int nr = d.wcnt;
-    if ((int)threadIdx.x < kWave) {
-        // wave 0 (nr <= 64 runs): the runs, and a bitmap of the positions
-        // where runs start with, per 32 positions, the number of starts
-        // before them, so that a position's run is one popcount away.  The
-        // steps are LDS operations of one wave, which complete in order.
-        const int lane = threadIdx.x;
-        for (int j = lane; j < kMapWords; j += kWave) run_map[j].x = 0u;
-        if (lane < nr) {
-            const int rp = g.runs[2 * (d.woff + lane) + 1];
-            run_x[lane] = g.runs[2 * (d.woff + lane)];
-            run_p[lane] = rp;
-            atomicOr(&run_map[rp >> 5].x, 1u << (rp & 31));
-        }
-        if (lane == 0) run_p[nr] = d.width;
-        int before = 0;
-        for (int j0 = 0; j0 < kMapWords; j0 += kWave) {
-            const int j = j0 + lane;
-            const int c = j < kMapWords ? __popc(run_map[j].x) : 0;
-            int incl = c;
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int t = __shfl_up(incl, o);
-                if (lane >= o) incl += t;
-            }
-            if (j < kMapWords) run_map[j].y = (uint32_t)(before + incl - c);
-            before += __shfl(incl, kWave - 1);
-        }
-    }
+    cwin_load_runs<kMapWords>(g.runs, d, run_x, run_p, run_map);
     __syncthreads();
-    // stage the window: position w lies in the run r with run_p[r] <= w <
-    // run_p[r+1], r = (run starts at positions <= w) - 1 (run_p[0] = 0)
+    // stage the window: position w lies in run cwin_run_of(w)
     constexpr int kStage = Regs::kProd / kBlock;
     A xs[kStage];
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
         const int w = min((int)threadIdx.x + i * kBlock, d.width - 1);
-        const uint2 m = run_map[w >> 5];
-        const int lo = (int)m.y + __popc(m.x & ((2u << (w & 31)) - 1u)) - 1;
+        const int lo = cwin_run_of(run_map, w);
         xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
     }
 #pragma unroll
@@ -263,8 +275,10 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
     using Regs = typename CwinRegsSel<V, NT>::type;
+    constexpr int kMapWords = Regs::kProd / 32;
     __shared__ A buf[Regs::kProd];
     __shared__ int32_t run_x[kCwinMaxRunsDev], run_p[kCwinMaxRunsDev + 1];
+    __shared__ uint2 run_map[kMapWords];
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -292,24 +306,14 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
             cur.load(g.lidx, g.lidx12, g.val, more ? ln : li, dn.s, dn.e);
             __syncthreads();
         } else {
-            const int nr = d.wcnt;
-            if ((int)threadIdx.x < nr) {
-                run_x[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x)];
-                run_p[threadIdx.x] = g.runs[2 * (d.woff + threadIdx.x) + 1];
-            }
-            if (threadIdx.x == 0) run_p[nr] = d.width;
+            cwin_load_runs<kMapWords>(g.runs, d, run_x, run_p, run_map);
             __syncthreads();
             constexpr int kStage = Regs::kProd / kBlock;
             A xs[kStage];
 #pragma unroll
             for (int i = 0; i < kStage; ++i) {
                 const int w = min((int)threadIdx.x + i * kBlock, d.width - 1);
-                int lo = 0, hi = nr - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (run_p[mid] <= w) lo = mid;
-                    else hi = mid - 1;
-                }
+                const int lo = cwin_run_of(run_map, w);
                 xs[i] = static_cast<A>(x[run_x[lo] + (w - run_p[lo])]);
             }
 #pragma unroll
