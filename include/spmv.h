@@ -82,8 +82,8 @@ typedef struct spmv_matrix spmv_matrix;
                               runs, at most tile_nnz staged words; other tiles
                               gather x directly.  With the default tile_nnz, AUTO
                               builds windows only for matrices of at least 512 MB
-                              (smaller ones are served from cache), and only
-                              binary64 products use them */
+                              (smaller ones are served from cache); products of
+                              every value precision use them */
 #define SPMV_WINDOW_OFF 1  /* direct L2 gathers everywhere */
 #define SPMV_WINDOW_RING 2 /* the paper's circular cache literally: one workgroup
                               walks a block of adjacent tiles, staging only the

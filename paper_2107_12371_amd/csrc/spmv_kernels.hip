@@ -486,22 +486,16 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             a.per_xcd = (M.n_cwin + 7) / 8;
             grid = 8 * a.per_xcd;
         }
-        // 8- and 4-byte values go through the windows (16M-row mesh matrix:
-        // FP64 0.60 vs 0.73 ms direct, FP32 0.42 vs 0.48, FP32 values with
-        // FP64 x 0.50 vs 0.56); bfloat16 products gain nothing from them
-        // (0.404 either way), so they treat the same tiles as direct tiles.
-        if constexpr (sizeof(V) >= 4) {
-            if (M.kernel == KV_PIPELINED && M.n_cwin >= 64) {
-                a.per_xcd = (M.n_cwin + 7) / 8;
-                const int resident = cwin_pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
-                a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
-                hipLaunchKernelGGL((k_cwin_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st,
-                                   a);
-            } else {
-                hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
-            }
+        // every value type goes through the windows (16M-row mesh matrix,
+        // with the popcount run lookup: FP64 0.567 vs 0.73 ms direct, FP32
+        // 0.327 vs 0.48, bfloat16 0.292 vs 0.405)
+        if (M.kernel == KV_PIPELINED && M.n_cwin >= 64) {
+            a.per_xcd = (M.n_cwin + 7) / 8;
+            const int resident = cwin_pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
+            a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
+            hipLaunchKernelGGL((k_cwin_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st, a);
         } else {
-            hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
     }
     if (M.n_long > 0) {
@@ -591,13 +585,11 @@ template <typename V, typename X, typename Y, typename A> static void warm_types
     pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
     pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
     pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
-    if constexpr (sizeof(V) == 8) {
-        cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_DOT>();
-        cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_RESID>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_PLAIN>();
-        cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
-        cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
-        cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
-    }
+    cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_DOT>();
+    cwin_pipe_occupancy<V, X, Y, A, 1024, EPI_RESID>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_PLAIN>();
+    cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_DOT>(); cwin_pipe_occupancy<V, X, Y, A, 2048, EPI_RESID>();
+    cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_PLAIN>(); cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_DOT>();
+    cwin_pipe_occupancy<V, X, Y, A, 4096, EPI_RESID>();
 }
 
 void prepare_launch_queries() {
