@@ -148,7 +148,8 @@ typedef struct spmv_info {
  * spmv_create: validate a host CSR matrix, build the analysis plan and copy
  * everything the products need to device memory.
  *   n_rows, n_cols  >= 0
- *   nnz             stored entries, 0 <= nnz <= 2^31 - 64
+ *   nnz             stored entries, 0 <= nnz <= 2^31 - 2^16 (the kernels'
+ *                   32-bit entry offsets reach a tile past the last entry)
  *   row_ptr         int32[n_rows + 1]: row_ptr[0] = 0, non-decreasing,
  *                   row_ptr[n_rows] = nnz
  *   col_idx         int32[nnz], each in [0, n_cols); unsorted columns and
@@ -181,7 +182,8 @@ int spmv_get_info(const spmv_matrix *A, spmv_info *info);
  * The call only enqueues kernels on `stream` (no allocation, copy, memset or
  * synchronisation), so a caller may record it into a HIP graph by stream
  * capture and replay it; the same holds for the other spmv_apply_* calls
- * and spmv_spmm / bsr3_spmm.
+ * and spmv_spmm / bsr3_spmm.  On a matrix without stored entries (nnz = 0)
+ * these calls only fill y with zeros: x is never read and may be NULL.
  */
 int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
 
@@ -202,7 +204,8 @@ int spmv_apply_bf16(const spmv_matrix *A, const float *x, float *y, void *stream
  * spmv_create_bsr3: a matrix of dense 3x3 blocks in block-CSR form, as
  * produced by coupled three-component operators on a mesh (velocity u, v, w
  * per cell; paper Sec. 2: row i = cell i, its blocks = neighbour cells).
- *   n_block_rows, n_block_cols >= 0; nnz_blocks stored blocks
+ *   n_block_rows, n_block_cols >= 0; nnz_blocks stored blocks,
+ *              0 <= nnz_blocks <= (2^31 - 2^16) / 9
  *   brow_ptr   int32[n_block_rows + 1] (same rules as CSR row_ptr)
  *   bcol_idx   int32[nnz_blocks] in [0, n_block_cols)
  *   bvalues    double[9 * nnz_blocks], each block row-major

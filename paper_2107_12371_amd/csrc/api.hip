@@ -124,6 +124,11 @@ static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, voi
     if (A->M.n_rows == 0) return SPMV_OK;
     DeviceGuard g(A->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
+    if (A->M.nnz == 0) {
+        // no stored entry: y = 0 without reading x (which may be NULL or empty)
+        const hipError_t z = launch_zero_fill<Y>(y, A->M.n_rows, static_cast<hipStream_t>(stream));
+        return z == hipSuccess ? SPMV_OK : hip_fail(z, "zero fill");
+    }
     hipError_t e = launch_spmv<V, X, Y, Acc>(A->M, val, x, y, EPI_PLAIN, nullptr, nullptr, nullptr,
                                              static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "spmv launch");
@@ -422,6 +427,10 @@ extern "C" int spmv_spmm(const spmv_matrix *A, int32_t k, const double *X, doubl
         return fail(SPMV_EINVAL, "X and Y overlap");
     DeviceGuard g(A->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
+    if (A->M.nnz == 0) {
+        const hipError_t z = launch_zero_fill<double>(Y, (int64_t)k * A->M.n_rows, static_cast<hipStream_t>(stream));
+        return z == hipSuccess ? SPMV_OK : hip_fail(z, "zero fill");
+    }
     const hipError_t e = launch_spmm(A, X, Y, k, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "spmm launch");
     return SPMV_OK;
@@ -447,6 +456,10 @@ static int spmm_typed(const spmv_matrix *A, const V *val, int32_t k, const T *X,
     if (ny == 0) return SPMV_OK;
     DeviceGuard g(A->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "making the matrix's device current");
+    if (A->M.nnz == 0) {
+        const hipError_t z = launch_zero_fill<T>(Y, (int64_t)ny, static_cast<hipStream_t>(stream));
+        return z == hipSuccess ? SPMV_OK : hip_fail(z, "zero fill");
+    }
     hipError_t e = launch_bsr3<V, T>(A->M, val, k, X, Y, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "bsr3 launch");
     return SPMV_OK;
@@ -493,7 +506,7 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     *out = nullptr;
     if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP | SPMV_DEVICE_PTRS))
         return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
-    if (nnz_blocks > (int64_t)(INT32_MAX / 9) - 64) return fail(SPMV_EINVAL, "too many blocks");
+    if (nnz_blocks > kMaxNnz / 9) return fail(SPMV_EINVAL, "nnz_blocks = %lld exceeds (2^31 - 2^16) / 9", (long long)nnz_blocks);
     if (flags & SPMV_DEVICE_PTRS) {
         if (n_block_rows < 0 || nnz_blocks < 0)
             return fail(SPMV_EINVAL, "n_block_rows = %d, nnz_blocks = %lld", n_block_rows, (long long)nnz_blocks);

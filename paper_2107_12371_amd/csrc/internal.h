@@ -22,6 +22,11 @@ const char *last_error();
 // invalidates the capture; holding this lock on both sides keeps them apart.
 std::mutex &capture_gate();
 
+// Largest accepted number of stored entries (scalar CSR): 2^31 - 2^16, so
+// that every 32-bit entry offset a kernel forms (at most a 4096-entry tile,
+// or a 510-block tile of 9 values, past the last entry) stays below 2^31.
+constexpr int64_t kMaxNnz = (int64_t(1) << 31) - (int64_t(1) << 16);
+
 // Host-side CSR validation (paper Sec. 4.2 storage: int32 columns, row
 // pointers).  Returns SPMV_OK or SPMV_EINVAL with a message.
 int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,

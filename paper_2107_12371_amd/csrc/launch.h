@@ -41,6 +41,11 @@ template <typename V, typename X, typename Y, typename A>
 hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
                        double *part, const int *done, hipStream_t st);
 
+// y[0..n) = 0 with a fill kernel (never a memset node, so a product on a
+// matrix without stored entries stays capturable like any other); the
+// products take this path when nnz = 0 and never touch x then.
+template <typename T> hipError_t launch_zero_fill(T *y, int64_t n, hipStream_t st);
+
 // Opts every window-kernel instantiation into up to 8192 ring words of
 // dynamic LDS.  Called once when a matrix with window blocks is created.
 hipError_t prepare_window_kernels();

@@ -51,8 +51,10 @@ std::mutex &capture_gate() {
 int validate_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col_idx) {
     if (n_rows < 0 || n_cols < 0) return fail(SPMV_EINVAL, "negative dimension (%d x %d)", n_rows, n_cols);
-    if (nnz < 0 || nnz > (int64_t)INT32_MAX - 64)
-        return fail(SPMV_EINVAL, "nnz = %lld outside [0, 2^31 - 64]", (long long)nnz);
+    // the kernels index entries with 32-bit offsets up to a tile (or a
+    // 3x3-block tile) past the last one, so nnz keeps 2^16 of headroom
+    if (nnz < 0 || nnz > kMaxNnz)
+        return fail(SPMV_EINVAL, "nnz = %lld outside [0, 2^31 - 2^16]", (long long)nnz);
     if (!row_ptr) return fail(SPMV_EINVAL, "row_ptr is NULL");
     if (nnz > 0 && !col_idx) return fail(SPMV_EINVAL, "col_idx is NULL with nnz > 0");
     if (row_ptr[0] != 0) return fail(SPMV_EINVAL, "row_ptr[0] = %d, expected 0", row_ptr[0]);

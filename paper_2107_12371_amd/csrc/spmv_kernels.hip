@@ -391,7 +391,20 @@ __global__ __launch_bounds__(kBlock) void k_window(SpmvArgs<V, X, Y> g) {
     }
 }
 
+template <typename T> __global__ __launch_bounds__(kBlock) void k_fill_zero(T *__restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) y[i] = T(0);
+}
+
 // ---------------------------------------------------------------- launch
+
+template <typename T> hipError_t launch_zero_fill(T *y, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3((unsigned)blocks), dim3(kBlock), 0, st, y, n);
+    return hipGetLastError();
+}
+template hipError_t launch_zero_fill<double>(double *, int64_t, hipStream_t);
+template hipError_t launch_zero_fill<float>(float *, int64_t, hipStream_t);
 
 // Resident workgroups per CU of the pipelined kernel (queried once per
 // instantiation; every thread that races here computes the same value).

@@ -4,7 +4,8 @@
 // under AddressSanitizer.  Device memory is host memory, copies are memcpy,
 // kernel launches and graph replays do nothing.
 //
-// Two behaviours are scripted:
+// Kernel launches are logged by name (mock_launch_log).  Two behaviours are
+// scripted:
 //  * a 96-byte device-to-host copy is the CG solver reading its scalar state
 //    (10 doubles, 4 int32): it reads back a converged state, so every solve
 //    takes the capture -> replay -> confirm path and ends;
@@ -17,9 +18,33 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 
 namespace {
 thread_local int t_device = 0;
+
+// host stub -> registered device name, and the names of launched kernels.
+// Constructed on first use: the compiler's registration hooks run from other
+// objects' static constructors, possibly before this file's globals exist.
+struct Registry {
+    std::mutex mu;
+    std::map<const void *, std::string> names;
+    std::string log;
+};
+Registry &registry() {
+    static Registry *r = new Registry();
+    return *r;
+}
+
+void record_launch(const void *f) {
+    Registry &g = registry();
+    std::lock_guard<std::mutex> lk(g.mu);
+    auto it = g.names.find(f);
+    g.log += it == g.names.end() ? std::string("?") : it->second;
+    g.log += '\n';
+}
 std::atomic<long> n_h2d{0};
 
 long fail_every() {
@@ -115,7 +140,13 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *, in
     return hipSuccess;
 }
 hipError_t hipFuncSetAttribute(const void *, hipFuncAttribute, int) { return hipSuccess; }
-hipError_t hipLaunchKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) { return hipSuccess; }
+// kernel launches are recorded by the device name the compiler registered
+// for the host stub (mock_launch_log), so a driver can check which kernels a
+// call launched
+hipError_t hipLaunchKernel(const void *f, dim3, dim3, void **, size_t, hipStream_t) {
+    record_launch(f);
+    return hipSuccess;
+}
 
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
 hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
@@ -141,8 +172,23 @@ void **__hipRegisterFatBinary(const void *) {
     static void *handle = nullptr;
     return &handle;
 }
-void __hipRegisterFunction(void **, const void *, char *, const char *, unsigned int, void *, void *, dim3 *, dim3 *,
-                           int *) {}
+void __hipRegisterFunction(void **, const void *host, char *, const char *name, unsigned int, void *, void *, dim3 *,
+                           dim3 *, int *) {
+    Registry &g = registry();
+    std::lock_guard<std::mutex> lk(g.mu);
+    g.names[host] = name ? name : "";
+}
+
+// Mangled device names of the kernels launched since the last call, one per
+// line; the log is cleared.  The returned buffer is valid until the next call.
+const char *mock_launch_log(void) {
+    static std::string out;
+    Registry &g = registry();
+    std::lock_guard<std::mutex> lk(g.mu);
+    out.swap(g.log);
+    g.log.clear();
+    return out.c_str();
+}
 void __hipUnregisterFatBinary(void **) {}
 void __hipRegisterVar(void **, void *, char *, const char *, int, size_t, int, int) {}
 hipError_t __hipPushCallConfiguration(dim3, dim3, size_t, hipStream_t) { return hipSuccess; }

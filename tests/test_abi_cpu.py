@@ -54,6 +54,24 @@ def test_validation_errors():
     assert "row_ptr" in str(_bad(2, 2, [0, 2, 1], [0, 1]))
 
 
+def test_nnz_limit_leaves_headroom_for_tile_offsets():
+    # the kernels form 32-bit entry offsets up to a tile past the last entry,
+    # so the largest accepted nnz is 2^31 - 2^16; one more is rejected before
+    # any array is read (row_ptr here is too short to be read at all)
+    L = spmv.lib()
+    n_tiles = ctypes.c_int32()
+    lim = (1 << 31) - (1 << 16)
+    for nnz, code in ((lim + 1, spmv.SPMV_EINVAL), ((1 << 31) - 64, spmv.SPMV_EINVAL)):
+        rc = L.spmv_plan_inspect(1, 1, nnz, np.zeros(2, np.int32).ctypes.data, None, None,
+                                 ctypes.byref(n_tiles), None, None, None, None, None, None, None, None, None)
+        assert rc == code
+        assert "2^31 - 2^16" in spmv.lib().spmv_last_error().decode()
+    h = ctypes.c_void_p()
+    rc = L.spmv_create_bsr3(1, 1, lim // 9 + 1, np.zeros(2, np.int32).ctypes.data, None, None, 0,
+                            ctypes.byref(h))
+    assert rc == spmv.SPMV_EINVAL and not h.value
+
+
 def test_create_rejects_malformed_input_before_touching_the_device():
     L = spmv.lib()
     h = ctypes.c_void_p()

@@ -176,6 +176,26 @@ def test_pcg_config0_against_oracle(cfg0, pcg_ref):
     assert info.iterations < 0.8 * ref.iterations
 
 
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_pcg_bf16_first_iterates_match_the_oracle(cfg0, k):
+    # k steps from zero (tol = 0, so the cap ends the solve) against the
+    # oracle's k-step iterate, whose preconditioner is pinned to a dense
+    # M^-1 built from the bfloat16 copy.  The GPU applies that copy to an
+    # FP32 vector with FP32 sums, which moves the iterate by about 5e-8
+    # relative (emulated on the CPU); the same steps with the FP32 or
+    # binary64 values in the preconditioner move it by about 1e-3, so the
+    # 1e-6 bound tells the two apart.
+    A, b, _ = cfg0
+    ref, _ = oracle.pcg_bf16(A, b, tol=0.0, max_iter=k)
+    assert ref.status == 1 and ref.iterations == k
+    with spmv.Matrix.from_csr(A, bf16=True) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=0.0, max_iter=k, mode=spmv.CG_PCG_BF16,
+                       raise_on_error=False)
+    assert info.status == spmv.SPMV_ENOTCONV and info.iterations == k
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
 def test_pcg_diagonal_one_iteration_and_reproducible():
     n = 4000
     d = np.tile([1.0, 2.5, 4.0, 7.0, 0.375], n // 5)

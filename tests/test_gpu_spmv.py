@@ -72,6 +72,26 @@ def test_zero_nnz_and_zero_rows():
     A = mg.CSR(4, 3, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0))
     y, _ = run64(A, np.ones(3))
     assert np.all(y == 0.0)
+    # without stored entries every product only zero-fills its output (a y
+    # full of NaN comes back zero), with a real x and with no column at all
+    for n_cols in (3, 0):
+        Z = mg.CSR(4, n_cols, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        with spmv.Matrix.from_csr(Z, fp32=True, bf16=True) as M:
+            x64 = torch.ones(n_cols, dtype=torch.float64, device=DEV)
+            x32 = torch.ones(n_cols, dtype=torch.float32, device=DEV)
+            for fn, x, dt in ((M.apply, x64, torch.float64), (M.apply_f32, x32, torch.float32),
+                              (M.apply_f32v, x64, torch.float64), (M.apply_bf16, x32, torch.float32)):
+                y = torch.full((4,), float("nan"), dtype=dt, device=DEV)
+                fn(x, y)
+                assert bool(torch.all(y == 0))
+            Y = torch.full((4, 3), float("nan"), dtype=torch.float64, device=DEV)
+            M.spmm(torch.ones((n_cols, 3), dtype=torch.float64, device=DEV), Y)
+            assert bool(torch.all(Y == 0))
+    B = mg.CSR(2, 2, np.zeros(3, np.int32), np.zeros(0, np.int32), np.zeros((0, 3, 3)))
+    with spmv.Matrix.from_bsr3(2, 2, B.row_ptr, B.col_idx, B.values) as M:
+        Y = torch.full((6, 2), float("nan"), dtype=torch.float64, device=DEV)
+        M.spmm(torch.ones((6, 2), dtype=torch.float64, device=DEV), Y)
+        assert bool(torch.all(Y == 0))
     A = mg.CSR(0, 3, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
     with spmv.Matrix.from_csr(A) as M:
         y = M.apply(to_dev(np.ones(3)))
@@ -313,6 +333,53 @@ def test_fp32_dyadic_bitwise():
     with spmv.Matrix.from_csr(A, fp32=True) as M:
         y32 = M.apply_f32(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
     assert np.array_equal(y32, y_ref)
+
+
+def _bf16_bits(a):
+    """bfloat16 rounding of float32(a) by the bit recipe (add 0x7fff plus the
+    lowest kept bit, truncate): nearest, ties to even."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("window", [spmv.WINDOW_OFF, spmv.WINDOW_AUTO])
+def test_bf16_dyadic_bitwise(window):
+    # Values m/1024 (11 significant bits) are not bfloat16 numbers; their
+    # bfloat16 roundings have 8 bits and x = k/64 (|k| <= 64) has 7, so every
+    # product is a multiple of 2^-14 and every partial sum of a row stays
+    # below 2^6: exact in FP32 in any order.  The bfloat16 product must
+    # therefore equal the oracle run on the rounded values bit for bit, and
+    # a path that read the FP32 or binary64 values would give the oracle's
+    # result on the unrounded ones, which differs on most rows.
+    A = mg.config0(dyadic=True)
+    x = mg.dyadic_x32(A.n_cols, seed=5)
+    At = mg.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, _bf16_bits(A.values))
+    assert np.count_nonzero(At.values != A.values) > A.nnz // 2
+    y16_ref, _ = oracle.spmv(At, x)
+    y_unrounded, _ = oracle.spmv(A, x)
+    params = {"tile_nnz": 2048, "window_mode": window}
+    with spmv.Matrix.from_csr(A, bf16=True, params=params) as M:
+        assert (M.info["n_window_tiles"] > 0) == (window == spmv.WINDOW_AUTO)
+        y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y16, y16_ref)
+    assert np.count_nonzero(y16 != y_unrounded) > A.n_rows // 2
+
+
+def test_bf16_rounding_is_visible():
+    # on non-dyadic values the bfloat16 product's error against the binary64
+    # oracle is of the order of 2^-9 of the row scale; an FP32-value product
+    # stays below (m + 2) 2^-24, four orders smaller
+    A = mg.config0()
+    x = mg.uniform(A.n_cols, 19, 0)
+    y_ref, bound, m = _bounds(A, x)
+    with spmv.Matrix.from_csr(A, bf16=True) as M:
+        y16 = M.apply_bf16(to_dev(x, torch.float32)).cpu().numpy().astype(np.float64)
+    ratio = np.abs(y16 - y_ref) / np.maximum(bound, 1e-300)
+    assert np.all(ratio <= 1.01 * (2.0 ** -8 + (m + 1) * 2.0 ** -24))
+    assert np.max(ratio) > 2.0 ** -12
+    assert np.max(ratio) > 100 * np.max((m + 2) * 2.0 ** -24)
 
 
 def test_missing_copies_and_bad_arguments():

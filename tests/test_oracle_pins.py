@@ -412,6 +412,62 @@ def test_pcg_zero_rhs_and_bad_diagonal():
     assert r.status == 3
 
 
+def _dense_bf16_pcg(Ad, b, k, w=None, rounded=True):
+    """k steps of textbook preconditioned CG (Saad, Alg. 9.1) from x0 = 0 in
+    dense numpy, with the preconditioner formed here as a dense matrix:
+    A~ = the bfloat16 rounding of A's entries by the bit recipe (or A itself
+    when rounded is False), w = 1.9 / max_i sum_j |a~_ij| / sqrt(d_i d_j)
+    unless given, M^-1 = w D^-1 (2 I - w A~ D^-1).  Returns (x_k, w)."""
+    nz = np.nonzero(Ad)
+    At = np.zeros_like(Ad)
+    At[nz] = _bf16_bits_round(Ad[nz]) if rounded else Ad[nz]
+    dinv = 1.0 / np.diag(Ad)
+    if w is None:
+        w = 1.9 / np.max(np.abs(At) @ np.sqrt(dinv) * np.sqrt(dinv))
+    Dinv = np.diag(dinv)
+    Minv = w * Dinv @ (2.0 * np.eye(len(b)) - w * At @ Dinv)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = Minv @ r
+    p = z.copy()
+    rho = r @ z
+    for _ in range(k):
+        q = Ad @ p
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = Minv @ r
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return x, w
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_pcg_bf16_iterates_match_a_dense_preconditioner(k):
+    # The preconditioner's action is pinned through the iterates: after k
+    # steps from zero the oracle's x must equal dense PCG with an explicitly
+    # built M^-1 in the bfloat16 copy.  Values U[0.5, 1.5) are not bfloat16
+    # numbers, so reading the binary64 values instead of the rounded copy
+    # moves the iterate by about 2^-9 relative, and any change of the
+    # polynomial's coefficients moves it by far more; the tolerance is the
+    # rounding noise of two summation orders over six steps.
+    A = mg.lattice(6, 5, 5, "stencil27", seed=97)
+    Ad = _dense(A)
+    assert np.count_nonzero(Ad) == A.nnz
+    b = mg.uniform(A.n_rows, 97, 1)
+    x_ref, w_ref = _dense_bf16_pcg(Ad, b, k)
+    r, w = oracle.pcg_bf16(A, b, tol=0.0, max_iter=k)
+    assert r.status == 1 and r.iterations == k
+    assert abs(w - w_ref) <= 1e-14 * w_ref
+    scale = np.max(np.abs(x_ref))
+    assert np.max(np.abs(r.x - x_ref)) <= 1e-12 * scale
+    # the pin can see the rounding: the same steps with the binary64 values
+    # in the polynomial (same weight) land more than 1000x the tolerance away
+    x64, _ = _dense_bf16_pcg(Ad, b, k, w=w_ref, rounded=False)
+    assert np.max(np.abs(x64 - x_ref)) > 1e-9 * scale
+
+
 # ------------------------------------- preconditioned CG (Jacobi)
 
 def _badly_scaled(seed):

@@ -3,6 +3,10 @@ against a mock HIP runtime (tests/host_mock/mock_hip.cpp) under
 AddressSanitizer and ThreadSanitizer, driven with the serving tests' request
 mixes.
 
+A second driver (abi_driver.cpp) calls the product entry points on
+matrices without stored entries and checks, through the mock's launch log,
+that they only zero-fill y and never launch a kernel that reads x.
+
 The regression case: when a matrix upload fails, the request reports the
 error and the matrix must not stay marked resident without a device handle
 (that state made the next request on the matrix dereference a null handle in
@@ -44,31 +48,41 @@ def _build(tmp_path_factory, sanitizer):
     for f in (os.path.splitext(src)[0] for src in LIB_SOURCES.CXX_SOURCES):
         jobs.append([CLANG, "-O1", "-g", "-std=c++17", "-fPIC", f"-fsanitize={sanitizer}", *inc, "-c",
                      os.path.join(CSRC, f + ".cpp"), "-o", str(out / (f + ".o"))])
-    jobs.append([CLANG, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizer}", *inc, "-c",
-                 os.path.join(MOCK, "server_driver.cpp"), "-o", str(out / "server_driver.o")])
+    drivers = ("server_driver", "abi_driver")
+    for d in drivers:
+        jobs.append([CLANG, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizer}", *inc, "-c",
+                     os.path.join(MOCK, d + ".cpp"), "-o", str(out / (d + ".drv"))])
     procs = [subprocess.Popen(j, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True) for j in jobs]
     for j, p in zip(jobs, procs):
         log = p.communicate()[0]
         assert p.returncode == 0, f"{' '.join(j)}\n{log}"
     objs = sorted(str(p) for p in out.glob("*.o"))
-    exe = str(out / "server_driver")
-    r = subprocess.run([CLANG, f"-fsanitize={sanitizer}", "-g", "-o", exe, *objs, "-lpthread"],
-                       capture_output=True, text=True)
-    assert r.returncode == 0, r.stdout + r.stderr
-    return exe, out
+    exes = {}
+    for d in drivers:
+        exe = str(out / d)
+        r = subprocess.run([CLANG, f"-fsanitize={sanitizer}", "-g", "-o", exe, str(out / (d + ".drv")), *objs,
+                            "-lpthread"], capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
+        exes[d] = exe
+    return exes, out
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
-    exe, out = _build(tmp_path_factory, "address")
-    yield exe
+def drivers_asan(tmp_path_factory):
+    exes, out = _build(tmp_path_factory, "address")
+    yield exes
     shutil.rmtree(out, ignore_errors=True)
 
 
 @pytest.fixture(scope="module")
+def driver(drivers_asan):
+    return drivers_asan["server_driver"]
+
+
+@pytest.fixture(scope="module")
 def driver_tsan(tmp_path_factory):
-    exe, out = _build(tmp_path_factory, "thread")
-    yield exe
+    exes, out = _build(tmp_path_factory, "thread")
+    yield exes["server_driver"]
     shutil.rmtree(out, ignore_errors=True)
 
 
@@ -108,3 +122,14 @@ def test_server_threads_race_free(driver_tsan, every):
     completed, failed, upload_failed = run(driver_tsan, 6, every)
     assert completed > 0
     assert (upload_failed > 0) == (every is not None)
+
+
+def test_products_without_stored_entries_never_read_x(drivers_asan):
+    # nnz = 0 (also with no column at all): every product entry point accepts
+    # x = NULL, returns SPMV_OK and launches only the zero fill of y; a
+    # matrix with entries still launches its product kernel and rejects a
+    # NULL x
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+    r = subprocess.run([drivers_asan["abi_driver"]], capture_output=True, text=True, env=env, timeout=120)
+    assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert r.returncode == 0 and "summary failures=0" in r.stdout, r.stdout[-4000:] + r.stderr[-2000:]
