@@ -65,6 +65,9 @@ typedef struct spmv_matrix spmv_matrix;
 #define SPMV_VALUES_FP32 0x1u   /* also keep an FP32 copy of the values */
 #define SPMV_VALUES_BF16 0x2u   /* also keep a BF16 copy of the values */
 #define SPMV_NO_XCD_REMAP 0x4u  /* keep launch order = tile order (no XCD grouping) */
+#define SPMV_XCD_CONTIGUOUS 0x10u /* 3x3 block CSR: deal one contiguous range of tiles to each
+                                     XCD instead of chunks of 16 tiles in turn (scalar CSR:
+                                     spmv_params.xcd_chunk = -2) */
 #define SPMV_DEVICE_PTRS 0x8u   /* row_ptr, col_idx and values are device (or managed)
                                    arrays of the current device, holding n_rows + 1, nnz
                                    and nnz elements (9 nnz_blocks values for block CSR);
@@ -110,6 +113,13 @@ typedef struct spmv_params {
     int32_t sell_sigma;    /* SELL: rows are sorted by length inside windows of
                               this many rows, a multiple of 64 (0: 4096; 64 keeps
                               the row order) */
+    int32_t xcd_chunk;     /* CSR row tiles: how tiles are dealt to the 8 XCDs
+                              (each has its own L2).  c (a power of two <= 4096):
+                              chunks of c consecutive tiles dealt to the XCDs in
+                              turn, so all XCDs work near the same rows and share
+                              one band of x in the memory-side cache (0: 16);
+                              -2: one contiguous range of tiles per XCD; -1: no
+                              grouping (same as SPMV_NO_XCD_REMAP) */
 } spmv_params;
 
 /* Storage formats of a scalar handle. */

@@ -27,6 +27,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 U64 = 2.0 ** -53
 SPMV_RTOL = 1e-12
@@ -38,13 +39,21 @@ def gamma(m) -> np.ndarray:
     return m * U64 / (1.0 - m * U64)
 
 
+def _compile(path: str, extra: list[str]) -> None:
+    tmp = path + ".tmp"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                    "-shared", "-Wall", *extra, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` (plain C, -O2, no FP contraction, no OpenMP)."""
+    """Compile ``liboracle.so`` (plain C, -O2, no FP contraction, no OpenMP:
+    the checker) and ``liboracle_omp.so`` (the same source with OpenMP, used
+    only to time the product on all host cores)."""
     if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                        "-shared", "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB_PATH)
+        _compile(_LIB_PATH, [])
+    if force or not os.path.exists(_OMP_PATH):
+        _compile(_OMP_PATH, ["-fopenmp"])
     return _LIB_PATH
 
 
@@ -74,6 +83,48 @@ def _L():
         lib.oracle_pcg_jacobi.argtypes = [i32, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
+
+
+_omp_lib = None
+
+
+def spmv_all_cores(A, x) -> np.ndarray:
+    """y = A x with the OpenMP timing build of ``oracle_spmv``: rows split
+    statically over OMP_NUM_THREADS threads, each row summed as in the
+    single-threaded checker (so the result is the same bits).  For timing
+    the oracle on all host cores; the tests check against ``spmv``."""
+    global _omp_lib
+    if _omp_lib is None:
+        if not os.path.exists(_OMP_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_OMP_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        lib.oracle_spmv.restype = None
+        lib.oracle_spmv.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        _omp_lib = lib
+    rp, ci, va = _csr(A)
+    x = _c(x, np.float64)
+    if x.shape[0] < A.n_cols:
+        raise ValueError("x too short")
+    y = np.empty(A.n_rows, np.float64)
+    _omp_lib.oracle_spmv(A.n_rows, _ptr(rp), _ptr(ci), _ptr(va), _ptr(x), _ptr(y), None)
+    return y
+
+
+def all_cores_threads() -> int:
+    """Threads the OpenMP timing build runs the product on."""
+    if _omp_lib is None:
+        spmv_all_cores(_Empty(), np.zeros(0))
+    return int(_omp_lib.oracle_threads())
+
+
+class _Empty:
+    n_rows = n_cols = 0
+    row_ptr = np.zeros(1, np.int32)
+    col_idx = np.zeros(0, np.int32)
+    values = np.zeros(0)
 
 
 def _c(a, dt):

@@ -9,7 +9,9 @@
  *
  * Precision: binary64 throughout, compiled with -ffp-contract=off so every
  * product and sum is rounded separately, in ascending index order, single
- * threaded.  Obviously correct beats fast here.
+ * threaded.  Obviously correct beats fast here.  A second build of this same
+ * file with OpenMP (liboracle_omp.so) exists only to time oracle_spmv on all
+ * host cores; it splits rows between threads and changes no row's sum.
  *
  * What is computed and where it comes from:
  *
@@ -63,6 +65,18 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads oracle_spmv runs on in this build (1 without OpenMP). */
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* y_i and bound_i for one row */
 static void row_sum(const int32_t *row_ptr, const int32_t *col_idx, const double *values,
@@ -79,8 +93,15 @@ static void row_sum(const int32_t *row_ptr, const int32_t *col_idx, const double
     *bi = b;
 }
 
+/* The row loop is the only place OpenMP may split work: the timing build
+ * (liboracle_omp.so, -fopenmp) runs rows on all host cores with a static
+ * schedule, each row summed exactly as here; the checker build has no
+ * OpenMP and runs single-threaded. */
 void oracle_spmv(int32_t n_rows, const int32_t *row_ptr, const int32_t *col_idx,
                  const double *values, const double *x, double *y, double *bound) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int32_t i = 0; i < n_rows; ++i) {
         double yi, bi;
         row_sum(row_ptr, col_idx, values, x, i, &yi, &bi);

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libspmv_gfx950.so")
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE = 0, -1, -2, -3
 SPMV_ENOTCONV, SPMV_EBUDGET, SPMV_ENOTSUP, SPMV_EBREAK = -4, -5, -6, -7
 SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP, SPMV_DEVICE_PTRS = 0x1, 0x2, 0x4, 0x8
+SPMV_XCD_CONTIGUOUS = 0x10
 WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
 FORMAT_CSR, FORMAT_SELL = 0, 1
 CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V, CG_PCG_JACOBI = 0, 1, 2, 3, 4
@@ -47,7 +48,8 @@ class spmv_params(ctypes.Structure):
     _fields_ = [("tile_nnz", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
                 ("window_block", ctypes.c_int32), ("window_gap", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("format", ctypes.c_int32), ("sell_sigma", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("format", ctypes.c_int32), ("sell_sigma", ctypes.c_int32),
+                ("xcd_chunk", ctypes.c_int32)]
 
 
 class spmv_info(ctypes.Structure):
@@ -299,14 +301,16 @@ class Matrix:
 
     @classmethod
     def from_bsr3(cls, n_block_rows: int, n_block_cols: int, brow_ptr, bcol_idx, bvalues, *,
-                  fp32: bool = False, xcd_remap: bool = True) -> "Matrix":
+                  fp32: bool = False, xcd_remap: bool = True, xcd_contiguous: bool = False) -> "Matrix":
         """A resident 3x3 block-CSR matrix (``spmv_create_bsr3``); bvalues has
-        9 row-major values per block."""
+        9 row-major values per block.  xcd_contiguous deals one contiguous
+        range of tiles to each XCD (SPMV_XCD_CONTIGUOUS) instead of chunks."""
         rp, ci, _ = _host_csr(brow_ptr, bcol_idx, None)
         va = np.ascontiguousarray(bvalues, dtype=np.float64).reshape(-1)
         if va.shape[0] != 9 * ci.shape[0]:
             raise ValueError("bvalues must hold 9 values per block")
         flags = (SPMV_VALUES_FP32 if fp32 else 0) | (0 if xcd_remap else SPMV_NO_XCD_REMAP)
+        flags |= SPMV_XCD_CONTIGUOUS if xcd_contiguous else 0
         h = ctypes.c_void_p()
         _check(lib().spmv_create_bsr3(n_block_rows, n_block_cols, ci.shape[0], _ptr(rp), _ptr(ci),
                                       _ptr(va), flags, ctypes.byref(h)), "spmv_create_bsr3")

@@ -163,6 +163,8 @@ template <typename T> static int fetch_device(const T *src, size_t n, std::vecto
 static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col_idx, const double *values, uint32_t flags, const spmv_params &p,
                        spmv_matrix **out) {
+    if (p.xcd_chunk < -2 || p.xcd_chunk > 4096 || (p.xcd_chunk > 0 && (p.xcd_chunk & (p.xcd_chunk - 1))))
+        return fail(SPMV_EINVAL, "xcd_chunk = %d must be -2, -1, 0 or a power of two <= 4096", p.xcd_chunk);
     SellPlan S;
     int rc = build_sell_plan(n_rows, row_ptr, p.sell_sigma, S);
     if (rc) return rc;
@@ -183,7 +185,11 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     M.n_rows = n_rows;
     M.n_cols = n_cols;
     M.nnz = nnz;
-    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    const int chunk = p.xcd_chunk ? p.xcd_chunk : kDefaultXcdChunk;
+    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP) && chunk != -1;
+    M.xcd_chunk_log2 = -1;  // -2: one contiguous range per XCD
+    for (int c = 0; c <= 12; ++c)
+        if (chunk == (1 << c)) M.xcd_chunk_log2 = c;
     int64_t total = S.n_entries;
     for (size_t i = 0; i < S.long_rows.size(); ++i) total += row_ptr[S.long_rows[i] + 1] - row_ptr[S.long_rows[i]];
     const size_t tot = (size_t)total, tot_pad = tot + kPad;
@@ -303,7 +309,10 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     M.nnz = nnz;
     M.tile_nnz = P.tile_nnz;
     M.ring_words = P.ring_words;
-    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP) && P.xcd_chunk != -1;
+    M.xcd_chunk_log2 = -1;  // -2: one contiguous range per XCD
+    for (int c = 0; c <= 12; ++c)
+        if (P.xcd_chunk == (1 << c)) M.xcd_chunk_log2 = c;
     const size_t nz = (size_t)nnz, nz_pad = ((nz + 3) & ~(size_t)3) + kPad;
     rc = U.put(&M.row_ptr, row_ptr, (size_t)n_rows + 1, (size_t)n_rows + 1);
     if (!rc) rc = U.put(&M.col, col_idx, nz, nz_pad);
@@ -504,7 +513,7 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     clear_error();
     if (!out) return fail(SPMV_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP | SPMV_DEVICE_PTRS))
+    if (flags & ~(SPMV_VALUES_FP32 | SPMV_NO_XCD_REMAP | SPMV_DEVICE_PTRS | SPMV_XCD_CONTIGUOUS))
         return fail(SPMV_EINVAL, "unknown flags 0x%x", flags);
     if (nnz_blocks > kMaxNnz / 9) return fail(SPMV_EINVAL, "nnz_blocks = %lld exceeds (2^31 - 2^16) / 9", (long long)nnz_blocks);
     if (flags & SPMV_DEVICE_PTRS) {
@@ -543,6 +552,7 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     M.n_cols = n_block_cols;
     M.nnz = nnz_blocks;
     M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
+    M.xcd_chunk_log2 = (flags & SPMV_XCD_CONTIGUOUS) ? -1 : kDefaultXcdChunkLog2;
     const size_t nb = (size_t)nnz_blocks;
     rc = U.put(&M.row_ptr, brow_ptr, (size_t)n_block_rows + 1, 0);
     if (!rc) rc = U.put(&M.col, bcol_idx, nb, nb + kPad);

@@ -21,6 +21,7 @@ template <typename V, typename T> struct BsrArgs {
     const int32_t *tiles;  // n_tiles + 1 block-row boundaries
     int32_t n_tiles;
     int32_t per_xcd;
+    int32_t chunk_log2;     // XCD assignment of tiles (xcd_tile)
     int32_t ldx, ldy, off;  // leading dimensions and first column of this launch
 };
 

@@ -21,7 +21,7 @@
 // and are discarded by a select, never by multiplying with zero, so Inf/NaN
 // in X behave as in the definition.  A block row with more than 510 blocks
 // forms its own tile and reads its values straight from global memory.
-// Tiles go to XCDs in contiguous runs as in the scalar kernels.
+// Tiles go to XCDs in chunks as in the scalar kernels.
 //
 // Per output the sum is sum over blocks (ascending) of a_r0 x0 + a_r1 x1 +
 // a_r2 x2, left to right, whatever K, JL and U are: a column of a k-column
@@ -211,8 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_bsr3(BsrArgs<V, T> g) {
     using S = BsrStage<V>;
     __shared__ i32x4 sval_raw[S::kTrips * kBlock];
     __shared__ i32x4 scol_raw[S::kColVecs];
-    const int b = blockIdx.x;
-    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    const int li = xcd_tile(blockIdx.x, g.per_xcd, g.chunk_log2);
     if (li >= g.n_tiles) return;
     const int t = (int)threadIdx.x;
     const int R0 = g.tiles[li], R1 = g.tiles[li + 1];
@@ -273,12 +272,9 @@ hipError_t launch_bsr3(const DevMatrix &M, const V *val, int k, const T *X, T *Y
     g.n_tiles = M.n_bsr_tiles;
     g.ldx = k;
     g.ldy = k;
-    int grid = M.n_bsr_tiles;
-    g.per_xcd = 0;
-    if (M.xcd_remap && M.n_bsr_tiles >= 16) {
-        g.per_xcd = (M.n_bsr_tiles + 7) / 8;
-        grid = 8 * g.per_xcd;
-    }
+    g.per_xcd = M.xcd_remap && M.n_bsr_tiles >= 16 ? (M.n_bsr_tiles + 7) / 8 : 0;
+    g.chunk_log2 = M.xcd_chunk_log2;
+    const int grid = xcd_grid(M.n_bsr_tiles, g.per_xcd, g.chunk_log2);
     // right-hand sides in chunks of 8, 4, 2, 1 columns
     int off = 0;
     while (off < k) {

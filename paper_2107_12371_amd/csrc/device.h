@@ -58,6 +58,7 @@ struct DevMatrix {
     uint16_t *lidx = nullptr;        // window-relative column per stored entry (+ padding)
     uint32_t *lidx12 = nullptr;      // 2048-entry tiles: packed 12-bit positions per tile and lane
     bool xcd_remap = true;
+    int32_t xcd_chunk_log2 = -1;     // XCD assignment (xcd_tile): -1 one contiguous range per XCD
     int32_t kernel = KV_AUTO;        // direct-gather kernel variant
     int32_t block = 1;                // 1: scalar CSR, 3: 3x3 block CSR
     int32_t n_bsr_tiles = 0;
@@ -70,6 +71,30 @@ struct DevMatrix {
     uint8_t *sell_len = nullptr;      // entries per slot
     int32_t *sell_ptr = nullptr;      // n_slices + 1 entry offsets
 };
+
+// Tile taken by workgroup b.  The dispatcher deals workgroups to the 8 XCDs
+// in turn (b mod 8); the j-th workgroup of an XCD (j = b / 8) takes
+//  - chunk_log2 < 0: tile xcd * per_xcd + j, one contiguous range per XCD
+//    (each XCD's L2 walks its own band of x);
+//  - chunk_log2 = c >= 0: tile j mod 2^c of chunk (j >> c) * 8 + xcd, i.e.
+//    chunks of 2^c consecutive tiles dealt to the XCDs in turn, so that all
+//    XCDs work near the same rows and share one band of x in the MALL;
+//  - per_xcd = 0: tile b (no XCD grouping).
+__device__ __forceinline__ int xcd_tile(int b, int per_xcd, int chunk_log2) {
+    if (per_xcd == 0) return b;
+    const int x = b & 7, j = b >> 3;
+    if (chunk_log2 < 0) return x * per_xcd + j;
+    return ((((j >> chunk_log2) << 3) + x) << chunk_log2) + (j & ((1 << chunk_log2) - 1));
+}
+
+// Workgroups that cover n tiles under xcd_tile (some past n exit at once).
+inline int xcd_grid(int n, int per_xcd, int chunk_log2) {
+    if (per_xcd == 0) return n;
+    if (chunk_log2 < 0) return 8 * per_xcd;
+    const int c = 1 << chunk_log2;
+    const int groups = ((n + c - 1) / c + 7) / 8;
+    return groups * 8 * c;
+}
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));

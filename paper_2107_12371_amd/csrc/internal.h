@@ -39,6 +39,9 @@ enum SegKind : int32_t { SEG_STREAM = 0, SEG_LONG = 1, SEG_WINDOW = 2, SEG_CWIN 
 // differently: 1024-entry capacity, at most 128 rows).
 constexpr int KV_WAVE_PLAN = 3;
 
+// Tiles per chunk when tiles are dealt to the XCDs (spmv_params.xcd_chunk = 0).
+constexpr int kDefaultXcdChunk = 16, kDefaultXcdChunkLog2 = 4;
+
 // Compact per-tile windows: at most this many words and runs per tile.
 constexpr int kCwinMaxRuns = 64;  // must equal the kernels' kCwinMaxRunsDev
 
@@ -49,6 +52,7 @@ struct Plan {
     int64_t nnz = 0;
     int32_t tile_nnz = 0, tile_rows = 0;
     int32_t window_mode = 0, ring_words = 0, window_block = 0, kernel = 0;
+    int32_t xcd_chunk = 0;           // spmv_params.xcd_chunk (validated; 0 replaced by the default)
     std::vector<int32_t> seg_bound;  // n_seg + 1 row boundaries
     std::vector<int32_t> seg_kind;   // SegKind per segment
     std::vector<int32_t> win_off;    // first staged x word (window segments)

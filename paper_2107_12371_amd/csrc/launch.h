@@ -19,7 +19,8 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     double *part;           // EPI_DOT / EPI_RESID: one partial per segment
     const TileDesc *desc;   // tiles of this launch
     int32_t n_list;         // number of tiles
-    int32_t per_xcd;        // > 0: tiles [x*per_xcd, (x+1)*per_xcd) belong to XCD x
+    int32_t per_xcd;        // > 0: XCD grouping of tiles (xcd_tile), 0: tile = workgroup
+    int32_t chunk_log2;     // XCD grouping: -1 contiguous range per XCD, c: chunks of 2^c tiles
     int32_t wg_per_xcd;     // pipelined kernel: workgroups per XCD
     const int *done;        // optional: non-zero makes the launch a no-op (CG)
     const int32_t *win_blk_ptr;

@@ -184,6 +184,8 @@ static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         return fail(SPMV_EINVAL, "ring_words = %d must be a power of two in [256, 8192]", ring);
     if (p.window_block < 0) return fail(SPMV_EINVAL, "window_block = %d < 0", p.window_block);
     if (p.kernel < 0 || p.kernel > 3) return fail(SPMV_EINVAL, "kernel = %d unknown", p.kernel);
+    if (p.xcd_chunk < -2 || p.xcd_chunk > 4096 || (p.xcd_chunk > 0 && (p.xcd_chunk & (p.xcd_chunk - 1))))
+        return fail(SPMV_EINVAL, "xcd_chunk = %d must be -2, -1, 0 or a power of two <= 4096", p.xcd_chunk);
     if (p.kernel == KV_WAVE_PLAN) {
         // wavefront tiles: 1024-entry capacity, two rows per lane
         if (p.tile_nnz && p.tile_nnz != 1024)
@@ -201,6 +203,9 @@ static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     // entries (its aligned span then fits tnz exactly).
     const int cap = tnz - 3;
     P.kernel = p.kernel;
+    // chunks of 16 tiles: 0.521 ms against 0.568 ms for one contiguous range
+    // per XCD on the 16M-row mesh matrix (chunks of 4 to 64 within 1%)
+    P.xcd_chunk = p.xcd_chunk ? p.xcd_chunk : kDefaultXcdChunk;
 
     // ---- segmentation into stream tiles and long rows
     int32_t r = 0;

@@ -45,8 +45,7 @@ template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_sell(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
-    const int b = blockIdx.x;
-    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    const int li = xcd_tile(blockIdx.x, g.per_xcd, g.chunk_log2);
     if (li >= g.n_list) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = li * (kBlock / kWave) + (int)threadIdx.x / kWave;
@@ -106,12 +105,9 @@ void launch_sell_slices(const DevMatrix &M, SpmvArgs<V, X, Y> g, int epi, hipStr
     a.sell_len = M.sell_len;
     a.sell_ptr = M.sell_ptr;
     a.n_slices = M.n_slices;
-    int grid = M.n_sell_wg;
-    a.per_xcd = 0;
-    if (M.xcd_remap && M.n_sell_wg >= 16) {
-        a.per_xcd = (M.n_sell_wg + 7) / 8;
-        grid = 8 * a.per_xcd;
-    }
+    a.per_xcd = M.xcd_remap && M.n_sell_wg >= 16 ? (M.n_sell_wg + 7) / 8 : 0;
+    a.chunk_log2 = M.xcd_chunk_log2;
+    const int grid = xcd_grid(M.n_sell_wg, a.per_xcd, a.chunk_log2);
     switch (epi) {
         case EPI_DOT: hipLaunchKernelGGL((k_sell<V, X, Y, A, EPI_DOT>), dim3(grid), dim3(kBlock), 0, st, a); break;
         case EPI_RESID: hipLaunchKernelGGL((k_sell<V, X, Y, A, EPI_RESID>), dim3(grid), dim3(kBlock), 0, st, a); break;

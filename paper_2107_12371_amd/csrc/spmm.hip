@@ -59,6 +59,7 @@ __device__ __forceinline__ void load_cols(const double *__restrict__ xr, int j0,
 // re-read its last entry and are discarded by a select).
 template <int KC, int U, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_spmm_tiles(const TileDesc *__restrict__ desc, int n_list, int per_xcd,
+                                                       int chunk_log2,
                                                        const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val, const double *__restrict__ X,
@@ -66,8 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(const TileDesc *__restric
     extern __shared__ __align__(16) unsigned char smem[];
     double *sv = reinterpret_cast<double *>(smem);
     int32_t *sc = reinterpret_cast<int32_t *>(sv + cap);
-    const int b = blockIdx.x;
-    const int li = per_xcd ? (b & 7) * per_xcd + (b >> 3) : b;
+    const int li = xcd_tile(blockIdx.x, per_xcd, chunk_log2);
     if (li >= n_list) return;
     const TileDesc d = desc[li];
     const int n = min(d.e - d.s, cap);  // the host sizes cap to the largest tile
@@ -128,19 +128,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm_long(const TileDesc *__restrict
 template <int KC, int U>
 static void launch_tiles(const TileDesc *desc, int n, bool remap, const DevMatrix &M, const double *X, double *Y,
                          int k, int cap, hipStream_t st) {
-    int grid = n, per_xcd = 0;
-    if (remap && n >= 16) {
-        per_xcd = (n + 7) / 8;
-        grid = 8 * per_xcd;
-    }
+    const int per_xcd = remap && n >= 16 ? (n + 7) / 8 : 0;
+    const int chunk_log2 = M.xcd_chunk_log2;
+    const int grid = xcd_grid(n, per_xcd, chunk_log2);
     const size_t lds = (size_t)cap * (sizeof(double) + sizeof(int32_t));
     const bool vec = KC >= 2 && k % 2 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
     if (vec)
         hipLaunchKernelGGL((k_spmm_tiles<KC, U, true>), dim3(grid), dim3(kBlock), lds, st, desc, n, per_xcd,
-                           M.row_ptr, M.col, M.val64, X, Y, k, cap);
+                           chunk_log2, M.row_ptr, M.col, M.val64, X, Y, k, cap);
     else
         hipLaunchKernelGGL((k_spmm_tiles<KC, U, false>), dim3(grid), dim3(kBlock), lds, st, desc, n, per_xcd,
-                           M.row_ptr, M.col, M.val64, X, Y, k, cap);
+                           chunk_log2, M.row_ptr, M.col, M.val64, X, Y, k, cap);
 }
 
 hipError_t launch_spmm(const spmv_matrix *A, const double *X, double *Y, int k, hipStream_t st) {

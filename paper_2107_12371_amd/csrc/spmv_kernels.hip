@@ -53,8 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(SpmvArgs<V, X, Y> g) {
     __shared__ A prod[TileRegs<V, NT>::kProd];
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
-    const int b = blockIdx.x;
-    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    const int li = xcd_tile(blockIdx.x, g.per_xcd, g.chunk_log2);
     if (li >= g.n_list) return;
     const TileDesc d = g.desc[li];
     const X *__restrict__ x = g.x;
@@ -218,8 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_cwin(SpmvArgs<V, X, Y> g) {
     __shared__ uint2 run_map[kMapWords];  // per 32 window positions: run-start bits, starts before them
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
-    const int b = blockIdx.x;
-    const int li = g.per_xcd ? (b & 7) * g.per_xcd + (b >> 3) : b;
+    const int li = xcd_tile(blockIdx.x, g.per_xcd, g.chunk_log2);
     if (li >= g.n_list) return;
     const TileDesc d = g.desc[li];
     const X *__restrict__ x = g.x;
@@ -477,12 +475,10 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
             hipLaunchKernelGGL((k_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st, a);
         } else {
-            int grid = M.n_stream;
             a.per_xcd = 0;
-            if (M.xcd_remap && M.n_stream >= 16) {
-                a.per_xcd = (M.n_stream + 7) / 8;
-                grid = 8 * a.per_xcd;
-            }
+            a.chunk_log2 = M.xcd_chunk_log2;
+            if (M.xcd_remap && M.n_stream >= 16) a.per_xcd = (M.n_stream + 7) / 8;
+            const int grid = xcd_grid(M.n_stream, a.per_xcd, a.chunk_log2);
             hipLaunchKernelGGL((k_stream<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
     }
@@ -493,17 +489,16 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
         a.runs = M.runs;
         a.lidx = M.lidx;
         a.lidx12 = M.lidx12;
-        int grid = M.n_cwin;
         a.per_xcd = 0;
-        if (M.xcd_remap && M.n_cwin >= 16) {
-            a.per_xcd = (M.n_cwin + 7) / 8;
-            grid = 8 * a.per_xcd;
-        }
+        a.chunk_log2 = M.xcd_chunk_log2;
+        if (M.xcd_remap && M.n_cwin >= 16) a.per_xcd = (M.n_cwin + 7) / 8;
+        const int grid = xcd_grid(M.n_cwin, a.per_xcd, a.chunk_log2);
         // every value type goes through the windows (16M-row mesh matrix,
         // with the popcount run lookup: FP64 0.567 vs 0.73 ms direct, FP32
         // 0.327 vs 0.48, bfloat16 0.292 vs 0.405)
         if (M.kernel == KV_PIPELINED && M.n_cwin >= 64) {
             a.per_xcd = (M.n_cwin + 7) / 8;
+            a.chunk_log2 = -1;
             const int resident = cwin_pipe_occupancy<V, X, Y, A, NT, EPI>() * (cu_count() / 8);
             a.wg_per_xcd = std::max(1, std::min(a.per_xcd, resident));
             hipLaunchKernelGGL((k_cwin_pipe<V, X, Y, A, NT, EPI>), dim3(8 * a.wg_per_xcd), dim3(kBlock), 0, st, a);
@@ -554,6 +549,7 @@ template <typename V, typename X, typename Y, typename A>
 hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
                        double *part, const int *done, hipStream_t st) {
     SpmvArgs<V, X, Y> g{};
+    g.chunk_log2 = -1;
     g.row_ptr = M.row_ptr;
     g.col = M.col;
     g.val = val;

@@ -264,6 +264,25 @@ def test_kernel_variants_bitwise_identical(cfg1):
     assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
 
 
+@pytest.mark.parametrize("window", [spmv.WINDOW_OFF, spmv.WINDOW_AUTO])
+def test_xcd_assignments_bitwise_identical(cfg1, window):
+    # which workgroup takes which tile changes nothing in any row's sum:
+    # chunks of 1, 16 (the default) and 4096 tiles, one contiguous range per
+    # XCD and no grouping all give the same bits, FP64 and FP32, and SELL too
+    A = cfg1["rcm"]
+    x = mg.uniform(A.n_cols, 31, 0)
+    ys = []
+    for c in (0, 1, 16, 4096, -2, -1):
+        params = {"tile_nnz": 2048, "window_mode": window, "xcd_chunk": c}
+        with spmv.Matrix.from_csr(A, fp32=True, params=params) as M:
+            ys.append((M.apply(to_dev(x)).cpu().numpy(), M.apply_f32(to_dev(x, torch.float32)).cpu().numpy()))
+    for y64, y32 in ys[1:]:
+        assert np.array_equal(y64, ys[0][0]) and np.array_equal(y32, ys[0][1])
+    assert_parity(ys[0][0], A, x)
+    sel = [run64(A, x, params={"format": spmv.FORMAT_SELL, "xcd_chunk": c})[0] for c in (0, -2, 2)]
+    assert np.array_equal(sel[0], sel[1]) and np.array_equal(sel[0], sel[2]) and np.array_equal(sel[0], ys[0][0])
+
+
 def test_config1_orderings_agree(cfg1):
     # the same operator in two orderings: both are the RCM / random
     # renumbering of one natural-order matrix, so y must agree after mapping
@@ -485,6 +504,19 @@ def test_bsr3_config3_shape_bitwise_dyadic():
         Y = M.spmm(to_dev(X)).cpu().numpy()
     Yr, _ = oracle.bsr3_spmm(A, X)
     assert np.array_equal(Y, Yr)
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_bsr3_xcd_assignments_bitwise_identical(k):
+    A = mg.bsr3(40, 30, 20, seed=64)
+    X = mg.uniform(3 * A.n_cols * k, 12, 0).reshape(3 * A.n_cols, k)
+    outs = []
+    for kw in ({}, {"xcd_contiguous": True}, {"xcd_remap": False}):
+        with spmv.Matrix.from_csr(A, **kw) as M:
+            outs.append(M.spmm(to_dev(X)).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    Yr, Bd = oracle.bsr3_spmm(A, X)
+    assert np.all(np.abs(outs[0] - Yr) <= 1e-12 * Bd)
 
 
 def test_bsr3_rejects_misuse():

@@ -169,6 +169,16 @@ def test_against_scipy_csr(case):
     assert np.all(np.abs(y - S @ x) <= 2 * oracle.gamma(m) * b + 0.0)
 
 
+def test_all_cores_timing_build_gives_the_same_bits():
+    # the OpenMP build only splits rows between threads; each row is the
+    # checker's sum, so the results are identical
+    A = mg.knn(24, seed=33)
+    x = mg.uniform(A.n_cols, 4, 1)
+    y, _ = oracle.spmv(A, x)
+    assert np.array_equal(oracle.spmv_all_cores(A, x), y)
+    assert oracle.all_cores_threads() >= 1
+
+
 def test_spmv_rows_matches_full():
     A = mg.config0()
     x = mg.uniform(A.n_cols, 4, 0)
