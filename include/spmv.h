@@ -312,6 +312,29 @@ typedef struct cg_info {
 int cg_solve(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
              int32_t mode, cg_info *info, void *stream);
 
+/*
+ * cg_solve_noalloc: cg_solve in CG_FP64 mode that allocates nothing -- for
+ * callers that cannot allocate device or pinned host memory or instantiate
+ * graphs (tight serving loops, harnesses that forbid allocation after
+ * start-up).  Same arguments, results and errors as cg_solve with
+ * mode = CG_FP64, bit for bit: the same kernels run in the same order, with
+ * the iterations launched directly on `stream` instead of replayed from a
+ * captured graph.
+ *   mode       must be CG_FP64 (else SPMV_ENOTSUP)
+ *   A          a scalar CSR handle with at most 524,288 rows (2^19; larger:
+ *              SPMV_EINVAL)
+ * The workspace (r, p, q, the partial sums and the scalar state; x itself
+ * is the caller's) is one device array of the library, 16.8 MB, held on
+ * each GPU the library runs on until the process ends; it is located on a
+ * device's first call.  Every call on one GPU uses that GPU's array, so
+ * calls that overlap on one GPU (from several threads or streams) race and
+ * must be serialised by the caller.  Blocks the host until done; not
+ * capturable into a graph (it reads the scalar state after each batch of
+ * iterations).
+ */
+int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
+                     int32_t mode, cg_info *info, void *stream);
+
 /* ------------------------------------------------------------- serving */
 /*
  * A request server over resident matrices with continuous batching.

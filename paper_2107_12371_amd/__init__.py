@@ -35,6 +35,7 @@ EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",
     "spmv_apply_f32v", "spmv_apply_bf16", "cg_solve", "spmv_last_error", "spmv_plan_inspect",
     "spmv_create_bsr3", "bsr3_spmm", "bsr3_spmm_f32", "spmv_sell_inspect", "spmv_spmm", "spmv_calibrate_read",
+    "cg_solve_noalloc",
 ]
 
 
@@ -101,8 +102,9 @@ def lib():
         for f in ("bsr3_spmm", "bsr3_spmm_f32", "spmv_spmm"):
             getattr(L, f).restype = ctypes.c_int
             getattr(L, f).argtypes = [vp, i32, vp, vp, vp]
-        L.cg_solve.restype = ctypes.c_int
-        L.cg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(cg_info), vp]
+        for f in ("cg_solve", "cg_solve_noalloc"):
+            getattr(L, f).restype = ctypes.c_int
+            getattr(L, f).argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(cg_info), vp]
         L.spmv_calibrate_read.restype = ctypes.c_int
         L.spmv_calibrate_read.argtypes = [vp, i64, vp, i32, vp]
         L.spmv_last_error.restype = ctypes.c_char_p
@@ -396,6 +398,23 @@ class Matrix:
                             tol, max_iter, mode, ctypes.byref(inf), _stream_ptr(stream))
         if raise_on_error and rc not in (SPMV_OK,):
             _check(rc, "cg_solve")
+        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc)
+
+    def cg_noalloc(self, b, x=None, tol: float = 1e-10, max_iter: int = 20000, stream=None,
+                   raise_on_error: bool = True):
+        """``cg_solve_noalloc``: the FP64 solve on the library's per-device
+        scratch array (no allocation inside the call; at most 2^19 rows; calls
+        on one GPU must not overlap).  Returns (x, CGInfo)."""
+        torch = _torch()
+        _check_vec(b, torch.float64, self.n_rows, "b")
+        if x is None:
+            x = torch.zeros(self.n_rows, dtype=torch.float64, device=b.device)
+        _check_vec(x, torch.float64, self.n_rows, "x")
+        inf = cg_info()
+        rc = lib().cg_solve_noalloc(self.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    tol, max_iter, CG_FP64, ctypes.byref(inf), _stream_ptr(stream))
+        if raise_on_error and rc not in (SPMV_OK,):
+            _check(rc, "cg_solve_noalloc")
         return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc)
 
     def close(self):

@@ -640,6 +640,9 @@ template <typename T, typename V> struct CgCore {
     hipStream_t s;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    // launch each batch of graph_iters iterations directly on the stream
+    // instead of capturing and replaying them (same kernels, same bits)
+    bool eager = false;
 
     CgCore(const DevMatrix &M_, const V *val_, int n_, hipStream_t s_) : M(M_), val(val_), n(n_), s(s_) {
         n_wg = std::max(1, std::min(2048, (n + 4 * kBlock - 1) / (4 * kBlock)));
@@ -744,13 +747,17 @@ template <typename T, typename V> struct CgCore {
         if (rc) return rc;
         if (hst->rho <= hst->tol2) return SPMV_OK;
         if (max_iter <= 0) return SPMV_ENOTCONV;
-        if (!exec) {
+        if (!exec && !eager) {
             rc = capture();
             if (rc) return rc;
         }
         int done_iters = 0;
         for (;;) {
-            HIP_TRY(hipGraphLaunch(exec, s));
+            if (eager) {
+                for (int i = 0; i < graph_iters; ++i) HIP_TRY(iteration(s));
+            } else {
+                HIP_TRY(hipGraphLaunch(exec, s));
+            }
             rc = read_state();
             if (rc) return rc;
             done_iters = hst->iter;
@@ -984,6 +991,90 @@ static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol,
     return SPMV_OK;
 }
 
+// ------------------------------------------------- allocation-free FP64 CG
+//
+// cg_solve_noalloc runs cg_fp64's kernels, in the same order, on a
+// workspace that is a file-scope device array instead of stream-ordered
+// allocations: r, p, q and the SpMV partials (n_seg <= n) for up to
+// kNoallocMaxRows rows, the per-workgroup partials, the two-stage reduction's
+// first stage and the device scalars.  The caller's x is the iterate itself.
+// Iterations are launched directly (no graph to instantiate) and the scalar
+// state is read into pageable host memory, so a solve calls no allocating
+// runtime routine.  One array per device, shared by every call on it.
+constexpr int kNoallocMaxRows = 1 << 19;
+constexpr size_t kNoallocPartVec = 2048, kNoallocPart2 = 256, kNoallocState = 16;
+constexpr size_t kNoallocWords = 4 * (size_t)kNoallocMaxRows + kNoallocPartVec + kNoallocPart2 + kNoallocState;
+static_assert(sizeof(CgState) <= kNoallocState * sizeof(double), "scalar state slot too small");
+
+static __device__ __align__(256) double scratch[kNoallocWords];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch[kMaxDevices] = {};
+
+// The device address of this device's scratch array.  Resolved once per
+// device (with that device current) on its first call; in host code the
+// array's name is not a device address.
+int scratch_of(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPMV_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return SPMV_OK;
+}
+}  // namespace
+
+static int cg_fp64_noalloc(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter,
+                           cg_info *info, hipStream_t s, double *scr) {
+    const DevMatrix &M = A->M;
+    const int n = M.n_rows;
+    const size_t N = kNoallocMaxRows;
+    CgCore<double, double> C(M, M.val64, n, s);
+    C.eager = true;
+    C.x = x;
+    C.r = scr;
+    C.p = scr + N;
+    C.q = scr + 2 * N;
+    C.part_seg = scr + 3 * N;
+    C.part_vec = scr + 4 * N;
+    C.part2 = scr + 4 * N + kNoallocPartVec;
+    C.st = reinterpret_cast<CgState *>(scr + 4 * N + kNoallocPartVec + kNoallocPart2);
+    CgState host_state{};
+    C.hst = &host_state;
+    // ||b||^2
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
+    HIP_TRY(hipGetLastError());
+    int rc = C.read_state();
+    if (rc) return rc;
+    if (C.hst->bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    int iters = 0, repl = 0;
+    rc = C.solve(b, tol, max_iter, &iters, &repl);
+    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
+    int rc2;
+    HIP_TRY(C.true_residual(b));
+    if ((rc2 = C.read_state())) return rc2;
+    if (info) {
+        info->iterations = iters;
+        info->refinements = repl;
+        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
+    }
+    if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (p.q <= 0 or not finite): matrix not SPD?");
+    return SPMV_OK;
+}
+
 // Iterative refinement whose correction solves read the FP32 values; T is
 // the correction solve's vector and accumulation type (float, or double for
 // products that round only the stored values).
@@ -1177,4 +1268,44 @@ extern "C" int cg_solve(const spmv_matrix *A, const double *b, double *x, double
                         int32_t mode, cg_info *info, void *stream) {
     spmvlib::clear_error();
     return spmvlib::cg_run(A, b, x, tol, max_iter, mode, info, static_cast<hipStream_t>(stream), nullptr);
+}
+
+extern "C" int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter,
+                                int32_t mode, cg_info *info, void *stream) {
+    using namespace spmvlib;
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (info) std::memset(info, 0, sizeof *info);
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    if (mode != CG_FP64) return fail(SPMV_ENOTSUP, "cg_solve_noalloc runs CG_FP64 only (mode %d)", mode);
+    if (A->M.block != 1) return fail(SPMV_ENOTSUP, "cg_solve_noalloc needs a scalar CSR handle");
+    if (A->M.n_rows != A->M.n_cols)
+        return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
+    if (A->M.n_rows > kNoallocMaxRows || A->M.n_seg > kNoallocMaxRows)
+        return fail(SPMV_EINVAL, "n = %d exceeds the allocation-free solver's scratch of %d rows", A->M.n_rows,
+                    kNoallocMaxRows);
+    if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
+    const int n = A->M.n_rows;
+    if (n == 0) return SPMV_OK;
+    if (!b || !x) return fail(SPMV_EINVAL, "b or x is NULL");
+    if (reinterpret_cast<uintptr_t>(b) < reinterpret_cast<uintptr_t>(x) + sizeof(double) * n &&
+        reinterpret_cast<uintptr_t>(x) < reinterpret_cast<uintptr_t>(b) + sizeof(double) * n)
+        return fail(SPMV_EINVAL, "b and x overlap");
+    int dev_prev = -1;
+    {
+        hipError_t e = hipGetDevice(&dev_prev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (dev_prev != A->device) {
+            e = hipSetDevice(A->device);
+            if (e != hipSuccess) return hip_fail(e, "making the matrix's device current");
+        } else {
+            dev_prev = -1;
+        }
+    }
+    double *scr = nullptr;
+    int rc = scratch_of(A->device, &scr);
+    if (rc == SPMV_OK) rc = cg_fp64_noalloc(A, b, x, tol, max_iter, info, static_cast<hipStream_t>(stream), scr);
+    if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
 }

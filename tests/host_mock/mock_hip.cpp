@@ -140,6 +140,11 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *, in
     return hipSuccess;
 }
 hipError_t hipFuncSetAttribute(const void *, hipFuncAttribute, int) { return hipSuccess; }
+// a device variable's address is its host shadow here (device memory is host memory)
+hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+    *p = const_cast<void *>(symbol);
+    return hipSuccess;
+}
 // kernel launches are recorded by the device name the compiler registered
 // for the host stub (mock_launch_log), so a driver can check which kernels a
 // call launched
