@@ -66,7 +66,8 @@ typedef struct spmv_matrix spmv_matrix;
 #define SPMV_VALUES_BF16 0x2u   /* also keep a BF16 copy of the values */
 #define SPMV_NO_XCD_REMAP 0x4u  /* keep launch order = tile order (no XCD grouping) */
 #define SPMV_XCD_CONTIGUOUS 0x10u /* 3x3 block CSR: deal one contiguous range of tiles to each
-                                     XCD instead of chunks of 16 tiles in turn (scalar CSR:
+                                     XCD even when the matrix takes 256 MB or more (where the
+                                     default deals chunks of 16 tiles in turn; scalar CSR:
                                      spmv_params.xcd_chunk = -2) */
 #define SPMV_DEVICE_PTRS 0x8u   /* row_ptr, col_idx and values are device (or managed)
                                    arrays of the current device, holding n_rows + 1, nnz
@@ -117,9 +118,12 @@ typedef struct spmv_params {
                               (each has its own L2).  c (a power of two <= 4096):
                               chunks of c consecutive tiles dealt to the XCDs in
                               turn, so all XCDs work near the same rows and share
-                              one band of x in the memory-side cache (0: 16);
-                              -2: one contiguous range of tiles per XCD; -1: no
-                              grouping (same as SPMV_NO_XCD_REMAP) */
+                              one band of x in the memory-side cache; -2: one
+                              contiguous range of tiles per XCD, whose L2 holds
+                              its band; -1: no grouping (same as
+                              SPMV_NO_XCD_REMAP).  0: chunks of 16 for matrices of
+                              at least 256 MB (beyond the memory-side cache), -2
+                              for smaller ones */
 } spmv_params;
 
 /* Storage formats of a scalar handle. */

@@ -185,7 +185,7 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     M.n_rows = n_rows;
     M.n_cols = n_cols;
     M.nnz = nnz;
-    const int chunk = p.xcd_chunk ? p.xcd_chunk : kDefaultXcdChunk;
+    const int chunk = p.xcd_chunk ? p.xcd_chunk : default_xcd_chunk(12 * nnz + 4 * (int64_t)n_rows);
     M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP) && chunk != -1;
     M.xcd_chunk_log2 = -1;  // -2: one contiguous range per XCD
     for (int c = 0; c <= 12; ++c)
@@ -552,7 +552,8 @@ extern "C" int spmv_create_bsr3(int32_t n_block_rows, int32_t n_block_cols, int6
     M.n_cols = n_block_cols;
     M.nnz = nnz_blocks;
     M.xcd_remap = !(flags & SPMV_NO_XCD_REMAP);
-    M.xcd_chunk_log2 = (flags & SPMV_XCD_CONTIGUOUS) ? -1 : kDefaultXcdChunkLog2;
+    M.xcd_chunk_log2 = (flags & SPMV_XCD_CONTIGUOUS) || default_xcd_chunk(76 * nnz_blocks + 4 * (int64_t)n_block_rows) < 0
+                           ? -1 : kDefaultXcdChunkLog2;
     const size_t nb = (size_t)nnz_blocks;
     rc = U.put(&M.row_ptr, brow_ptr, (size_t)n_block_rows + 1, 0);
     if (!rc) rc = U.put(&M.col, bcol_idx, nb, nb + kPad);

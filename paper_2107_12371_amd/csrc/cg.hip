@@ -8,13 +8,17 @@
 //               stop if it passes, else continue from r = b - A x
 //            beta = rho' / rho;  p = r + beta p;  rho = rho'
 //
-// One iteration is three launches on small systems: the SpMV with the p.q
-// partial fused into its epilogue; the x/r update with the r.r partial,
-// whose workgroups each form alpha from the SpMV's partials; and the p
-// update, whose workgroups each form beta (and workgroup 0 the convergence
-// flag) from the r.r partials.  With more than 1,024 partials of either
-// kind that scalar takes a reduction launch of its own (five launches on
-// the largest systems).  All scalars live on the device;
+// On systems up to 1,048,576 rows whose product is plain row tiles, one
+// iteration is two launches: the SpMV, whose workgroups first form beta
+// (and workgroup 0 the convergence flag) from the r.r partials and then
+// gather p_new = r + beta p for every column (the previous iteration's p
+// update folded into this product's gathers), with the p.q partial in its
+// epilogue; and the x/r update, which writes p_new for its own rows beside
+// x and r, with the r.r partial, its workgroups each forming alpha from the
+// SpMV's partials.  Otherwise the p update is a launch of its own (three
+// launches), and with more than 1,024 partials of either kind that scalar
+// takes a reduction launch of its own (five launches on the largest
+// systems).  All scalars live on the device;
 // every kernel returns at once when the device flag `done` is set, so a
 // captured graph of several iterations can be replayed blindly and the host
 // synchronises once per replay.  Reductions are two-stage with a fixed
@@ -47,6 +51,7 @@
 #include "internal.h"
 #include "launch.h"
 #include "matrix.h"
+#include "tile.h"
 
 namespace spmvlib {
 
@@ -59,7 +64,13 @@ struct CgState {
     int32_t iter, max_iter, done, flags;
 };
 
-enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8 };
+// F_FRESH: the next fused product (k_spmv_pfused) takes beta from the state
+// instead of forming it from r.r partials, and records no step: set at the
+// start of a solve (beta = 0 with p = 0) and after a residual replacement
+// (beta = rt2 / rho); cleared by workgroup 0 of the following x/r update.
+// Within a launch only workgroup 0 of a reduction step changes other bits,
+// and never this one, so every workgroup reads the same value.
+enum : int32_t { F_CONVERGED = 1, F_BREAKDOWN = 2, F_MAXITER = 4, F_BADDIAG = 8, F_FRESH = 16 };
 enum : int {
     R_BB = 0, R_RHO0 = 1, R_ALPHA = 2, R_BETA = 3, R_TRUE = 4, R_RR = 5, R_RZ = 6, R_RZ0 = 7, R_DIAG = 8,
     R_BETA_DEFER = 9, R_RZ_DEFER = 10
@@ -184,14 +195,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restric
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
-// After a failed true-residual check: continue from r = b - A x.
-__global__ void k_replace(CgState *st) {
+// After a failed true-residual check: continue from r = b - A x.  With
+// `fresh` the p update p = r + beta p is left to the fused product.
+__global__ void k_replace(CgState *st, int fresh) {
     st->beta = st->rt2 / st->rho;
     st->rho = st->rt2;
     st->rho_new = st->rt2;
     st->flags = 0;
     st->done = st->iter >= st->max_iter ? 1 : 0;
     if (st->done) st->flags = F_MAXITER;
+    if (fresh) st->flags |= F_FRESH;
+}
+
+// Start of a fused solve: p = 0 (set by the caller) and beta = 0, so the
+// first fused product gathers p_new = r.
+__global__ void k_set_fresh(CgState *st) {
+    st->beta = 0.0;
+    st->flags |= F_FRESH;
 }
 
 __global__ void k_init_state(CgState *st, double tol, int max_iter) {
@@ -301,6 +321,96 @@ __global__ __launch_bounds__(kBlock) void k_update_p_force(int n, T *__restrict_
                                                            const CgState *st) {
     const T b = static_cast<T>(st->beta);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = r[i] + b * p[i];
+}
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The SpMV of a fused iteration: q = A p_new with p_new = r + beta p formed
+// for every gathered column and for the tile's own rows (the p.q partial of
+// the epilogue), exactly as k_update_p_fold forms it (fma(beta, p, r), beta
+// rounded to T).  beta comes from the r.r partials, summed as
+// sum_partials sums them, and workgroup 0 records the step (R_BETA_DEFER),
+// unless F_FRESH hands beta over in the state.  The tile's stream and row
+// data are loaded before the partials are summed, so the reduction's
+// latency overlaps the matrix stream.  Same q and p.q partials, bit for
+// bit, as the p update followed by the plain SpMV on p_new.
+template <typename T, typename V, int NT>
+__global__ __launch_bounds__(kBlock) void k_spmv_pfused(const TileDesc *__restrict__ desc, int n_list, int per_xcd,
+                                                        int chunk_log2, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col, const V *__restrict__ val,
+                                                        const T *__restrict__ p, const T *__restrict__ r,
+                                                        T *__restrict__ q, double *__restrict__ part_pq, CgState *st,
+                                                        const double *__restrict__ part_rr, int n_rr) {
+    __shared__ T prod[TileRegs<V, NT>::kProd];
+    __shared__ double sh[kBlock / kWave];
+    __shared__ double rr_all;
+    if (st->done) return;
+    const int li = xcd_tile(blockIdx.x, per_xcd, chunk_log2);
+    if (li >= n_list) return;
+    const TileDesc d = desc[li];
+    TileRegs<V, NT> t;
+    t.load(col, val, d.s, d.e);
+    RowPre<T, EPI_DOT> pre;
+    pre.load(row_ptr, p, static_cast<const T *>(nullptr), d.r0, d.r1, d.s & ~3);  // op = p of the tile's rows
+    T r_row[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) r_row[i] = r[min(d.r0 + (int)threadIdx.x + i * kBlock, d.r1 - 1)];
+    double beta;
+    if (st->flags & F_FRESH) {
+        beta = st->beta;
+    } else {
+        const double t0 = sum_partials(part_rr, n_rr, sh);
+        if (threadIdx.x == 0) rr_all = t0;
+        __syncthreads();
+        const double tt = rr_all;
+        const double rho = st->rho;
+        if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_BETA_DEFER, tt);
+        if (!isfinite(tt) || tt <= st->tol2) return;
+        beta = tt / rho;
+    }
+    const T b = static_cast<T>(beta);
+    T xv[TileRegs<V, NT>::kMaxPass][4];
+    t.gather([p, r, b](int c) { return fma_t(b, p[c], r[c]); }, xv);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) pre.op[i] = fma_t(b, pre.op[i], r_row[i]);
+    t.products(xv, prod);
+    __syncthreads();
+    tile_rows<T, T, EPI_DOT>(pre, d.r0, d.r1, prod, q, part_pq, d.seg, sh);
+}
+
+// The x/r update of a fused iteration: p_new = r + beta p (as the fused
+// product formed it) is written for this workgroup's rows, then x += alpha
+// p_new, r -= alpha q and the r.r partial, as k_update_xr.  Workgroup 0
+// clears F_FRESH.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_xpr(int n, int chunk, T *__restrict__ x, T *__restrict__ r,
+                                                       T *__restrict__ p, const T *__restrict__ q, CgState *st,
+                                                       const double *__restrict__ part_pq, int n_pq,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    __shared__ double pq_all;
+    if (st->done) return;
+    double alpha;
+    if (!form_alpha(st, part_pq, n_pq, sh, &pq_all, alpha)) return;
+    const T a = static_cast<T>(alpha);
+    const T b = static_cast<T>(st->beta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->flags &= ~F_FRESH;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double dd = 0.0;
+#pragma unroll 4
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
+        const T ri0 = r[i];
+        const T pn = fma_t(b, p[i], ri0);
+        const T xi = x[i] + a * pn;
+        const T ri = ri0 - a * q[i];
+        p[i] = pn;
+        x[i] = xi;
+        r[i] = ri;
+        dd += static_cast<double>(ri) * static_cast<double>(ri);
+    }
+    const double tt = block_sum(dd, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tt;
 }
 
 template <typename T>
@@ -643,11 +753,17 @@ template <typename T, typename V> struct CgCore {
     // launch each batch of graph_iters iterations directly on the stream
     // instead of capturing and replaying them (same kernels, same bits)
     bool eager = false;
+    // two launches per iteration (k_spmv_pfused + k_update_xpr): the
+    // product is plain row tiles (no windows, no long rows) and every
+    // workgroup can sum the r.r partials itself
+    bool fused = false;
 
     CgCore(const DevMatrix &M_, const V *val_, int n_, hipStream_t s_) : M(M_), val(val_), n(n_), s(s_) {
         n_wg = std::max(1, std::min(2048, (n + 4 * kBlock - 1) / (4 * kBlock)));
         chunk = (n + n_wg - 1) / n_wg;
         graph_iters = n >= (1 << 20) ? 8 : (n >= (1 << 16) ? 16 : 32);
+        fused = n_wg <= kFoldBeta && M.block == 1 && M.format == SPMV_FORMAT_CSR && M.n_stream > 0 &&
+                M.n_cwin == 0 && M.n_blk == 0 && M.n_long == 0 && M.n_seg == M.n_stream;
     }
     ~CgCore() {
         if (!exec && !graph) return;
@@ -678,7 +794,29 @@ template <typename T, typename V> struct CgCore {
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, t, part2, nb, st, mode);
     }
 
+    template <int NT> void launch_pfused_nt(hipStream_t t, int per_xcd, int grid) {
+        hipLaunchKernelGGL((k_spmv_pfused<T, V, NT>), dim3(grid), dim3(kBlock), 0, t, M.stream_desc, M.n_stream,
+                           per_xcd, M.xcd_chunk_log2, M.row_ptr, M.col, val, p, r, q, part_seg, st, part_vec, n_wg);
+    }
+
+    // one iteration in two launches (three with a reduction launch for alpha)
+    hipError_t fused_iteration(hipStream_t t) {
+        const int per_xcd = M.xcd_remap && M.n_stream >= 16 ? (M.n_stream + 7) / 8 : 0;
+        const int grid = xcd_grid(M.n_stream, per_xcd, M.xcd_chunk_log2);
+        switch (M.tile_nnz) {
+            case 1024: launch_pfused_nt<1024>(t, per_xcd, grid); break;
+            case 2048: launch_pfused_nt<2048>(t, per_xcd, grid); break;
+            default: launch_pfused_nt<4096>(t, per_xcd, grid); break;
+        }
+        const bool fold_alpha = M.n_seg <= kFoldAlpha;
+        if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, t);
+        hipLaunchKernelGGL((k_update_xpr<T>), dim3(n_wg), dim3(kBlock), 0, t, n, chunk, x, r, p, q, st, part_seg,
+                           fold_alpha ? M.n_seg : -1, part_vec);
+        return hipGetLastError();
+    }
+
     hipError_t iteration(hipStream_t t) {
+        if (fused) return fused_iteration(t);
         const int *done = &st->done;
         hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t);
         if (e != hipSuccess) return e;
@@ -741,7 +879,13 @@ template <typename T, typename V> struct CgCore {
         hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol, max_iter);
         HIP_TRY(true_residual(b));
         reduce(part_seg, M.n_seg, R_RHO0, s);
-        hipLaunchKernelGGL((k_copy<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r);
+        if (fused) {
+            // p = 0 and beta = 0: the first fused product gathers p_new = r
+            hipLaunchKernelGGL((k_zero<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p);
+            hipLaunchKernelGGL(k_set_fresh, dim3(1), dim3(1), 0, s, st);
+        } else {
+            hipLaunchKernelGGL((k_copy<T, T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r);
+        }
         HIP_TRY(hipGetLastError());
         int rc = read_state();
         if (rc) return rc;
@@ -773,8 +917,9 @@ template <typename T, typename V> struct CgCore {
                 if (hst->rt2 <= hst->tol2) break;
                 // recursive residual drifted from the true one: replace it
                 ++*replacements;
-                hipLaunchKernelGGL(k_replace, dim3(1), dim3(1), 0, s, st);
-                hipLaunchKernelGGL((k_update_p_force<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r, st);
+                hipLaunchKernelGGL(k_replace, dim3(1), dim3(1), 0, s, st, fused ? 1 : 0);
+                if (!fused)
+                    hipLaunchKernelGGL((k_update_p_force<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p, r, st);
                 HIP_TRY(hipGetLastError());
                 rc = read_state();
                 if (rc) return rc;
@@ -820,7 +965,9 @@ struct PcgCore : CgCore<double, double> {
     bool jacobi;
 
     PcgCore(const DevMatrix &M_, int n_, hipStream_t s_, bool jacobi_)
-        : CgCore<double, double>(M_, M_.val64, n_, s_), jacobi(jacobi_) {}
+        : CgCore<double, double>(M_, M_.val64, n_, s_), jacobi(jacobi_) {
+        fused = false;  // preconditioned iterations have kernels of their own
+    }
 
     hipError_t pcg_iteration(hipStream_t ts) {
         const int *done = &st->done;

@@ -39,8 +39,17 @@ enum SegKind : int32_t { SEG_STREAM = 0, SEG_LONG = 1, SEG_WINDOW = 2, SEG_CWIN 
 // differently: 1024-entry capacity, at most 128 rows).
 constexpr int KV_WAVE_PLAN = 3;
 
-// Tiles per chunk when tiles are dealt to the XCDs (spmv_params.xcd_chunk = 0).
+// The default XCD assignment of tiles (spmv_params.xcd_chunk = 0): a matrix
+// that does not fit the 256 MB memory-side cache is dealt to the XCDs in
+// chunks of 16 tiles, so that all XCDs stream near the same rows and share
+// one band of x there (16M-row mesh matrix, 3.2 GB: 0.518 against 0.567 ms
+// with one contiguous range per XCD; 3x3 blocks with 8 columns, 2.7 GB:
+// 0.98 against 1.18 ms); a smaller one keeps one contiguous range per XCD,
+// whose private L2 then holds that range's band (2M-row kNN matrix, 165 MB,
+// warm: 30.2 against 34.7 us with chunks).
 constexpr int kDefaultXcdChunk = 16, kDefaultXcdChunkLog2 = 4;
+constexpr int64_t kXcdChunkMinBytes = int64_t(256) << 20;
+inline int default_xcd_chunk(int64_t matrix_bytes) { return matrix_bytes >= kXcdChunkMinBytes ? kDefaultXcdChunk : -2; }
 
 // Compact per-tile windows: at most this many words and runs per tile.
 constexpr int kCwinMaxRuns = 64;  // must equal the kernels' kCwinMaxRunsDev

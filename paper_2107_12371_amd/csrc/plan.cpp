@@ -203,9 +203,7 @@ static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     // entries (its aligned span then fits tnz exactly).
     const int cap = tnz - 3;
     P.kernel = p.kernel;
-    // chunks of 16 tiles: 0.521 ms against 0.568 ms for one contiguous range
-    // per XCD on the 16M-row mesh matrix (chunks of 4 to 64 within 1%)
-    P.xcd_chunk = p.xcd_chunk ? p.xcd_chunk : kDefaultXcdChunk;
+    P.xcd_chunk = p.xcd_chunk ? p.xcd_chunk : default_xcd_chunk(12 * nnz + 4 * (int64_t)n_rows);
 
     // ---- segmentation into stream tiles and long rows
     int32_t r = 0;
