@@ -213,27 +213,38 @@ def cpu_baseline(A, x, budget_s: float):
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS", "unset")}
 
 
-def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, preload: bool = False, log=log):
-    """Request stream: a pool of 32^3-style mesh matrices with log-uniform
-    10^3..10^6 rows; each request picks a matrix uniformly and asks for
-    k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is uploaded
-    on its first request (that request pays for it), or, with `preload`, while
-    the pool is registered.  Arrivals are Poisson at 0.7x the closed-loop
-    capacity measured on a burst of requests."""
-    import threading
+SERVE_PHASES = ("latency_s", "queue_s", "wait_s", "copy_in_s", "compute_s", "copy_out_s", "graph_s")
+
+
+def serving_pool(pool_size: int, seed: int, log=log):
+    """The serving pool: 32^3-style mesh matrices with log-uniform 10^3..10^6
+    rows, generated on all host cores."""
+    from concurrent.futures import ThreadPoolExecutor
 
     import meshgen as mg
-    import paper_2107_12371_amd as spmv
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(1e3), np.log(1e6), pool_size)).astype(int)
     t0 = time.perf_counter()
-    pool = []
-    for i, n in enumerate(sizes):
-        pool.append(mg.serving_matrix(int(n), seed ^ (i + 1)))
-        if (i + 1) % 128 == 0:
-            log(f"serving pool: {i + 1} of {pool_size} matrices generated")
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        pool = list(ex.map(lambda i: mg.serving_matrix(int(sizes[i]), seed ^ (i + 1)), range(pool_size)))
     log(f"serving pool: {pool_size} matrices, {sum(A.n_rows for A in pool)} rows "
         f"({time.perf_counter() - t0:.1f} s)")
+    return pool
+
+
+def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = False, log=log):
+    """Request stream over `pool`: each request picks a matrix uniformly and
+    asks for k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is
+    uploaded on its first request (that request pays for it), or, with
+    `preload`, while the pool is registered.  Arrivals are Poisson at 0.7x
+    the closed-loop capacity measured on a burst of requests.  Reports
+    p50/p99 latency per op with its parts: queue (submit -> admission), wait
+    (admission -> a lane or slot starts), copy in, compute (the round's
+    launch or the whole solve), copy out, and the CG graph capture."""
+    import threading
+
+    import paper_2107_12371_amd as spmv
+    pool_size = len(pool)
 
     def make(i):
         r = np.random.default_rng(seed * 7919 + i)
@@ -259,7 +270,6 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, preloa
     # closed-loop capacity: two bursts of requests on matrices drawn as in the
     # stream, the second one timed
     burst = [make(-1 - i) for i in range(min(64, n_requests))]
-    tb = time.perf_counter()
     for t in [submit(r) for r in burst]:
         srv.wait(t)
     burst2 = [make(-1000 - i) for i in range(min(64, n_requests))]
@@ -286,7 +296,8 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, preloa
     t1 = time.perf_counter()
     th.start()
     th.join()
-    lat, lat_cg, lat_spmv, iters, fails, errors = [], [], [], [], 0, {}
+    phases = {"cg": {k: [] for k in SERVE_PHASES}, "spmv": {k: [] for k in SERVE_PHASES}}
+    iters, fails, errors, n_ok = [], 0, {}, 0
     for r, t in zip(reqs, tickets):
         _, res = srv.wait(t)
         if res.status != 0:
@@ -294,47 +305,50 @@ def serving_run(n_requests: int, pool_size: int, seed: int, cg_mode: int, preloa
             key = f"status {res.status}: {res.message}"
             errors[key] = errors.get(key, 0) + 1
             continue
-        lat.append(res.latency_s)
-        (lat_cg if r[0] == "cg" else lat_spmv).append(res.latency_s)
+        n_ok += 1
+        for k in SERVE_PHASES:
+            phases[r[0]][k].append(getattr(res, k))
         if r[0] == "cg":
             iters.append(res.iterations)
     wall = time.perf_counter() - t1
     st = srv.stats()
     srv.close()
-    q = lambda a, f: float(np.quantile(np.array(a), f)) if a else None
-    out = {"requests": n_requests, "pool": pool_size, "arrival_rate_rps": round(lam, 2),
-           "closed_loop_capacity_rps": round(cap, 2), "cg_mode": "mixed" if cg_mode else "fp64",
-           "preload": preload,
-           "p50_ms": round(1e3 * q(lat, 0.5), 3), "p99_ms": round(1e3 * q(lat, 0.99), 3),
-           "p50_cg_ms": round(1e3 * q(lat_cg, 0.5), 3) if lat_cg else None,
-           "p99_cg_ms": round(1e3 * q(lat_cg, 0.99), 3) if lat_cg else None,
-           "p50_spmv_ms": round(1e3 * q(lat_spmv, 0.5), 3) if lat_spmv else None,
-           "p99_spmv_ms": round(1e3 * q(lat_spmv, 0.99), 3) if lat_spmv else None,
-           "throughput_rps": round(len(lat) / wall, 2), "cg_solves_per_s": round(len(lat_cg) / wall, 2),
+
+    def q(a, f):
+        return round(1e3 * float(np.quantile(np.array(a), f)), 3) if a else None
+
+    lat_all = phases["cg"]["latency_s"] + phases["spmv"]["latency_s"]
+    out = {"requests": n_requests, "pool": pool_size, "pool_rows": int(sum(A.n_rows for A in pool)),
+           "arrival_rate_rps": round(lam, 2), "closed_loop_capacity_rps": round(cap, 2),
+           "cg_mode": "mixed" if cg_mode else "fp64", "preload": preload,
+           "p50_ms": q(lat_all, 0.5), "p99_ms": q(lat_all, 0.99),
+           "p50_cg_ms": q(phases["cg"]["latency_s"], 0.5), "p99_cg_ms": q(phases["cg"]["latency_s"], 0.99),
+           "p50_spmv_ms": q(phases["spmv"]["latency_s"], 0.5), "p99_spmv_ms": q(phases["spmv"]["latency_s"], 0.99),
+           "throughput_rps": round(n_ok / wall, 2), "cg_solves_per_s": round(len(phases["cg"]["latency_s"]) / wall, 2),
            "mean_cg_iterations": round(float(np.mean(iters)), 1) if iters else None,
+           "breakdown_ms_p50_p99": {op: {k[:-2]: [q(v, 0.5), q(v, 0.99)] for k, v in ph.items()}
+                                    for op, ph in phases.items()},
            "failed": fails, "errors": errors, "rounds": st["rounds"], "uploads": st["uploads"],
            "evictions": st["evictions"], "peak_budget_bytes": st["peak_bytes"]}
-    log(f"serving: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, {out['throughput_rps']} req/s "
-        f"at {out['arrival_rate_rps']} req/s offered")
+    log(f"serving{' (preloaded)' if preload else ''}: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
+        f"{out['throughput_rps']} req/s at {out['arrival_rate_rps']} req/s offered; "
+        f"breakdown {out['breakdown_ms_p50_p99']}")
     return out
 
 
-def serving_in_child(args, preload: bool = False) -> dict:
-    """The serving stream in a child process of its own, so that whatever
-    happens there cannot take the headline measurement with it."""
+def serving_in_child(args) -> dict:
+    """The serving streams (uploads on first touch, then a preloaded pool) in
+    a child process of its own, so that whatever happens there cannot take
+    the headline measurement with it."""
     import subprocess
     cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
            "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool)]
-    if preload:
-        cmd.append("--serve-preload")
     try:
-        r = subprocess.run(cmd, capture_output=True, text=True, timeout=400)
+        # progress lines go straight to this process's stderr as they come
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
     except subprocess.TimeoutExpired:
         log("serving: child timed out")
-        return {"failed": "timed out after 400 s"}
-    for line in r.stderr.splitlines():
-        if line.startswith("[bench]"):
-            print(line, file=sys.stderr, flush=True)
+        return {"failed": "timed out after 900 s"}
     if r.returncode != 0:
         log(f"serving: child exited with status {r.returncode}")
         return {"failed": f"child exit status {r.returncode}"}
@@ -562,13 +576,11 @@ def main():
                     help="CPU oracle budget, split between the single-threaded and the all-core build")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--serve-requests", type=int, default=512,
-                    help="requests in the serving stream (the full workload is 4096)")
-    ap.add_argument("--serve-pool", type=int, default=32,
-                    help="matrices in the serving pool (1024 in the full workload)")
+    ap.add_argument("--serve-requests", type=int, default=4096, help="requests in the serving stream")
+    ap.add_argument("--serve-pool", type=int, default=1024, help="matrices in the serving pool")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-preload", action="store_true",
-                    help="serving: upload the pool while registering it instead of on first request")
+                    help="serving (with --serve-only): only the stream over a pool uploaded while registering")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary (the bench runs it this way "
                          "in a child process)")
@@ -586,8 +598,13 @@ def main():
     if args.serve_only:
         import paper_2107_12371_amd as spmv
         import meshgen as mg
-        print(json.dumps(serving_run(args.serve_requests, args.serve_pool, mg.seed_for(4), spmv.CG_FP64,
-                                     preload=args.serve_preload)), flush=True)
+        pool = serving_pool(args.serve_pool, mg.seed_for(4))
+        out = {}
+        for name, pre in (("first_touch", False), ("preloaded", True)):
+            if args.serve_preload and not pre:
+                continue
+            out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre)
+        print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -616,6 +633,21 @@ def main():
     y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
 
     B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+    read_ceiling = None
+    if not args.no_extras:
+        # the read ceiling of this part: a plain streaming read of 4 GiB (far
+        # beyond L2 and the 256 MB MALL) at several grid sizes, the best kept.
+        # It runs before the headline: after the host-side set-up the part's
+        # clocks are low and take a few dozen launches to settle, which would
+        # otherwise fall into the W warm-up and first timed launches.
+        buf = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+        best = 0.0
+        for wg_per_cu in (2, 4, 8, 16, 32):
+            part = torch.empty(256 * wg_per_cu, dtype=torch.float64, device="cuda")
+            tr = time_launches(lambda: spmv.calibrate_read(buf, part), 20, 3, torch, WARM_S)
+            best = max(best, buf.numel() * 8 / tr / 1e9)
+        del buf, part
+        read_ceiling = best
     torch.cuda.synchronize()
     t_step = time_launches(lambda: M.apply(x, y), args.steps, args.warmup, torch)
     gbs = B / t_step / 1e9
@@ -648,19 +680,13 @@ def main():
                 "launch_ms_p10_p50_p90": [round(v * 1e3, 4) for v in per]}
 
     extras = {}
+    if read_ceiling:
+        roofline["read_ceiling_GBs"] = round(read_ceiling, 1)
+        roofline["frac_of_read_ceiling"] = round(gbs / read_ceiling, 4)
+        roofline["before_timed_region"] = "read-ceiling calibration (streaming reads of 4 GiB)"
+        log(f"read ceiling (streaming read of 4 GiB): {read_ceiling:.1f} GB/s; "
+            f"headline {100 * gbs / read_ceiling:.1f}% of it")
     if not args.no_extras:
-        # the read ceiling of this part: a plain streaming read of 4 GiB (far
-        # beyond L2 and the 256 MB MALL) at several grid sizes, the best kept
-        buf = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
-        best = 0.0
-        for wg_per_cu in (2, 4, 8, 16, 32):
-            part = torch.empty(256 * wg_per_cu, dtype=torch.float64, device="cuda")
-            tr = time_launches(lambda: spmv.calibrate_read(buf, part), 20, 3, torch, WARM_S)
-            best = max(best, buf.numel() * 8 / tr / 1e9)
-        del buf, part
-        roofline["read_ceiling_GBs"] = round(best, 1)
-        roofline["frac_of_read_ceiling"] = round(gbs / best, 4)
-        log(f"read ceiling (streaming read of 4 GiB): {best:.1f} GB/s; headline {100 * gbs / best:.1f}% of it")
         x32 = x.float()
         y32 = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
         t32 = time_launches(lambda: M.apply_f32(x32, y32), max(10, args.steps // 2), 3, torch, WARM_S)
@@ -737,8 +763,9 @@ def main():
         extras["configs"] = config_lines(torch)
         torch.cuda.empty_cache()
     if not args.no_extras and not args.no_serve:
-        extras["serving"] = serving_in_child(args)                       # uploads on first touch
-        extras["serving_preloaded"] = serving_in_child(args, preload=True)
+        sv = serving_in_child(args)
+        extras["serving"] = sv.get("first_touch", sv)              # uploads on first touch
+        extras["serving_preloaded"] = sv.get("preloaded", sv)
 
     cpu = None
     if not args.no_cpu:

@@ -298,6 +298,8 @@ typedef struct cg_info {
                                   restarts from the true residual (PCG) */
     double rel_residual;       /* true ||b - A x||_2 / ||b||_2 in binary64 at exit */
     double seconds;            /* wall time of the solve on the host clock */
+    double graph_seconds;      /* part of seconds spent capturing and instantiating the
+                                  iteration graph (0 for cg_solve_noalloc) */
 } cg_info;
 
 /*
@@ -374,7 +376,19 @@ typedef struct srv_result {
     int32_t op;           /* SRV_SPMV or SRV_CG */
     double rel_residual;  /* CG: true relative residual */
     double latency_s;     /* submit -> result in the caller's buffer */
-    double queue_s;       /* submit -> admission */
+    double queue_s;       /* submit -> admission (budget, a free CG slot) */
+    double wait_s;        /* admission -> an SpMV lane or CG slot starts on it (matrix upload,
+                             a free lane, the round it joins) */
+    /* Measured with HIP events on the lane's or slot's stream (-1 if the
+     * request did not run): */
+    double copy_in_s;     /* input vectors to the device, with their buffers' allocation */
+    double compute_s;     /* device work: the round's multi-matrix launch (shared by the
+                             round's requests), or the whole CG solve */
+    double copy_out_s;    /* results back to the caller's buffer */
+    double graph_s;       /* CG: capturing and instantiating the iteration graph (host clock,
+                             part of compute_s) */
+    double dev_begin_s, dev_end_s; /* the device work's interval, in seconds on one device
+                             clock per server (comparable across requests) */
     char message[160];    /* why the request failed; empty when status is SPMV_OK */
 } srv_result;
 

@@ -67,7 +67,8 @@ class spmv_info(ctypes.Structure):
 
 class cg_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("graph_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -249,6 +250,7 @@ class CGInfo:
     rel_residual: float
     seconds: float
     status: int
+    graph_seconds: float = 0.0
 
 
 class Matrix:
@@ -398,7 +400,7 @@ class Matrix:
                             tol, max_iter, mode, ctypes.byref(inf), _stream_ptr(stream))
         if raise_on_error and rc not in (SPMV_OK,):
             _check(rc, "cg_solve")
-        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc)
+        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc, inf.graph_seconds)
 
     def cg_noalloc(self, b, x=None, tol: float = 1e-10, max_iter: int = 20000, stream=None,
                    raise_on_error: bool = True):
@@ -415,7 +417,7 @@ class Matrix:
                                     tol, max_iter, CG_FP64, ctypes.byref(inf), _stream_ptr(stream))
         if raise_on_error and rc not in (SPMV_OK,):
             _check(rc, "cg_solve_noalloc")
-        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc)
+        return x, CGInfo(inf.iterations, inf.refinements, inf.rel_residual, inf.seconds, rc, inf.graph_seconds)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -449,7 +451,9 @@ class srv_config(ctypes.Structure):
 class srv_result(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("op", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("latency_s", ctypes.c_double),
-                ("queue_s", ctypes.c_double), ("_message", ctypes.c_char * 160)]
+                ("queue_s", ctypes.c_double), ("wait_s", ctypes.c_double), ("copy_in_s", ctypes.c_double),
+                ("compute_s", ctypes.c_double), ("copy_out_s", ctypes.c_double), ("graph_s", ctypes.c_double),
+                ("dev_begin_s", ctypes.c_double), ("dev_end_s", ctypes.c_double), ("_message", ctypes.c_char * 160)]
 
     @property
     def message(self) -> str:

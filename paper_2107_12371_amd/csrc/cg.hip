@@ -841,8 +841,16 @@ template <typename T, typename V> struct CgCore {
     // Captures graph_iters calls of iter(stream) into one replayable graph,
     // with the capture gate held (one capture at a time in the process, and
     // none during the library's synchronous runtime work).
+    double capture_s = 0.0;  // host time spent capturing and instantiating
+
     template <typename F> int capture_with(F &&iter) {
         std::lock_guard<std::mutex> lock(capture_gate());
+        const auto t0 = std::chrono::steady_clock::now();
+        struct Timer {
+            double &acc;
+            std::chrono::steady_clock::time_point t0;
+            ~Timer() { acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+        } timer{capture_s, t0};
         hipStream_t cs;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1131,6 +1139,7 @@ static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol,
     if (info) {
         info->iterations = iters;
         info->refinements = repl;
+        info->graph_seconds = C.capture_s;
         info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
     }
     if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
@@ -1215,6 +1224,7 @@ static int cg_fp64_noalloc(const spmv_matrix *A, const double *b, double *x, dou
     if (info) {
         info->iterations = iters;
         info->refinements = repl;
+        info->graph_seconds = C.capture_s;
         info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
     }
     if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
@@ -1290,6 +1300,7 @@ static int cg_mixed(const spmv_matrix *A, const double *b, double *x, double tol
     if (info) {
         info->iterations = iters;
         info->refinements = outer;
+        info->graph_seconds = O.capture_s + I.capture_s;
         info->rel_residual = std::sqrt(O.hst->rt2 / bb);
     }
     if (status == SPMV_ENOTCONV) return fail(status, "mixed CG did not reach tol = %g within %d iterations", tol, max_iter);
@@ -1340,6 +1351,7 @@ static int cg_pcg(const spmv_matrix *A, const double *b, double *x, double tol, 
     if (info) {
         info->iterations = iters;
         info->refinements = restarts;
+        info->graph_seconds = C.capture_s;
         info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
     }
     if (rc == SPMV_ENOTCONV) return fail(rc, "PCG did not reach tol = %g within %d iterations", tol, max_iter);

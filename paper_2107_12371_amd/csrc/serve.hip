@@ -96,6 +96,13 @@ struct Request {
     double tol = 0.0;
     uint64_t extra = 0;
     Clock::time_point t_submit, t_start, t_done;
+    Clock::time_point t_run{};  // a lane or slot began its work
+    // from HIP events on the lane's or slot's stream: host -> device copies
+    // (with the buffers' stream-ordered allocation), the device work, the
+    // copies back; the device work's interval on the server's device clock
+    double copy_in_s = -1.0, compute_s = -1.0, copy_out_s = -1.0;
+    double dev_begin_s = -1.0, dev_end_s = -1.0;
+    double graph_s = 0.0;       // CG: graph capture and instantiation inside the solve
     bool done = false;
     int status = SPMV_OK;
     char message[160] = {0};
@@ -116,10 +123,48 @@ struct MatrixEntry {
     char error[160] = {0};
 };
 
+// Four events on a worker's stream: before the copies in, before the device
+// work, after it, after the copies out.
+struct PhaseEvents {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ok = false;
+    hipError_t create() {
+        for (auto &e : ev) {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        ok = true;
+        return hipSuccess;
+    }
+    void destroy() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t s) const {
+        if (ok) (void)hipEventRecord(ev[i], s);
+    }
+    // after the stream has synchronised: phase times, and the device-work
+    // interval relative to the reference event `ref`
+    void fill(Request *r, hipEvent_t ref) const {
+        if (!ok) return;
+        float a = 0, b = 0, c = 0;
+        if (hipEventElapsedTime(&a, ev[0], ev[1]) == hipSuccess) r->copy_in_s = 1e-3 * a;
+        if (hipEventElapsedTime(&b, ev[1], ev[2]) == hipSuccess) r->compute_s = 1e-3 * b;
+        if (hipEventElapsedTime(&c, ev[2], ev[3]) == hipSuccess) r->copy_out_s = 1e-3 * c;
+        float t0 = 0, t1 = 0;
+        if (ref && hipEventElapsedTime(&t0, ref, ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&t1, ref, ev[2]) == hipSuccess) {
+            r->dev_begin_s = 1e-3 * t0;
+            r->dev_end_s = 1e-3 * t1;
+        }
+    }
+};
+
 struct Slot {
     std::thread th;
     hipStream_t stream = nullptr;
     void *pinned = nullptr;
+    PhaseEvents pe;
     Request *job = nullptr;
 };
 
@@ -131,6 +176,7 @@ struct Lane {
     hipStream_t stream = nullptr;
     MultiItem *items_host = nullptr;  // pinned staging of the round's item table
     size_t items_cap = 0;
+    PhaseEvents pe;
     std::vector<Request *> job;
     bool busy = false;
 };
@@ -166,6 +212,7 @@ struct Server {
     std::vector<double> latencies;
     Clock::time_point t_first{}, t_last{};
     bool any_submit = false;
+    hipEvent_t ref_event = nullptr;  // zero of the device clock the requests' intervals are read on
 
     explicit Server(const srv_config &c) : cfg(c), policy(c.hbm_budget_bytes) {}
 
@@ -277,6 +324,8 @@ struct Server {
         const hipStream_t batch = ln.stream;
         clear_error();
         (void)hipGetLastError();  // drop an error an earlier call of this thread left behind
+        const Clock::time_point t_run = Clock::now();
+        ln.pe.mark(0, batch);
         std::vector<MultiItem> items;
         std::vector<std::pair<Request *, std::pair<double *, double *>>> bufs;
         int total = 0;
@@ -306,6 +355,7 @@ struct Server {
                 total += M.n_stream;
             }
         }
+        ln.pe.mark(1, batch);
         if (err == SPMV_OK && !items.empty()) {
             if (items.size() > ln.items_cap) {
                 std::lock_guard<std::mutex> gate(capture_gate());
@@ -335,6 +385,7 @@ struct Server {
                 if (e != hipSuccess) err = hip_fail(e, "server round launch");
             }
         }
+        ln.pe.mark(2, batch);
         for (auto &b : bufs) {
             Request *r = b.first;
             const size_t nout = (size_t)r->k * r->A->M.n_rows;
@@ -343,6 +394,7 @@ struct Server {
                 if (e != hipSuccess) err = hip_fail(e, "server result copy");
             }
         }
+        ln.pe.mark(3, batch);
         hipError_t e = hipStreamSynchronize(batch);
         if (e != hipSuccess && err == SPMV_OK) err = hip_fail(e, "server round");
         for (auto &b : bufs) {
@@ -352,6 +404,8 @@ struct Server {
         std::lock_guard<std::mutex> lk(mu);
         ++rounds;
         for (Request *r : round) {
+            r->t_run = t_run;
+            if (e == hipSuccess) ln.pe.fill(r, ref_event);
             policy.release(r->mid, r->extra);
             --in_flight_spmv;
             finish_locked(r, err);
@@ -416,6 +470,8 @@ struct Server {
             const int n = A ? A->M.n_rows : 0;
             double *db = nullptr, *dx = nullptr;
             int rc = SPMV_OK;
+            const Clock::time_point t_run = Clock::now();
+            sl.pe.mark(0, sl.stream);
             hipError_t e = dev_err != hipSuccess ? dev_err : hipMallocAsync(reinterpret_cast<void **>(&db), 8 * (size_t)std::max(n, 1), sl.stream);
             if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&dx), 8 * (size_t)std::max(n, 1), sl.stream);
             if (e == hipSuccess) e = hipMemcpyAsync(db, r->in, 8 * (size_t)n, hipMemcpyHostToDevice, sl.stream);
@@ -428,17 +484,23 @@ struct Server {
             } else if (e != hipSuccess) {
                 rc = hip_fail(e, "server solve buffers");
             } else {
+                sl.pe.mark(1, sl.stream);
                 rc = cg_run(A, db, dx, r->tol, r->max_iter, cfg.cg_mode, &info, sl.stream, sl.pinned);
+                sl.pe.mark(2, sl.stream);
                 if (rc == SPMV_OK || rc == SPMV_ENOTCONV) {
                     e = hipMemcpyAsync(r->out, dx, 8 * (size_t)n, hipMemcpyDeviceToHost, sl.stream);
+                    sl.pe.mark(3, sl.stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
                     if (e != hipSuccess) rc = hip_fail(e, "server solve result");
+                    else sl.pe.fill(r, ref_event);
                 }
             }
             if (db) (void)hipFreeAsync(db, sl.stream);
             if (dx) (void)hipFreeAsync(dx, sl.stream);
             (void)hipStreamSynchronize(sl.stream);
             std::lock_guard<std::mutex> lk(mu);
+            r->t_run = t_run;
+            r->graph_s = info.graph_seconds;
             r->iterations = info.iterations;
             r->rel_residual = info.rel_residual;
             policy.release(r->mid, r->extra);
@@ -579,18 +641,28 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     for (auto &sl : S->slots) {
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipHostMalloc(&sl.pinned, 256, hipHostMallocDefault);
+        if (e == hipSuccess) e = sl.pe.create();
         if (e != hipSuccess) break;
     }
-    for (size_t i = 0; i < S->lanes.size() && e == hipSuccess; ++i)
+    for (size_t i = 0; i < S->lanes.size() && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&S->lanes[i].stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = S->lanes[i].pe.create();
+    }
+    if (e == hipSuccess) e = hipEventCreate(&S->ref_event);
+    if (e == hipSuccess) e = hipEventRecord(S->ref_event, S->lanes[0].stream);
+    if (e == hipSuccess) e = hipEventSynchronize(S->ref_event);
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "server streams");
         for (auto &t : S->slots) {
             if (t.stream) (void)hipStreamDestroy(t.stream);
             if (t.pinned) (void)hipHostFree(t.pinned);
+            t.pe.destroy();
         }
-        for (auto &ln : S->lanes)
+        for (auto &ln : S->lanes) {
             if (ln.stream) (void)hipStreamDestroy(ln.stream);
+            ln.pe.destroy();
+        }
+        if (S->ref_event) (void)hipEventDestroy(S->ref_event);
         delete S;
         return rc;
     }
@@ -689,6 +761,16 @@ static void fill_result(const Request *r, srv_result *res) {
         res->latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
         res->queue_s = std::chrono::duration<double>(r->t_start - r->t_submit).count();
         if (res->queue_s < 0) res->queue_s = 0;
+        if (r->t_run != Clock::time_point{}) {
+            res->wait_s = std::chrono::duration<double>(r->t_run - r->t_start).count();
+            if (res->wait_s < 0) res->wait_s = 0;
+        }
+        res->copy_in_s = r->copy_in_s;
+        res->compute_s = r->compute_s;
+        res->copy_out_s = r->copy_out_s;
+        res->graph_s = r->graph_s;
+        res->dev_begin_s = r->dev_begin_s;
+        res->dev_end_s = r->dev_end_s;
     }
 }
 
@@ -780,11 +862,14 @@ extern "C" int srv_destroy(spmv_server *srv) {
     for (auto &sl : S->slots) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
+        sl.pe.destroy();
     }
     for (auto &ln : S->lanes) {
         if (ln.items_host) (void)hipHostFree(ln.items_host);
         if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        ln.pe.destroy();
     }
+    if (S->ref_event) (void)hipEventDestroy(S->ref_event);
     for (auto &kv : S->all) delete kv.second;
     delete S;
     delete srv;

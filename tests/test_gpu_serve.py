@@ -214,3 +214,57 @@ def test_one_lane_and_small_rounds(pool):
             out, res = srv.wait(t)
             _check(pool, r, out, res)
         assert srv.stats()["rounds"] >= len(reqs)
+
+
+def test_large_request_takes_a_round_of_its_own(pool):
+    # k = 32 vectors on the 150K-row matrix move 9.6 M words (>= 2^22): the
+    # request gets a round of its own while small requests keep batching;
+    # every column is checked against the oracle
+    A = pool[-1]
+    big = mg.uniform(32 * A.n_cols, 61, 3).reshape(32, A.n_cols)
+    assert 32 * (A.n_rows + A.n_cols) >= 1 << 22
+    small = [("spmv", i % 4, mg.uniform(pool[i % 4].n_cols * 2, 70 + i, 3).reshape(2, pool[i % 4].n_cols))
+             for i in range(8)]
+    with spmv.Server(n_slots=2) as srv:
+        for M in pool:
+            srv.add_matrix(M)
+        srv.wait(srv.submit_spmv(len(pool) - 1, big[:1]))        # upload the matrix first
+        t_big = srv.submit_spmv(len(pool) - 1, big)
+        t_small = [_submit(srv, r) for r in small]
+        out, res = srv.wait(t_big)
+        _ok(res)
+        for j in range(32):
+            y_ref, bound = oracle.spmv(A, big[j])
+            assert oracle.spmv_accept(out[j], y_ref, bound).all(), j
+        others = []
+        for r, t in zip(small, t_small):
+            o, rs = srv.wait(t)
+            _check(pool, r, o, rs)
+            others.append(rs)
+    # the large request's device interval is shared with no other request's
+    assert res.compute_s > 0 and res.dev_end_s > res.dev_begin_s >= 0
+    assert all((o.dev_begin_s, o.dev_end_s) != (res.dev_begin_s, res.dev_end_s) for o in others)
+
+
+def test_cg_solves_and_spmv_rounds_overlap_on_the_device(pool):
+    # solver slots and SpMV lanes work on their own streams: in a mix, at
+    # least one CG solve's device interval overlaps an SpMV round's, and
+    # every request's phase times are consistent with its latency
+    reqs = [("cg", 4 + (i % 2), mg.uniform(pool[4 + (i % 2)].n_rows, 80 + i, 4)) for i in range(4)]
+    reqs += [("spmv", i % 6, mg.uniform(pool[i % 6].n_cols * 4, 90 + i, 3).reshape(4, pool[i % 6].n_cols))
+             for i in range(40)]
+    with spmv.Server(n_slots=4, preload=True) as srv:
+        for M in pool:
+            srv.add_matrix(M)
+        srv.drain()
+        tickets = [_submit(srv, r) for r in reqs]
+        done = [srv.wait(t) for t in tickets]
+    spans = {"cg": [], "spmv": []}
+    for r, (out, res) in zip(reqs, done):
+        _check(pool, r, out, res)
+        assert res.compute_s > 0 and res.copy_in_s >= 0 and res.copy_out_s >= 0
+        assert res.compute_s <= res.latency_s and res.queue_s + res.wait_s <= res.latency_s
+        assert res.dev_end_s > res.dev_begin_s >= 0
+        spans[r[0]].append((res.dev_begin_s, res.dev_end_s))
+    overlap = any(c0 < s1 and s0 < c1 for c0, c1 in spans["cg"] for s0, s1 in spans["spmv"])
+    assert overlap, (spans["cg"], spans["spmv"][:8])
