@@ -469,7 +469,7 @@ def config_lines(torch, log=log) -> dict:
 
 
 CASES = ("bsr3_k1_fp64", "bsr3_k8_fp64", "bsr3_k1_fp32", "bsr3_k8_fp32", "bsr3_k4_fp64", "bsr3_k4_fp32",
-         "spmm_k8", "sell", "fp32", "csr_direct", "copy")
+         "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k")
 
 
 def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibration: bool) -> list[dict]:
@@ -482,7 +482,9 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       sell        SELL-C-sigma (sigma 4096) on the same matrix
       fp32        FP32 values / x / accumulation on the same matrix (compact windows)
       csr_direct  FP64 with direct gathers (no windows) on the same matrix
-      copy        a plain 1 GiB device copy (the counter calibration)"""
+      copy        a plain 1 GiB device copy (the counter calibration)
+      cg_fp64_16m   48 FP64 CG iterations on the same matrix (per step)
+      cg_fp64_c50k  FP64 CG to 1e-10 on the 49,336-row tet-like stand-in (per step)"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -513,6 +515,18 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
             sv = 4 if fp32 else 8
             out["alg_bytes"] = A.nnz * (9 * sv + 4) + 4 * (A.n_rows + 1) + sv * 3 * k * (A.n_cols + A.n_rows)
             out["flops"] = 2 * 9 * A.nnz * k
+        elif name.startswith("cg_fp64"):
+            A = mat("hex") if name.endswith("16m") else mg.table1_matrix("C50K")
+            b = torch.as_tensor(mg.uniform(A.n_rows, 7, 1), device="cuda")
+            with spmv.Matrix.from_csr(A) as M:
+                it = 48 if name.endswith("16m") else 20000
+                tol = 0.0 if name.endswith("16m") else 1e-10
+                M.cg(b, tol=tol, max_iter=it, raise_on_error=False)  # captures the graph once
+                t = time_launches(lambda: M.cg(b, tol=tol, max_iter=it, raise_on_error=False), steps, warmup, torch)
+                _, info = M.cg(b, tol=tol, max_iter=it, raise_on_error=False)
+            out["iterations"] = info.iterations
+            out["us_per_iteration"] = round(t * 1e6 / max(info.iterations, 1), 2)
+            out["alg_bytes"] = 0
         elif name == "copy":
             buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(buf)
@@ -543,7 +557,8 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
                     out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
             del x
         out["ms_per_launch"] = round(t * 1e3, 5)
-        out["GBs"] = round(out["alg_bytes"] / t / 1e9, 1)
+        if out["alg_bytes"]:
+            out["GBs"] = round(out["alg_bytes"] / t / 1e9, 1)
         if "flops" in out:
             out["GFLOPs"] = round(out["flops"] / t / 1e9, 1)
         log(f"case {name}: {out}")

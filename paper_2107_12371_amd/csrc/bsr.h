@@ -9,7 +9,7 @@
 
 namespace spmvlib {
 
-constexpr int kBsrRows = 85;     // block rows per tile (3 lanes each)
+constexpr int kBsrRows = 84;     // block rows per tile (3 lanes each: 21 per wavefront)
 constexpr int kBsrBlocks = 510;  // stored 3x3 blocks staged in LDS per tile
 
 template <typename V, typename T> struct BsrArgs {

@@ -146,6 +146,55 @@ __device__ __forceinline__ void bsr_pairs(const BsrArgs<V, T> &g, int R0, int R1
     }
 }
 
+// Pass 2, one column: three adjacent lanes (a triad) per block row, lane r
+// computing scalar row 3 br + r.  Each lane gathers only x[3 bc + r] of a
+// block and takes the block's other two x values from its triad siblings
+// by lane shuffle, so a block costs one gather per lane instead of three
+// (the three lanes used to fetch the same three words each).  A wavefront
+// holds 21 triads (lane 63 idles), so a triad never straddles two
+// wavefronts; its three lanes share the block row, hence the loop bounds,
+// and take every shuffle together.  Same per-output sum as bsr_pairs.
+template <typename V, typename T, int U, typename VP, typename CP>
+__device__ __forceinline__ void bsr_triads(const BsrArgs<V, T> &g, int R0, int R1, int q0, VP vals, CP cols) {
+    constexpr int kTriads = kWave / 3;                  // 21 per wavefront
+    constexpr int kRowsPerPass = kTriads * (kBlock / kWave);
+    const int lane = (int)threadIdx.x & (kWave - 1), wave = (int)threadIdx.x / kWave;
+    const int r = lane % 3, first = lane - r;           // lane 63: r = 0, a triad of its own, never stored
+    const int nbr = R1 - R0;
+    for (int brl0 = wave * kTriads; brl0 < nbr; brl0 += kRowsPerPass) {
+        const int brl = brl0 + lane / 3;
+        const bool live = lane < 3 * kTriads && brl < nbr;
+        const int br = R0 + min(brl, nbr - 1);
+        const int a = g.brow_ptr[br], z = g.brow_ptr[br + 1];
+        T acc = T(0);
+        for (int q = a; q < z; q += U) {
+            int qq[U];
+            T xo[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                qq[u] = min(q + u, z - 1) - q0;
+                xo[u] = g.X[(size_t)(3 * cols[qq[u]] + r) * g.ldx + g.off];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const T x0 = __shfl(xo[u], first, kWave);
+                const T x1 = __shfl(xo[u], first + 1, kWave);
+                const T x2 = __shfl(xo[u], first + 2, kWave);
+                const T a0 = static_cast<T>(vals[9 * (size_t)qq[u] + 3 * r]);
+                const T a1 = static_cast<T>(vals[9 * (size_t)qq[u] + 3 * r + 1]);
+                const T a2 = static_cast<T>(vals[9 * (size_t)qq[u] + 3 * r + 2]);
+                const bool in_row = q + u < z;
+                T s = acc;
+                s += a0 * x0;
+                s += a1 * x1;
+                s += a2 * x2;
+                acc = in_row ? s : acc;
+            }
+        }
+        if (live) g.Y[(size_t)(3 * br + r) * g.ldy + g.off] = acc;
+    }
+}
+
 // Pass 2, one lane per (block row, column group): the lane gathers each X
 // row once and accumulates the three scalar rows of its block row.  Same
 // per-output summation order as bsr_pairs.
@@ -203,6 +252,7 @@ __device__ __forceinline__ void bsr_pass2(const BsrArgs<V, T> &g, int R0, int R1
     using Sh = BsrShape<T, K>;
     static_assert(K % Sh::JL == 0, "column groups must split K");
     if constexpr (Sh::ROWS) bsr_blockrows<V, T, K, Sh::JL, Sh::U, VEC>(g, R0, R1, q0, vals, cols);
+    else if constexpr (K == 1) bsr_triads<V, T, Sh::U>(g, R0, R1, q0, vals, cols);
     else bsr_pairs<V, T, K, Sh::JL, Sh::U>(g, R0, R1, q0, vals, cols);
 }
 
