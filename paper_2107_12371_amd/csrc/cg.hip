@@ -331,10 +331,13 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 // the epilogue), exactly as k_update_p_fold forms it (fma(beta, p, r), beta
 // rounded to T).  beta comes from the r.r partials, summed as
 // sum_partials sums them, and workgroup 0 records the step (R_BETA_DEFER),
-// unless F_FRESH hands beta over in the state.  The tile's stream and row
-// data are loaded before the partials are summed, so the reduction's
-// latency overlaps the matrix stream.  Same q and p.q partials, bit for
-// bit, as the p update followed by the plain SpMV on p_new.
+// unless F_FRESH hands beta over in the state.  On these small systems the
+// launch is a chain of memory round trips, so every load that does not
+// depend on another is issued before any is waited for: the descriptor and
+// the state together, then the tile's stream, the row data and the r.r
+// partials, then the gathers of p and r, all before beta is formed.  Same
+// q and p.q partials, bit for bit, as the p update followed by the plain
+// SpMV on p_new.
 template <typename T, typename V, int NT>
 __global__ __launch_bounds__(kBlock) void k_spmv_pfused(const TileDesc *__restrict__ desc, int n_list, int per_xcd,
                                                         int chunk_log2, const int32_t *__restrict__ row_ptr,
@@ -342,36 +345,48 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pfused(const TileDesc *__restri
                                                         const T *__restrict__ p, const T *__restrict__ r,
                                                         T *__restrict__ q, double *__restrict__ part_pq, CgState *st,
                                                         const double *__restrict__ part_rr, int n_rr) {
-    __shared__ T prod[TileRegs<V, NT>::kProd];
+    using Regs = TileRegs<V, NT>;
+    __shared__ T prod[Regs::kProd];
     __shared__ double sh[kBlock / kWave];
     __shared__ double rr_all;
-    if (st->done) return;
     const int li = xcd_tile(blockIdx.x, per_xcd, chunk_log2);
     if (li >= n_list) return;
     const TileDesc d = desc[li];
-    TileRegs<V, NT> t;
+    const int done = st->done, flags = st->flags;
+    const double rho = st->rho, tol2 = st->tol2, beta_state = st->beta;
+    Regs t;
     t.load(col, val, d.s, d.e);
     RowPre<T, EPI_DOT> pre;
     pre.load(row_ptr, p, static_cast<const T *>(nullptr), d.r0, d.r1, d.s & ~3);  // op = p of the tile's rows
     T r_row[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) r_row[i] = r[min(d.r0 + (int)threadIdx.x + i * kBlock, d.r1 - 1)];
-    double beta;
-    if (st->flags & F_FRESH) {
-        beta = st->beta;
-    } else {
-        const double t0 = sum_partials(part_rr, n_rr, sh);
+    const bool fresh = (flags & F_FRESH) != 0;
+    double part = 0.0;  // this lane's share of the r.r sum, in sum_partials' order
+    if (!fresh) {
+#pragma unroll 4
+        for (int i = (int)threadIdx.x; i < n_rr; i += kBlock) part += part_rr[i];
+    }
+    T pv[Regs::kMaxPass][4], rv[Regs::kMaxPass][4];
+    t.gather([p](int c) { return p[c]; }, pv);
+    t.gather([r](int c) { return r[c]; }, rv);
+    if (done) return;
+    double beta = beta_state;
+    if (!fresh) {
+        const double t0 = block_sum(part, sh);
         if (threadIdx.x == 0) rr_all = t0;
         __syncthreads();
         const double tt = rr_all;
-        const double rho = st->rho;
         if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_BETA_DEFER, tt);
-        if (!isfinite(tt) || tt <= st->tol2) return;
+        if (!isfinite(tt) || tt <= tol2) return;
         beta = tt / rho;
     }
     const T b = static_cast<T>(beta);
-    T xv[TileRegs<V, NT>::kMaxPass][4];
-    t.gather([p, r, b](int c) { return fma_t(b, p[c], r[c]); }, xv);
+    T xv[Regs::kMaxPass][4];
+#pragma unroll
+    for (int ps = 0; ps < Regs::kMaxPass; ++ps)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[ps][j] = fma_t(b, pv[ps][j], rv[ps][j]);
 #pragma unroll
     for (int i = 0; i < 2; ++i) pre.op[i] = fma_t(b, pre.op[i], r_row[i]);
     t.products(xv, prod);
@@ -382,32 +397,69 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pfused(const TileDesc *__restri
 // The x/r update of a fused iteration: p_new = r + beta p (as the fused
 // product formed it) is written for this workgroup's rows, then x += alpha
 // p_new, r -= alpha q and the r.r partial, as k_update_xr.  Workgroup 0
-// clears F_FRESH.
+// clears F_FRESH.  The fused path runs on at most 1,024 workgroups, so a
+// workgroup's chunk holds at most 1,024 rows, four per lane: the state, the
+// p.q partials and all of the lane's vector elements are loaded before any
+// is waited for (one memory round trip instead of three).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_xpr(int n, int chunk, T *__restrict__ x, T *__restrict__ r,
                                                        T *__restrict__ p, const T *__restrict__ q, CgState *st,
                                                        const double *__restrict__ part_pq, int n_pq,
                                                        double *__restrict__ part) {
+    constexpr int kRows = 4;  // rows per lane: chunk <= kRows * kBlock
     __shared__ double sh[kBlock / kWave];
     __shared__ double pq_all;
-    if (st->done) return;
-    double alpha;
-    if (!form_alpha(st, part_pq, n_pq, sh, &pq_all, alpha)) return;
-    const T a = static_cast<T>(alpha);
-    const T b = static_cast<T>(st->beta);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->flags &= ~F_FRESH;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    double dd = 0.0;
+    const int done = st->done;
+    const double rho_new = st->rho_new, alpha_state = st->alpha, beta = st->beta;
+    T xs[kRows], ps[kRows], rs[kRows], qs[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+        const int i = min(lo + (int)threadIdx.x + u * kBlock, n - 1);
+        xs[u] = x[i];
+        ps[u] = p[i];
+        rs[u] = r[i];
+        qs[u] = q[i];
+    }
+    double s = 0.0;  // this lane's share of the p.q sum, in sum_partials' order
+    if (n_pq >= 0) {
 #pragma unroll 4
-    for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
-        const T ri0 = r[i];
-        const T pn = fma_t(b, p[i], ri0);
-        const T xi = x[i] + a * pn;
-        const T ri = ri0 - a * q[i];
-        p[i] = pn;
-        x[i] = xi;
-        r[i] = ri;
-        dd += static_cast<double>(ri) * static_cast<double>(ri);
+        for (int i = (int)threadIdx.x; i < n_pq; i += kBlock) s += part_pq[i];
+    }
+    if (done) return;
+    double alpha = alpha_state;
+    if (n_pq >= 0) {
+        const double t = block_sum(s, sh);
+        if (threadIdx.x == 0) pq_all = t;
+        __syncthreads();
+        const double pq = pq_all;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) apply_reduction(st, R_ALPHA, pq);
+            return;
+        }
+        alpha = rho_new / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->alpha = alpha;
+            st->rho = rho_new;
+        }
+    }
+    const T a = static_cast<T>(alpha);
+    const T b = static_cast<T>(beta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->flags &= ~F_FRESH;
+    double dd = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+        const int i = lo + (int)threadIdx.x + u * kBlock;
+        if (i < hi) {
+            const T pn = fma_t(b, ps[u], rs[u]);
+            const T xi = xs[u] + a * pn;
+            const T ri = rs[u] - a * qs[u];
+            p[i] = pn;
+            x[i] = xi;
+            r[i] = ri;
+            dd += static_cast<double>(ri) * static_cast<double>(ri);
+        }
     }
     const double tt = block_sum(dd, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = tt;
@@ -762,7 +814,8 @@ template <typename T, typename V> struct CgCore {
         n_wg = std::max(1, std::min(2048, (n + 4 * kBlock - 1) / (4 * kBlock)));
         chunk = (n + n_wg - 1) / n_wg;
         graph_iters = n >= (1 << 20) ? 8 : (n >= (1 << 16) ? 16 : 32);
-        fused = n_wg <= kFoldBeta && M.block == 1 && M.format == SPMV_FORMAT_CSR && M.n_stream > 0 &&
+        fused = n_wg <= kFoldBeta && chunk <= 4 * kBlock && M.block == 1 && M.format == SPMV_FORMAT_CSR &&
+                M.n_stream > 0 &&
                 M.n_cwin == 0 && M.n_blk == 0 && M.n_long == 0 && M.n_seg == M.n_stream;
     }
     ~CgCore() {
