@@ -319,8 +319,8 @@ def test_fp32_paths_within_derived_bounds():
 
 def test_reduced_precision_on_a_compact_window_handle(cfg1):
     # on a handle planned with compact windows, FP32 values (with FP32 or
-    # FP64 x) go through the windows and BF16 through direct gathers over the
-    # same tiles; every precision equals the direct-gather handle bit for bit
+    # FP64 x) and BF16 values go through the windows too; every precision
+    # equals the direct-gather handle bit for bit
     A = cfg1["rcm"]
     x = mg.uniform(A.n_cols, 22, 0)
     y_ref, bound, m = _bounds(A, x)
