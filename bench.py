@@ -726,6 +726,13 @@ def main():
                 fm[name] = {"ms": round(tf * 1e3, 4), "GBs": round(B / tf / 1e9, 1)}
                 if name == "sell":
                     fm[name]["padding"] = round(M2.info["sell_entries"] / A.nnz - 1, 4)
+        # the same lattice in its natural (lexicographic) order instead of RCM
+        An = mg.config2(m=args.m, ordering="natural")
+        with spmv.Matrix.from_csr(An) as M2:
+            tn = time_launches(lambda: M2.apply(x, y), max(10, args.steps // 2), 3, torch, WARM_S)
+            fm["natural_order"] = {"ms": round(tn * 1e3, 4), "GBs": round(B / tn / 1e9, 1),
+                                   "window_tiles": M2.info["n_window_tiles"], "tiles": M2.info["n_tiles"]}
+        del An
         extras["formats_16M"] = fm
         log(f"formats: {fm}")
         # k = 8 right-hand sides in one product (values read once) vs 8 products
