@@ -213,7 +213,7 @@ def cpu_baseline(A, x, budget_s: float):
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS", "unset")}
 
 
-SERVE_PHASES = ("latency_s", "queue_s", "wait_s", "copy_in_s", "compute_s", "copy_out_s", "graph_s")
+SERVE_PHASES = ("latency_s", "queue_s", "wait_s", "copy_in_s", "compute_s", "copy_out_s", "graph_s", "kernel_s")
 
 
 def serving_pool(pool_size: int, seed: int, log=log):
@@ -232,7 +232,8 @@ def serving_pool(pool_size: int, seed: int, log=log):
     return pool
 
 
-def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = False, log=log):
+def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = False, persistent_wgs: int = 0,
+                rate: float = 0.0, log=log):
     """Request stream over `pool`: each request picks a matrix uniformly and
     asks for k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is
     uploaded on its first request (that request pays for it), or, with
@@ -240,7 +241,11 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     the closed-loop capacity measured on a burst of requests.  Reports
     p50/p99 latency per op with its parts: queue (submit -> admission), wait
     (admission -> a lane or slot starts), copy in, compute (the round's
-    launch or the whole solve), copy out, and the CG graph capture."""
+    launch or the whole solve), copy out, and the CG graph capture.  With
+    persistent_wgs > 0 the SpMV rounds go to the persistent multi-matrix
+    kernel of that many workgroups instead of one launch each.  rate > 0
+    sets the arrival rate (requests/s) instead of 0.7x the capacity, so that
+    two runs can be compared at the same load."""
     import threading
 
     import paper_2107_12371_amd as spmv
@@ -256,7 +261,8 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
         return ("cg", mid, r.uniform(-1, 1, A.n_rows))
 
     # the pool fits the budget, so matrices stay resident once uploaded
-    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=preload)
+    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=preload,
+                      persistent_wgs=persistent_wgs)
     t0 = time.perf_counter()
     for A in pool:
         srv.add_matrix(A)
@@ -277,7 +283,7 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     for t in [submit(r) for r in burst2]:
         srv.wait(t)
     cap = len(burst2) / (time.perf_counter() - tb)
-    lam = 0.7 * cap
+    lam = rate if rate > 0 else 0.7 * cap
     reqs = [make(i) for i in range(n_requests)]
     gaps = np.random.default_rng(seed + 1).exponential(1.0 / lam, n_requests)
     tickets = [None] * n_requests
@@ -307,7 +313,9 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
             continue
         n_ok += 1
         for k in SERVE_PHASES:
-            phases[r[0]][k].append(getattr(res, k))
+            v = getattr(res, k)
+            if not (k == "kernel_s" and v < 0):   # kernel_s: persistent-kernel rounds only
+                phases[r[0]][k].append(v)
         if r[0] == "cg":
             iters.append(res.iterations)
     wall = time.perf_counter() - t1
@@ -321,6 +329,8 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     out = {"requests": n_requests, "pool": pool_size, "pool_rows": int(sum(A.n_rows for A in pool)),
            "arrival_rate_rps": round(lam, 2), "closed_loop_capacity_rps": round(cap, 2),
            "cg_mode": "mixed" if cg_mode else "fp64", "preload": preload,
+           "spmv_rounds": (f"persistent kernel, {persistent_wgs} workgroups, {st['persist_launches']} launches"
+                           if persistent_wgs else "one launch per round"),
            "p50_ms": q(lat_all, 0.5), "p99_ms": q(lat_all, 0.99),
            "p50_cg_ms": q(phases["cg"]["latency_s"], 0.5), "p99_cg_ms": q(phases["cg"]["latency_s"], 0.99),
            "p50_spmv_ms": q(phases["spmv"]["latency_s"], 0.5), "p99_spmv_ms": q(phases["spmv"]["latency_s"], 0.99),
@@ -330,7 +340,8 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
                                     for op, ph in phases.items()},
            "failed": fails, "errors": errors, "rounds": st["rounds"], "uploads": st["uploads"],
            "evictions": st["evictions"], "peak_budget_bytes": st["peak_bytes"]}
-    log(f"serving{' (preloaded)' if preload else ''}: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
+    log(f"serving{' (preloaded)' if preload else ''}{' (persistent)' if persistent_wgs else ''}: "
+        f"p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
         f"{out['throughput_rps']} req/s at {out['arrival_rate_rps']} req/s offered; "
         f"breakdown {out['breakdown_ms_p50_p99']}")
     return out
@@ -342,7 +353,8 @@ def serving_in_child(args) -> dict:
     the headline measurement with it."""
     import subprocess
     cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
-           "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool)]
+           "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool),
+           "--serve-persistent", str(args.serve_persistent)]
     try:
         # progress lines go straight to this process's stderr as they come
         r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
@@ -594,6 +606,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096, help="requests in the serving stream")
     ap.add_argument("--serve-pool", type=int, default=1024, help="matrices in the serving pool")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-persistent", type=int, default=256,
+                    help="workgroups of the persistent multi-matrix kernel in the third serving stream "
+                         "(0: no such stream)")
     ap.add_argument("--serve-preload", action="store_true",
                     help="serving (with --serve-only): only the stream over a pool uploaded while registering")
     ap.add_argument("--serve-only", action="store_true",
@@ -615,10 +630,14 @@ def main():
         import meshgen as mg
         pool = serving_pool(args.serve_pool, mg.seed_for(4))
         out = {}
-        for name, pre in (("first_touch", False), ("preloaded", True)):
-            if args.serve_preload and not pre:
+        for name, pre, pw in (("first_touch", False, 0), ("preloaded", True, 0),
+                              ("preloaded_persistent", True, args.serve_persistent)):
+            if (args.serve_preload and not pre) or (name.endswith("persistent") and pw <= 0):
                 continue
-            out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre)
+            # the persistent stream arrives at the preloaded stream's rate
+            rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else 0.0
+            out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
+                                    persistent_wgs=pw, rate=rate)
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -788,6 +807,8 @@ def main():
         sv = serving_in_child(args)
         extras["serving"] = sv.get("first_touch", sv)              # uploads on first touch
         extras["serving_preloaded"] = sv.get("preloaded", sv)
+        if args.serve_persistent > 0:
+            extras["serving_preloaded_persistent"] = sv.get("preloaded_persistent", sv)
 
     cpu = None
     if not args.no_cpu:

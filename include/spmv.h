@@ -349,8 +349,11 @@ int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double to
  * free up, uploading a registered matrix on first use and evicting the least
  * recently used idle matrices to stay within hbm_budget_bytes.  Admitted SpMV
  * requests join the next round, in which one multi-matrix kernel launch
- * covers all of the round's vectors; CG requests run on solver slots (one
- * stream each, graph-captured iterations) concurrently with the rounds.
+ * covers all of the round's vectors, or, with persistent_wgs > 0, the round
+ * is queued to one long-lived multi-matrix kernel that works the tiles of
+ * every queued round as they arrive (the analogue of a task queue feeding
+ * accelerator kernels, paper Sec. 3.2); CG requests run on solver slots
+ * (one stream each, graph-captured iterations) concurrently with the rounds.
  * A request's result is bitwise identical alone and in any mix.
  * Latency is measured from srv_submit until the result is in `out`.
  */
@@ -367,6 +370,12 @@ typedef struct srv_config {
     int32_t preload;           /* 1: upload each matrix in the background as it is added, while it
                                   fits in the free budget without evicting (0: on first request) */
     int32_t n_lanes;           /* SpMV rounds in flight at once, each on its own stream, <= 16 (0: 4) */
+    int32_t persistent_wgs;    /* > 0: SpMV rounds run on one persistent multi-matrix kernel of this
+                                  many worker workgroups (plus one that watches the queue; capped at
+                                  what the device holds at once), which lanes feed through a queue
+                                  in host memory; 0: one launch per round */
+    int32_t persist_idle_us;   /* the persistent kernel ends after this long without work and is
+                                  launched again when work comes, <= 10^7 (0: 20000) */
 } srv_config;
 
 typedef struct srv_result {
@@ -389,6 +398,9 @@ typedef struct srv_result {
                              part of compute_s) */
     double dev_begin_s, dev_end_s; /* the device work's interval, in seconds on one device
                              clock per server (comparable across requests) */
+    double kernel_s;      /* SpMV on the persistent kernel: its busy time on the round, from
+                             the round's first claimed tile to its last (device clock, part of
+                             compute_s); -1 otherwise */
     char message[160];    /* why the request failed; empty when status is SPMV_OK */
 } srv_result;
 
@@ -398,6 +410,7 @@ typedef struct srv_stats {
     double p50_s, p99_s, mean_s, max_s; /* latency of completed requests */
     double wall_s;          /* first submit -> last completion */
     double throughput_rps;  /* completed / wall_s */
+    int64_t persist_launches; /* launches of the persistent kernel (0 without one) */
 } srv_stats;
 
 /* Creates the server on the current device (cfg NULL: defaults). */

@@ -26,10 +26,12 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -56,6 +58,23 @@ struct MultiItem {
 
 constexpr int kServeTile = 1024;  // tile capacity of server matrices
 
+// y rows of one stream tile d of item it (a plain FP64 product, rows summed
+// in the matrix's plan order).  Ends with prod still being read by the row
+// sums: a caller that reuses prod synchronises first.
+template <int NT>
+__device__ __forceinline__ void multi_tile(const MultiItem &it, const TileDesc &d, double *prod, double *sh) {
+    const double *__restrict__ x = it.x;
+    TileRegs<double, NT> t;
+    t.load(it.col, it.val, d.s, d.e);
+    RowPre<double, EPI_PLAIN> pre;
+    pre.load(it.row_ptr, x, static_cast<const double *>(nullptr), d.r0, d.r1, d.s & ~3);
+    double xv[TileRegs<double, NT>::kMaxPass][4];
+    t.gather([x](int c) { return x[c]; }, xv);
+    t.products(xv, prod);
+    __syncthreads();
+    tile_rows<double, double, EPI_PLAIN>(pre, d.r0, d.r1, prod, it.y, nullptr, 0, sh);
+}
+
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_multi(const MultiItem *__restrict__ items, int n_items, int total) {
     __shared__ double prod[TileRegs<double, NT>::kProd];
@@ -69,17 +88,354 @@ __global__ __launch_bounds__(kBlock) void k_multi(const MultiItem *__restrict__ 
         else hi = mid - 1;
     }
     const MultiItem it = items[lo];
-    const TileDesc d = it.desc[b - it.tile_begin];
-    const double *__restrict__ x = it.x;
-    TileRegs<double, NT> t;
-    t.load(it.col, it.val, d.s, d.e);
-    RowPre<double, EPI_PLAIN> pre;
-    pre.load(it.row_ptr, x, static_cast<const double *>(nullptr), d.r0, d.r1, d.s & ~3);
-    double xv[TileRegs<double, NT>::kMaxPass][4];
-    t.gather([x](int c) { return x[c]; }, xv);
-    t.products(xv, prod);
-    __syncthreads();
-    tile_rows<double, double, EPI_PLAIN>(pre, d.r0, d.r1, prod, it.y, nullptr, 0, sh);
+    multi_tile<NT>(it, it.desc[b - it.tile_begin], prod, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent multi-matrix kernel.  Instead of one launch per round, a lane
+// publishes its round (the MultiItem table already on the device) to a queue
+// and one long-lived launch works the tiles of every published round, from
+// whichever lane, as they come:
+//  * the host half of the queue is coherent pinned host memory: the host
+//    writes the rounds and their count, the kernel writes each round's
+//    completion;
+//  * workgroup 0 is the doorbell: it alone polls host memory (so the host
+//    link carries one poller, not hundreds), copies each new round into the
+//    device half of the queue and readies the round's ring slot (claim and
+//    finish counters);
+//  * every other workgroup takes chunks of consecutive tiles, oldest round
+//    first, with one fetch-and-add on the round's claim word, works them and
+//    counts them finished; the workgroup that finishes a round's last tile
+//    publishes the round's completion to the host.  A claim word carries its
+//    round's tag, so a workgroup whose add lands after the slot has passed to
+//    a later round knows which round's chunk it got, and works that one;
+//  * every wave ends by itself: when the host asks it to stop, or when no
+//    work has come for the idle time.  The host launches again whenever it
+//    publishes work and finds the last launch ended.
+// Memory ordering: the host makes a round's buffers complete on the device
+// before publishing it; the doorbell's system-scope acquire, its
+// device-scope release of the slot, and the workers' acquire of the slot
+// order those buffers before the tiles' reads.  Each wave's system-scope
+// release after its rows, and the finishing counter's acquire-release, order
+// every y row before the completion store the host reads.
+
+constexpr int kRing = 64;        // ring slots; round r may reuse slot r % kRing once round r - kRing is complete
+constexpr int kStageTiles = 8;   // tile descriptors staged in LDS at once
+
+struct PersistEntry {
+    uint64_t tag;      // round + 1
+    uint64_t items;    // device address of the round's MultiItem table
+    uint64_t n_items;
+    uint64_t shape;    // tiles << 32 | tiles per claim
+};
+
+// Host half (coherent pinned host memory).
+struct PersistQueue {
+    alignas(128) uint64_t published;  // host: rounds published so far
+    alignas(128) uint64_t stop;       // host: 1 asks the kernel to end
+    alignas(128) PersistEntry ring[kRing];
+    alignas(128) uint64_t done[kRing];  // kernel: round + 1 once the round's tiles are all finished
+    alignas(128) uint64_t span[kRing];  // kernel: clock ticks from the round's first claim to its last tile
+};
+
+// Device half (device memory, zeroed when the server is created).
+struct PersistState {
+    alignas(128) uint64_t published;  // the doorbell's copy
+    alignas(128) uint64_t stop;
+    alignas(128) uint64_t activity;   // clock of the latest publication or claim
+    alignas(128) PersistEntry ring[kRing];
+    alignas(128) uint64_t claim[kRing];     // claim words (claim_word)
+    alignas(128) uint32_t finished[kRing];  // tiles finished of the slot's round
+    alignas(128) uint64_t t_first[kRing];   // clock of the round's first claim
+};
+
+// A slot's claim word: the round's tag (round + 1 mod 2^24), its chunk
+// count m (< 2^20) and the chunks claimed so far (an add past m takes
+// nothing; the field has room for more such adds than there are workgroups).
+// Each field is read from the add's own result, so a late add that lands on
+// the slot's next round still knows whether it got a chunk, and of which
+// round, without reading the entry of a round that may be complete.
+constexpr uint64_t kChunkBits = 20;
+constexpr uint64_t kMaxChunks = (uint64_t(1) << kChunkBits) - (uint64_t(1) << 16);
+__host__ __device__ constexpr uint64_t claim_word(uint64_t round, uint64_t chunks) {
+    return ((round + 1) & 0xFFFFFFull) << 40 | chunks << kChunkBits;
+}
+
+__device__ __forceinline__ uint64_t ld_acq_sys(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_acq_dev(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_rlx_dev(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx_dev(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// True once neither this wave nor any other has seen work for idle_ticks.
+__device__ __forceinline__ bool persist_idle(const PersistState *st, uint64_t last, uint64_t idle_ticks) {
+    const uint64_t t = now_ticks(), a = ld_rlx_dev(&st->activity);
+    return t - (a > last ? a : last) > idle_ticks && t > a;
+}
+
+// Workgroup 0, lane 0: copies the host's newly published rounds into device
+// memory until stopped or idle.  A slot's round is complete before the host
+// publishes the next round of that slot, so its counters are free to reset.
+__device__ void persist_doorbell(PersistQueue *q, PersistState *st, uint64_t idle_ticks, uint64_t max_polls) {
+    if (threadIdx.x != 0) return;
+    uint64_t seen = ld_rlx_dev(&st->published);
+    uint64_t last = now_ticks(), polls = 0;
+    for (;;) {
+        // relaxed polls (an acquire would invalidate this XCD's caches on
+        // every poll); the acquire fence follows only a change
+        const uint64_t stop = __hip_atomic_load(&q->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t p = __hip_atomic_load(&q->published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (p > seen) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            for (uint64_t r = seen; r < p; ++r) {
+                const int s = int(r % kRing);
+                const PersistEntry *h = &q->ring[s];
+                PersistEntry *d = &st->ring[s];
+                const uint64_t shape = ld_acq_sys(&h->shape);
+                st_rlx_dev(&d->items, ld_acq_sys(&h->items));
+                st_rlx_dev(&d->n_items, ld_acq_sys(&h->n_items));
+                st_rlx_dev(&d->shape, shape);
+                __hip_atomic_store(&st->finished[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the claim word now counts round r's chunks; a worker whose
+                // add reads it also sees the entry written above
+                const uint64_t n = shape >> 32, g = shape & 0xFFFFFFFFull;
+                __hip_atomic_store(&st->claim[s], claim_word(r, (n + g - 1) / g), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&d->tag, r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            last = now_ticks();
+            st_rlx_dev(&st->activity, last);
+            __hip_atomic_store(&st->published, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            seen = p;
+            polls = 0;
+        }
+        if (stop) {
+            __hip_atomic_store(&st->stop, uint64_t(1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        // the poll count bounds the wait even if the clock were to stand still
+        if (persist_idle(st, last, idle_ticks) || ++polls > 8 * max_polls) return;
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+struct Chunk {
+    uint64_t round;   // the round the tiles belong to (-1: end)
+    uint32_t first;   // first tile
+    uint32_t count;   // tiles
+    uint32_t n;       // tiles of the round
+};
+
+// Lane 0: the next chunk this workgroup works.  r is the oldest round the
+// workgroup may still find work in.
+__device__ Chunk persist_claim(PersistState *st, uint64_t &r, uint64_t &pub, uint64_t &last, uint64_t idle_ticks,
+                               uint64_t max_polls) {
+    uint64_t polls = 0;
+    for (;;) {
+        if (r >= pub) {
+            pub = ld_rlx_dev(&st->published);
+            if (r >= pub) {
+                if (ld_rlx_dev(&st->stop) || persist_idle(st, last, idle_ticks) || ++polls > max_polls)
+                    return Chunk{~uint64_t(0), 0, 0, 0};
+                // ~2 us between polls at first, ~14 us once idle for a while:
+                // a thousand workgroups polling one word load one memory
+                // channel that every other kernel also uses
+                __builtin_amdgcn_s_sleep(64);
+                if (polls > 32) {
+                    __builtin_amdgcn_s_sleep(127);
+                    __builtin_amdgcn_s_sleep(127);
+                    __builtin_amdgcn_s_sleep(127);
+                }
+                continue;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the entries of the rounds below pub
+        }
+        const int s = int(r % kRing);
+        PersistEntry *en = &st->ring[s];
+        const uint64_t tag = ld_acq_dev(&en->tag);
+        if (tag > r + 1) {  // the slot holds a later round: r is complete
+            ++r;
+            continue;
+        }
+        if (tag < r + 1) {  // not visible yet (cannot persist: published was read after it)
+            if (++polls > max_polls) return Chunk{~uint64_t(0), 0, 0, 0};
+            continue;
+        }
+        const uint64_t mask = (uint64_t(1) << kChunkBits) - 1;
+        {  // a load first: a taken-out round costs no add
+            const uint64_t w = ld_rlx_dev(&st->claim[s]);
+            if ((w & mask) >= ((w >> kChunkBits) & mask)) {
+                ++r;
+                continue;
+            }
+        }
+        const uint64_t v = __hip_atomic_fetch_add(&st->claim[s], uint64_t(1), __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t j = v & mask, m = (v >> kChunkBits) & mask;
+        if (j >= m) {  // every chunk of the slot's round is taken; that round is r or later, so r is done
+            ++r;
+            continue;
+        }
+        // chunk j of round x (r, or a later round of the slot, unfinished
+        // while this chunk is: its entry is still in the slot)
+        const uint64_t x = r + (((v >> 40) - (r + 1)) & 0xFFFFFFull);
+        const uint64_t shape = ld_rlx_dev(&en->shape);
+        const uint32_t n = uint32_t(shape >> 32), g = uint32_t(shape);
+        const uint64_t first = j * g;
+        last = now_ticks();
+        st_rlx_dev(&st->activity, last);
+        if (j == 0) st_rlx_dev(&st->t_first[s], last);
+        return Chunk{x, uint32_t(first), uint32_t(n - first < g ? n - first : g), n};
+    }
+}
+
+// s_waitcnt immediate of gfx9: vmcnt 0 (bits 3:0 and 15:14), expcnt and
+// lgkmcnt left at their maxima (7 in bits 6:4, 15 in bits 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+constexpr int kItemWords = (int)(sizeof(MultiItem) / 8);
+static_assert(sizeof(MultiItem) % 8 == 0 && kItemWords <= kWave, "MultiItem staged as 8-byte words");
+static_assert(offsetof(MultiItem, desc) == 0 && offsetof(MultiItem, tile_begin) % 8 == 0 &&
+                  offsetof(MultiItem, n_tiles) == offsetof(MultiItem, tile_begin) + 4,
+              "MultiItem layout");
+static_assert(sizeof(TileDesc) == 32 && kStageTiles * 8 <= kWave, "descriptors staged one word per lane");
+
+// max_polls bounds each wave's run of empty polls (a backstop of the idle
+// clock: far more polls than the idle time holds).
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_persist(PersistQueue *q, PersistState *st, uint64_t r_start,
+                                                    uint64_t idle_ticks, uint64_t max_polls) {
+    if (blockIdx.x == 0) {
+        persist_doorbell(q, st, idle_ticks, max_polls);
+        return;
+    }
+    __shared__ double prod[TileRegs<double, NT>::kProd];
+    __shared__ double sh[kBlock / kWave];
+    __shared__ uint64_t w_it[kItemWords];          // the current item
+    __shared__ int32_t w_d[kStageTiles * 8];       // descriptors of the staged tiles
+    __shared__ uint64_t w_round;
+    __shared__ uint32_t w_first, w_count, w_stage;
+    const int lane = threadIdx.x;
+    // wave 0's state (lane 0's copy is the one used)
+    uint64_t r = r_start, pub = 0, last = now_ticks();
+    uint64_t it_round = ~uint64_t(0);  // the round and tile range of the item in w_it
+    int32_t it_begin = 0, it_tiles = 0;
+    uint32_t n = 0;
+    for (;;) {
+        if (threadIdx.x < kWave) {
+            Chunk c{};
+            if (lane == 0) c = persist_claim(st, r, pub, last, idle_ticks, max_polls);
+            if (lane == 0) {
+                w_round = c.round;
+                w_first = c.first;
+                w_count = c.count;
+                n = c.n;
+            }
+        }
+        __syncthreads();
+        const uint64_t x = w_round;
+        if (x == ~uint64_t(0)) return;
+        const uint32_t end = w_first + w_count;
+        for (uint32_t t = w_first; t < end;) {
+            if (threadIdx.x < kWave) {
+                // the item holding tile t: a 64-way search over the round's
+                // item table (sorted by first tile, every item at least one
+                // tile), one load per lane a step
+                const PersistEntry *en = &st->ring[x % kRing];
+                if (x != it_round || (int32_t)t < it_begin || (int32_t)t >= it_begin + it_tiles) {
+                    const MultiItem *tab = reinterpret_cast<const MultiItem *>(ld_rlx_dev(&en->items));
+                    int hi = (int)ld_rlx_dev(&en->n_items), lo = 0;
+                    while (hi - lo > 1) {
+                        const int step = (hi - lo + kWave - 1) / kWave;
+                        const int idx = lo + lane * step;
+                        bool le = false;
+                        if (idx < hi)
+                            le = __hip_atomic_load(&tab[idx].tile_begin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                                 (int32_t)t;
+                        const unsigned long long m = __ballot(le);  // a prefix of lanes; lane 0 always set
+                        lo += (63 - __builtin_clzll(m)) * step;
+                        hi = min(lo + step, hi);
+                    }
+                    const uint64_t *src = reinterpret_cast<const uint64_t *>(tab + lo);
+                    const uint64_t wv = lane < kItemWords ? ld_rlx_dev(src + lane) : 0;
+                    if (lane < kItemWords) w_it[lane] = wv;
+                    const uint64_t range =
+                        __shfl((unsigned long long)wv, (int)(offsetof(MultiItem, tile_begin) / 8), kWave);
+                    it_begin = (int32_t)(uint32_t)range;
+                    it_tiles = (int32_t)(uint32_t)(range >> 32);
+                    it_round = x;
+                }
+                // descriptors of up to kStageTiles tiles of this item, one
+                // word per lane
+                const uint32_t item_end = (uint32_t)(it_begin + it_tiles);
+                const uint32_t stage_end = min(min(end, item_end), t + (uint32_t)kStageTiles);
+                const uint64_t dp = __shfl((unsigned long long)w_it[0], 0, kWave);
+                const int32_t *dsrc = reinterpret_cast<const int32_t *>(reinterpret_cast<const TileDesc *>(dp) +
+                                                                        ((int32_t)t - it_begin));
+                if (lane < (int)(stage_end - t) * 8)
+                    w_d[lane] = __hip_atomic_load(dsrc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) w_stage = stage_end - t;
+            }
+            __syncthreads();
+            const uint32_t ns = w_stage;
+            // the staged tiles in a two-deep pipeline: the next tile's
+            // stream loads go out right after this tile's gathers, so their
+            // latency hides behind this tile's products and row sums
+            const MultiItem &it = *reinterpret_cast<const MultiItem *>(w_it);
+            const TileDesc *dd = reinterpret_cast<const TileDesc *>(w_d);
+            const double *__restrict__ xx = it.x;
+            TileRegs<double, NT> ta, tb;
+            RowPre<double, EPI_PLAIN> pa, pb;
+            auto load = [&](TileRegs<double, NT> &tr, RowPre<double, EPI_PLAIN> &pr, uint32_t u) {
+                const TileDesc d = dd[u];
+                tr.load(it.col, it.val, d.s, d.e);
+                pr.load(it.row_ptr, xx, static_cast<const double *>(nullptr), d.r0, d.r1, d.s & ~3);
+            };
+            auto step = [&](TileRegs<double, NT> &cur, RowPre<double, EPI_PLAIN> &pcur, TileRegs<double, NT> &nxt,
+                            RowPre<double, EPI_PLAIN> &pnxt, uint32_t u) {
+                double xv[TileRegs<double, NT>::kMaxPass][4];
+                cur.gather([xx](int c) { return xx[c]; }, xv);
+                if (u + 1 < ns) load(nxt, pnxt, u + 1);
+                cur.products(xv, prod);
+                __syncthreads();
+                const TileDesc d = dd[u];
+                tile_rows<double, double, EPI_PLAIN>(pcur, d.r0, d.r1, prod, it.y, nullptr, 0, sh);
+                __syncthreads();  // prod, and after the last tile w_it and w_d, free for reuse
+            };
+            load(ta, pa, 0);
+            for (uint32_t u = 0; u < ns; u += 2) {
+                step(ta, pa, tb, pb, u);
+                if (u + 1 < ns) step(tb, pb, ta, pa, u + 1);
+            }
+            t += ns;
+        }
+        // every wave's rows reach the L2 (its stores complete) before the
+        // barrier; thread 0's system-scope release then writes that L2 back
+        // once for the workgroup (one writeback per chunk: each one is a
+        // device-wide serialised step, so one per wave would cost five times
+        // as much)
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int s = int(x % kRing);
+            const uint32_t cnt = w_count;
+            const uint32_t old =
+                __hip_atomic_fetch_add(&st->finished[s], cnt, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (old + cnt == n) {  // the round's last tiles: tell the host
+                __hip_atomic_store(&q->span[s], now_ticks() - ld_rlx_dev(&st->t_first[s]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&q->done[s], x + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
 }
 
 namespace {
@@ -103,6 +459,7 @@ struct Request {
     double copy_in_s = -1.0, compute_s = -1.0, copy_out_s = -1.0;
     double dev_begin_s = -1.0, dev_end_s = -1.0;
     double graph_s = 0.0;       // CG: graph capture and instantiation inside the solve
+    double kernel_s = -1.0;     // SpMV on the persistent kernel: the round's first claim to its last tile
     bool done = false;
     int status = SPMV_OK;
     char message[160] = {0};
@@ -181,6 +538,25 @@ struct Lane {
     bool busy = false;
 };
 
+// The persistent kernel's host side (cfg.persistent_wgs > 0).
+struct Persist {
+    PersistQueue *q = nullptr;   // coherent pinned host memory
+    PersistQueue *qd = nullptr;  // its device address
+    PersistState *st = nullptr;  // device memory
+    hipStream_t stream = nullptr;
+    hipEvent_t end = nullptr;  // recorded after each launch
+    bool launched = false;
+    std::mutex mu;
+    std::condition_variable cv;  // a ring slot freed
+    uint64_t next = 0;           // rounds published
+    std::set<uint64_t> open;     // published rounds not yet seen complete
+    int wgs = 0;                 // workgroups per launch (doorbell included)
+    uint64_t idle_ticks = 0;     // wall-clock ticks of idle time before a launch ends
+    uint64_t max_polls = 0;      // empty polls a worker wave makes at most in a row (8x for the doorbell)
+    double tick_s = 0.0;         // seconds per tick
+    int64_t launches = 0;
+};
+
 // Requests moving at least this many vector words between host and device
 // get rounds of their own.
 constexpr int64_t kLargeRequestWords = int64_t(1) << 22;
@@ -213,6 +589,7 @@ struct Server {
     Clock::time_point t_first{}, t_last{};
     bool any_submit = false;
     hipEvent_t ref_event = nullptr;  // zero of the device clock the requests' intervals are read on
+    Persist P;
 
     explicit Server(const srv_config &c) : cfg(c), policy(c.hbm_budget_bytes) {}
 
@@ -318,6 +695,76 @@ struct Server {
         }
     }
 
+    // Launches the persistent kernel unless a launch is still running.
+    // Caller holds P.mu.
+    int persist_ensure_locked() {
+        if (P.launched) {
+            const hipError_t q = hipEventQuery(P.end);
+            if (q == hipErrorNotReady) return SPMV_OK;
+            if (q != hipSuccess) return hip_fail(q, "persistent kernel");
+        }
+        const uint64_t r0 = P.open.empty() ? P.next : *P.open.begin();
+        hipLaunchKernelGGL((k_persist<kServeTile>), dim3(P.wgs), dim3(kBlock), 0, P.stream, P.qd, P.st, r0,
+                           P.idle_ticks, P.max_polls);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(P.end, P.stream);
+        if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+        P.launched = true;
+        ++P.launches;
+        return SPMV_OK;
+    }
+
+    // Publishes a round whose item table and vectors are complete on the
+    // device, and waits until the persistent kernel has finished it.
+    int persist_round(const MultiItem *ditems, int n_items, int total, double *kernel_s) {
+        uint64_t seq;
+        int rc;
+        {
+            std::unique_lock<std::mutex> lk(P.mu);
+            // the slot's previous round (P.next - kRing) must be complete
+            P.cv.wait(lk, [&] { return P.open.empty() || *P.open.begin() + kRing > P.next; });
+            seq = P.next;
+            PersistEntry &en = P.q->ring[seq % kRing];
+            // about two claims per worker on a large round (each chunk ends
+            // with an L2 writeback), one tile each on a small one
+            const int64_t workers = std::max(1, P.wgs - 1);
+            int64_t g = std::min<int64_t>(512, std::max<int64_t>(1, (total + 2 * workers - 1) / (2 * workers)));
+            g = std::max<int64_t>(g, ((int64_t)total + (int64_t)kMaxChunks - 1) / (int64_t)kMaxChunks);
+            en.items = reinterpret_cast<uint64_t>(ditems);
+            en.n_items = (uint64_t)n_items;
+            en.shape = ((uint64_t)(uint32_t)total << 32) | (uint64_t)g;
+            __atomic_store_n(&en.tag, seq + 1, __ATOMIC_RELEASE);
+            __atomic_store_n(&P.q->published, seq + 1, __ATOMIC_RELEASE);
+            ++P.next;
+            P.open.insert(seq);
+            rc = persist_ensure_locked();
+        }
+        // the kernel finishes the round, or, if the launch ended first (its
+        // idle time ran out as the round came), a new launch does; a launch
+        // fault ends the wait with its error
+        const uint64_t *done = &P.q->done[seq % kRing];
+        const Clock::time_point t0 = Clock::now();
+        Clock::time_point t_check = t0;
+        while (rc == SPMV_OK && __atomic_load_n(done, __ATOMIC_ACQUIRE) != seq + 1) {
+            const Clock::time_point t = Clock::now();
+            // yield while the round is young, then sleep in short steps
+            if (t - t0 < std::chrono::microseconds(500)) std::this_thread::yield();
+            else std::this_thread::sleep_for(std::chrono::microseconds(20));
+            if (t - t_check > std::chrono::microseconds(50)) {
+                t_check = t;
+                std::lock_guard<std::mutex> lk(P.mu);
+                if (__atomic_load_n(done, __ATOMIC_ACQUIRE) != seq + 1) rc = persist_ensure_locked();
+            }
+            if (t - t0 > std::chrono::seconds(120)) rc = fail(SPMV_EDEVICE, "persistent kernel: round not finished in 120 s");
+        }
+        if (rc != SPMV_OK) return rc;  // the round stays open: its buffers are never freed
+        *kernel_s = (double)__atomic_load_n(&P.q->span[seq % kRing], __ATOMIC_RELAXED) * P.tick_s;
+        std::lock_guard<std::mutex> lk(P.mu);
+        P.open.erase(seq);
+        P.cv.notify_all();
+        return SPMV_OK;
+    }
+
     // One round on lane ln: every SpMV vector of the round's requests in one
     // launch.  Frees the lane when done.
     void run_round(std::vector<Request *> &round, Lane &ln) {
@@ -330,6 +777,8 @@ struct Server {
         std::vector<std::pair<Request *, std::pair<double *, double *>>> bufs;
         int total = 0;
         int err = SPMV_OK;
+        bool abandoned = false;
+        double kernel_s = -1.0;  // persistent kernel: its busy time on the round
         for (Request *r : round) {
             const DevMatrix &M = r->A->M;
             double *din = nullptr, *dout = nullptr;
@@ -376,12 +825,20 @@ struct Server {
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(ditems, ln.items_host, items.size() * sizeof(MultiItem), hipMemcpyHostToDevice,
                                        batch);
-                if (e == hipSuccess) {
+                bool keep = false;  // buffers a round that never finished may still be read from
+                if (e == hipSuccess && P.wgs > 0) {
+                    e = hipStreamSynchronize(batch);
+                    if (e == hipSuccess) {
+                        err = persist_round(ditems, (int)items.size(), total, &kernel_s);
+                        keep = err != SPMV_OK;
+                    }
+                } else if (e == hipSuccess) {
                     hipLaunchKernelGGL((k_multi<kServeTile>), dim3(total), dim3(kBlock), 0, batch, ditems,
                                        (int)items.size(), total);
                     e = hipGetLastError();
                 }
-                if (ditems) (void)hipFreeAsync(ditems, batch);
+                if (ditems && !keep) (void)hipFreeAsync(ditems, batch);
+                if (keep) abandoned = true;
                 if (e != hipSuccess) err = hip_fail(e, "server round launch");
             }
         }
@@ -398,6 +855,7 @@ struct Server {
         hipError_t e = hipStreamSynchronize(batch);
         if (e != hipSuccess && err == SPMV_OK) err = hip_fail(e, "server round");
         for (auto &b : bufs) {
+            if (abandoned) break;
             if (b.second.first) (void)hipFreeAsync(b.second.first, batch);
             if (b.second.second) (void)hipFreeAsync(b.second.second, batch);
         }
@@ -405,6 +863,7 @@ struct Server {
         ++rounds;
         for (Request *r : round) {
             r->t_run = t_run;
+            r->kernel_s = kernel_s;
             if (e == hipSuccess) ln.pe.fill(r, ref_event);
             policy.release(r->mid, r->extra);
             --in_flight_spmv;
@@ -611,6 +1070,63 @@ struct Server {
 
 using namespace spmvlib;
 
+// The persistent kernel's queue, stream and launch size: one workgroup more
+// than asked (the doorbell), capped by how many fit on the device at once.
+static hipError_t persist_create(Server &S) {
+    Persist &P = S.P;
+    int cus = 0, per_cu = 0, khz = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S.device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S.device);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_persist<kServeTile>),
+                                                         kBlock, 0);
+    if (e != hipSuccess) return e;
+    if (cus <= 0 || per_cu <= 0 || khz <= 0) return hipErrorInvalidDevice;
+    P.wgs = (int)std::min<int64_t>((int64_t)S.cfg.persistent_wgs + 1, (int64_t)cus * per_cu);
+    P.idle_ticks = (uint64_t)S.cfg.persist_idle_us * (uint64_t)khz / 1000u;
+    // a worker's empty poll sleeps at least 4,096 cycles (>= 1.6 us at the
+    // top clock), the doorbell's 512: 16 polls (128 for the doorbell) per
+    // microsecond of idle time outlast the idle clock many times over
+    P.max_polls = 16ull * (uint64_t)S.cfg.persist_idle_us + 1024;
+    P.tick_s = 1e-3 / (double)khz;
+    e = hipHostMalloc(reinterpret_cast<void **>(&P.q), sizeof(PersistQueue), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        P.q = nullptr;
+        return e;
+    }
+    std::memset(P.q, 0, sizeof(PersistQueue));
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&P.qd), P.q, 0);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&P.st), sizeof(PersistState));
+    if (e == hipSuccess) e = hipMemset(P.st, 0, sizeof(PersistState));
+    // a stream of its own hardware queue (a CU-masked stream never shares
+    // one), so that no other stream's work waits behind a running launch
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    for (int i = 0; i < cus; ++i) mask[(size_t)i / 32] |= 1u << (i % 32);
+    if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&P.stream, (uint32_t)mask.size(), mask.data());
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P.end, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
+}
+
+// Stops a running launch (every wave sees the stop flag within its poll
+// period), waits for it, frees the queue.
+static void persist_destroy(Server &S) {
+    Persist &P = S.P;
+    if (P.q) __atomic_store_n(&P.q->stop, uint64_t(1), __ATOMIC_RELEASE);
+    if (P.stream) {
+        (void)hipStreamSynchronize(P.stream);
+        (void)hipStreamDestroy(P.stream);
+        P.stream = nullptr;
+    }
+    if (P.end) (void)hipEventDestroy(P.end);
+    P.end = nullptr;
+    if (P.st) (void)hipFree(P.st);
+    P.st = nullptr;
+    if (P.q) (void)hipHostFree(P.q);
+    P.q = nullptr;
+    P.wgs = 0;
+}
+
 struct spmv_server {
     Server *s;
 };
@@ -628,6 +1144,10 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     if (cfg.n_lanes <= 0) cfg.n_lanes = 4;
     if (cfg.n_lanes > 16) return fail(SPMV_EINVAL, "n_lanes = %d exceeds 16", cfg.n_lanes);
     if (cfg.cg_mode != CG_FP64 && cfg.cg_mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown cg_mode");
+    if (cfg.persistent_wgs < 0 || cfg.persist_idle_us < 0)
+        return fail(SPMV_EINVAL, "persistent_wgs and persist_idle_us must be >= 0");
+    if (cfg.persist_idle_us == 0) cfg.persist_idle_us = 20000;
+    if (cfg.persist_idle_us > 10000000) return fail(SPMV_EINVAL, "persist_idle_us = %d exceeds 10 s", cfg.persist_idle_us);
     auto *S = new (std::nothrow) Server(cfg);
     if (!S) return fail(SPMV_ENOMEM, "host allocation failed");
     hipError_t e = hipGetDevice(&S->device);
@@ -651,8 +1171,10 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     if (e == hipSuccess) e = hipEventCreate(&S->ref_event);
     if (e == hipSuccess) e = hipEventRecord(S->ref_event, S->lanes[0].stream);
     if (e == hipSuccess) e = hipEventSynchronize(S->ref_event);
+    if (e == hipSuccess && cfg.persistent_wgs > 0) e = persist_create(*S);
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "server streams");
+        persist_destroy(*S);
         for (auto &t : S->slots) {
             if (t.stream) (void)hipStreamDestroy(t.stream);
             if (t.pinned) (void)hipHostFree(t.pinned);
@@ -769,6 +1291,7 @@ static void fill_result(const Request *r, srv_result *res) {
         res->compute_s = r->compute_s;
         res->copy_out_s = r->copy_out_s;
         res->graph_s = r->graph_s;
+        res->kernel_s = r->kernel_s;
         res->dev_begin_s = r->dev_begin_s;
         res->dev_end_s = r->dev_end_s;
     }
@@ -818,6 +1341,7 @@ extern "C" int srv_get_stats(spmv_server *srv, srv_stats *st) {
     st->failed = S->failed;
     st->rounds = S->rounds;
     st->uploads = S->policy.uploads();
+    st->persist_launches = S->P.launches;
     st->evictions = S->policy.evictions();
     st->used_bytes = (int64_t)S->policy.used();
     st->peak_bytes = (int64_t)S->policy.peak();
@@ -859,6 +1383,7 @@ extern "C" int srv_destroy(spmv_server *srv) {
     for (auto &m : S->mats)
         if (m.dev) (void)spmv_destroy(m.dev);
     std::lock_guard<std::mutex> gate(capture_gate());
+    persist_destroy(*S);
     for (auto &sl : S->slots) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);

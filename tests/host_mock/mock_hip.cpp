@@ -115,6 +115,14 @@ hipError_t hipStreamDestroy(hipStream_t s) {
     return hipSuccess;
 }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipExtStreamCreateWithCUMask(hipStream_t *s, uint32_t, const uint32_t *) {
+    return hipStreamCreateWithFlags(s, 0);
+}
+hipError_t hipDeviceSynchronize(void) { return hipSuccess; }
+hipError_t hipHostGetDevicePointer(void **d, void *h, unsigned int) {
+    *d = h;
+    return hipSuccess;
+}
 // events exist but time nothing: every interval reads zero
 hipError_t hipEventCreate(hipEvent_t *e) {
     *e = reinterpret_cast<hipEvent_t>(new int(4));
@@ -124,6 +132,8 @@ hipError_t hipEventDestroy(hipEvent_t e) {
     delete reinterpret_cast<int *>(e);
     return hipSuccess;
 }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned int) { return hipEventCreate(e); }
+hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) {

@@ -88,6 +88,16 @@ def test_create_rejects_malformed_input_before_touching_the_device():
     assert L.spmv_get_info(None, None) == spmv.SPMV_EINVAL
 
 
+def test_server_configuration_is_checked_before_touching_the_device():
+    L = spmv.lib()
+    for bad in ({"persistent_wgs": -1}, {"persist_idle_us": -5}, {"persist_idle_us": 10_000_001},
+                {"n_lanes": 17}, {"n_slots": 65}, {"cg_mode": 7}):
+        cfg = spmv.srv_config(**bad)
+        h = ctypes.c_void_p()
+        assert L.srv_create(ctypes.byref(cfg), ctypes.byref(h)) == spmv.SPMV_EINVAL and not h.value
+        assert list(bad)[0].split("_")[-1] in spmv.lib().spmv_last_error().decode()
+
+
 def check_plan(A, params=None):
     P = spmv.plan_inspect(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, params)
     info = P["info"]
