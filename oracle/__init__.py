@@ -79,6 +79,8 @@ def _L():
         lib.oracle_cg.argtypes = [i32, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_pcg_bf16.restype = ctypes.c_int
         lib.oracle_pcg_bf16.argtypes = [i32, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_cg1.restype = ctypes.c_int
+        lib.oracle_cg1.argtypes = [i32, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_pcg_jacobi.restype = ctypes.c_int
         lib.oracle_pcg_jacobi.argtypes = [i32, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp, vp]
         _lib = lib
@@ -215,6 +217,23 @@ def cg(A, b, tol: float = 1e-10, max_iter: int = 10000, x0=None) -> CGResult:
                         _ptr(al), _ptr(be))
     k = it.value
     return CGResult(x, int(st), k, rr.value, al[:k].copy(), be[:k].copy())
+
+
+def cg1(A, b, tol: float = 1e-10, max_iter: int = 10000, x0=None) -> CGResult:
+    """CG with one reduction phase per iteration (Chronopoulos-Gear, see
+    oracle.c); the result carries no coefficients, `alphas` holds the number
+    of restarts from the true residual as its only element."""
+    rp, ci, va = _csr(A)
+    n = A.n_rows
+    b = _c(b, np.float64)
+    x = np.zeros(n, np.float64) if x0 is None else _c(x0, np.float64).copy()
+    work = [np.empty(n, np.float64) for _ in range(4)]
+    it = ctypes.c_int32(0)
+    rs = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    st = _L().oracle_cg1(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(b), _ptr(x), tol, max_iter,
+                         *[_ptr(a) for a in work], ctypes.byref(it), ctypes.byref(rs), ctypes.byref(rr))
+    return CGResult(x, int(st), it.value, rr.value, np.array([rs.value]), np.zeros(0))
 
 
 def pcg_bf16(A, b, tol: float = 1e-10, max_iter: int = 10000, x0=None):

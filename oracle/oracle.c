@@ -51,6 +51,14 @@
  *                  preconditioned CG (e.g. Saad, Iterative Methods for Sparse
  *                  Linear Systems, Alg. 9.1) on top, stopping and confirming as
  *                  oracle_cg does.
+ *  oracle_cg1      conjugate gradients with one reduction phase per
+ *                  iteration (Chronopoulos & Gear, J. Comput. Appl. Math. 25,
+ *                  1989, with s = 1): besides x, r and p it carries w = A r
+ *                  and s = A p, updated by recurrence (s = w + beta s), so the
+ *                  two inner products an iteration needs, r.r and w.r, are
+ *                  taken together after the one product w = A r, and alpha
+ *                  follows from them as r.r / (w.r - beta r.r / alpha_prev).
+ *                  In exact arithmetic its iterates are those of oracle_cg.
  *  oracle_pcg_jacobi the same preconditioned CG with the Jacobi
  *                  preconditioner M = D = diag(A) (duplicates summed), i.e.
  *                  z = D^-1 r: the first preconditioner of the scope's
@@ -217,6 +225,93 @@ int oracle_cg(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const d
         if (betas) betas[it - 1] = beta;
         for (int32_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
         rho = rho_new;
+    }
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    *rel_res = sqrt(dot(n, r, r)) / nb;
+    return status;
+}
+
+/*
+ * CG with one reduction phase per iteration (Chronopoulos-Gear).  Work
+ * arrays r, p, w, s (n each) are supplied by the caller; x holds x0 on
+ * entry and the last iterate on exit.
+ *
+ *   r = b - A x;  w = A r;  gamma = r.r;  delta = w.r
+ *   alpha = gamma / delta;  beta = 0;  p = 0;  s = 0
+ *   repeat:  p = r + beta p;  s = w + beta s
+ *            x = x + alpha p;  r = r - alpha s;  w = A r
+ *            gamma' = r.r;  delta' = w.r
+ *            if sqrt(gamma') <= tol ||b||: confirm with the true residual;
+ *               stop if it passes, otherwise start again from r = b - A x
+ *            beta = gamma' / gamma
+ *            alpha = gamma' / (delta' - beta gamma' / alpha);  gamma = gamma'
+ *
+ * Returns 0 when converged, 1 when max_iter was reached, 2 on breakdown
+ * (a denominator of alpha not positive and finite).  *iters is the number
+ * of iterations done, *restarts the restarts from the true residual and
+ * *rel_res the true relative residual ||b - A x|| / ||b|| at exit.
+ */
+static int cg1_start(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+                     const double *b, const double *x, double *r, double *p, double *w, double *s,
+                     double *gamma, double *alpha) {
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    for (int32_t i = 0; i < n; ++i) {
+        double yi, bi;
+        row_sum(row_ptr, col_idx, values, r, i, &yi, &bi);
+        w[i] = yi;
+        p[i] = 0.0;
+        s[i] = 0.0;
+    }
+    *gamma = dot(n, r, r);
+    double delta = dot(n, w, r);
+    if (!(delta > 0.0) || !isfinite(delta)) return 2;
+    *alpha = *gamma / delta;
+    return 0;
+}
+
+int oracle_cg1(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *values,
+               const double *b, double *x, double tol, int32_t max_iter,
+               double *r, double *p, double *w, double *s,
+               int32_t *iters, int32_t *restarts, double *rel_res) {
+    double nb = sqrt(dot(n, b, b));
+    *iters = 0;
+    *restarts = 0;
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        *rel_res = 0.0;
+        return 0;
+    }
+    double gamma, alpha, beta = 0.0;
+    int status = 1;
+    residual(n, row_ptr, col_idx, values, b, x, r);
+    if (sqrt(dot(n, r, r)) <= tol * nb) status = 0;
+    else if (cg1_start(n, row_ptr, col_idx, values, b, x, r, p, w, s, &gamma, &alpha)) status = 2;
+    for (int32_t it = 1; it <= max_iter && status == 1; ++it) {
+        for (int32_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        for (int32_t i = 0; i < n; ++i) s[i] = w[i] + beta * s[i];
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * s[i];
+        for (int32_t i = 0; i < n; ++i) {
+            double yi, bi;
+            row_sum(row_ptr, col_idx, values, r, i, &yi, &bi);
+            w[i] = yi;
+        }
+        double gamma_new = dot(n, r, r);
+        double delta = dot(n, w, r);
+        *iters = it;
+        if (sqrt(gamma_new) <= tol * nb) {
+            residual(n, row_ptr, col_idx, values, b, x, r);
+            if (sqrt(dot(n, r, r)) <= tol * nb) { status = 0; break; }
+            ++*restarts;
+            if (cg1_start(n, row_ptr, col_idx, values, b, x, r, p, w, s, &gamma, &alpha)) { status = 2; break; }
+            beta = 0.0;
+            continue;
+        }
+        beta = gamma_new / gamma;
+        double den = delta - beta * gamma_new / alpha;
+        if (!(den > 0.0) || !isfinite(den)) { status = 2; break; }
+        alpha = gamma_new / den;
+        gamma = gamma_new;
     }
     residual(n, row_ptr, col_idx, values, b, x, r);
     *rel_res = sqrt(dot(n, r, r)) / nb;

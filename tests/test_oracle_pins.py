@@ -347,6 +347,77 @@ def test_cg_zero_rhs_and_max_iter():
     assert r.status == 1 and r.iterations == 3 and r.rel_residual > 1e-12
 
 
+# ---------------- CG with one reduction phase per iteration (Chronopoulos-Gear)
+
+def test_cg1_first_iterate_closed_form():
+    # x0 = 0: x1 = alpha0 r0 = (b.b / b.Ab) b
+    A = mg.lattice(6, 5, 5, "stencil27", seed=93, shift=0.1)
+    b = mg.uniform(A.n_rows, 93, 1)
+    D = _dense(A)
+    r = oracle.cg1(A, b, tol=0.0, max_iter=1)
+    assert r.status == 1 and r.iterations == 1
+    alpha0 = (b @ b) / (b @ (D @ b))
+    assert np.allclose(r.x, alpha0 * b, rtol=1e-14, atol=0.0)
+
+
+@pytest.mark.parametrize("k", [2, 5, 12])
+def test_cg1_iterates_match_textbook_cg(k):
+    # the same Krylov iterates as Hestenes-Stiefel CG (pinned above) in exact
+    # arithmetic; in binary64 they agree to rounding over the first steps
+    # (a dropped beta s term, a wrong sign or alpha = gamma / delta alone
+    # moves them by O(1) from the second step on)
+    A = mg.lattice(6, 5, 5, "stencil27", seed=94, shift=0.1)
+    b = mg.uniform(A.n_rows, 94, 1)
+    r1 = oracle.cg1(A, b, tol=0.0, max_iter=k)
+    r0 = oracle.cg(A, b, tol=0.0, max_iter=k)
+    assert r1.iterations == r0.iterations == k
+    assert np.linalg.norm(r1.x - r0.x) <= 1e-13 * np.linalg.norm(r0.x)
+
+
+def test_cg1_terminates_in_d_steps_for_d_eigenvalues():
+    n, evals = 60, np.array([1.0, 2.5, 4.0, 7.0])
+    d = np.repeat(evals, n // len(evals))
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = mg.uniform(n, 3, 0)
+    r = oracle.cg1(A, b, tol=1e-12, max_iter=100)
+    assert r.status == 0 and r.iterations <= len(evals)
+    assert np.allclose(r.x, b / d, rtol=1e-11)
+
+
+def test_cg1_against_dense_lapack_solve():
+    A = mg.lattice(5, 4, 4, "extras", seed=81, shift=0.05)
+    D = _dense(A)
+    b = mg.uniform(A.n_rows, 81, 1)
+    tol = 1e-10
+    r = oracle.cg1(A, b, tol=tol, max_iter=1000)
+    xs = np.linalg.solve(D, b)
+    assert r.status == 0
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) <= 2 * np.linalg.cond(D) * tol
+    assert np.linalg.norm(b - D @ r.x) / np.linalg.norm(b) <= tol * 1.01
+    assert abs(r.rel_residual - np.linalg.norm(b - D @ r.x) / np.linalg.norm(b)) <= 1e-3 * tol
+
+
+def test_cg1_restarts_from_the_true_residual_when_the_recurrence_drifts():
+    # at tol = 1e-15 the recursive r.r falls below tol^2 ||b||^2 before the
+    # true residual does: the solve restarts from r = b - A x and still ends
+    # below tol (the restart count is returned as the only element of alphas)
+    A = mg.lattice(6, 5, 5, "stencil27", seed=94, shift=0.1)
+    b = mg.uniform(A.n_rows, 94, 1)
+    D = _dense(A)
+    r = oracle.cg1(A, b, tol=1e-15, max_iter=600)
+    assert r.status == 0 and r.alphas[0] >= 1
+    assert np.linalg.norm(b - D @ r.x) / np.linalg.norm(b) <= 1e-15
+
+
+def test_cg1_zero_rhs_and_max_iter():
+    A = mg.config0()
+    r = oracle.cg1(A, np.zeros(A.n_rows), tol=1e-10)
+    assert r.status == 0 and r.iterations == 0 and np.all(r.x == 0)
+    b = mg.uniform(A.n_rows, 5, 1)
+    r = oracle.cg1(A, b, tol=1e-12, max_iter=3)
+    assert r.status == 1 and r.iterations == 3 and r.rel_residual > 1e-12
+
+
 # ------------------------------------- preconditioned CG (bfloat16 copy)
 
 def _bf16_bits_round(a):
