@@ -462,8 +462,8 @@ def config_lines(torch, log=log) -> dict:
             tg = time_graph(lambda: M.apply(x, y), 100, 10, torch)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 30, torch, scratch)
             cg = {}
-            for mode_name, mode in (("fp64", spmv.CG_FP64), ("pcg_bf16", spmv.CG_PCG_BF16),
-                                    ("pcg_jacobi", spmv.CG_PCG_JACOBI)):
+            for mode_name, mode in (("fp64", spmv.CG_FP64), ("fp64_one_reduction", spmv.CG_FP64_ONE_REDUCTION),
+                                    ("pcg_bf16", spmv.CG_PCG_BF16), ("pcg_jacobi", spmv.CG_PCG_JACOBI)):
                 best = None
                 for _ in range(3):
                     _, info = M.cg(b, tol=1e-10, mode=mode)
@@ -481,7 +481,8 @@ def config_lines(torch, log=log) -> dict:
 
 
 CASES = ("bsr3_k1_fp64", "bsr3_k8_fp64", "bsr3_k1_fp32", "bsr3_k8_fp32", "bsr3_k4_fp64", "bsr3_k4_fp32",
-         "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k")
+         "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k", "cg1_fp64_c50k",
+         "cg1_fp64_c800k", "cg_fp64_c800k")
 
 
 def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibration: bool) -> list[dict]:
@@ -496,7 +497,9 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       csr_direct  FP64 with direct gathers (no windows) on the same matrix
       copy        a plain 1 GiB device copy (the counter calibration)
       cg_fp64_16m   48 FP64 CG iterations on the same matrix (per step)
-      cg_fp64_c50k  FP64 CG to 1e-10 on the 49,336-row tet-like stand-in (per step)"""
+      cg_fp64_c50k  FP64 CG to 1e-10 on the 49,336-row tet-like stand-in (per step)
+      cg1_fp64_c50k the same with one reduction per iteration (one launch each)
+      cg_fp64_c800k, cg1_fp64_c800k  both on the 775,058-row stand-in"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -527,15 +530,17 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
             sv = 4 if fp32 else 8
             out["alg_bytes"] = A.nnz * (9 * sv + 4) + 4 * (A.n_rows + 1) + sv * 3 * k * (A.n_cols + A.n_rows)
             out["flops"] = 2 * 9 * A.nnz * k
-        elif name.startswith("cg_fp64"):
-            A = mat("hex") if name.endswith("16m") else mg.table1_matrix("C50K")
+        elif name.startswith("cg"):
+            A = mat("hex") if name.endswith("16m") else mg.table1_matrix(name.split("_")[-1].upper())
             b = torch.as_tensor(mg.uniform(A.n_rows, 7, 1), device="cuda")
+            mode = spmv.CG_FP64_ONE_REDUCTION if name.startswith("cg1") else spmv.CG_FP64
             with spmv.Matrix.from_csr(A) as M:
                 it = 48 if name.endswith("16m") else 20000
                 tol = 0.0 if name.endswith("16m") else 1e-10
-                M.cg(b, tol=tol, max_iter=it, raise_on_error=False)  # captures the graph once
-                t = time_launches(lambda: M.cg(b, tol=tol, max_iter=it, raise_on_error=False), steps, warmup, torch)
-                _, info = M.cg(b, tol=tol, max_iter=it, raise_on_error=False)
+                M.cg(b, tol=tol, max_iter=it, mode=mode, raise_on_error=False)  # captures the graph once
+                t = time_launches(lambda: M.cg(b, tol=tol, max_iter=it, mode=mode, raise_on_error=False), steps,
+                                  warmup, torch)
+                _, info = M.cg(b, tol=tol, max_iter=it, mode=mode, raise_on_error=False)
             out["iterations"] = info.iterations
             out["us_per_iteration"] = round(t * 1e6 / max(info.iterations, 1), 2)
             out["alg_bytes"] = 0

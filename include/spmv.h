@@ -291,6 +291,18 @@ int bsr3_spmm_f32(const spmv_matrix *A, int32_t k, const float *X, float *Y, voi
                            summed), all in binary64 (needs a CSR-format handle;
                            SPMV_EBREAK if a diagonal entry is not positive and
                            finite) */
+#define CG_FP64_ONE_REDUCTION 5 /* binary64 CG with one reduction phase per
+                           iteration (Chronopoulos-Gear: w = A r and s = A p
+                           carried by recurrence, r.r and w.r taken together),
+                           one launch per iteration; the same Krylov iterates
+                           as CG_FP64 in exact arithmetic, and restarts from the
+                           true residual when the recursive one has drifted
+                           (counted in cg_info.refinements).  For small systems,
+                           whose iterations are bound by launch latency: needs a
+                           CSR handle of plain row tiles (the default plan of a
+                           matrix under 512 MB, or window_mode SPMV_WINDOW_OFF;
+                           no row longer than a tile) with at most 4,096 tiles,
+                           else SPMV_ENOTSUP */
 
 typedef struct cg_info {
     int32_t iterations;        /* total CG iterations (inner iterations for MIXED) */

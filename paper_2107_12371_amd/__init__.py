@@ -29,7 +29,7 @@ SPMV_VALUES_FP32, SPMV_VALUES_BF16, SPMV_NO_XCD_REMAP, SPMV_DEVICE_PTRS = 0x1, 0
 SPMV_XCD_CONTIGUOUS = 0x10
 WINDOW_AUTO, WINDOW_OFF, WINDOW_RING = 0, 1, 2
 FORMAT_CSR, FORMAT_SELL = 0, 1
-CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V, CG_PCG_JACOBI = 0, 1, 2, 3, 4
+CG_FP64, CG_MIXED_FP32, CG_PCG_BF16, CG_MIXED_FP32V, CG_PCG_JACOBI, CG_FP64_ONE_REDUCTION = 0, 1, 2, 3, 4, 5
 
 EXPORTED = [
     "spmv_create", "spmv_destroy", "spmv_get_info", "spmv_apply", "spmv_apply_f32",

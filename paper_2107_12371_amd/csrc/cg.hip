@@ -394,6 +394,181 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pfused(const TileDesc *__restri
     tile_rows<T, T, EPI_DOT>(pre, d.r0, d.r1, prod, q, part_pq, d.seg, sh);
 }
 
+// ------------------------------------------------ one reduction per iteration
+//
+// CG with one reduction phase per iteration (Chronopoulos and Gear, J.
+// Comput. Appl. Math. 25, 1989): besides x, r and p it carries w = A r and
+// s = A p (by the recurrence s = w + beta s), so that r.r and w.r are taken
+// together after the single product and
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+// with gamma = r.r and delta = w.r.  One launch is one iteration: each
+// workgroup (one row tile) sums the previous launch's gamma and delta
+// partials, forms alpha and beta, and then forms, for every column it
+// gathers and every row it owns,
+//   s_new = w + beta s,  r_new = r - alpha s_new       (gathered: the product's input)
+//   p_new = r + beta p,  x_new = x + alpha p_new       (own rows only)
+// and w_new = A r_new with the gamma and delta partials of its rows.  r, w
+// and s are read at other workgroups' rows, so they alternate between two
+// copies by launch parity, as do the partials and the scalar slots: no
+// workgroup reads anything another workgroup of the same launch writes.
+
+struct Cg1Scalars {
+    double gamma;   // r.r of the step the slot's launch finished checking
+    double alpha;   // the alpha and beta that launch used
+    double beta;
+    int32_t fresh;  // 1: the reading launch takes alpha and beta from here (a start)
+    int32_t iter;   // iterations completed
+};
+
+// Start or restart: r (the true residual), w = A r with its w.r partials and
+// st->rt2 = r.r are in place, p = s = 0.  Sets the slot the first launch
+// reads: alpha0 = r.r / w.r, beta = 0.
+__global__ __launch_bounds__(kBlock) void k_cg1_start(CgState *st, Cg1Scalars *slot,
+                                                      const double *__restrict__ part_wr, int n) {
+    __shared__ double sh[kBlock / kWave];
+    const double delta = sum_partials(part_wr, n, sh);
+    if (threadIdx.x != 0) return;
+    const double gamma = st->rt2;
+    st->rho = gamma;
+    st->rho_new = gamma;
+    st->flags = 0;
+    st->done = st->iter >= st->max_iter ? 1 : 0;
+    if (st->done) st->flags = F_MAXITER;
+    if (!(delta > 0.0) || !isfinite(delta)) {
+        st->flags |= F_BREAKDOWN;
+        st->done = 1;
+    }
+    slot->gamma = gamma;
+    slot->alpha = gamma / delta;
+    slot->beta = 0.0;
+    slot->fresh = 1;
+    slot->iter = st->iter;
+}
+
+template <typename T, typename V, int NT>
+__global__ __launch_bounds__(kBlock) void k_cg1(const TileDesc *__restrict__ desc, int n_list, int per_xcd,
+                                                int chunk_log2, const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col, const V *__restrict__ val,
+                                                T *__restrict__ x, T *__restrict__ p,
+                                                const T *__restrict__ r_in, const T *__restrict__ w_in,
+                                                const T *__restrict__ s_in, T *__restrict__ r_out,
+                                                T *__restrict__ w_out, T *__restrict__ s_out,
+                                                const double *__restrict__ gam_in, const double *__restrict__ del_in,
+                                                double *__restrict__ gam_out, double *__restrict__ del_out,
+                                                int n_part, const Cg1Scalars *__restrict__ sc_in,
+                                                Cg1Scalars *__restrict__ sc_out, CgState *st) {
+    using Regs = TileRegs<V, NT>;
+    __shared__ T prod[Regs::kProd];
+    __shared__ double sh[kBlock / kWave], sh2[kBlock / kWave];
+    __shared__ double sums[2];
+    const int li = xcd_tile(blockIdx.x, per_xcd, chunk_log2);
+    if (li >= n_list) return;
+    // every load that does not depend on another goes out before any wait:
+    // descriptor and scalars, the tile's stream and rows, own-row vector
+    // elements, the partials, then the gathers
+    const TileDesc d = desc[li];
+    const int done = st->done, max_iter = st->max_iter;
+    const double tol2 = st->tol2;
+    const Cg1Scalars S = *sc_in;
+    Regs t;
+    t.load(col, val, d.s, d.e);
+    RowPre<T, EPI_DOT> pre;
+    pre.load(row_ptr, r_in, static_cast<const T *>(nullptr), d.r0, d.r1, d.s & ~3);  // op = r of own rows
+    T w_row[2], s_row[2], p_row[2], x_row[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int j = min(d.r0 + (int)threadIdx.x + i * kBlock, d.r1 - 1);
+        w_row[i] = w_in[j];
+        s_row[i] = s_in[j];
+        p_row[i] = p[j];
+        x_row[i] = x[j];
+    }
+    double pg = 0.0, pd = 0.0;  // this lane's shares of the gamma and delta sums, in sum_partials' order
+    if (!S.fresh) {
+#pragma unroll 4
+        for (int i = (int)threadIdx.x; i < n_part; i += kBlock) {
+            pg += gam_in[i];
+            pd += del_in[i];
+        }
+    }
+    T rv[Regs::kMaxPass][4], wv[Regs::kMaxPass][4], sv[Regs::kMaxPass][4];
+    t.gather([r_in](int c) { return r_in[c]; }, rv);
+    t.gather([w_in](int c) { return w_in[c]; }, wv);
+    t.gather([s_in](int c) { return s_in[c]; }, sv);
+    if (done) return;
+    double alpha = S.alpha, beta = S.beta, gamma = S.gamma;
+    int iter = S.iter;
+    if (!S.fresh) {
+        const double g0 = block_sum(pg, sh);
+        const double d0 = block_sum(pd, sh2);
+        if (threadIdx.x == 0) {
+            sums[0] = g0;
+            sums[1] = d0;
+        }
+        __syncthreads();
+        const double g = sums[0], dl = sums[1];
+        iter += 1;  // the previous launch's iteration, now checked
+        beta = g / S.gamma;
+        const double den = dl - beta * g / S.alpha;
+        alpha = g / den;
+        gamma = g;
+        // every workgroup takes the same decision from the same sums;
+        // workgroup 0 records it
+        int32_t stop = 0;
+        if (!isfinite(g)) stop = F_BREAKDOWN;
+        else if (g <= tol2) stop = F_CONVERGED;
+        else if (!(den > 0.0) || !isfinite(den)) stop = F_BREAKDOWN;
+        else if (iter >= max_iter) stop = F_MAXITER;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->iter = iter;
+            st->rho = g;
+            st->rho_new = g;
+            st->pq = dl;
+            if (stop) {
+                st->flags |= stop;
+                st->done = 1;
+            }
+        }
+        if (stop) return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc_out->gamma = gamma;
+        sc_out->alpha = alpha;
+        sc_out->beta = beta;
+        sc_out->fresh = 0;
+        sc_out->iter = iter;
+        st->alpha = alpha;
+        st->beta = beta;
+    }
+    const T a = static_cast<T>(alpha), b = static_cast<T>(beta);
+    T xv[Regs::kMaxPass][4];
+#pragma unroll
+    for (int ps = 0; ps < Regs::kMaxPass; ++ps)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[ps][j] = fma_t(-a, fma_t(b, sv[ps][j], wv[ps][j]), rv[ps][j]);
+    double gp = 0.0;  // r_new.r_new over own rows
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int j = d.r0 + (int)threadIdx.x + i * kBlock;
+        const T sn = fma_t(b, s_row[i], w_row[i]);
+        const T rn = fma_t(-a, sn, pre.op[i]);
+        const T pn = fma_t(b, p_row[i], pre.op[i]);
+        if (j < d.r1) {
+            s_out[j] = sn;
+            r_out[j] = rn;
+            p[j] = pn;
+            x[j] = fma_t(a, pn, x_row[i]);
+            gp += static_cast<double>(rn) * static_cast<double>(rn);
+        }
+        pre.op[i] = rn;
+    }
+    t.products(xv, prod);
+    const double gt = block_sum(gp, sh2);
+    if (threadIdx.x == 0) gam_out[d.seg] = gt;
+    __syncthreads();
+    tile_rows<T, T, EPI_DOT>(pre, d.r0, d.r1, prod, w_out, del_out, d.seg, sh);
+}
+
 // The x/r update of a fused iteration: p_new = r + beta p (as the fused
 // product formed it) is written for this workgroup's rows, then x += alpha
 // p_new, r -= alpha q and the r.r partial, as k_update_xr.  Workgroup 0
@@ -1203,6 +1378,171 @@ static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol,
     return SPMV_OK;
 }
 
+// ------------------------------------------------ one-reduction CG driver
+//
+// One launch of k_cg1 per iteration, graph_iters (even) of them per graph
+// replay: the launch of parity j reads copy j of r, w, s and of the partials
+// written by the launch before it, and slot 1 - j of the scalars, and writes
+// the other copies, so each replay starts from copy 0 and slot 1.  Start and
+// restart (after the recursive r.r met the tolerance but the true residual
+// did not): r = b - A x, w = A r with the w.r partials, p = s = 0, and
+// k_cg1_start sets slot 1 to alpha0 = r.r / w.r, beta = 0.
+
+// Plain row tiles only, and at most this many of them, so that every
+// workgroup can sum the previous launch's partials itself.
+constexpr int kCg1MaxTiles = 4096;
+
+bool cg1_eligible(const DevMatrix &M) {
+    return M.block == 1 && M.format == SPMV_FORMAT_CSR && M.n_stream > 0 && M.n_cwin == 0 && M.n_blk == 0 &&
+           M.n_long == 0 && M.n_seg == M.n_stream && M.n_stream <= kCg1MaxTiles &&
+           (M.tile_nnz == 1024 || M.tile_nnz == 2048 || M.tile_nnz == 4096);
+}
+
+struct Cg1Core : CgCore<double, double> {
+    double *r2 = nullptr, *w[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
+    double *gam[2] = {nullptr, nullptr}, *del[2] = {nullptr, nullptr};
+    Cg1Scalars *sc = nullptr;  // two slots
+    Cg1Core(const DevMatrix &M_, int n_, hipStream_t s_) : CgCore<double, double>(M_, M_.val64, n_, s_) {
+        fused = false;
+    }
+
+    template <int NT> void launch_nt(hipStream_t t, int par, int per_xcd, int grid) {
+        const double *r_in = par ? r2 : r;
+        double *r_out = par ? r : r2;
+        hipLaunchKernelGGL((k_cg1<double, double, NT>), dim3(grid), dim3(kBlock), 0, t, M.stream_desc, M.n_stream,
+                           per_xcd, M.xcd_chunk_log2, M.row_ptr, M.col, val, x, p, r_in, w[par], sv[par], r_out,
+                           w[1 - par], sv[1 - par], gam[1 - par], del[1 - par], gam[par], del[par], M.n_seg,
+                           sc + (1 - par), sc + par, st);
+    }
+
+    hipError_t iteration1(hipStream_t t, int par) {
+        const int per_xcd = M.xcd_remap && M.n_stream >= 16 ? (M.n_stream + 7) / 8 : 0;
+        const int grid = xcd_grid(M.n_stream, per_xcd, M.xcd_chunk_log2);
+        switch (M.tile_nnz) {
+            case 1024: launch_nt<1024>(t, par, per_xcd, grid); break;
+            case 2048: launch_nt<2048>(t, par, per_xcd, grid); break;
+            default: launch_nt<4096>(t, par, per_xcd, grid); break;
+        }
+        return hipGetLastError();
+    }
+
+    // r = b - A x (copy 0), w = A r, p = s = 0, slot 1 set; st->rt2 = r.r
+    hipError_t start(const double *b) {
+        hipError_t e = true_residual(b);
+        if (e != hipSuccess) return e;
+        e = launch_spmv<double, double, double, double>(M, val, r, w[0], EPI_DOT, nullptr, part_seg, nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cg1_start, dim3(1), dim3(kBlock), 0, s, st, sc + 1, part_seg, M.n_seg);
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, p);
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, sv[0]);
+        return hipGetLastError();
+    }
+
+    int solve1(const double *b, double tol, int max_iter, int *iters, int *restarts) {
+        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol, max_iter);
+        HIP_TRY(start(b));
+        int rc = read_state();
+        if (rc) return rc;
+        if (hst->rt2 <= hst->tol2) return SPMV_OK;
+        if (max_iter <= 0) return SPMV_ENOTCONV;
+        if (hst->flags & F_BREAKDOWN) return SPMV_EBREAK;
+        if (!exec) {
+            int j = 0;
+            rc = capture_with([this, &j](hipStream_t t) { return iteration1(t, (j++) & 1); });
+            if (rc) return rc;
+        }
+        for (;;) {
+            HIP_TRY(hipGraphLaunch(exec, s));
+            rc = read_state();
+            if (rc) return rc;
+            if (hst->flags & F_BREAKDOWN) {
+                *iters += hst->iter;
+                return SPMV_EBREAK;
+            }
+            if (hst->flags & F_CONVERGED) {
+                HIP_TRY(true_residual(b));
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->rt2 <= hst->tol2) break;
+                ++*restarts;  // the recursive residual drifted from the true one
+                HIP_TRY(start(b));
+                rc = read_state();
+                if (rc) return rc;
+                if (hst->flags & F_BREAKDOWN) {
+                    *iters += hst->iter;
+                    return SPMV_EBREAK;
+                }
+                if (hst->flags & F_MAXITER) {
+                    *iters += hst->iter;
+                    return SPMV_ENOTCONV;
+                }
+                continue;
+            }
+            if ((hst->flags & F_MAXITER) || hst->iter >= max_iter) {
+                *iters += hst->iter;
+                return SPMV_ENOTCONV;
+            }
+        }
+        *iters += hst->iter;
+        return SPMV_OK;
+    }
+};
+
+static int cg_fp64_one_reduction(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter,
+                                 cg_info *info, hipStream_t s, void *pinned) {
+    const DevMatrix &M = A->M;
+    if (!cg1_eligible(M))
+        return fail(SPMV_ENOTSUP,
+                    "one-reduction CG needs a CSR handle of plain row tiles (no windows, no row longer than a "
+                    "tile) with at most %d tiles (this one: %d plain tiles, %d window tiles, %d ring blocks, %d long "
+                    "rows)",
+                    kCg1MaxTiles, M.n_stream, M.n_cwin, M.n_blk, M.n_long);
+    const int n = M.n_rows;
+    Buffers B(s);
+    Cg1Core C(M, n, s);
+    int rc = alloc_core(B, C);
+    if (rc) return rc;
+    HIP_TRY(B.alloc(&C.r2, (size_t)n));
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(B.alloc(&C.w[k], (size_t)n));
+        HIP_TRY(B.alloc(&C.sv[k], (size_t)n));
+        HIP_TRY(B.alloc(&C.gam[k], (size_t)M.n_seg));
+        HIP_TRY(B.alloc(&C.del[k], (size_t)M.n_seg));
+    }
+    HIP_TRY(B.alloc(&C.sc, 2));
+    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
+    C.hst = static_cast<CgState *>(B.host);
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
+    HIP_TRY(hipGetLastError());
+    rc = C.read_state();
+    if (rc) return rc;
+    if (C.hst->bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    int iters = 0, restarts = 0;
+    rc = C.solve1(b, tol, max_iter, &iters, &restarts);
+    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
+    int rc2;
+    HIP_TRY(C.true_residual(b));
+    if ((rc2 = C.read_state())) return rc2;
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, C.x);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->refinements = restarts;
+        info->graph_seconds = C.capture_s;
+        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
+    }
+    if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (w.r - beta r.r / alpha <= 0 or not finite): matrix not SPD?");
+    return SPMV_OK;
+}
+
 // ------------------------------------------------- allocation-free FP64 CG
 //
 // cg_solve_noalloc runs cg_fp64's kernels, in the same order, on a
@@ -1425,7 +1765,7 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     if (A->M.n_rows != A->M.n_cols) return fail(SPMV_EINVAL, "CG needs a square matrix (%d x %d)", A->M.n_rows, A->M.n_cols);
     if (!(tol >= 0.0) || max_iter < 0) return fail(SPMV_EINVAL, "tol must be >= 0 and max_iter >= 0");
     if (mode != CG_FP64 && mode != CG_MIXED_FP32 && mode != CG_PCG_BF16 && mode != CG_MIXED_FP32V &&
-        mode != CG_PCG_JACOBI)
+        mode != CG_PCG_JACOBI && mode != CG_FP64_ONE_REDUCTION)
         return fail(SPMV_EINVAL, "unknown CG mode %d", mode);
     if ((mode == CG_MIXED_FP32 || mode == CG_MIXED_FP32V) && !A->M.val32)
         return fail(SPMV_ENOTSUP, "mixed-precision CG needs the FP32 copy (create with SPMV_VALUES_FP32)");
@@ -1453,6 +1793,8 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
     int rc;
     if (mode == CG_FP64) {
         rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);
+    } else if (mode == CG_FP64_ONE_REDUCTION) {
+        rc = cg_fp64_one_reduction(A, b, x, tol, max_iter, info, s, pinned_state);
     } else if (mode == CG_PCG_BF16 || mode == CG_PCG_JACOBI) {
         rc = cg_pcg(A, b, x, tol, max_iter, info, s, pinned_state, mode == CG_PCG_JACOBI);
     } else {

@@ -111,7 +111,7 @@ def test_cg_rejects_bad_input():
             M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_MIXED_FP32V)
         assert e.value.code == spmv.SPMV_ENOTSUP
         with pytest.raises(spmv.SpmvError) as e:
-            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=5)
+            M.cg(torch.ones(B.n_rows, dtype=torch.float64, device=DEV), mode=6)
         assert e.value.code == spmv.SPMV_EINVAL
 
 
@@ -346,3 +346,115 @@ def test_table1_c400k_against_oracle(mode):
     kappa = gershgorin_kappa(A, 1e-3)
     assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 2 * kappa * tol
     assert abs(info.iterations - ref.iterations) <= 0.1 * ref.iterations
+
+
+# -------------- one reduction per iteration (Chronopoulos-Gear, one launch)
+
+def _cg1_params(tile=1024):
+    return {"window_mode": spmv.WINDOW_OFF, "tile_nnz": tile}
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("k", [1, 2, 5, 12])
+def test_cg1_first_iterates_match_the_oracle(cfg0, tile, k):
+    # k steps from zero (tol = 0: the cap ends the solve) against the
+    # oracle's k-step iterate (pinned to textbook CG): the two differ only in
+    # summation order and fused multiply-adds, about 1e-16 relative a step;
+    # a dropped term or a sign moves the iterate by O(1) from the second step
+    A, b, _ = cfg0
+    ref = oracle.cg1(A, b, tol=0.0, max_iter=k)
+    assert ref.status == 1 and ref.iterations == k
+    with spmv.Matrix.from_csr(A, params=_cg1_params(tile)) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=0.0, max_iter=k, mode=spmv.CG_FP64_ONE_REDUCTION,
+                       raise_on_error=False)
+    assert info.status == spmv.SPMV_ENOTCONV and info.iterations == k
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("name", ["config0", "C50K"])
+def test_cg1_converges_like_the_oracle_and_textbook_cg(name):
+    A = mg.config0() if name == "config0" else mg.table1_matrix(name)
+    b = mg.uniform(A.n_rows, 17, 3)
+    tol = 1e-10
+    ref = oracle.cg1(A, b, tol=tol, max_iter=20000)
+    assert ref.status == 0
+    with spmv.Matrix.from_csr(A, params=_cg1_params()) as M:
+        bd = torch.as_tensor(b, device=DEV)
+        x, info = M.cg(bd, tol=tol, mode=spmv.CG_FP64_ONE_REDUCTION)
+        x2, _ = M.cg(bd, tol=tol, mode=spmv.CG_FP64_ONE_REDUCTION)
+        _, info_hs = M.cg(bd, tol=tol, mode=spmv.CG_FP64)
+    assert torch.equal(x, x2)  # bitwise reproducible
+    x = x.cpu().numpy()
+    rr = true_rel_residual(A, x, b)
+    assert info.status == 0 and rr <= 1.05 * tol and abs(info.rel_residual - rr) <= 0.05 * tol
+    assert abs(info.iterations - ref.iterations) <= 0.1 * ref.iterations
+    assert abs(info.iterations - info_hs.iterations) <= 0.1 * info_hs.iterations
+    kappa = gershgorin_kappa(A, 1e-3) if name == "config0" else None
+    if kappa:
+        assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 2 * kappa * tol
+
+
+def test_cg1_on_the_largest_table1_system():
+    # C800K: 3,753 tiles, close to the 4,096 every workgroup sums itself
+    A = mg.table1_matrix("C800K")
+    b = mg.uniform(A.n_rows, 18, 3)
+    tol = 1e-10
+    with spmv.Matrix.from_csr(A, params=_cg1_params()) as M:
+        assert M.info["n_tiles"] == 3753
+        bd = torch.as_tensor(b, device=DEV)
+        x, info = M.cg(bd, tol=tol, mode=spmv.CG_FP64_ONE_REDUCTION)
+        _, info_hs = M.cg(bd, tol=tol, mode=spmv.CG_FP64)
+    rr = true_rel_residual(A, x.cpu().numpy(), b)
+    assert info.status == 0 and rr <= 1.05 * tol
+    assert abs(info.iterations - info_hs.iterations) <= 0.1 * info_hs.iterations
+
+
+def test_cg1_restarts_from_the_true_residual():
+    # at tol = 1e-15 the recursive r.r meets the tolerance before the true
+    # residual does (the oracle restarts too); the solve restarts from
+    # r = b - A x and ends near the binary64 floor
+    A = mg.lattice(6, 5, 5, "stencil27", seed=94, shift=0.1)
+    b = mg.uniform(A.n_rows, 94, 1)
+    ref = oracle.cg1(A, b, tol=1e-15, max_iter=600)
+    assert ref.status == 0 and ref.alphas[0] >= 1
+    with spmv.Matrix.from_csr(A, params=_cg1_params()) as M:
+        x, info = M.cg(torch.as_tensor(b, device=DEV), tol=1e-15, max_iter=600,
+                       mode=spmv.CG_FP64_ONE_REDUCTION, raise_on_error=False)
+    assert info.status in (spmv.SPMV_OK, spmv.SPMV_ENOTCONV) and info.refinements >= 1
+    assert true_rel_residual(A, x.cpu().numpy(), b) <= 1e-14
+
+
+def test_cg1_breakdown_zero_rhs_and_rejections(cfg0):
+    # w.r = 0 at the start on an indefinite diagonal system (the oracle
+    # breaks down before its first step too)
+    n = 64
+    d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = np.zeros(n)
+    b[0], b[1] = 1.0, 1.0
+    ref = oracle.cg1(A, b, tol=1e-10, max_iter=100)
+    assert ref.status == 2 and ref.iterations == 0
+    with spmv.Matrix.from_csr(A, params=_cg1_params()) as M:
+        _, info = M.cg(torch.as_tensor(b, device=DEV), mode=spmv.CG_FP64_ONE_REDUCTION, raise_on_error=False)
+        assert info.status == spmv.SPMV_EBREAK and info.iterations == 0
+    # a later breakdown at the oracle's step
+    n = 200
+    d = np.linspace(1.0, 10.0, n)
+    d[-3:] = -np.linspace(0.5, 5.0, 3)
+    A = mg.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = np.ones(n)
+    ref = oracle.cg1(A, b, tol=1e-10, max_iter=1000)
+    assert ref.status == 2
+    with spmv.Matrix.from_csr(A, params=_cg1_params()) as M:
+        _, info = M.cg(torch.as_tensor(b, device=DEV), tol=1e-10, max_iter=1000,
+                       mode=spmv.CG_FP64_ONE_REDUCTION, raise_on_error=False)
+    assert info.status == spmv.SPMV_EBREAK and info.iterations == ref.iterations
+    A0, b0, _ = cfg0
+    with spmv.Matrix.from_csr(A0, params=_cg1_params()) as M:
+        x, info = M.cg(torch.zeros(A0.n_rows, dtype=torch.float64, device=DEV), mode=spmv.CG_FP64_ONE_REDUCTION)
+        assert info.status == 0 and info.iterations == 0 and not x.any()
+    with spmv.Matrix.from_csr(A0, params={"window_mode": spmv.WINDOW_RING}) as M:  # not plain row tiles
+        with pytest.raises(spmv.SpmvError) as e:
+            M.cg(torch.as_tensor(b0, device=DEV), mode=spmv.CG_FP64_ONE_REDUCTION)
+        assert e.value.code == spmv.SPMV_ENOTSUP and "one-reduction" in str(e.value)
