@@ -213,6 +213,7 @@ def cpu_baseline(A, x, budget_s: float):
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS", "unset")}
 
 
+CG1_MAX_ROWS = 200_000
 SERVE_PHASES = ("latency_s", "queue_s", "wait_s", "copy_in_s", "compute_s", "copy_out_s", "graph_s", "kernel_s")
 
 
@@ -261,8 +262,10 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
         return ("cg", mid, r.uniform(-1, 1, A.n_rows))
 
     # the pool fits the budget, so matrices stay resident once uploaded
+    # FP64 solves of matrices up to 200,000 rows take one reduction per
+    # iteration (measured faster per iteration there, slower above)
     srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=preload,
-                      persistent_wgs=persistent_wgs)
+                      persistent_wgs=persistent_wgs, cg1_max_rows=CG1_MAX_ROWS)
     t0 = time.perf_counter()
     for A in pool:
         srv.add_matrix(A)
@@ -328,7 +331,8 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     lat_all = phases["cg"]["latency_s"] + phases["spmv"]["latency_s"]
     out = {"requests": n_requests, "pool": pool_size, "pool_rows": int(sum(A.n_rows for A in pool)),
            "arrival_rate_rps": round(lam, 2), "closed_loop_capacity_rps": round(cap, 2),
-           "cg_mode": "mixed" if cg_mode else "fp64", "preload": preload,
+           "cg_mode": "mixed" if cg_mode else f"fp64 (one reduction per iteration up to {CG1_MAX_ROWS:,} rows)",
+           "preload": preload,
            "spmv_rounds": (f"persistent kernel, {persistent_wgs} workgroups, {st['persist_launches']} launches"
                            if persistent_wgs else "one launch per round"),
            "p50_ms": q(lat_all, 0.5), "p99_ms": q(lat_all, 0.99),
@@ -338,6 +342,7 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
            "mean_cg_iterations": round(float(np.mean(iters)), 1) if iters else None,
            "breakdown_ms_p50_p99": {op: {k[:-2]: [q(v, 0.5), q(v, 0.99)] for k, v in ph.items()}
                                     for op, ph in phases.items()},
+           "cg_solver_reuses": st["solver_reuses"], "cg_solvers_kept_bytes": st["solver_cached_bytes"],
            "failed": fails, "errors": errors, "rounds": st["rounds"], "uploads": st["uploads"],
            "evictions": st["evictions"], "peak_budget_bytes": st["peak_bytes"]}
     log(f"serving{' (preloaded)' if preload else ''}{' (persistent)' if persistent_wgs else ''}: "

@@ -366,6 +366,10 @@ int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double to
  * every queued round as they arrive (the analogue of a task queue feeding
  * accelerator kernels, paper Sec. 3.2); CG requests run on solver slots
  * (one stream each, graph-captured iterations) concurrently with the rounds.
+ * The device workspace and captured iteration graph of each FP64 solve are
+ * kept per matrix (up to hbm_budget_bytes / 16 in all, least recently used
+ * dropped first, dropped with an evicted matrix, outside hbm_budget_bytes),
+ * so a later solve on the same matrix from any slot only replays.
  * A request's result is bitwise identical alone and in any mix.
  * Latency is measured from srv_submit until the result is in `out`.
  */
@@ -388,6 +392,9 @@ typedef struct srv_config {
                                   in host memory; 0: one launch per round */
     int32_t persist_idle_us;   /* the persistent kernel ends after this long without work and is
                                   launched again when work comes, <= 10^7 (0: 20000) */
+    int32_t cg1_max_rows;      /* with cg_mode CG_FP64, solves on matrices of at most this many rows
+                                  use CG_FP64_ONE_REDUCTION (faster per iteration on small systems;
+                                  0: never) */
 } srv_config;
 
 typedef struct srv_result {
@@ -423,6 +430,8 @@ typedef struct srv_stats {
     double wall_s;          /* first submit -> last completion */
     double throughput_rps;  /* completed / wall_s */
     int64_t persist_launches; /* launches of the persistent kernel (0 without one) */
+    int64_t solver_reuses;    /* CG solves that replayed a kept solver (no capture) */
+    int64_t solver_cached_bytes; /* device bytes of the kept solvers */
 } srv_stats;
 
 /* Creates the server on the current device (cfg NULL: defaults). */

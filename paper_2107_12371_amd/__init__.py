@@ -446,7 +446,7 @@ class srv_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
                 ("cg_mode", ctypes.c_int32), ("max_round_tiles", ctypes.c_int32), ("preload", ctypes.c_int32),
                 ("n_lanes", ctypes.c_int32), ("persistent_wgs", ctypes.c_int32),
-                ("persist_idle_us", ctypes.c_int32)]
+                ("persist_idle_us", ctypes.c_int32), ("cg1_max_rows", ctypes.c_int32)]
 
 
 class srv_result(ctypes.Structure):
@@ -468,7 +468,8 @@ class srv_stats(ctypes.Structure):
                 ("used_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("p50_s", ctypes.c_double),
                 ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("throughput_rps", ctypes.c_double),
-                ("persist_launches", ctypes.c_int64)]
+                ("persist_launches", ctypes.c_int64), ("solver_reuses", ctypes.c_int64),
+                ("solver_cached_bytes", ctypes.c_int64)]
 
 
 EXPORTED += ["srv_create", "srv_add_matrix", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
@@ -536,10 +537,10 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 0, n_slots: int = 0, cg_mode: int = CG_FP64,
                  max_round_tiles: int = 0, preload: bool = False, n_lanes: int = 0,
-                 persistent_wgs: int = 0, persist_idle_us: int = 0):
+                 persistent_wgs: int = 0, persist_idle_us: int = 0, cg1_max_rows: int = 0):
         L = _serve_lib()
         cfg = srv_config(hbm_budget_bytes, n_slots, cg_mode, max_round_tiles, 1 if preload else 0, n_lanes,
-                         persistent_wgs, persist_idle_us)
+                         persistent_wgs, persist_idle_us, cg1_max_rows)
         h = ctypes.c_void_p()
         _check(L.srv_create(ctypes.byref(cfg), ctypes.byref(h)), "srv_create")
         self._h = h

@@ -46,6 +46,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 
 #include "device.h"
 #include "internal.h"
@@ -926,6 +927,7 @@ int grid_for(int n) { return std::max(1, std::min(4096, (n + kBlock - 1) / kBloc
 struct Buffers {
     hipStream_t s;
     std::vector<void *> dev;
+    size_t bytes = 0;  // device bytes held
     void *host = nullptr;
     bool own_host = false;
     explicit Buffers(hipStream_t s_) : s(s_) {}
@@ -941,6 +943,7 @@ struct Buffers {
         hipError_t e = hipMallocAsync(&q, sizeof(T) * std::max<size_t>(n, 1), s);
         if (e == hipSuccess) {
             dev.push_back(q);
+            bytes += sizeof(T) * std::max<size_t>(n, 1);
             *p = static_cast<T *>(q);
         }
         return e;
@@ -1336,48 +1339,6 @@ struct PcgCore : CgCore<double, double> {
 
 }  // namespace
 
-static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
-                   hipStream_t s, void *pinned) {
-    const DevMatrix &M = A->M;
-    const int n = M.n_rows;
-    Buffers B(s);
-    CgCore<double, double> C(M, M.val64, n, s);
-    int rc = alloc_core(B, C);
-    if (rc) return rc;
-    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
-    C.hst = static_cast<CgState *>(B.host);
-    // ||b||^2
-    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
-    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
-    HIP_TRY(hipGetLastError());
-    rc = C.read_state();
-    if (rc) return rc;
-    if (C.hst->bb == 0.0) {
-        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
-        HIP_TRY(hipStreamSynchronize(s));
-        if (info) info->rel_residual = 0.0;
-        return SPMV_OK;
-    }
-    int iters = 0, repl = 0;
-    rc = C.solve(b, tol, max_iter, &iters, &repl);
-    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
-    int rc2;
-    HIP_TRY(C.true_residual(b));
-    if ((rc2 = C.read_state())) return rc2;
-    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, C.x);
-    HIP_TRY(hipStreamSynchronize(s));
-    if (info) {
-        info->iterations = iters;
-        info->refinements = repl;
-        info->graph_seconds = C.capture_s;
-        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
-    }
-    if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
-    if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (p.q <= 0 or not finite): matrix not SPD?");
-    return SPMV_OK;
-}
-
 // ------------------------------------------------ one-reduction CG driver
 //
 // One launch of k_cg1 per iteration, graph_iters (even) of them per graph
@@ -1488,35 +1449,140 @@ struct Cg1Core : CgCore<double, double> {
     }
 };
 
-static int cg_fp64_one_reduction(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter,
-                                 cg_info *info, hipStream_t s, void *pinned) {
-    const DevMatrix &M = A->M;
-    if (!cg1_eligible(M))
-        return fail(SPMV_ENOTSUP,
-                    "one-reduction CG needs a CSR handle of plain row tiles (no windows, no row longer than a "
-                    "tile) with at most %d tiles (this one: %d plain tiles, %d window tiles, %d ring blocks, %d long "
-                    "rows)",
-                    kCg1MaxTiles, M.n_stream, M.n_cwin, M.n_blk, M.n_long);
-    const int n = M.n_rows;
-    Buffers B(s);
-    Cg1Core C(M, n, s);
-    int rc = alloc_core(B, C);
-    if (rc) return rc;
-    HIP_TRY(B.alloc(&C.r2, (size_t)n));
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(B.alloc(&C.w[k], (size_t)n));
-        HIP_TRY(B.alloc(&C.sv[k], (size_t)n));
-        HIP_TRY(B.alloc(&C.gam[k], (size_t)M.n_seg));
-        HIP_TRY(B.alloc(&C.del[k], (size_t)M.n_seg));
+// ------------------------------------------------------- solver cache
+struct CgCache {
+    uint64_t serial = 0;  // the matrix handle's serial (0: empty)
+    int mode = -1;
+    hipStream_t s = nullptr;
+    void *pinned = nullptr;
+    std::unique_ptr<Buffers> B;
+    std::unique_ptr<CgCore<double, double>> C;
+    std::unique_ptr<Cg1Core> C1;
+    // the same handle and mode; the stream and a lent pinned mirror may
+    // differ (the last solve synchronised its stream, so the workspace is idle)
+    bool matches(const spmv_matrix *A, int m, void *pn) const {
+        return serial == A->serial && mode == m && (pn == pinned || (pn && pinned));
     }
-    HIP_TRY(B.alloc(&C.sc, 2));
-    HIP_TRY(B.host_state(pinned, 2 * sizeof(CgState)));
-    C.hst = static_cast<CgState *>(B.host);
+    // the cores first: their graphs are destroyed before the buffers they use
+    void clear() {
+        C.reset();
+        C1.reset();
+        B.reset();
+        serial = 0;
+        mode = -1;
+    }
+};
+
+void cg_cache_free(CgCache *c) {
+    if (!c) return;
+    c->clear();
+    delete c;
+}
+
+size_t cg_cache_bytes(const CgCache *c) { return c && c->B ? c->B->bytes : 0; }
+
+// The workspace and core of a solve: the cached ones when the cache holds
+// this (matrix, mode, stream, pinned mirror), else new ones, which go into
+// the cache when there is one.
+template <typename Core, typename Make>
+static int acquire_core(CgCache *cache, std::unique_ptr<Core> CgCache::*slot, const spmv_matrix *A, int mode,
+                        hipStream_t s, void *pinned, std::unique_ptr<Buffers> &ownB, std::unique_ptr<Core> &ownC,
+                        Core *&core, Make &&make) {
+    if (cache && (cache->*slot) && cache->matches(A, mode, pinned)) {
+        core = (cache->*slot).get();
+        // this solve's stream and pinned mirror (the captured graph uses neither)
+        core->s = s;
+        cache->B->s = s;
+        cache->s = s;
+        if (pinned) {
+            cache->B->host = pinned;
+            cache->pinned = pinned;
+            core->hst = static_cast<CgState *>(pinned);
+        }
+        return SPMV_OK;
+    }
+    if (cache) cache->clear();
+    ownB.reset(new (std::nothrow) Buffers(s));
+    if (!ownB) return fail(SPMV_ENOMEM, "host allocation failed");
+    int rc = make(*ownB, ownC);
+    if (rc) return rc;
+    HIP_TRY(ownB->host_state(pinned, 2 * sizeof(CgState)));
+    ownC->hst = static_cast<CgState *>(ownB->host);
+    core = ownC.get();
+    if (cache) {
+        cache->serial = A->serial;
+        cache->mode = mode;
+        cache->s = s;
+        cache->pinned = pinned;
+        cache->B = std::move(ownB);
+        cache->*slot = std::move(ownC);
+    }
+    return SPMV_OK;
+}
+
+static int cg_fp64_body(CgCore<double, double> &C, const double *b, double *x, double tol, int max_iter,
+                        cg_info *info, hipStream_t s) {
+    const int n = C.n;
+    const double capture0 = C.capture_s;
+    // ||b||^2
     hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
     hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
     HIP_TRY(hipGetLastError());
-    rc = C.read_state();
+    int rc = C.read_state();
+    if (rc) return rc;
+    if (C.hst->bb == 0.0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (info) info->rel_residual = 0.0;
+        return SPMV_OK;
+    }
+    int iters = 0, repl = 0;
+    rc = C.solve(b, tol, max_iter, &iters, &repl);
+    if (rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) return rc;
+    int rc2;
+    HIP_TRY(C.true_residual(b));
+    if ((rc2 = C.read_state())) return rc2;
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, C.x);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->refinements = repl;
+        info->graph_seconds = C.capture_s - capture0;
+        info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
+    }
+    if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
+    if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (p.q <= 0 or not finite): matrix not SPD?");
+    return SPMV_OK;
+}
+
+static int cg_fp64(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter, cg_info *info,
+                   hipStream_t s, void *pinned, CgCache *cache) {
+    const DevMatrix &M = A->M;
+    std::unique_ptr<Buffers> ownB;
+    std::unique_ptr<CgCore<double, double>> ownC;
+    CgCore<double, double> *C = nullptr;
+    int rc = acquire_core(cache, &CgCache::C, A, CG_FP64, s, pinned, ownB, ownC, C,
+                          [&](Buffers &B, std::unique_ptr<CgCore<double, double>> &c) {
+                              c.reset(new (std::nothrow) CgCore<double, double>(M, M.val64, M.n_rows, s));
+                              if (!c) return fail(SPMV_ENOMEM, "host allocation failed");
+                              return alloc_core(B, *c);
+                          });
+    if (!rc) rc = cg_fp64_body(*C, b, x, tol, max_iter, info, s);
+    // a solve that failed on the device leaves its workspace in no known state
+    if (cache && rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) cache->clear();
+    return rc;
+}
+
+static int cg1_body(Cg1Core &C, const double *b, double *x, double tol, int max_iter, cg_info *info,
+                    hipStream_t s) {
+    const int n = C.n;
+    const double capture0 = C.capture_s;
+    hipLaunchKernelGGL((k_dot_part<double>), dim3(C.n_wg), dim3(kBlock), 0, s, n, C.chunk, b, b, C.part_vec);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, C.part_vec, C.n_wg, C.st, (int)R_BB);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, C.x, x);
+    HIP_TRY(hipGetLastError());
+    int rc = C.read_state();
     if (rc) return rc;
     if (C.hst->bb == 0.0) {
         hipLaunchKernelGGL((k_zero<double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
@@ -1535,12 +1601,46 @@ static int cg_fp64_one_reduction(const spmv_matrix *A, const double *b, double *
     if (info) {
         info->iterations = iters;
         info->refinements = restarts;
-        info->graph_seconds = C.capture_s;
+        info->graph_seconds = C.capture_s - capture0;
         info->rel_residual = std::sqrt(C.hst->rt2 / C.hst->bb);
     }
     if (rc == SPMV_ENOTCONV) return fail(rc, "CG did not reach tol = %g within %d iterations", tol, max_iter);
     if (rc == SPMV_EBREAK) return fail(rc, "CG breakdown (w.r - beta r.r / alpha <= 0 or not finite): matrix not SPD?");
     return SPMV_OK;
+}
+
+static int cg_fp64_one_reduction(const spmv_matrix *A, const double *b, double *x, double tol, int max_iter,
+                                 cg_info *info, hipStream_t s, void *pinned, CgCache *cache) {
+    const DevMatrix &M = A->M;
+    if (!cg1_eligible(M))
+        return fail(SPMV_ENOTSUP,
+                    "one-reduction CG needs a CSR handle of plain row tiles (no windows, no row longer than a "
+                    "tile) with at most %d tiles (this one: %d plain tiles, %d window tiles, %d ring blocks, %d long "
+                    "rows)",
+                    kCg1MaxTiles, M.n_stream, M.n_cwin, M.n_blk, M.n_long);
+    const int n = M.n_rows;
+    std::unique_ptr<Buffers> ownB;
+    std::unique_ptr<Cg1Core> ownC;
+    Cg1Core *C = nullptr;
+    int rc = acquire_core(cache, &CgCache::C1, A, CG_FP64_ONE_REDUCTION, s, pinned, ownB, ownC, C,
+                          [&](Buffers &B, std::unique_ptr<Cg1Core> &c) {
+                              c.reset(new (std::nothrow) Cg1Core(M, n, s));
+                              if (!c) return fail(SPMV_ENOMEM, "host allocation failed");
+                              int r = alloc_core(B, *c);
+                              if (r) return r;
+                              HIP_TRY(B.alloc(&c->r2, (size_t)n));
+                              for (int k = 0; k < 2; ++k) {
+                                  HIP_TRY(B.alloc(&c->w[k], (size_t)n));
+                                  HIP_TRY(B.alloc(&c->sv[k], (size_t)n));
+                                  HIP_TRY(B.alloc(&c->gam[k], (size_t)M.n_seg));
+                                  HIP_TRY(B.alloc(&c->del[k], (size_t)M.n_seg));
+                              }
+                              HIP_TRY(B.alloc(&c->sc, 2));
+                              return (int)SPMV_OK;
+                          });
+    if (!rc) rc = cg1_body(*C, b, x, tol, max_iter, info, s);
+    if (cache && rc != SPMV_OK && rc != SPMV_ENOTCONV && rc != SPMV_EBREAK) cache->clear();
+    return rc;
 }
 
 // ------------------------------------------------- allocation-free FP64 CG
@@ -1757,7 +1857,7 @@ static int cg_pcg(const spmv_matrix *A, const double *b, double *x, double tol, 
 }
 
 int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t max_iter, int32_t mode,
-           cg_info *info, hipStream_t s, void *pinned_state) {
+           cg_info *info, hipStream_t s, void *pinned_state, CgCache **cache) {
     auto t0 = std::chrono::steady_clock::now();
     if (info) std::memset(info, 0, sizeof *info);
     if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
@@ -1791,10 +1891,15 @@ int cg_run(const spmv_matrix *A, const double *b, double *x, double tol, int32_t
         }
     }
     int rc;
+    CgCache *cc = nullptr;
+    if (cache && (mode == CG_FP64 || mode == CG_FP64_ONE_REDUCTION)) {
+        if (!*cache) *cache = new (std::nothrow) CgCache();
+        cc = *cache;
+    }
     if (mode == CG_FP64) {
-        rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state);
+        rc = cg_fp64(A, b, x, tol, max_iter, info, s, pinned_state, cc);
     } else if (mode == CG_FP64_ONE_REDUCTION) {
-        rc = cg_fp64_one_reduction(A, b, x, tol, max_iter, info, s, pinned_state);
+        rc = cg_fp64_one_reduction(A, b, x, tol, max_iter, info, s, pinned_state, cc);
     } else if (mode == CG_PCG_BF16 || mode == CG_PCG_JACOBI) {
         rc = cg_pcg(A, b, x, tol, max_iter, info, s, pinned_state, mode == CG_PCG_JACOBI);
     } else {

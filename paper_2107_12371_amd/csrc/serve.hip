@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <mutex>
 #include <set>
 #include <thread>
@@ -523,6 +524,7 @@ struct Slot {
     void *pinned = nullptr;
     PhaseEvents pe;
     Request *job = nullptr;
+    CgCache *cache = nullptr;  // the solver checked out for the running solve
 };
 
 // An SpMV lane: a worker thread with its own stream that runs one round at a
@@ -590,6 +592,63 @@ struct Server {
     bool any_submit = false;
     hipEvent_t ref_event = nullptr;  // zero of the device clock the requests' intervals are read on
     Persist P;
+    // Solvers (device workspace + captured iteration graph of an FP64 solve)
+    // kept per matrix handle, by its serial, for the next solve on it from
+    // any slot: checked out while a solve runs, least recently used dropped
+    // beyond solver_cap bytes, dropped with their matrix.  Under `mu`.
+    struct SolverEntry {
+        CgCache *c;
+        uint64_t bytes;
+        std::list<uint64_t>::iterator lru;
+    };
+    std::unordered_map<uint64_t, SolverEntry> solvers;
+    std::list<uint64_t> solver_lru;  // front: most recently checked in
+    uint64_t solver_bytes = 0, solver_cap = 0;
+    int64_t solver_hits = 0, solver_solves = 0;
+
+    CgCache *checkout_solver_locked(uint64_t serial) {
+        auto it = solvers.find(serial);
+        if (it == solvers.end()) return nullptr;
+        CgCache *c = it->second.c;
+        solver_bytes -= it->second.bytes;
+        solver_lru.erase(it->second.lru);
+        solvers.erase(it);
+        ++solver_hits;
+        return c;
+    }
+
+    // Returns the solvers to free (outside the lock: freeing takes the
+    // capture gate).
+    std::vector<CgCache *> checkin_solver_locked(uint64_t serial, CgCache *c) {
+        std::vector<CgCache *> out;
+        if (!c) return out;
+        const uint64_t b = cg_cache_bytes(c);
+        if (b == 0 || b > solver_cap || solvers.count(serial)) {
+            out.push_back(c);  // empty, too large, or another slot's solver is already kept
+            return out;
+        }
+        solver_lru.push_front(serial);
+        solvers[serial] = SolverEntry{c, b, solver_lru.begin()};
+        solver_bytes += b;
+        while (solver_bytes > solver_cap && !solver_lru.empty()) {
+            const uint64_t victim = solver_lru.back();
+            auto it = solvers.find(victim);
+            solver_bytes -= it->second.bytes;
+            out.push_back(it->second.c);
+            solver_lru.pop_back();
+            solvers.erase(it);
+        }
+        return out;
+    }
+
+    void drop_solver_locked(uint64_t serial, std::vector<CgCache *> &out) {
+        auto it = solvers.find(serial);
+        if (it == solvers.end()) return;
+        solver_bytes -= it->second.bytes;
+        solver_lru.erase(it->second.lru);
+        out.push_back(it->second.c);
+        solvers.erase(it);
+    }
 
     explicit Server(const srv_config &c) : cfg(c), policy(c.hbm_budget_bytes) {}
 
@@ -944,7 +1003,16 @@ struct Server {
                 rc = hip_fail(e, "server solve buffers");
             } else {
                 sl.pe.mark(1, sl.stream);
-                rc = cg_run(A, db, dx, r->tol, r->max_iter, cfg.cg_mode, &info, sl.stream, sl.pinned);
+                // FP64 solves of small matrices take one reduction per iteration
+                const int mode = cfg.cg_mode == CG_FP64 && n <= cfg.cg1_max_rows && cg1_eligible(A->M)
+                                     ? CG_FP64_ONE_REDUCTION
+                                     : cfg.cg_mode;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    sl.cache = checkout_solver_locked(A->serial);
+                    ++solver_solves;
+                }
+                rc = cg_run(A, db, dx, r->tol, r->max_iter, mode, &info, sl.stream, sl.pinned, &sl.cache);
                 sl.pe.mark(2, sl.stream);
                 if (rc == SPMV_OK || rc == SPMV_ENOTCONV) {
                     e = hipMemcpyAsync(r->out, dx, 8 * (size_t)n, hipMemcpyDeviceToHost, sl.stream);
@@ -957,15 +1025,24 @@ struct Server {
             if (db) (void)hipFreeAsync(db, sl.stream);
             if (dx) (void)hipFreeAsync(dx, sl.stream);
             (void)hipStreamSynchronize(sl.stream);
-            std::lock_guard<std::mutex> lk(mu);
-            r->t_run = t_run;
-            r->graph_s = info.graph_seconds;
-            r->iterations = info.iterations;
-            r->rel_residual = info.rel_residual;
-            policy.release(r->mid, r->extra);
-            sl.job = nullptr;
-            finish_locked(r, rc);
-            cv_sched.notify_all();
+            std::vector<CgCache *> to_free;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                // the solver goes back before the matrix's pin is released,
+                // so an eviction of the matrix finds it
+                if (A) to_free = checkin_solver_locked(A->serial, sl.cache);
+                else if (sl.cache) to_free.push_back(sl.cache);
+                sl.cache = nullptr;
+                r->t_run = t_run;
+                r->graph_s = info.graph_seconds;
+                r->iterations = info.iterations;
+                r->rel_residual = info.rel_residual;
+                policy.release(r->mid, r->extra);
+                sl.job = nullptr;
+                finish_locked(r, rc);
+                cv_sched.notify_all();
+            }
+            for (CgCache *c : to_free) cg_cache_free(c);
         }
     }
 
@@ -980,6 +1057,7 @@ struct Server {
         std::vector<int> evict;
         for (;;) {
             std::vector<spmv_matrix *> evicted;
+            std::vector<CgCache *> dropped;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_sched.wait_for(lk, std::chrono::microseconds(500), [&] { return stop || wake; });
@@ -1013,7 +1091,10 @@ struct Server {
                     }
                     if (v == BudgetLRU::WAIT) { ++it; continue; }
                     for (int m : evict) {  // idle and resident: never uploading
-                        if (mats[m].dev) evicted.push_back(mats[m].dev);
+                        if (mats[m].dev) {
+                            drop_solver_locked(mats[m].dev->serial, dropped);
+                            evicted.push_back(mats[m].dev);
+                        }
                         mats[m].dev = nullptr;
                     }
                     MatrixEntry &m = mats[r->mid];
@@ -1061,6 +1142,7 @@ struct Server {
                     cv_lane.notify_all();
                 }
             }
+            for (CgCache *c : dropped) cg_cache_free(c);
             for (spmv_matrix *d : evicted) (void)spmv_destroy(d);
         }
     }
@@ -1144,12 +1226,14 @@ extern "C" int srv_create(const srv_config *cfg_in, spmv_server **out) {
     if (cfg.n_lanes <= 0) cfg.n_lanes = 4;
     if (cfg.n_lanes > 16) return fail(SPMV_EINVAL, "n_lanes = %d exceeds 16", cfg.n_lanes);
     if (cfg.cg_mode != CG_FP64 && cfg.cg_mode != CG_MIXED_FP32) return fail(SPMV_EINVAL, "unknown cg_mode");
+    if (cfg.cg1_max_rows < 0) return fail(SPMV_EINVAL, "cg1_max_rows must be >= 0");
     if (cfg.persistent_wgs < 0 || cfg.persist_idle_us < 0)
         return fail(SPMV_EINVAL, "persistent_wgs and persist_idle_us must be >= 0");
     if (cfg.persist_idle_us == 0) cfg.persist_idle_us = 20000;
     if (cfg.persist_idle_us > 10000000) return fail(SPMV_EINVAL, "persist_idle_us = %d exceeds 10 s", cfg.persist_idle_us);
     auto *S = new (std::nothrow) Server(cfg);
     if (!S) return fail(SPMV_ENOMEM, "host allocation failed");
+    S->solver_cap = cfg.hbm_budget_bytes / 16;
     hipError_t e = hipGetDevice(&S->device);
     if (e != hipSuccess) {
         delete S;
@@ -1342,6 +1426,8 @@ extern "C" int srv_get_stats(spmv_server *srv, srv_stats *st) {
     st->rounds = S->rounds;
     st->uploads = S->policy.uploads();
     st->persist_launches = S->P.launches;
+    st->solver_reuses = S->solver_hits;
+    st->solver_cached_bytes = (int64_t)S->solver_bytes;
     st->evictions = S->policy.evictions();
     st->used_bytes = (int64_t)S->policy.used();
     st->peak_bytes = (int64_t)S->policy.peak();
@@ -1380,6 +1466,13 @@ extern "C" int srv_destroy(spmv_server *srv) {
         if (sl.th.joinable()) sl.th.join();
     for (auto &ln : S->lanes)
         if (ln.th.joinable()) ln.th.join();
+    for (auto &kv : S->solvers) cg_cache_free(kv.second.c);  // before the gate: freeing a graph takes it
+    S->solvers.clear();
+    S->solver_lru.clear();
+    for (auto &sl : S->slots) {
+        cg_cache_free(sl.cache);
+        sl.cache = nullptr;
+    }
     for (auto &m : S->mats)
         if (m.dev) (void)spmv_destroy(m.dev);
     std::lock_guard<std::mutex> gate(capture_gate());

@@ -268,3 +268,60 @@ def test_cg_solves_and_spmv_rounds_overlap_on_the_device(pool):
         spans[r[0]].append((res.dev_begin_s, res.dev_end_s))
     overlap = any(c0 < s1 and s0 < c1 for c0, c1 in spans["cg"] for s0, s1 in spans["spmv"])
     assert overlap, (spans["cg"], spans["spmv"][:8])
+
+
+def test_solvers_are_kept_per_matrix_and_small_matrices_take_one_reduction(pool):
+    # the server keeps each matrix's FP64 solver (workspace and captured
+    # graph): a later solve on the same matrix captures nothing and gives the
+    # same bits as a direct cg_solve; with cg1_max_rows covering the matrix
+    # it solves with one reduction per iteration, bitwise as the direct
+    # CG_FP64_ONE_REDUCTION solve on a handle with the server's plan
+    A = pool[2]
+    b = mg.uniform(A.n_rows, 21, 4)
+    params = {"tile_nnz": 1024, "kernel": 1, "window_mode": spmv.WINDOW_OFF}
+    with spmv.Matrix.from_csr(A, params=params) as M:
+        bd = torch.as_tensor(b, device="cuda")
+        x_hs, _ = M.cg(bd, tol=1e-8)
+        x_1r, _ = M.cg(bd, tol=1e-8, mode=spmv.CG_FP64_ONE_REDUCTION)
+    x_hs, x_1r = x_hs.cpu().numpy(), x_1r.cpu().numpy()
+    assert not np.array_equal(x_hs, x_1r)   # the two methods round differently
+    other = mg.uniform(pool[1].n_rows, 22, 4)
+    for cg1_rows, want in ((0, x_hs), (A.n_rows, x_1r)):
+        with spmv.Server(n_slots=1, cg1_max_rows=cg1_rows, preload=True) as srv:
+            for M_ in pool[:4]:
+                srv.add_matrix(M_)
+            srv.drain()
+            outs = []
+            for mid in (2, 2, 1, 2):
+                rhs = b if mid == 2 else other
+                out, res = srv.wait(srv.submit_cg(mid, rhs, tol=1e-8))
+                _check(pool, ("cg", mid, rhs), out, res)
+                outs.append((mid, out.copy(), res.graph_s))
+            st = srv.stats()
+        assert outs[0][2] > 0 and outs[1][2] == 0 and outs[2][2] > 0 and outs[3][2] == 0
+        assert st["solver_reuses"] == 2 and st["solver_cached_bytes"] > 0
+        for mid, out, _ in outs:
+            if mid == 2:
+                assert np.array_equal(out, want)
+
+
+def test_kept_solvers_follow_their_matrices_out(pool):
+    # under a budget that forces evictions, CG requests cycling over four
+    # matrices: a kept solver is dropped with its evicted matrix and never
+    # used for the matrix uploaded again later (results stay the oracle's)
+    small = pool[:4]
+    est = lambda A: 12 * (A.nnz + 20) + 4 * (A.n_rows + 1) + 64 * (A.nnz // 512 + 16)
+    cg_bytes = lambda A: 56 * A.n_rows + 8 * (A.nnz // 1000 + 4096)  # b, x and the workspace
+    # room for the largest matrix and one solve on it, not for all four
+    budget = int(1.1 * est(small[3]) + cg_bytes(small[3]) + (200 << 10))
+    assert sum(est(A) for A in small) + cg_bytes(small[3]) > budget
+    reqs = [("cg", i % 4, mg.uniform(small[i % 4].n_rows, 300 + i, 4)) for i in range(12)]
+    with spmv.Server(hbm_budget_bytes=budget, n_slots=1, cg1_max_rows=20000) as srv:
+        for A in small:
+            srv.add_matrix(A)
+        for r in reqs:
+            out, res = srv.wait(_submit(srv, r))
+            _check(small, r, out, res)
+        st = srv.stats()
+    assert st["evictions"] > 0 and st["failed"] == 0
+    assert st["solver_cached_bytes"] <= budget // 16
