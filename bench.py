@@ -234,7 +234,7 @@ def serving_pool(pool_size: int, seed: int, log=log):
 
 
 def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = False, persistent_wgs: int = 0,
-                rate: float = 0.0, log=log):
+                rate: float = 0.0, budget: int = 200 << 30, log=log):
     """Request stream over `pool`: each request picks a matrix uniformly and
     asks for k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is
     uploaded on its first request (that request pays for it), or, with
@@ -246,7 +246,9 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     persistent_wgs > 0 the SpMV rounds go to the persistent multi-matrix
     kernel of that many workgroups instead of one launch each.  rate > 0
     sets the arrival rate (requests/s) instead of 0.7x the capacity, so that
-    two runs can be compared at the same load."""
+    two runs can be compared at the same load.  `budget` caps resident
+    matrices + request buffers (a small one forces evictions, and requests
+    that could never fit fail with SPMV_EBUDGET)."""
     import threading
 
     import paper_2107_12371_amd as spmv
@@ -264,7 +266,7 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     # the pool fits the budget, so matrices stay resident once uploaded
     # FP64 solves of matrices up to 200,000 rows take one reduction per
     # iteration (measured faster per iteration there, slower above)
-    srv = spmv.Server(hbm_budget_bytes=200 << 30, n_slots=8, cg_mode=cg_mode, preload=preload,
+    srv = spmv.Server(hbm_budget_bytes=budget, n_slots=8, cg_mode=cg_mode, preload=preload,
                       persistent_wgs=persistent_wgs, cg1_max_rows=CG1_MAX_ROWS)
     t0 = time.perf_counter()
     for A in pool:
@@ -307,8 +309,10 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     th.join()
     phases = {"cg": {k: [] for k in SERVE_PHASES}, "spmv": {k: [] for k in SERVE_PHASES}}
     iters, fails, errors, n_ok = [], 0, {}, 0
-    for r, t in zip(reqs, tickets):
+    for i, (r, t) in enumerate(zip(reqs, tickets)):
         _, res = srv.wait(t)
+        if i % 512 == 511:
+            log(f"serving: {i + 1} of {n_requests} requests done")
         if res.status != 0:
             fails += 1
             key = f"status {res.status}: {res.message}"
@@ -330,6 +334,7 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
 
     lat_all = phases["cg"]["latency_s"] + phases["spmv"]["latency_s"]
     out = {"requests": n_requests, "pool": pool_size, "pool_rows": int(sum(A.n_rows for A in pool)),
+           "budget_bytes": budget,
            "arrival_rate_rps": round(lam, 2), "closed_loop_capacity_rps": round(cap, 2),
            "cg_mode": "mixed" if cg_mode else f"fp64 (one reduction per iteration up to {CG1_MAX_ROWS:,} rows)",
            "preload": preload,
@@ -648,6 +653,12 @@ def main():
             rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else 0.0
             out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
                                     persistent_wgs=pw, rate=rate)
+        if not args.serve_preload:
+            # budget exhaustion: 192 requests over the pool's first 128
+            # matrices (2.6 GB) under 1 GiB, so matrices are evicted and
+            # uploaded again, and the largest SpMV requests (up to 64 x 2 x 10^6
+            # words) can never fit
+            out["budget_1GiB"] = serving_run(pool[:128], 192, mg.seed_for(4) + 1, spmv.CG_FP64, budget=1 << 30)
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -819,6 +830,7 @@ def main():
         extras["serving_preloaded"] = sv.get("preloaded", sv)
         if args.serve_persistent > 0:
             extras["serving_preloaded_persistent"] = sv.get("preloaded_persistent", sv)
+        extras["serving_budget_1GiB"] = sv.get("budget_1GiB", sv)
 
     cpu = None
     if not args.no_cpu:

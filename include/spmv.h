@@ -359,7 +359,9 @@ int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double to
  * Requests (k SpMVs, or a CG solve) are submitted at any time from any
  * thread; a scheduler thread admits them as device memory and solver slots
  * free up, uploading a registered matrix on first use and evicting the least
- * recently used idle matrices to stay within hbm_budget_bytes.  Admitted SpMV
+ * recently used idle matrices to stay within hbm_budget_bytes (a request
+ * that has waited 50 ms for memory is admitted before any younger one, so
+ * small requests cannot starve a large one).  Admitted SpMV
  * requests join the next round, in which one multi-matrix kernel launch
  * covers all of the round's vectors, or, with persistent_wgs > 0, the round
  * is queued to one long-lived multi-matrix kernel that works the tiles of

@@ -559,6 +559,11 @@ struct Persist {
     int64_t launches = 0;
 };
 
+// A request that has waited this long for device memory holds back every
+// younger one (none is admitted before it), so a request that fits only in
+// a nearly empty budget is not starved by a stream of small ones.
+constexpr auto kStarveAfter = std::chrono::milliseconds(50);
+
 // Requests moving at least this many vector words between host and device
 // get rounds of their own.
 constexpr int64_t kLargeRequestWords = int64_t(1) << 22;
@@ -1068,12 +1073,25 @@ struct Server {
                     incoming.pop_front();
                 }
                 // admission: reserve memory (evicting idle matrices), start
-                // uploads, give each CG request a slot
+                // uploads, give each CG request a slot; in arrival order,
+                // younger requests passing one that waits for memory until it
+                // has waited kStarveAfter
+                const Clock::time_point now = Clock::now();
+                bool held = false;
                 for (auto it = pending.begin(); it != pending.end();) {
                     Request *r = *it;
                     if (dev_err != hipSuccess) {  // this thread cannot reach the device
                         it = pending.erase(it);
                         finish_locked(r, hip_fail(dev_err, "server scheduler thread: hipSetDevice"));
+                        continue;
+                    }
+                    if (held) {
+                        if (policy.never(r->mid, r->extra)) {
+                            it = pending.erase(it);
+                            finish_locked(r, fail(SPMV_EBUDGET, "request needs more than the device budget"));
+                        } else {
+                            ++it;
+                        }
                         continue;
                     }
                     int slot = -1;
@@ -1089,7 +1107,11 @@ struct Server {
                         finish_locked(r, fail(SPMV_EBUDGET, "request needs more than the device budget"));
                         continue;
                     }
-                    if (v == BudgetLRU::WAIT) { ++it; continue; }
+                    if (v == BudgetLRU::WAIT) {
+                        held = now - r->t_submit > kStarveAfter;
+                        ++it;
+                        continue;
+                    }
                     for (int m : evict) {  // idle and resident: never uploading
                         if (mats[m].dev) {
                             drop_solver_locked(mats[m].dev->serial, dropped);

@@ -63,6 +63,9 @@ class BudgetLRU {
         return ADMIT;
     }
 
+    // True when a request on matrix i with `extra` bytes could never fit.
+    bool never(int i, uint64_t extra) const { return m_[i].bytes + extra > budget_; }
+
     // Uploads matrix i ahead of any request if it fits in the free budget
     // without evicting anything; returns whether it was made resident.
     bool preload(int i) {

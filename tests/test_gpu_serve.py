@@ -325,3 +325,43 @@ def test_kept_solvers_follow_their_matrices_out(pool):
         st = srv.stats()
     assert st["evictions"] > 0 and st["failed"] == 0
     assert st["solver_cached_bytes"] <= budget // 16
+
+
+def test_a_large_request_is_not_starved_by_small_ones(pool):
+    # the budget holds the 150K-row matrix and a 16-vector request on it only
+    # when the 30K-row matrix is not pinned by a request in flight.  CG solves
+    # on the 30K-row matrix arrive every 0.5 ms for 1 s on four slots, so
+    # their lifetimes overlap and the matrix stays pinned; a large request
+    # that arrived among them is admitted only because, after 50 ms of
+    # waiting, younger requests are no longer admitted before it (without
+    # that rule it waits for the whole stream)
+    import time
+    big, small = pool[-1], pool[3]
+    est = lambda A: 12 * (A.nnz + 20) + 4 * (A.n_rows + 1) + 64 * (A.nnz // 512 + 16)
+    k = 16
+    big_extra = 8 * k * (big.n_rows + big.n_cols)
+    small_need = est(small) + 56 * small.n_rows
+    budget = int(1.05 * est(big) + big_extra + (1 << 20))
+    assert est(big) + big_extra + small_need > budget   # not both at once
+    X = mg.uniform(k * big.n_cols, 77, 3).reshape(k, big.n_cols)
+    b = mg.uniform(small.n_rows, 78, 4)
+    with spmv.Server(hbm_budget_bytes=budget, n_slots=4) as srv:
+        for M in pool:
+            srv.add_matrix(M)
+        tickets = [srv.submit_cg(3, b, tol=1e-8) for _ in range(8)]
+        t_big = srv.submit_spmv(len(pool) - 1, X)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 1.0:
+            tickets.append(srv.submit_cg(3, b, tol=1e-8))
+            time.sleep(0.0005)
+        out, res = srv.wait(t_big)
+        _ok(res)
+        outs = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert res.latency_s < 0.4, res.latency_s   # admitted while the stream still ran
+    assert st["evictions"] > 0 and st["peak_bytes"] <= budget
+    for j in range(0, k, 5):
+        y_ref, bound = oracle.spmv(big, X[j])
+        assert oracle.spmv_accept(out[j], y_ref, bound).all()
+    for x, rs in outs[::100]:
+        _check(pool, ("cg", 3, b), x, rs)
