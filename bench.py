@@ -202,6 +202,14 @@ def cpu_baseline(A, x, budget_s: float):
     threads = oracle.all_cores_threads()
     repsn, pern = timed(lambda: oracle.spmv_all_cores(A, x), 400)
     cpu = _cpu_model()
+    # the oracle's CG (single-threaded, as it stands) per iteration on the
+    # same matrix: 3 iterations minus 1, so the setup (b.b, r = b - A x0) cancels
+    t0 = time.perf_counter()
+    oracle.cg(A, x, tol=0.0, max_iter=1)
+    t1 = time.perf_counter()
+    oracle.cg(A, x, tol=0.0, max_iter=3)
+    t2 = time.perf_counter()
+    cg_it = max((t2 - t1) - (t1 - t0), 0.0) / 2
     return {"value": round(B / pern / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"{repsn} full FP64 SpMVs of the same 16M-row matrix with the oracle's OpenMP timing build "
                       f"(rows split statically over {threads} threads, each row summed as in the checker), "
@@ -210,6 +218,7 @@ def cpu_baseline(A, x, budget_s: float):
                               "ms_per_spmv": round(per1 * 1e3, 2),
                               "sample": f"{reps1} full FP64 SpMVs with the single-threaded checker build"},
             "ms_per_spmv": round(pern * 1e3, 2), "cpu_model": cpu,
+            "cg_ms_per_iteration_single_thread": round(cg_it * 1e3, 1),
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS", "unset")}
 
 

@@ -785,8 +785,12 @@ struct Server {
         int rc;
         {
             std::unique_lock<std::mutex> lk(P.mu);
-            // the slot's previous round (P.next - kRing) must be complete
-            P.cv.wait(lk, [&] { return P.open.empty() || *P.open.begin() + kRing > P.next; });
+            // the slot's previous round (P.next - kRing) must be complete; a
+            // round that never completed (its lane reported the error) keeps
+            // its slot, so the wait is bounded
+            if (!P.cv.wait_for(lk, std::chrono::seconds(120),
+                               [&] { return P.open.empty() || *P.open.begin() + kRing > P.next; }))
+                return fail(SPMV_EDEVICE, "persistent kernel: queue slot not free in 120 s");
             seq = P.next;
             PersistEntry &en = P.q->ring[seq % kRing];
             // about two claims per worker on a large round (each chunk ends
