@@ -494,6 +494,8 @@ def config_lines(torch, log=log) -> dict:
                     "GBs_cold_p50": round(B / c50 / 1e9, 1), "cg_1e-10": cg,
                     "paper_fpga_cached_s": paper.get(name)}
     del scratch
+    t1["paper_fpga_board"] = ("Xilinx ADM-PCIE-7V3 (two DDR3 channels at 1333 MT/s), 4 cached IPs, Table 2; "
+                              "time units not stated, read as seconds; context, not a target")
     out["table1_sizes_tet_like"] = t1
     log(f"Table 1 sizes: {t1}")
     return out
