@@ -243,7 +243,7 @@ def serving_pool(pool_size: int, seed: int, log=log):
 
 
 def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = False, persistent_wgs: int = 0,
-                rate: float = 0.0, budget: int = 200 << 30, log=log):
+                rate: float = 0.0, budget: int = 200 << 30, lanes: int = 0, log=log):
     """Request stream over `pool`: each request picks a matrix uniformly and
     asks for k ~ U{1..64} SpMVs or a CG solve to 1e-8 (50/50).  A matrix is
     uploaded on its first request (that request pays for it), or, with
@@ -276,7 +276,7 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     # FP64 solves of matrices up to 200,000 rows take one reduction per
     # iteration (measured faster per iteration there, slower above)
     srv = spmv.Server(hbm_budget_bytes=budget, n_slots=8, cg_mode=cg_mode, preload=preload,
-                      persistent_wgs=persistent_wgs, cg1_max_rows=CG1_MAX_ROWS)
+                      persistent_wgs=persistent_wgs, cg1_max_rows=CG1_MAX_ROWS, n_lanes=lanes)
     t0 = time.perf_counter()
     for A in pool:
         srv.add_matrix(A)
@@ -632,6 +632,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096, help="requests in the serving stream")
     ap.add_argument("--serve-pool", type=int, default=1024, help="matrices in the serving pool")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-lanes", type=int, default=0, help="SpMV lanes of the server (0: its default, 4)")
     ap.add_argument("--serve-persistent", type=int, default=256,
                     help="workgroups of the persistent multi-matrix kernel in the third serving stream "
                          "(0: no such stream)")
@@ -663,7 +664,7 @@ def main():
             # the persistent stream arrives at the preloaded stream's rate
             rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else 0.0
             out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
-                                    persistent_wgs=pw, rate=rate)
+                                    persistent_wgs=pw, rate=rate, lanes=args.serve_lanes)
         if not args.serve_preload:
             # budget exhaustion: 192 requests over the pool's first 128
             # matrices (2.6 GB) under 1 GiB, so matrices are evicted and

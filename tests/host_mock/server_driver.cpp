@@ -76,7 +76,13 @@ int main(int argc, char **argv) {
             const int mid = (int)(rng() % (rep % 4 == 3 ? 4 : kCopies * pool.size()));
             const int n = pool[mid % pool.size()].n;
             int rc;
-            if (rng() % 2) {
+            if (t % 12 == 5) {
+                // a large request: 16 vectors on the 150,000-row matrix
+                const int k = 16, nb = pool[5].n;
+                in[t].assign((size_t)k * nb, 1.0);
+                out[t].assign((size_t)k * nb, 0.0);
+                rc = srv_submit(S, 5, SRV_SPMV, k, in[t].data(), out[t].data(), 0.0, 0, &ticket[t]);
+            } else if (rng() % 2) {
                 const int k = 1 + (int)(rng() % 8);
                 in[t].assign((size_t)k * n, 1.0);
                 out[t].assign((size_t)k * n, 0.0);
