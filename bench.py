@@ -387,6 +387,36 @@ def serving_in_child(args) -> dict:
     return json.loads(lines[-1]) if lines else {"failed": "no summary from the child"}
 
 
+def long_rows_matrix():
+    """The 126^3 kNN matrix (RCM) with 16 rows replaced by rows of 2^20
+    entries each (16.8 M more stored entries): a few very long rows."""
+    import meshgen as mg
+    return mg.with_long_rows(mg.config1("rcm"), 16, 1 << 20, mg.seed_for(1) + 16)
+
+
+def long_row_line(torch, base_ms: float) -> dict:
+    """The long-rows matrix: one workgroup per long row (spmv_apply) against
+    one workgroup per 16,384-entry piece and a combine launch
+    (spmv_apply_ws), same bits; the kNN matrix alone beside them."""
+    import meshgen as mg
+    import paper_2107_12371_amd as spmv
+    A = long_rows_matrix()
+    x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+    B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+    with spmv.Matrix.from_csr(A) as M:
+        ws = torch.empty(max(M.workspace_bytes // 8, 1), dtype=torch.float64, device="cuda")
+        t1 = time_launches(lambda: M.apply(x, y), 20, 3, torch, WARM_S)
+        y1 = y.clone()
+        t2 = time_launches(lambda: M.apply_ws(x, y, ws=ws), 100, 5, torch, WARM_S)
+        same = bool(torch.equal(y, y1))
+        inf = M.info
+    return {"rows": A.n_rows, "nnz": A.nnz, "long_rows": inf["n_long_rows"], "pieces": inf["n_long_pieces"],
+            "one_workgroup_per_row_ms": round(t1 * 1e3, 4), "pieces_ms": round(t2 * 1e3, 4),
+            "GBs_pieces": round(B / t2 / 1e9, 1), "speedup": round(t1 / t2, 2), "same_bits": same,
+            "knn_alone_ms": base_ms}
+
+
 def config_lines(torch, log=log) -> dict:
     """Per-configuration lines besides the headline (outside the timed region):
     the 32^3 mesh with the LDS ring window vs direct gathers, the 126^3 kNN
@@ -440,6 +470,8 @@ def config_lines(torch, log=log) -> dict:
     out["knn126_2M_rows_100_spmv"] = c1
     del scratch
     log(f"126^3 kNN: {c1}")
+    out["knn126_with_16_rows_of_1M"] = long_row_line(torch, c1["rcm"]["ms"])
+    log(f"long rows: {out['knn126_with_16_rows_of_1M']}")
     A = mg.config3()
     c3 = {"block_rows": A.n_rows, "blocks": A.nnz}
     with spmv.Matrix.from_csr(A, fp32=True) as M:
@@ -503,7 +535,7 @@ def config_lines(torch, log=log) -> dict:
 
 CASES = ("bsr3_k1_fp64", "bsr3_k8_fp64", "bsr3_k1_fp32", "bsr3_k8_fp32", "bsr3_k4_fp64", "bsr3_k4_fp32",
          "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k", "cg1_fp64_c50k",
-         "cg1_fp64_c800k", "cg_fp64_c800k")
+         "cg1_fp64_c800k", "cg_fp64_c800k", "long_rows_one_wg", "long_rows_pieces")
 
 
 def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibration: bool) -> list[dict]:
@@ -520,7 +552,11 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       cg_fp64_16m   48 FP64 CG iterations on the same matrix (per step)
       cg_fp64_c50k  FP64 CG to 1e-10 on the 49,336-row tet-like stand-in (per step)
       cg1_fp64_c50k the same with one reduction per iteration (one launch each)
-      cg_fp64_c800k, cg1_fp64_c800k  both on the 775,058-row stand-in"""
+      cg_fp64_c800k, cg1_fp64_c800k  both on the 775,058-row stand-in
+      long_rows_one_wg  the 126^3 kNN matrix with 16 rows of 2^20 entries,
+                  one workgroup per long row (spmv_apply)
+      long_rows_pieces  the same, one workgroup per 16,384-entry piece
+                  (spmv_apply_ws)"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -565,6 +601,21 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
             out["iterations"] = info.iterations
             out["us_per_iteration"] = round(t * 1e6 / max(info.iterations, 1), 2)
             out["alg_bytes"] = 0
+        elif name.startswith("long_rows"):
+            if "long" not in mats:
+                mats["long"] = long_rows_matrix()
+            A = mats["long"]
+            x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+            y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+            with spmv.Matrix.from_csr(A) as M:
+                ws = torch.empty(max(M.workspace_bytes // 8, 1), dtype=torch.float64, device="cuda")
+                if name.endswith("pieces"):
+                    t = time_launches(lambda: M.apply_ws(x, y, ws=ws), steps, warmup, torch)
+                else:
+                    t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
+                out["info"] = {k: M.info[k] for k in ("n_long_rows", "n_long_pieces")}
+            out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+            del x, y, ws
         elif name == "copy":
             buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(buf)

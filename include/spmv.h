@@ -156,6 +156,8 @@ typedef struct spmv_info {
     int32_t format;         /* SPMV_FORMAT_* of a scalar handle */
     int32_t n_slices;       /* SELL: slices of 64 rows */
     int64_t sell_entries;   /* SELL: stored slots including padding (long rows excluded) */
+    int32_t n_long_pieces;  /* pieces of 16,384 stored entries over the long rows */
+    int64_t workspace_bytes; /* spmv_workspace_bytes of the handle */
 } spmv_info;
 
 /*
@@ -200,6 +202,35 @@ int spmv_get_info(const spmv_matrix *A, spmv_info *info);
  * these calls only fill y with zeros: x is never read and may be NULL.
  */
 int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
+
+/*
+ * Rows longer than a tile (spmv_info.n_long_rows) are summed in pieces of
+ * 16,384 stored entries: per piece, lane-strided fused multiply-adds and a
+ * fixed-shape workgroup sum in binary64; per row, the pieces' sums added in
+ * piece order in binary64 (paper Sec. 2: the row's products summed, here in
+ * an order fixed by the row's length alone).  spmv_apply walks a row's
+ * pieces on one workgroup.  spmv_apply_ws gives each piece a workgroup of its
+ * own and adds the pieces' sums in a second launch, so a matrix with a few
+ * very long rows (a dense coupling row, a global constraint) spreads them
+ * over the whole GPU; the bits are the same as spmv_apply's.
+ *
+ * spmv_workspace_bytes: device bytes that spmv_apply_ws needs for the handle:
+ * 8 per long-row piece when some row has more than one piece, else 0.
+ * Errors: SPMV_EINVAL (NULL argument).
+ *
+ * spmv_apply_ws: spmv_apply with the pieces of the long rows side by side.
+ *   ws        caller-owned device memory of at least ws_bytes bytes, 8-byte
+ *             aligned, holding the pieces' sums between the two launches;
+ *             not to be shared by products that may run at the same time
+ *             (a product on another stream, another caller).  NULL when
+ *             spmv_workspace_bytes is 0.
+ *   ws_bytes  >= spmv_workspace_bytes(A), else SPMV_EINVAL; ws must not
+ *             overlap x or y (SPMV_EINVAL).
+ * Otherwise as spmv_apply (including capture into a HIP graph).  On block-
+ * CSR handles and on handles without such rows it is spmv_apply.
+ */
+int spmv_workspace_bytes(const spmv_matrix *A, size_t *bytes);
+int spmv_apply_ws(const spmv_matrix *A, const double *x, double *y, void *ws, size_t ws_bytes, void *stream);
 
 /* y = A32 x with the FP32 copy of the values, FP32 x/y, FP32 accumulation
  * (needs SPMV_VALUES_FP32, else SPMV_ENOTSUP). */

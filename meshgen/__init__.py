@@ -395,3 +395,34 @@ def random_csr(n_rows: int, n_cols: int, seed: int, mean_len: float = 4.0,
     ci = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
     va = rng.uniform(-1.0, 1.0, ci.shape[0])
     return CSR(n_rows, n_cols, rp.astype(np.int32), ci, va, 1)
+
+
+def with_long_rows(A: CSR, n_long: int, length: int, seed: int) -> CSR:
+    """A copy of A in which n_long rows, spread evenly over the matrix, are
+    replaced by rows of `length` entries over sorted distinct random columns
+    (a coupling row over a subset of the cells, such as a global constraint),
+    values U[-1, 1)."""
+    if length > A.n_cols:
+        raise ValueError("length exceeds n_cols")
+    rng = np.random.default_rng(seed)
+    where = np.linspace(0, A.n_rows - 1, n_long + 2)[1:-1].astype(np.int64)
+    lens = np.diff(A.row_ptr).astype(np.int64)
+    new_lens = lens.copy()
+    new_lens[where] = length
+    rp = np.zeros(A.n_rows + 1, np.int64)
+    rp[1:] = np.cumsum(new_lens)
+    if rp[-1] > (1 << 31) - (1 << 16):
+        raise ValueError("too many stored entries")
+    keep = np.ones(A.n_rows, bool)
+    keep[where] = False
+    old_row = np.repeat(np.arange(A.n_rows), lens)
+    m = keep[old_row]
+    pos = rp[old_row[m]] + (np.arange(A.nnz)[m] - A.row_ptr[old_row[m]].astype(np.int64))
+    ci = np.empty(int(rp[-1]), np.int32)
+    va = np.empty(int(rp[-1]), np.float64)
+    ci[pos] = A.col_idx[m]
+    va[pos] = A.values[m]
+    for r in where:
+        ci[rp[r]:rp[r + 1]] = np.sort(rng.choice(A.n_cols, size=length, replace=False))
+        va[rp[r]:rp[r + 1]] = rng.uniform(-1.0, 1.0, length)
+    return CSR(A.n_rows, A.n_cols, rp.astype(np.int32), ci, va, 1)

@@ -62,7 +62,8 @@ class spmv_info(ctypes.Structure):
                 ("window_words", ctypes.c_int64), ("n_runs", ctypes.c_int64), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("block_size", ctypes.c_int32), ("format", ctypes.c_int32), ("n_slices", ctypes.c_int32),
-                ("sell_entries", ctypes.c_int64)]
+                ("sell_entries", ctypes.c_int64), ("n_long_pieces", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class cg_info(ctypes.Structure):
@@ -98,6 +99,10 @@ def lib():
         for f in ("spmv_apply", "spmv_apply_f32", "spmv_apply_f32v", "spmv_apply_bf16"):
             getattr(L, f).restype = ctypes.c_int
             getattr(L, f).argtypes = [vp, vp, vp, vp]
+        L.spmv_workspace_bytes.restype = ctypes.c_int
+        L.spmv_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.spmv_apply_ws.restype = ctypes.c_int
+        L.spmv_apply_ws.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.spmv_create_bsr3.restype = ctypes.c_int
         L.spmv_create_bsr3.argtypes = [i32, i32, i64, vp, vp, vp, u32, ctypes.POINTER(vp)]
         for f in ("bsr3_spmm", "bsr3_spmm_f32", "spmv_spmm"):
@@ -374,6 +379,31 @@ class Matrix:
         """y = A x in binary64 (``spmv_apply``)."""
         torch = _torch()
         return self._apply("spmv_apply", x, y, torch.float64, torch.float64, stream)
+
+    @property
+    def workspace_bytes(self) -> int:
+        """Device bytes that ``apply_ws`` needs (``spmv_workspace_bytes``)."""
+        n = ctypes.c_size_t()
+        _check(lib().spmv_workspace_bytes(self.handle, ctypes.byref(n)), "spmv_workspace_bytes")
+        return int(n.value)
+
+    def apply_ws(self, x, y=None, ws=None, stream=None):
+        """y = A x with the long rows' pieces on a workgroup each
+        (``spmv_apply_ws``); ws: a device tensor of at least
+        ``workspace_bytes`` bytes, allocated here when None."""
+        torch = _torch()
+        _check_vec(x, torch.float64, self.n_cols, "x")
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+        _check_vec(y, torch.float64, self.n_rows, "y")
+        need = self.workspace_bytes
+        if ws is None and need:
+            ws = torch.empty((need + 7) // 8, dtype=torch.float64, device=x.device)
+        wp = ws.data_ptr() if ws is not None else None
+        wb = ws.numel() * ws.element_size() if ws is not None else 0
+        _check(lib().spmv_apply_ws(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                   ctypes.c_void_p(wp), wb, _stream_ptr(stream)), "spmv_apply_ws")
+        return y
 
     def apply_f32(self, x, y=None, stream=None):
         torch = _torch()

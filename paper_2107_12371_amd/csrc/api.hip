@@ -107,6 +107,28 @@ struct Uploader {
     }
 };
 
+static_assert(kLongPiece == kLongPieceHost, "long-row piece size differs between host and kernels");
+
+// The pieces of the long rows (d: their descriptors, in long_desc order).
+// The piece tables go to the device only when some row has more than one
+// piece; otherwise every product walks each long row on one workgroup.
+static int upload_long_pieces(Uploader &U, DevMatrix &M, const std::vector<TileDesc> &d) {
+    std::vector<int32_t> ptr(d.size() + 1, 0);
+    for (size_t i = 0; i < d.size(); ++i) ptr[i + 1] = ptr[i] + long_row_pieces((int64_t)d[i].e - d[i].s);
+    M.n_long_pieces = ptr.back();
+    if (M.n_long_pieces <= M.n_long) return SPMV_OK;
+    std::vector<int32_t> owner((size_t)M.n_long_pieces);
+    for (size_t i = 0; i < d.size(); ++i)
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) owner[(size_t)p] = (int32_t)i;
+    int rc = U.put(&M.long_piece_ptr, ptr.data(), ptr.size(), 0);
+    if (!rc) rc = U.put(&M.piece_long, owner.data(), owner.size(), 0);
+    return rc;
+}
+
+static int64_t workspace_bytes_of(const DevMatrix &M) {
+    return M.piece_long ? (int64_t)sizeof(double) * M.n_long_pieces : 0;
+}
+
 static int check_apply(const spmv_matrix *A, const void *x, size_t xs, const void *y, size_t ys) {
     if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
     if (A->M.n_rows > 0 && !y) return fail(SPMV_EINVAL, "y is NULL");
@@ -117,7 +139,8 @@ static int check_apply(const spmv_matrix *A, const void *x, size_t xs, const voi
 }
 
 template <typename V, typename X, typename Y, typename Acc>
-static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, void *stream) {
+static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, void *stream,
+                       double *long_ws = nullptr) {
     clear_error();
     int rc = check_apply(A, x, sizeof(X), y, sizeof(Y));
     if (rc) return rc;
@@ -130,7 +153,7 @@ static int apply_typed(const spmv_matrix *A, const V *val, const X *x, Y *y, voi
         return z == hipSuccess ? SPMV_OK : hip_fail(z, "zero fill");
     }
     hipError_t e = launch_spmv<V, X, Y, Acc>(A->M, val, x, y, EPI_PLAIN, nullptr, nullptr, nullptr,
-                                             static_cast<hipStream_t>(stream));
+                                             static_cast<hipStream_t>(stream), long_ws);
     if (e != hipSuccess) return hip_fail(e, "spmv launch");
     return SPMV_OK;
 }
@@ -231,6 +254,7 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
             d[i].seg = M.n_sell_wg + i;
         }
         rc = U.put(&M.long_desc, d.data(), d.size(), 0);
+        if (!rc) rc = upload_long_pieces(U, M, d);
     }
     M.n_seg = M.n_sell_wg + M.n_long;
     if (!rc) prepare_launch_queries();
@@ -253,6 +277,8 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     I.format = SPMV_FORMAT_SELL;
     I.n_slices = S.n_slices;
     I.sell_entries = S.n_entries;
+    I.n_long_pieces = M.n_long_pieces;
+    I.workspace_bytes = workspace_bytes_of(M);
     *out = A;
     return SPMV_OK;
 }
@@ -350,7 +376,12 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     M.n_stream = (int32_t)P.stream_list.size();
     if (!rc && M.n_stream) rc = upload_descs(P.stream_list, &M.stream_desc);
     M.n_long = (int32_t)P.long_list.size();
-    if (!rc && M.n_long) rc = upload_descs(P.long_list, &M.long_desc);
+    if (!rc && M.n_long) {
+        std::vector<TileDesc> d;
+        for (int32_t sg : P.long_list) d.push_back(desc_of(sg));
+        rc = U.put(&M.long_desc, d.data(), d.size(), 0);
+        if (!rc) rc = upload_long_pieces(U, M, d);
+    }
     M.n_blk = P.win_blk_ptr.empty() ? 0 : (int32_t)P.win_blk_ptr.size() - 1;
     if (!rc && M.n_blk) {
         rc = upload_descs(P.win_list, &M.win_desc);
@@ -399,6 +430,8 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     I.has_bf16 = M.val16 != nullptr;
     I.device_bytes = A->bytes;
     I.block_size = 1;
+    I.n_long_pieces = M.n_long_pieces;
+    I.workspace_bytes = workspace_bytes_of(M);
     *out = A;
     return SPMV_OK;
 }
@@ -477,6 +510,31 @@ static int spmm_typed(const spmv_matrix *A, const V *val, int32_t k, const T *X,
 extern "C" int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream) {
     if (A && A->M.block == 3) return spmm_typed<double, double>(A, A->M.val64, 1, x, y, stream);
     return apply_typed<double, double, double, double>(A, A ? A->M.val64 : nullptr, x, y, stream);
+}
+
+extern "C" int spmv_workspace_bytes(const spmv_matrix *A, size_t *bytes) {
+    clear_error();
+    if (!A || !bytes) return fail(SPMV_EINVAL, "NULL argument");
+    *bytes = (size_t)workspace_bytes_of(A->M);
+    return SPMV_OK;
+}
+
+extern "C" int spmv_apply_ws(const spmv_matrix *A, const double *x, double *y, void *ws, size_t ws_bytes,
+                             void *stream) {
+    clear_error();
+    if (!A) return fail(SPMV_EINVAL, "matrix handle is NULL");
+    const size_t need = (size_t)workspace_bytes_of(A->M);
+    if (ws_bytes < need)
+        return fail(SPMV_EINVAL, "ws_bytes = %zu below the %zu bytes the long rows' pieces need", ws_bytes, need);
+    if (need && !ws) return fail(SPMV_EINVAL, "ws is NULL");
+    if (need && (reinterpret_cast<uintptr_t>(ws) & 7)) return fail(SPMV_EINVAL, "ws is not 8-byte aligned");
+    if (need && x && overlaps(ws, need, x, sizeof(double) * (size_t)A->M.n_cols))
+        return fail(SPMV_EINVAL, "ws and x overlap");
+    if (need && y && overlaps(ws, need, y, sizeof(double) * (size_t)A->M.n_rows))
+        return fail(SPMV_EINVAL, "ws and y overlap");
+    if (A->M.block == 3) return spmm_typed<double, double>(A, A->M.val64, 1, x, y, stream);
+    return apply_typed<double, double, double, double>(A, A->M.val64, x, y, stream,
+                                                       need ? static_cast<double *>(ws) : nullptr);
 }
 
 extern "C" int spmv_apply_f32(const spmv_matrix *A, const float *x, float *y, void *stream) {

@@ -974,6 +974,7 @@ template <typename T, typename V> struct CgCore {
     T *x, *r, *p, *q;
     double *part_seg, *part_vec;
     double *part2;      // first-stage sums of a two-stage reduction
+    double *long_ws = nullptr;  // the long rows' piece sums (several workgroups per long row)
     CgState *st;        // device
     CgState *hst;       // pinned host mirror
     int n_wg, chunk, graph_iters;
@@ -1052,7 +1053,7 @@ template <typename T, typename V> struct CgCore {
     hipError_t iteration(hipStream_t t) {
         if (fused) return fused_iteration(t);
         const int *done = &st->done;
-        hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t);
+        hipError_t e = launch_spmv<V, T, T, T>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, t, long_ws);
         if (e != hipSuccess) return e;
         const bool fold_alpha = M.n_seg <= kFoldAlpha;
         if (!fold_alpha) reduce(part_seg, M.n_seg, R_ALPHA, t);
@@ -1107,7 +1108,7 @@ template <typename T, typename V> struct CgCore {
 
     // r = b - A x and its squared norm into st->rt2 (values of type V)
     hipError_t true_residual(const T *b) {
-        hipError_t e = launch_spmv<V, T, T, T>(M, val, x, r, EPI_RESID, b, part_seg, nullptr, s);
+        hipError_t e = launch_spmv<V, T, T, T>(M, val, x, r, EPI_RESID, b, part_seg, nullptr, s, long_ws);
         if (e != hipSuccess) return e;
         reduce(part_seg, M.n_seg, R_TRUE, s);
         return hipGetLastError();
@@ -1190,6 +1191,7 @@ int alloc_core(Buffers &B, CgCore<T, V> &C) {
     HIP_TRY(B.alloc(&C.part_seg, (size_t)std::max(C.M.n_seg, 1)));
     HIP_TRY(B.alloc(&C.part_vec, (size_t)C.n_wg));
     HIP_TRY(B.alloc(&C.part2, (size_t)CgCore<T, V>::kStage1));
+    if (C.M.piece_long) HIP_TRY(B.alloc(&C.long_ws, (size_t)C.M.n_long_pieces));
     HIP_TRY(B.alloc(&C.st, 1));
     return SPMV_OK;
 }
@@ -1213,7 +1215,8 @@ struct PcgCore : CgCore<double, double> {
 
     hipError_t pcg_iteration(hipStream_t ts) {
         const int *done = &st->done;
-        hipError_t e = launch_spmv<double, double, double, double>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, ts);
+        hipError_t e = launch_spmv<double, double, double, double>(M, val, p, q, EPI_DOT, nullptr, part_seg, done, ts,
+                                                                     long_ws);
         if (e != hipSuccess) return e;
         if (jacobi) {
             const bool fold_alpha = M.n_seg <= kFoldAlpha;
@@ -1236,7 +1239,8 @@ struct PcgCore : CgCore<double, double> {
         // folded: the convergence test waits for the p update, so on the last
         // iteration the preconditioner runs once more (it writes neither x nor r)
         if (!fold_beta) reduce(part_vec, n_wg, R_RR, ts);
-        e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr, done, ts);
+        e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr, done, ts,
+                                                          long_ws);
         if (e != hipSuccess) return e;
         double *rz = fold_beta ? part_rz : part_vec;
         hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, ts, n, chunk, r, sv, dinv, z, st, rz, 0);
@@ -1273,7 +1277,7 @@ struct PcgCore : CgCore<double, double> {
         }
         hipLaunchKernelGGL(k_dinv_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, t, r, dinv);
         hipError_t e = launch_spmv<uint16_t, float, float, float>(M, M.val16, t, sv, EPI_PLAIN, nullptr, nullptr,
-                                                                  nullptr, s);
+                                                                  nullptr, s, long_ws);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_precond_z, dim3(n_wg), dim3(kBlock), 0, s, n, chunk, r, sv, dinv, z, st, part_vec, 1);
         reduce(part_vec, n_wg, R_RZ0, s);

@@ -12,6 +12,9 @@ constexpr int kWave = 64;
 constexpr int kEntriesPerLane = 4; // stored entries a lane streams per pass
 constexpr int kPad = 16;           // padding entries after col/val arrays
 constexpr int kCwinMaxRunsDev = 64; // compact windows: runs per tile (plan limit)
+// Rows longer than a tile are summed in pieces of this many stored entries
+// (one workgroup's share when the pieces of a row run side by side).
+constexpr int kLongPiece = 16384;
 
 // Epilogues of the row-tile kernels.
 enum Epilogue : int {
@@ -48,6 +51,10 @@ struct DevMatrix {
     TileDesc *stream_desc = nullptr; // direct-gather tiles, in row order
     int32_t n_long = 0;
     TileDesc *long_desc = nullptr;   // rows longer than a tile
+    int32_t n_long_pieces = 0;       // pieces of kLongPiece entries over the long rows
+    int32_t *long_piece_ptr = nullptr;  // n_long + 1 offsets into the pieces (only when
+                                        // some long row has more than one piece)
+    int32_t *piece_long = nullptr;      // per piece: its long row (index into long_desc)
     int32_t n_blk = 0;
     int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_desc
     TileDesc *win_desc = nullptr;    // window tiles, grouped by block

@@ -54,6 +54,10 @@ inline int default_xcd_chunk(int64_t matrix_bytes) { return matrix_bytes >= kXcd
 // Compact per-tile windows: at most this many words and runs per tile.
 constexpr int kCwinMaxRuns = 64;  // must equal the kernels' kCwinMaxRunsDev
 
+// Stored entries per piece of a long row (must equal the kernels' kLongPiece).
+constexpr int kLongPieceHost = 16384;
+inline int32_t long_row_pieces(int64_t len) { return (int32_t)((len + kLongPieceHost - 1) / kLongPieceHost); }
+
 // Analysis plan built once per matrix (the matrix is constant, so its
 // preprocessing is amortised -- paper Sec. 2).
 struct Plan {

@@ -32,15 +32,17 @@ template <typename V, typename X, typename Y> struct SpmvArgs {
     const uint8_t *sell_len;
     const int32_t *sell_ptr;
     int32_t n_slices;
+    double *long_ws;        // optional: one double per long-row piece (several workgroups per row)
 };
 
 // y = A x over all segments of M (direct tiles, long rows, window blocks),
 // launched on `st`.  V: stored value type (double, float, uint16_t = bf16),
 // X/Y: vector types, A: accumulation type.  `part` must hold M.n_seg doubles
-// when epi != EPI_PLAIN.
+// when epi != EPI_PLAIN.  `long_ws` (optional) holds M.n_long_pieces doubles:
+// then the pieces of the long rows run on a workgroup each (same bits).
 template <typename V, typename X, typename Y, typename A>
 hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
-                       double *part, const int *done, hipStream_t st);
+                       double *part, const int *done, hipStream_t st, double *long_ws = nullptr);
 
 // y[0..n) = 0 with a fill kernel (never a memset node, so a product on a
 // matrix without stored entries stays capturable like any other); the

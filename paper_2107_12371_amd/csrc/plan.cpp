@@ -443,6 +443,11 @@ extern "C" int spmv_plan_inspect(int32_t n_rows, int32_t n_cols, int64_t nnz, co
         info->window_words = P.window_words;
         info->n_runs = (int64_t)P.runs.size() / 2;
         info->block_size = 1;
+        int32_t pieces = 0;
+        for (int32_t sg : P.long_list)
+            pieces += long_row_pieces((int64_t)row_ptr[P.seg_bound[sg + 1]] - row_ptr[P.seg_bound[sg]]);
+        info->n_long_pieces = pieces;
+        info->workspace_bytes = pieces > (int32_t)P.long_list.size() ? (int64_t)sizeof(double) * pieces : 0;
     }
     return SPMV_OK;
 }

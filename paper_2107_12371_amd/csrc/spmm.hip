@@ -25,6 +25,7 @@
 #include "device.h"
 #include "launch.h"
 #include "spmm.h"
+#include "tile.h"
 
 namespace spmvlib {
 
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(const TileDesc *__restric
     }
 }
 
-// Row d.r0 (longer than a tile), column blockIdx.y.
+// Row d.r0 (longer than a tile), column blockIdx.y: the single-vector
+// long-row sum (its pieces in order) with x read from column j of X.
 __global__ __launch_bounds__(kBlock) void k_spmm_long(const TileDesc *__restrict__ desc,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ val, const double *__restrict__ X,
@@ -119,10 +121,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_long(const TileDesc *__restrict
     __shared__ double sh[kBlock / kWave];
     const TileDesc d = desc[blockIdx.x];
     const int j = (int)blockIdx.y;
-    double acc = 0.0;
-    for (int q = d.s + (int)threadIdx.x; q < d.e; q += kBlock) acc += val[q] * X[(size_t)col[q] * k + j];
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) Y[(size_t)d.r0 * k + j] = t;
+    const auto gx = [X, k, j](int c) { return X[(size_t)c * k + j]; };
+    double tot = 0.0;
+    for (int ps = d.s; ps < d.e; ps += kLongPiece) {
+        const double t = long_piece_sum<double>(val, col, ps, min(d.e, ps + kLongPiece), gx, sh);
+        tot = ps == d.s ? t : tot + t;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) Y[(size_t)d.r0 * k + j] = tot;
 }
 
 template <int KC, int U>

@@ -335,30 +335,69 @@ __global__ __launch_bounds__(kBlock) void k_cwin_pipe(SpmvArgs<V, X, Y> g) {
     }
 }
 
+// A long row's epilogue from its sum in double (thread 0 of k_long, one lane
+// of k_long_combine).
+template <typename V, typename X, typename Y, typename A, int EPI>
+__device__ __forceinline__ void long_row_store(const SpmvArgs<V, X, Y> &g, const TileDesc &d, double tot) {
+    const int r = d.r0;
+    const A sum = static_cast<A>(tot);
+    double dot;
+    if (EPI == EPI_RESID) {
+        const Y res = static_cast<Y>(g.b[r] - static_cast<Y>(sum));
+        g.y[r] = res;
+        dot = static_cast<double>(res) * static_cast<double>(res);
+    } else {
+        g.y[r] = static_cast<Y>(sum);
+        dot = static_cast<double>(sum) * static_cast<double>(g.x[r]);
+    }
+    if (EPI != EPI_PLAIN) g.part[d.seg] = dot;
+}
+
+// One workgroup per row longer than a tile, walking its pieces in order.
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long(SpmvArgs<V, X, Y> g) {
     __shared__ double sh[kBlock / kWave];
     if (g.done && *g.done) return;
     const TileDesc d = g.desc[blockIdx.x];
-    const int r = d.r0;
-    A acc = A(0);
-    for (int k = d.s + (int)threadIdx.x; k < d.e; k += kBlock)
-        acc += to_acc<A>(g.val[k]) * static_cast<A>(g.x[g.col[k]]);
-    // Fixed-shape reduction in double, then rounded to the accumulator type.
-    const double t = block_sum(static_cast<double>(acc), sh);
-    if (threadIdx.x == 0) {
-        const A sum = static_cast<A>(t);
-        double dot;
-        if (EPI == EPI_RESID) {
-            const Y res = static_cast<Y>(g.b[r] - static_cast<Y>(sum));
-            g.y[r] = res;
-            dot = static_cast<double>(res) * static_cast<double>(res);
-        } else {
-            g.y[r] = static_cast<Y>(sum);
-            dot = static_cast<double>(sum) * static_cast<double>(g.x[r]);
-        }
-        if (EPI != EPI_PLAIN) g.part[d.seg] = dot;
+    const X *__restrict__ x = g.x;
+    const auto gx = [x](int c) { return x[c]; };
+    double tot = 0.0;
+    for (int ps = d.s; ps < d.e; ps += kLongPiece) {
+        const double t = long_piece_sum<A>(g.val, g.col, ps, min(d.e, ps + kLongPiece), gx, sh);
+        tot = ps == d.s ? t : tot + t;
+        __syncthreads();  // sh is written again by the next piece
     }
+    if (threadIdx.x == 0) long_row_store<V, X, Y, A, EPI>(g, d, tot);
+}
+
+// Several workgroups per long row: one per piece, each piece's sum to ws.
+template <typename V, typename X, typename Y, typename A>
+__global__ __launch_bounds__(kBlock) void k_long_pieces(SpmvArgs<V, X, Y> g, const int32_t *__restrict__ piece_long,
+                                                        const int32_t *__restrict__ piece_ptr,
+                                                        double *__restrict__ ws) {
+    __shared__ double sh[kBlock / kWave];
+    if (g.done && *g.done) return;
+    const int pc = (int)blockIdx.x;
+    const int li = piece_long[pc];
+    const TileDesc d = g.desc[li];
+    const int ps = d.s + (pc - piece_ptr[li]) * kLongPiece;
+    const X *__restrict__ x = g.x;
+    const auto gx = [x](int c) { return x[c]; };
+    const double t = long_piece_sum<A>(g.val, g.col, ps, min(d.e, ps + kLongPiece), gx, sh);
+    if (threadIdx.x == 0) ws[pc] = t;
+}
+
+// ... then one lane per long row adds its pieces' sums in piece order.
+template <typename V, typename X, typename Y, typename A, int EPI>
+__global__ __launch_bounds__(kBlock) void k_long_combine(SpmvArgs<V, X, Y> g, const int32_t *__restrict__ piece_ptr,
+                                                         const double *__restrict__ ws) {
+    if (g.done && *g.done) return;
+    const int li = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (li >= g.n_list) return;
+    const int p0 = piece_ptr[li], p1 = piece_ptr[li + 1];
+    double tot = ws[p0];
+    for (int p = p0 + 1; p < p1; ++p) tot += ws[p];
+    long_row_store<V, X, Y, A, EPI>(g, g.desc[li], tot);
 }
 
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
@@ -453,6 +492,25 @@ static int cu_count() {
     return cus.load(std::memory_order_relaxed);
 }
 
+// Rows longer than a tile: with a workspace (g.long_ws) and a row of more
+// than one piece, one workgroup per piece and a combine launch; otherwise
+// one workgroup per row.  Both give the same bits.
+template <typename V, typename X, typename Y, typename A, int EPI>
+static void launch_long(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
+    if (M.n_long <= 0) return;
+    SpmvArgs<V, X, Y> a = g;
+    a.desc = M.long_desc;
+    a.n_list = M.n_long;
+    if (g.long_ws && M.piece_long) {
+        hipLaunchKernelGGL((k_long_pieces<V, X, Y, A>), dim3(M.n_long_pieces), dim3(kBlock), 0, st, a, M.piece_long,
+                           M.long_piece_ptr, g.long_ws);
+        hipLaunchKernelGGL((k_long_combine<V, X, Y, A, EPI>), dim3((M.n_long + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           st, a, M.long_piece_ptr, g.long_ws);
+    } else {
+        hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
+    }
+}
+
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
     if (M.n_stream > 0) {
@@ -506,12 +564,7 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
     }
-    if (M.n_long > 0) {
-        SpmvArgs<V, X, Y> a = g;
-        a.desc = M.long_desc;
-        a.n_list = M.n_long;
-        hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
-    }
+    launch_long<V, X, Y, A, EPI>(M, g, st);
     if (M.n_blk > 0) {
         SpmvArgs<V, X, Y> a = g;
         a.desc = M.win_desc;
@@ -526,12 +579,7 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
 template <typename V, typename X, typename Y, typename A, int EPI>
 static hipError_t launch_sell(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
     if (M.n_sell_wg > 0) launch_sell_slices<V, X, Y, A>(M, g, EPI, st);
-    if (M.n_long > 0) {
-        SpmvArgs<V, X, Y> a = g;
-        a.desc = M.long_desc;
-        a.n_list = M.n_long;
-        hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
-    }
+    launch_long<V, X, Y, A, EPI>(M, g, st);
     return hipGetLastError();
 }
 
@@ -547,8 +595,9 @@ static hipError_t launch_epi(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_
 
 template <typename V, typename X, typename Y, typename A>
 hipError_t launch_spmv(const DevMatrix &M, const V *val, const X *x, Y *y, int epi, const Y *b,
-                       double *part, const int *done, hipStream_t st) {
+                       double *part, const int *done, hipStream_t st, double *long_ws) {
     SpmvArgs<V, X, Y> g{};
+    g.long_ws = long_ws;
     g.chunk_log2 = -1;
     g.row_ptr = M.row_ptr;
     g.col = M.col;
@@ -621,15 +670,15 @@ hipError_t prepare_window_kernels() {
 
 template hipError_t launch_spmv<double, double, double, double>(const DevMatrix &, const double *, const double *,
                                                                 double *, int, const double *, double *,
-                                                                const int *, hipStream_t);
+                                                                const int *, hipStream_t, double *);
 template hipError_t launch_spmv<float, float, float, float>(const DevMatrix &, const float *, const float *,
                                                             float *, int, const float *, double *, const int *,
-                                                            hipStream_t);
+                                                            hipStream_t, double *);
 template hipError_t launch_spmv<float, double, double, double>(const DevMatrix &, const float *, const double *,
                                                                double *, int, const double *, double *,
-                                                               const int *, hipStream_t);
+                                                               const int *, hipStream_t, double *);
 template hipError_t launch_spmv<uint16_t, float, float, float>(const DevMatrix &, const uint16_t *,
                                                                const float *, float *, int, const float *,
-                                                               double *, const int *, hipStream_t);
+                                                               double *, const int *, hipStream_t, double *);
 
 }  // namespace spmvlib

@@ -278,4 +278,38 @@ __device__ __forceinline__ void tile_rows(const RowPre<Y, EPI, LANES> &pre, int 
     }
 }
 
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Rows longer than a tile are summed in pieces of kLongPiece stored entries.
+// One piece [s, e): lane t adds a_k * x[c_k] for k = s + t, s + t + kBlock,
+// ... in ascending k with fused multiply-adds into an accumulator of type A
+// (eight columns, then eight values, then eight gathers in flight per lane),
+// and block_sum adds the lanes' sums in double; the result is valid in
+// thread 0.  A row's sum is its pieces' sums added in piece order, in double,
+// then rounded to A: the same bits whether one workgroup walks the pieces or
+// each piece has a workgroup of its own.  `sh` is block_sum's scratch; the
+// caller separates two calls with a barrier.
+template <typename A, typename V, class Gather>
+__device__ __forceinline__ double long_piece_sum(const V *__restrict__ val, const int32_t *__restrict__ col, int s,
+                                                 int e, Gather gather, double *sh) {
+    constexpr int U = 8;
+    A acc = A(0);
+    int k = s + (int)threadIdx.x;
+    for (; k + (U - 1) * kBlock < e; k += U * kBlock) {
+        int32_t c[U];
+        A v[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = col[k + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = to_acc<A>(val[k + u * kBlock]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = static_cast<A>(gather(c[u]));
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = fma_acc(v[u], xv[u], acc);
+    }
+    for (; k < e; k += kBlock) acc = fma_acc(to_acc<A>(val[k]), static_cast<A>(gather(col[k])), acc);
+    return block_sum(static_cast<double>(acc), sh);
+}
+
 }  // namespace spmvlib

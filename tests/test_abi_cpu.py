@@ -208,6 +208,24 @@ def test_plan_invariants_edge_cases():
     assert P["info"]["n_tiles"] == 0
 
 
+def test_plan_long_row_pieces_and_workspace():
+    # rows longer than a tile are summed in pieces of 16,384 entries; the
+    # workspace of spmv_apply_ws holds one double per piece, and is needed
+    # only when some row has more than one piece
+    lens = [1021, 1022, 5000, 16384, 16385, 50_000, 0, 3]   # 1024-entry tiles hold 1021
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = (np.arange(rp[-1]) % 60_000).astype(np.int32)
+    P = check_plan(mg.CSR(len(lens), 60_000, rp, ci, np.ones(rp[-1]), 1), {"tile_nnz": 1024})
+    pieces = 1 + 1 + 1 + 2 + 4  # the rows of 1022, 5000, 16384, 16385 and 50000 entries
+    assert P["info"]["n_long_rows"] == 5 and P["info"]["n_long_pieces"] == pieces
+    assert P["info"]["workspace_bytes"] == 8 * pieces
+    # long rows of one piece each: nothing to split
+    rp1 = np.array([0, 5000, 5003, 21_387], np.int32)
+    P = check_plan(mg.CSR(3, 60_000, rp1, (np.arange(rp1[-1]) % 60_000).astype(np.int32), np.ones(rp1[-1]), 1),
+                   {"tile_nnz": 1024})
+    assert P["info"]["n_long_pieces"] == 2 and P["info"]["workspace_bytes"] == 0
+
+
 @pytest.mark.parametrize("ring", [256, 1024, 4096])
 def test_plan_window_forced_ring_sizes(ring):
     A = mg.lattice(16, 16, 16, "faces", seed=3)         # bandwidth 256: many tiles fit
