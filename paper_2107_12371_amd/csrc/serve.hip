@@ -843,6 +843,10 @@ struct Server {
         ln.pe.mark(0, batch);
         std::vector<MultiItem> items;
         std::vector<std::pair<Request *, std::pair<double *, double *>>> bufs;
+        // piece sums of long rows (products run one after another on the
+        // lane's stream, so one workspace serves the round)
+        double *lws = nullptr;
+        size_t lws_n = 0;
         int total = 0;
         int err = SPMV_OK;
         bool abandoned = false;
@@ -860,9 +864,22 @@ struct Server {
                 const double *x = din + (size_t)j * M.n_cols;
                 double *y = dout + (size_t)j * M.n_rows;
                 if (M.n_long > 0) {
-                    // rows longer than a tile: the matrix's own launch sequence
+                    // rows longer than a tile: the matrix's own launch
+                    // sequence, their pieces on a workgroup each
+                    if (M.piece_long && (size_t)M.n_long_pieces > lws_n) {
+                        if (lws) (void)hipFreeAsync(lws, batch);
+                        lws = nullptr;
+                        lws_n = 0;
+                        e = hipMallocAsync(reinterpret_cast<void **>(&lws), 8 * (size_t)M.n_long_pieces, batch);
+                        if (e != hipSuccess) {
+                            err = hip_fail(e, "server long-row workspace");
+                            lws = nullptr;
+                            continue;
+                        }
+                        lws_n = (size_t)M.n_long_pieces;
+                    }
                     e = launch_spmv<double, double, double, double>(M, M.val64, x, y, EPI_PLAIN, nullptr, nullptr,
-                                                                    nullptr, batch);
+                                                                    nullptr, batch, M.piece_long ? lws : nullptr);
                     if (e != hipSuccess) err = hip_fail(e, "server spmv");
                     continue;
                 }
@@ -927,6 +944,7 @@ struct Server {
             if (b.second.first) (void)hipFreeAsync(b.second.first, batch);
             if (b.second.second) (void)hipFreeAsync(b.second.second, batch);
         }
+        if (lws && !abandoned) (void)hipFreeAsync(lws, batch);
         std::lock_guard<std::mutex> lk(mu);
         ++rounds;
         for (Request *r : round) {

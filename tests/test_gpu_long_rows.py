@@ -261,3 +261,24 @@ def test_apply_ws_replays_from_a_graph(mats):
             got = y.cpu().numpy()
             ref = M.apply(to_dev(xr)).cpu().numpy()
             assert np.array_equal(got, ref), rep
+
+
+def test_server_products_and_solves_on_long_rows(mats, arrow):
+    # the server runs such matrices with their own launch sequence, pieces
+    # on a workgroup each: bitwise the handle's own product; CG solves to
+    # the requested tolerance
+    A = mats[0]
+    X = mg.uniform(3 * A.n_cols, 15, 1).reshape(3, A.n_cols)
+    b = mg.uniform(arrow.n_rows, 16, 4)
+    with spmv.Server(n_slots=2) as srv:
+        ia, ib = srv.add_matrix(A), srv.add_matrix(arrow)
+        t1, t2 = srv.submit_spmv(ia, X), srv.submit_cg(ib, b, tol=1e-9)
+        out, res = srv.wait(t1)
+        assert res.done == 1 and res.status == 0, res.message
+        xs, res2 = srv.wait(t2)
+        assert res2.done == 1 and res2.status == 0, res2.message
+    with spmv.Matrix.from_csr(A) as M:
+        for j in range(3):
+            assert np.array_equal(out[j], M.apply(to_dev(X[j])).cpu().numpy()), j
+    Ax, _ = oracle.spmv(arrow, xs)
+    assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= 1.05e-9
