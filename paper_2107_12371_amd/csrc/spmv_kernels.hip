@@ -387,17 +387,27 @@ __global__ __launch_bounds__(kBlock) void k_long_pieces(SpmvArgs<V, X, Y> g, con
     if (threadIdx.x == 0) ws[pc] = t;
 }
 
-// ... then one lane per long row adds its pieces' sums in piece order.
+// ... then one wavefront per long row adds its pieces' sums in piece order:
+// the lanes load 64 sums at once and every lane adds them one by one from
+// lane shuffles, so the loads need one round trip per 64 pieces.
 template <typename V, typename X, typename Y, typename A, int EPI>
 __global__ __launch_bounds__(kBlock) void k_long_combine(SpmvArgs<V, X, Y> g, const int32_t *__restrict__ piece_ptr,
                                                          const double *__restrict__ ws) {
     if (g.done && *g.done) return;
-    const int li = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (li >= g.n_list) return;
+    const int li = (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+    if (li >= g.n_list) return;  // the same for every lane of the wavefront
+    const int lane = (int)(threadIdx.x & (kWave - 1));
     const int p0 = piece_ptr[li], p1 = piece_ptr[li + 1];
-    double tot = ws[p0];
-    for (int p = p0 + 1; p < p1; ++p) tot += ws[p];
-    long_row_store<V, X, Y, A, EPI>(g, g.desc[li], tot);
+    double tot = 0.0;
+    for (int b = p0; b < p1; b += kWave) {
+        const int n = min(kWave, p1 - b);
+        const double v = lane < n ? ws[b + lane] : 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double w = __shfl(v, i, kWave);
+            tot = b == p0 && i == 0 ? w : tot + w;
+        }
+    }
+    if (lane == 0) long_row_store<V, X, Y, A, EPI>(g, g.desc[li], tot);
 }
 
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
@@ -504,8 +514,9 @@ static void launch_long(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st)
     if (g.long_ws && M.piece_long) {
         hipLaunchKernelGGL((k_long_pieces<V, X, Y, A>), dim3(M.n_long_pieces), dim3(kBlock), 0, st, a, M.piece_long,
                            M.long_piece_ptr, g.long_ws);
-        hipLaunchKernelGGL((k_long_combine<V, X, Y, A, EPI>), dim3((M.n_long + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           st, a, M.long_piece_ptr, g.long_ws);
+        constexpr int kRowsPerWg = kBlock / kWave;
+        hipLaunchKernelGGL((k_long_combine<V, X, Y, A, EPI>), dim3((M.n_long + kRowsPerWg - 1) / kRowsPerWg),
+                           dim3(kBlock), 0, st, a, M.long_piece_ptr, g.long_ws);
     } else {
         hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
     }
