@@ -686,6 +686,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=1024, help="matrices in the serving pool")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-lanes", type=int, default=0, help="SpMV lanes of the server (0: its default, 4)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="arrival rate of the serving streams in requests/s (0: 0.7x each stream's measured capacity)")
     ap.add_argument("--serve-persistent", type=int, default=256,
                     help="workgroups of the persistent multi-matrix kernel in the third serving stream "
                          "(0: no such stream)")
@@ -715,7 +717,7 @@ def main():
             if (args.serve_preload and not pre) or (name.endswith("persistent") and pw <= 0):
                 continue
             # the persistent stream arrives at the preloaded stream's rate
-            rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else 0.0
+            rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else args.serve_rate
             out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
                                     persistent_wgs=pw, rate=rate, lanes=args.serve_lanes)
         if not args.serve_preload:
