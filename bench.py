@@ -687,7 +687,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-lanes", type=int, default=0, help="SpMV lanes of the server (0: its default, 4)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
-                    help="arrival rate of the serving streams in requests/s (0: 0.7x each stream's measured capacity)")
+                    help="arrival rate of the serving streams in requests/s (0: the first stream arrives at 0.7x "
+                         "its measured capacity and the others at the same rate)")
     ap.add_argument("--serve-persistent", type=int, default=256,
                     help="workgroups of the persistent multi-matrix kernel in the third serving stream "
                          "(0: no such stream)")
@@ -716,8 +717,13 @@ def main():
                               ("preloaded_persistent", True, args.serve_persistent)):
             if (args.serve_preload and not pre) or (name.endswith("persistent") and pw <= 0):
                 continue
-            # the persistent stream arrives at the preloaded stream's rate
-            rate = out["preloaded"]["arrival_rate_rps"] if pw and "preloaded" in out else args.serve_rate
+            # one arrival rate for the streams that follow the first: that
+            # stream's (0.7x its measured capacity), so that uploads on first
+            # touch, a preloaded pool and the persistent kernel are compared at
+            # the same load; each stream still reports its own capacity
+            rate = args.serve_rate
+            if rate <= 0 and out:
+                rate = next(iter(out.values()))["arrival_rate_rps"]
             out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
                                     persistent_wgs=pw, rate=rate, lanes=args.serve_lanes)
         if not args.serve_preload:

@@ -223,16 +223,20 @@ def arrow():
 
 def test_cg_with_long_rows_split_equals_one_workgroup_per_row(arrow):
     A = arrow
-    with spmv.Matrix.from_csr(A, fp32=True) as M:
+    with spmv.Matrix.from_csr(A, fp32=True, bf16=True) as M:
         assert M.info["n_long_rows"] == 3 and M.workspace_bytes > 0
         b = to_dev(mg.uniform(A.n_rows, 13, 4))
         x1, i1 = M.cg(b, tol=1e-10)            # pieces on their own workgroups
         x2, i2 = M.cg_noalloc(b, tol=1e-10)    # one workgroup per long row
         assert i1.iterations == i2.iterations
         assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+        # the FP32 and bfloat16 products of the other solvers split the long
+        # rows the same way
         xm, im = M.cg(b, tol=1e-10, mode=spmv.CG_MIXED_FP32)
+        xj, ij = M.cg(b, tol=1e-10, mode=spmv.CG_PCG_JACOBI)
+        xp, ip = M.cg(b, tol=1e-10, mode=spmv.CG_PCG_BF16)
     bh = b.cpu().numpy()
-    for xs in (x1, xm):
+    for xs in (x1, xm, xj, xp):
         Ax, _ = oracle.spmv(A, xs.cpu().numpy())
         assert np.linalg.norm(bh - Ax) / np.linalg.norm(bh) <= 1.05e-10
 
