@@ -7,7 +7,7 @@ resident in HBM.  `value` = algorithmic bytes / time:
     B_alg = nnz * (8 + 4) + 4 * (n + 1) + 8 * n_cols + 8 * n
 (values, column indices, row pointers, x read once, y written once).
 
-Besides the JSON fields the driver needs, the line carries:
+Besides the contract fields (metric, value, unit, steps, config, ...), the line carries:
   roofline      for the dominant kernel (the row-tile kernel), HBM bound
   cpu_baseline  the CPU oracle timed on this host on the same matrix
   extras        FP32 SpMV bandwidth, FP64 vs mixed-precision CG to 1e-10,

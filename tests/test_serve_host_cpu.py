@@ -11,7 +11,7 @@ The regression case: when a matrix upload fails, the request reports the
 error and the matrix must not stay marked resident without a device handle
 (that state made the next request on the matrix dereference a null handle in
 a server thread).  Uploads are made to fail by the mock's
-MOCK_FAIL_COPY_EVERY knob; the driver counts the requests that failed with an
+MOCK_FAIL_COPY_EVERY knob; the test program counts the requests that failed with an
 upload's message."""
 import os
 import re
