@@ -404,6 +404,11 @@ int cg_solve_noalloc(const spmv_matrix *A, const double *b, double *x, double to
  * dropped first, dropped with an evicted matrix, outside hbm_budget_bytes),
  * so a later solve on the same matrix from any slot only replays.
  * A request's result is bitwise identical alone and in any mix.
+ * Input and output buffers of at least 4 MB move between the caller's
+ * (pageable) memory and the device through two pinned host buffers of
+ * 16 MB per lane (allocated on the lane's first such request, freed by
+ * srv_destroy), in chunks whose DMA overlaps the host copy of the next one,
+ * the host copies split over a few copy threads of the server.
  * Latency is measured from srv_submit until the result is in `out`.
  */
 typedef struct spmv_server spmv_server;
