@@ -686,6 +686,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=1024, help="matrices in the serving pool")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-lanes", type=int, default=0, help="SpMV lanes of the server (0: its default, 4)")
+    ap.add_argument("--serve-cg-mode", type=int, default=0,
+                    help="cg_mode of the serving streams' solves (0: CG_FP64, 1: CG_MIXED_FP32)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="arrival rate of the serving streams in requests/s (0: the first stream arrives at 0.7x "
                          "its measured capacity and the others at the same rate)")
@@ -724,7 +726,7 @@ def main():
             rate = args.serve_rate
             if rate <= 0 and out:
                 rate = next(iter(out.values()))["arrival_rate_rps"]
-            out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), spmv.CG_FP64, preload=pre,
+            out[name] = serving_run(pool, args.serve_requests, mg.seed_for(4), args.serve_cg_mode, preload=pre,
                                     persistent_wgs=pw, rate=rate, lanes=args.serve_lanes)
         if not args.serve_preload:
             # budget exhaustion: 192 requests over the pool's first 128
