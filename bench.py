@@ -397,26 +397,31 @@ def long_rows_matrix():
 
 
 def long_row_line(torch, base_ms: float) -> dict:
-    """The long-rows matrix: one workgroup per long row (spmv_apply) against
-    one workgroup per 16,384-entry piece and a combine launch
-    (spmv_apply_ws), same bits; the kNN matrix alone beside them."""
+    """The long-rows matrix: one workgroup per long row (spmv_params.long_rows
+    = 1) against one workgroup per 16,384-entry piece and a combine launch,
+    the pieces' sums kept in the output's own rows (spmv_apply, the default)
+    or in a caller's workspace (spmv_apply_ws); same bits; the kNN matrix
+    alone beside them."""
     import meshgen as mg
     import paper_2107_12371_amd as spmv
     A = long_rows_matrix()
     x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
     y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
     B = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+    with spmv.Matrix.from_csr(A, params={"long_rows": 1}) as M1:
+        t1 = time_launches(lambda: M1.apply(x, y), 20, 3, torch, WARM_S)
+        y1 = y.clone()
     with spmv.Matrix.from_csr(A) as M:
         ws = torch.empty(max(M.workspace_bytes // 8, 1), dtype=torch.float64, device="cuda")
-        t1 = time_launches(lambda: M.apply(x, y), 20, 3, torch, WARM_S)
-        y1 = y.clone()
-        t2 = time_launches(lambda: M.apply_ws(x, y, ws=ws), 100, 5, torch, WARM_S)
+        t2 = time_launches(lambda: M.apply(x, y), 100, 5, torch, WARM_S)
         same = bool(torch.equal(y, y1))
+        t3 = time_launches(lambda: M.apply_ws(x, y, ws=ws), 100, 5, torch, WARM_S)
+        same = same and bool(torch.equal(y, y1))
         inf = M.info
     return {"rows": A.n_rows, "nnz": A.nnz, "long_rows": inf["n_long_rows"], "pieces": inf["n_long_pieces"],
             "one_workgroup_per_row_ms": round(t1 * 1e3, 4), "pieces_ms": round(t2 * 1e3, 4),
-            "GBs_pieces": round(B / t2 / 1e9, 1), "speedup": round(t1 / t2, 2), "same_bits": same,
-            "knn_alone_ms": base_ms}
+            "pieces_caller_workspace_ms": round(t3 * 1e3, 4), "GBs_pieces": round(B / t2 / 1e9, 1),
+            "speedup": round(t1 / t2, 2), "same_bits": same, "knn_alone_ms": base_ms}
 
 
 def config_lines(torch, log=log) -> dict:
@@ -556,9 +561,9 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       cg1_fp64_c50k the same with one reduction per iteration (one launch each)
       cg_fp64_c800k, cg1_fp64_c800k  both on the 775,058-row stand-in
       long_rows_one_wg  the 126^3 kNN matrix with 16 rows of 2^20 entries,
-                  one workgroup per long row (spmv_apply)
-      long_rows_pieces  the same, one workgroup per 16,384-entry piece
-                  (spmv_apply_ws)"""
+                  one workgroup per long row (spmv_params.long_rows = 1)
+      long_rows_pieces  the same, one workgroup per 16,384-entry piece (the
+                  default spmv_apply, the pieces' sums in the output's rows)"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -609,15 +614,12 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
             A = mats["long"]
             x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
             y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
-            with spmv.Matrix.from_csr(A) as M:
-                ws = torch.empty(max(M.workspace_bytes // 8, 1), dtype=torch.float64, device="cuda")
-                if name.endswith("pieces"):
-                    t = time_launches(lambda: M.apply_ws(x, y, ws=ws), steps, warmup, torch)
-                else:
-                    t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
-                out["info"] = {k: M.info[k] for k in ("n_long_rows", "n_long_pieces")}
+            params = None if name.endswith("pieces") else {"long_rows": 1}
+            with spmv.Matrix.from_csr(A, params=params) as M:
+                t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
+                out["info"] = {k: M.info[k] for k in ("n_long_rows", "n_long_pieces", "y_scratch_ok")}
             out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
-            del x, y, ws
+            del x, y
         elif name == "copy":
             buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(buf)

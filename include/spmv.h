@@ -124,6 +124,11 @@ typedef struct spmv_params {
                               SPMV_NO_XCD_REMAP).  0: chunks of 16 for matrices of
                               at least 256 MB (beyond the memory-side cache), -2
                               for smaller ones */
+    int32_t long_rows;     /* rows longer than a tile: 0 (default) sums their
+                              pieces of 16,384 entries on a workgroup each wherever
+                              the product has scratch for the pieces' sums (see
+                              spmv_apply_ws), 1: one workgroup per row always.
+                              Same bits either way. */
 } spmv_params;
 
 /* Storage formats of a scalar handle. */
@@ -158,6 +163,9 @@ typedef struct spmv_info {
     int64_t sell_entries;   /* SELL: stored slots including padding (long rows excluded) */
     int32_t n_long_pieces;  /* pieces of 16,384 stored entries over the long rows */
     int64_t workspace_bytes; /* spmv_workspace_bytes of the handle */
+    int32_t y_scratch_ok;   /* 1: binary64 products split the long rows using the output
+                               vector as scratch (the rows of its longest run without a long
+                               row hold 8 bytes per piece) */
 } spmv_info;
 
 /*
@@ -208,11 +216,16 @@ int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
  * 16,384 stored entries: per piece, lane-strided fused multiply-adds and a
  * fixed-shape workgroup sum in binary64; per row, the pieces' sums added in
  * piece order in binary64 (paper Sec. 2: the row's products summed, here in
- * an order fixed by the row's length alone).  spmv_apply walks a row's
- * pieces on one workgroup.  spmv_apply_ws gives each piece a workgroup of its
- * own and adds the pieces' sums in a second launch, so a matrix with a few
- * very long rows (a dense coupling row, a global constraint) spreads them
- * over the whole GPU; the bits are the same as spmv_apply's.
+ * an order fixed by the row's length alone).  Each piece can run on a
+ * workgroup of its own, its sum going to scratch memory that a second launch
+ * adds up, so a matrix with a few very long rows (a dense coupling row, a
+ * global constraint) spreads them over the whole GPU; otherwise one
+ * workgroup walks a row's pieces.  The bits are the same either way.  The
+ * products (spmv_apply and its FP32/BF16 forms, spmv_spmm with k = 1, the
+ * solvers) take the scratch from the output vector itself: the longest run
+ * of rows without a long row, which the same call writes only afterwards,
+ * when it holds 8 bytes per piece (spmv_info.y_scratch_ok).  Where it does
+ * not, spmv_apply_ws takes the scratch from the caller.
  *
  * spmv_workspace_bytes: device bytes that spmv_apply_ws needs for the handle:
  * 8 per long-row piece when some row has more than one piece, else 0.

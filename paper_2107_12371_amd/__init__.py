@@ -50,7 +50,7 @@ class spmv_params(ctypes.Structure):
                 ("window_mode", ctypes.c_int32), ("ring_words", ctypes.c_int32),
                 ("window_block", ctypes.c_int32), ("window_gap", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("format", ctypes.c_int32), ("sell_sigma", ctypes.c_int32),
-                ("xcd_chunk", ctypes.c_int32)]
+                ("xcd_chunk", ctypes.c_int32), ("long_rows", ctypes.c_int32)]
 
 
 class spmv_info(ctypes.Structure):
@@ -63,7 +63,7 @@ class spmv_info(ctypes.Structure):
                 ("has_bf16", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("block_size", ctypes.c_int32), ("format", ctypes.c_int32), ("n_slices", ctypes.c_int32),
                 ("sell_entries", ctypes.c_int64), ("n_long_pieces", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("y_scratch_ok", ctypes.c_int32)]
 
 
 class cg_info(ctypes.Structure):

@@ -116,6 +116,20 @@ static int upload_long_pieces(Uploader &U, DevMatrix &M, const std::vector<TileD
     std::vector<int32_t> ptr(d.size() + 1, 0);
     for (size_t i = 0; i < d.size(); ++i) ptr[i + 1] = ptr[i] + long_row_pieces((int64_t)d[i].e - d[i].s);
     M.n_long_pieces = ptr.back();
+    // the longest run of rows without a long row (the long rows come in
+    // ascending order): a product's own output rows there are scratch for
+    // the pieces' sums until its row tiles write them
+    int32_t prev = -1;
+    M.y_ws_row = 0;
+    M.y_ws_rows = 0;
+    for (size_t i = 0; i <= d.size(); ++i) {
+        const int32_t next = i < d.size() ? d[i].r0 : M.n_rows;
+        if (next - (prev + 1) > M.y_ws_rows) {
+            M.y_ws_row = prev + 1;
+            M.y_ws_rows = next - (prev + 1);
+        }
+        prev = next;
+    }
     if (M.n_long_pieces <= M.n_long) return SPMV_OK;
     std::vector<int32_t> owner((size_t)M.n_long_pieces);
     for (size_t i = 0; i < d.size(); ++i)
@@ -188,6 +202,7 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
                        spmv_matrix **out) {
     if (p.xcd_chunk < -2 || p.xcd_chunk > 4096 || (p.xcd_chunk > 0 && (p.xcd_chunk & (p.xcd_chunk - 1))))
         return fail(SPMV_EINVAL, "xcd_chunk = %d must be -2, -1, 0 or a power of two <= 4096", p.xcd_chunk);
+    if (p.long_rows != 0 && p.long_rows != 1) return fail(SPMV_EINVAL, "long_rows = %d must be 0 or 1", p.long_rows);
     SellPlan S;
     int rc = build_sell_plan(n_rows, row_ptr, p.sell_sigma, S);
     if (rc) return rc;
@@ -205,6 +220,7 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     }
     DevMatrix &M = A->M;
     M.format = SPMV_FORMAT_SELL;
+    M.long_split = p.long_rows == 0;
     M.n_rows = n_rows;
     M.n_cols = n_cols;
     M.nnz = nnz;
@@ -279,6 +295,7 @@ static int create_sell(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_
     I.sell_entries = S.n_entries;
     I.n_long_pieces = M.n_long_pieces;
     I.workspace_bytes = workspace_bytes_of(M);
+    I.y_scratch_ok = M.piece_long && M.long_split && (int64_t)M.y_ws_rows >= M.n_long_pieces;
     *out = A;
     return SPMV_OK;
 }
@@ -330,6 +347,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
         return hip_fail(U.init, "upload stream");
     }
     DevMatrix &M = A->M;
+    M.long_split = !params || params->long_rows == 0;
     M.n_rows = n_rows;
     M.n_cols = n_cols;
     M.nnz = nnz;
@@ -432,6 +450,7 @@ extern "C" int spmv_create(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     I.block_size = 1;
     I.n_long_pieces = M.n_long_pieces;
     I.workspace_bytes = workspace_bytes_of(M);
+    I.y_scratch_ok = M.piece_long && M.long_split && (int64_t)M.y_ws_rows >= M.n_long_pieces;
     *out = A;
     return SPMV_OK;
 }

@@ -55,6 +55,8 @@ struct DevMatrix {
     int32_t *long_piece_ptr = nullptr;  // n_long + 1 offsets into the pieces (only when
                                         // some long row has more than one piece)
     int32_t *piece_long = nullptr;      // per piece: its long row (index into long_desc)
+    bool long_split = true;             // pieces on a workgroup each where scratch exists
+    int32_t y_ws_row = 0, y_ws_rows = 0;  // longest run of rows without a long row
     int32_t n_blk = 0;
     int32_t *win_blk_ptr = nullptr;  // n_blk + 1 offsets into win_desc
     TileDesc *win_desc = nullptr;    // window tiles, grouped by block

@@ -186,6 +186,7 @@ static int build_plan_once(int32_t n_rows, int32_t n_cols, int64_t nnz, const in
     if (p.kernel < 0 || p.kernel > 3) return fail(SPMV_EINVAL, "kernel = %d unknown", p.kernel);
     if (p.xcd_chunk < -2 || p.xcd_chunk > 4096 || (p.xcd_chunk > 0 && (p.xcd_chunk & (p.xcd_chunk - 1))))
         return fail(SPMV_EINVAL, "xcd_chunk = %d must be -2, -1, 0 or a power of two <= 4096", p.xcd_chunk);
+    if (p.long_rows != 0 && p.long_rows != 1) return fail(SPMV_EINVAL, "long_rows = %d must be 0 or 1", p.long_rows);
     if (p.kernel == KV_WAVE_PLAN) {
         // wavefront tiles: 1024-entry capacity, two rows per lane
         if (p.tile_nnz && p.tile_nnz != 1024)

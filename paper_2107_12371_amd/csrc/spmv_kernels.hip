@@ -502,21 +502,37 @@ static int cu_count() {
     return cus.load(std::memory_order_relaxed);
 }
 
-// Rows longer than a tile: with a workspace (g.long_ws) and a row of more
-// than one piece, one workgroup per piece and a combine launch; otherwise
-// one workgroup per row.  Both give the same bits.
+// The product's own output as scratch for the long rows' piece sums: the
+// rows of the longest run without a long row, which the row-tile launches
+// of the same product write only after the long rows' launches (8-byte
+// aligned; nullptr when the run is too short).
+template <typename Y> static double *y_scratch(const DevMatrix &M, Y *y) {
+    if (!y || M.y_ws_rows <= 0) return nullptr;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(y + M.y_ws_row);
+    const uintptr_t a = (p + 7) & ~uintptr_t(7);
+    const int64_t have = (int64_t)sizeof(Y) * M.y_ws_rows - (int64_t)(a - p);
+    return have >= (int64_t)sizeof(double) * M.n_long_pieces ? reinterpret_cast<double *>(a) : nullptr;
+}
+
+// Rows longer than a tile: with scratch for the pieces' sums (the caller's
+// workspace g.long_ws, else the output's own rows) and a row of more than
+// one piece, one workgroup per piece and a combine launch; otherwise one
+// workgroup per row.  Both give the same bits.  Launched before the row
+// tiles (the output's scratch rows are theirs to write afterwards).
 template <typename V, typename X, typename Y, typename A, int EPI>
 static void launch_long(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
     if (M.n_long <= 0) return;
     SpmvArgs<V, X, Y> a = g;
     a.desc = M.long_desc;
     a.n_list = M.n_long;
-    if (g.long_ws && M.piece_long) {
+    double *ws = nullptr;
+    if (M.piece_long && M.long_split) ws = g.long_ws ? g.long_ws : y_scratch(M, g.y);
+    if (ws) {
         hipLaunchKernelGGL((k_long_pieces<V, X, Y, A>), dim3(M.n_long_pieces), dim3(kBlock), 0, st, a, M.piece_long,
-                           M.long_piece_ptr, g.long_ws);
+                           M.long_piece_ptr, ws);
         constexpr int kRowsPerWg = kBlock / kWave;
         hipLaunchKernelGGL((k_long_combine<V, X, Y, A, EPI>), dim3((M.n_long + kRowsPerWg - 1) / kRowsPerWg),
-                           dim3(kBlock), 0, st, a, M.long_piece_ptr, g.long_ws);
+                           dim3(kBlock), 0, st, a, M.long_piece_ptr, ws);
     } else {
         hipLaunchKernelGGL((k_long<V, X, Y, A, EPI>), dim3(M.n_long), dim3(kBlock), 0, st, a);
     }
@@ -524,6 +540,7 @@ static void launch_long(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st)
 
 template <typename V, typename X, typename Y, typename A, int NT, int EPI>
 static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
+    launch_long<V, X, Y, A, EPI>(M, g, st);
     if (M.n_stream > 0) {
         SpmvArgs<V, X, Y> a = g;
         a.desc = M.stream_desc;
@@ -575,7 +592,6 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
             hipLaunchKernelGGL((k_cwin<V, X, Y, A, NT, EPI>), dim3(grid), dim3(kBlock), 0, st, a);
         }
     }
-    launch_long<V, X, Y, A, EPI>(M, g, st);
     if (M.n_blk > 0) {
         SpmvArgs<V, X, Y> a = g;
         a.desc = M.win_desc;
@@ -589,8 +605,8 @@ static hipError_t launch_nt(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t
 
 template <typename V, typename X, typename Y, typename A, int EPI>
 static hipError_t launch_sell(const DevMatrix &M, SpmvArgs<V, X, Y> g, hipStream_t st) {
-    if (M.n_sell_wg > 0) launch_sell_slices<V, X, Y, A>(M, g, EPI, st);
     launch_long<V, X, Y, A, EPI>(M, g, st);
+    if (M.n_sell_wg > 0) launch_sell_slices<V, X, Y, A>(M, g, EPI, st);
     return hipGetLastError();
 }
 

@@ -224,6 +224,12 @@ def test_plan_long_row_pieces_and_workspace():
     P = check_plan(mg.CSR(3, 60_000, rp1, (np.arange(rp1[-1]) % 60_000).astype(np.int32), np.ones(rp1[-1]), 1),
                    {"tile_nnz": 1024})
     assert P["info"]["n_long_pieces"] == 2 and P["info"]["workspace_bytes"] == 0
+    # spmv_params.long_rows is 0 (split where scratch exists) or 1
+    for bad in (-1, 2):
+        with pytest.raises(spmv.SpmvError) as e:
+            spmv.plan_inspect(3, 60_000, rp1, (np.arange(rp1[-1]) % 60_000).astype(np.int32),
+                              {"tile_nnz": 1024, "long_rows": bad})
+        assert e.value.code == spmv.SPMV_EINVAL
 
 
 @pytest.mark.parametrize("ring", [256, 1024, 4096])

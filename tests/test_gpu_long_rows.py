@@ -1,11 +1,13 @@
 """GPU parity of rows longer than a tile, summed in pieces of 16,384 stored
-entries: spmv_apply walks a row's pieces on one workgroup, spmv_apply_ws
-gives each piece a workgroup of its own and adds the pieces' sums in a
-second launch.  Both must give the same bits, meet the oracle's per-row
-bound (equal it bit for bit on dyadic inputs), and so must the products and
-solvers built on them: k-vector products, SELL handles, CG (whose workspace
-holds the piece sums) against the allocation-free solve (one workgroup per
-row), a graph-captured spmv_apply_ws.
+entries.  Each piece runs on a workgroup of its own and a second launch adds
+the pieces' sums, kept in scratch: the output vector's own rows (the longest
+run without a long row, written by the same call afterwards; spmv_apply and
+every product), or the caller's workspace (spmv_apply_ws).  Without scratch,
+or with spmv_params.long_rows = 1, one workgroup walks a row's pieces.  All
+must give the same bits, meet the oracle's per-row bound (equal it bit for
+bit on dyadic inputs), and so must the products and solvers built on them:
+k-vector products, SELL handles, FP32 and BF16 products, CG in every mode
+and the allocation-free solve, graph-captured products.
 
 Acceptance as in the other SpMV parity tests: binary64 within
 1e-12 * sum_k |a_ik||x_k| per row; FP32 within (m + 2) * 2^-24 of that bound
@@ -73,17 +75,48 @@ def assert_parity(y, A, x, rtol=oracle.SPMV_RTOL):
 def test_pieces_on_their_own_workgroups_equal_one_workgroup_per_row(mats, tile_nnz):
     A, _, where = mats
     x = mg.uniform(A.n_cols, 5, 1)
+    xd = to_dev(x)
     with spmv.Matrix.from_csr(A, params={"tile_nnz": tile_nnz}) as M:
         inf = M.info
         cap = tile_nnz - 3
         assert inf["n_long_rows"] == sum(1 for L in LENS if L > cap)
         assert inf["n_long_pieces"] == _pieces(LENS, cap)
         assert M.workspace_bytes == inf["workspace_bytes"] == 8 * inf["n_long_pieces"]
+        assert inf["y_scratch_ok"] == 1
+        y_out = M.apply(xd).cpu().numpy()        # scratch in the output's rows
+        y_ws = M.apply_ws(xd).cpu().numpy()      # scratch from the caller
+    with spmv.Matrix.from_csr(A, params={"tile_nnz": tile_nnz, "long_rows": 1}) as M1:
+        assert M1.info["y_scratch_ok"] == 0
+        y_one = M1.apply(xd).cpu().numpy()       # one workgroup per row
+        y_one_ws = M1.apply_ws(xd).cpu().numpy()  # long_rows = 1 holds with a workspace too
+    assert np.array_equal(y_out, y_ws)
+    assert np.array_equal(y_out, y_one)
+    assert np.array_equal(y_out, y_one_ws)
+    assert_parity(y_out, A, x)
+
+
+def test_no_room_in_the_output_falls_back_to_one_workgroup_per_row():
+    # long rows (3 pieces each) alternate with single short rows: no run of
+    # short rows holds the 96 pieces' sums, so spmv_apply walks each long
+    # row on one workgroup; spmv_apply_ws still splits; same bits
+    rl = np.full(64, 5)
+    rl[::2] = 40_000
+    rng = np.random.default_rng(75)
+    rp = np.concatenate([[0], np.cumsum(rl)]).astype(np.int32)
+    A = mg.CSR(64, 50_000, rp, rng.integers(0, 50_000, int(rp[-1])).astype(np.int32),
+               rng.uniform(-1.0, 1.0, int(rp[-1])), 1)
+    x = mg.uniform(A.n_cols, 17, 1)
+    with spmv.Matrix.from_csr(A, fp32=True, params={"tile_nnz": 1024}) as M:
+        assert M.info["n_long_pieces"] == 96 and M.info["y_scratch_ok"] == 0
         xd = to_dev(x)
         y1 = M.apply(xd).cpu().numpy()
         y2 = M.apply_ws(xd).cpu().numpy()
+        y32 = M.apply_f32(xd.float()).cpu().numpy()
     assert np.array_equal(y1, y2)
-    assert_parity(y2, A, x)
+    assert_parity(y1, A, x)
+    y_ref, bound = oracle.spmv(A, x)
+    m = np.maximum(np.diff(A.row_ptr), 1).astype(np.float64)
+    assert (np.abs(y32.astype(np.float64) - y_ref) <= 1.01 * (m + 2) * 2.0 ** -24 * bound).all()
 
 
 def test_dyadic_long_rows_equal_the_oracle_bitwise(mats):
@@ -172,25 +205,36 @@ def test_k_vector_products_on_long_rows_equal_single_products(mats):
 def test_sell_handle_long_rows(mats):
     A, _, _ = mats
     x = mg.uniform(A.n_cols, 11, 1)
+    xd = to_dev(x)
     with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL}) as M:
         assert M.info["n_long_pieces"] == _pieces(LENS, 255)
-        assert M.workspace_bytes == 8 * M.info["n_long_pieces"]
-        xd = to_dev(x)
+        assert M.workspace_bytes == 8 * M.info["n_long_pieces"] and M.info["y_scratch_ok"] == 1
         y1 = M.apply(xd).cpu().numpy()
         y2 = M.apply_ws(xd).cpu().numpy()
-    assert np.array_equal(y1, y2)
+    with spmv.Matrix.from_csr(A, params={"format": spmv.FORMAT_SELL, "long_rows": 1}) as M1:
+        y3 = M1.apply(xd).cpu().numpy()
+    assert np.array_equal(y1, y2) and np.array_equal(y1, y3)
     assert_parity(y2, A, x)
 
 
 def test_reduced_precision_long_rows(mats):
+    # the FP32 and BF16 products split the long rows in their output's rows
+    # (4 bytes each: two per piece sum); same bits as one workgroup per row
     A, _, _ = mats
     x = mg.uniform(A.n_cols, 12, 1)
     y_ref, bound = oracle.spmv(A, x)
     m = np.maximum(np.diff(A.row_ptr), 1).astype(np.float64)
+    x32 = to_dev(x, torch.float32)
+    with spmv.Matrix.from_csr(A, fp32=True, bf16=True, params={"long_rows": 1}) as M1:
+        one = [M1.apply_f32(x32).cpu().numpy(), M1.apply_bf16(x32).cpu().numpy(),
+               M1.apply_f32v(to_dev(x)).cpu().numpy()]
     with spmv.Matrix.from_csr(A, fp32=True, bf16=True) as M:
-        x32 = to_dev(x, torch.float32)
+        split = [M.apply_f32(x32).cpu().numpy(), M.apply_bf16(x32).cpu().numpy(),
+                 M.apply_f32v(to_dev(x)).cpu().numpy()]
         y32 = M.apply_f32(x32).cpu().numpy().astype(np.float64)
         y16 = M.apply_bf16(x32).cpu().numpy().astype(np.float64)
+    for a, b in zip(one, split):
+        assert np.array_equal(a, b)
     # x rounded to FP32 adds 2^-24 per product: inside the (m + 2) term
     assert (np.abs(y32 - y_ref) <= 1.01 * (m + 2) * 2.0 ** -24 * bound).all()
     assert (np.abs(y16 - y_ref) <= 1.01 * (2.0 ** -8 + (m + 1) * 2.0 ** -24) * bound).all()
@@ -226,10 +270,14 @@ def test_cg_with_long_rows_split_equals_one_workgroup_per_row(arrow):
     with spmv.Matrix.from_csr(A, fp32=True, bf16=True) as M:
         assert M.info["n_long_rows"] == 3 and M.workspace_bytes > 0
         b = to_dev(mg.uniform(A.n_rows, 13, 4))
-        x1, i1 = M.cg(b, tol=1e-10)            # pieces on their own workgroups
-        x2, i2 = M.cg_noalloc(b, tol=1e-10)    # one workgroup per long row
+        x1, i1 = M.cg(b, tol=1e-10)            # pieces' sums in the solver's workspace
+        x2, i2 = M.cg_noalloc(b, tol=1e-10)    # ... in the product's output rows
         assert i1.iterations == i2.iterations
         assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+        with spmv.Matrix.from_csr(A, params={"long_rows": 1}) as M1:
+            x3, i3 = M1.cg(b, tol=1e-10)       # one workgroup per long row
+        assert i3.iterations == i1.iterations
+        assert np.array_equal(x1.cpu().numpy(), x3.cpu().numpy())
         # the FP32 and bfloat16 products of the other solvers split the long
         # rows the same way
         xm, im = M.cg(b, tol=1e-10, mode=spmv.CG_MIXED_FP32)
@@ -241,30 +289,33 @@ def test_cg_with_long_rows_split_equals_one_workgroup_per_row(arrow):
         assert np.linalg.norm(bh - Ax) / np.linalg.norm(bh) <= 1.05e-10
 
 
-def test_apply_ws_replays_from_a_graph(mats):
+def test_split_products_replay_from_a_graph(mats):
     A, _, _ = mats
-    with spmv.Matrix.from_csr(A) as M:
+    with spmv.Matrix.from_csr(A, params={"long_rows": 1}) as M1, spmv.Matrix.from_csr(A) as M:
         x = torch.zeros(A.n_cols, dtype=torch.float64, device=DEV)
         y = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+        y2 = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
         ws = torch.empty(M.workspace_bytes // 8, dtype=torch.float64, device=DEV)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             M.apply_ws(x, y, ws=ws)
+            M.apply(x, y2)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             M.apply_ws(x, y, ws=ws)
+            M.apply(x, y2)
         for rep in range(3):
             xr = mg.uniform(A.n_cols, 14, rep)
             x.copy_(to_dev(xr))
             torch.cuda.synchronize()
             g.replay()
             torch.cuda.synchronize()
-            got = y.cpu().numpy()
-            ref = M.apply(to_dev(xr)).cpu().numpy()
-            assert np.array_equal(got, ref), rep
+            ref = M1.apply(to_dev(xr)).cpu().numpy()   # one workgroup per row, eagerly
+            assert np.array_equal(y.cpu().numpy(), ref), rep
+            assert np.array_equal(y2.cpu().numpy(), ref), rep
 
 
 def test_server_products_and_solves_on_long_rows(mats, arrow):
