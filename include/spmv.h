@@ -231,7 +231,10 @@ int spmv_apply(const spmv_matrix *A, const double *x, double *y, void *stream);
  * 8 per long-row piece when some row has more than one piece, else 0.
  * Errors: SPMV_EINVAL (NULL argument).
  *
- * spmv_apply_ws: spmv_apply with the pieces of the long rows side by side.
+ * spmv_apply_ws: spmv_apply with the long rows' pieces on a workgroup each
+ * and their sums in the caller's workspace, also where the output has no
+ * room for them (spmv_info.y_scratch_ok = 0); with spmv_params.long_rows = 1
+ * the handle keeps one workgroup per row here too.
  *   ws        caller-owned device memory of at least ws_bytes bytes, 8-byte
  *             aligned, holding the pieces' sums between the two launches;
  *             not to be shared by products that may run at the same time
