@@ -11,8 +11,10 @@
 // the rounded products one by one starting from zero, exactly as the
 // single-vector product sums a row, so column j of Y equals the
 // single-vector product of column j of X bit for bit.  A row longer than a
-// tile gets one workgroup per (row, column) with the lane-strided partial
-// sums and the fixed-shape reduction of the single-vector long-row kernel.
+// tile is summed as the single-vector product sums it (pieces of 16,384
+// entries): one workgroup per (piece, column) with the pieces' sums in Y's
+// rows of the longest run without a long row, or, without room there, one
+// workgroup per (row, column) walking the pieces.
 // The values are read once for all k columns, which is what the batched
 // requests of a serving workload need.  One column goes to the
 // single-vector product.  Measured on the 16M-row mesh matrix against k
@@ -131,6 +133,48 @@ __global__ __launch_bounds__(kBlock) void k_spmm_long(const TileDesc *__restrict
     if (threadIdx.x == 0) Y[(size_t)d.r0 * k + j] = tot;
 }
 
+// Several workgroups per long row: one per (piece, column), its sum to
+// ws[piece * k + column] ...
+__global__ __launch_bounds__(kBlock) void k_spmm_long_pieces(const TileDesc *__restrict__ desc,
+                                                             const int32_t *__restrict__ piece_long,
+                                                             const int32_t *__restrict__ piece_ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val,
+                                                             const double *__restrict__ X, double *__restrict__ ws,
+                                                             int k) {
+    __shared__ double sh[kBlock / kWave];
+    const int pc = (int)blockIdx.x, j = (int)blockIdx.y;
+    const int li = piece_long[pc];
+    const TileDesc d = desc[li];
+    const int ps = d.s + (pc - piece_ptr[li]) * kLongPiece;
+    const auto gx = [X, k, j](int c) { return X[(size_t)c * k + j]; };
+    const double t = long_piece_sum<double>(val, col, ps, min(d.e, ps + kLongPiece), gx, sh);
+    if (threadIdx.x == 0) ws[(size_t)pc * k + j] = t;
+}
+
+// ... then one wavefront per (long row, column) adds them in piece order,
+// 64 sums per load round trip, as the single-vector combine does.
+__global__ __launch_bounds__(kBlock) void k_spmm_long_combine(const TileDesc *__restrict__ desc,
+                                                              const int32_t *__restrict__ piece_ptr,
+                                                              const double *__restrict__ ws, double *__restrict__ Y,
+                                                              int n_long, int k) {
+    const int li = (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+    if (li >= n_long) return;  // the same for every lane of the wavefront
+    const int j = (int)blockIdx.y;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int p0 = piece_ptr[li], p1 = piece_ptr[li + 1];
+    double tot = 0.0;
+    for (int b = p0; b < p1; b += kWave) {
+        const int n = min(kWave, p1 - b);
+        const double v = lane < n ? ws[(size_t)(b + lane) * k + j] : 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double w = __shfl(v, i, kWave);
+            tot = b == p0 && i == 0 ? w : tot + w;
+        }
+    }
+    if (lane == 0) Y[(size_t)desc[li].r0 * k + j] = tot;
+}
+
 template <int KC, int U>
 static void launch_tiles(const TileDesc *desc, int n, bool remap, const DevMatrix &M, const double *X, double *Y,
                          int k, int cap, hipStream_t st) {
@@ -154,6 +198,21 @@ hipError_t launch_spmm(const spmv_matrix *A, const double *X, double *Y, int k, 
     if (k == 1) return launch_spmv<double, double, double, double>(M, M.val64, X, Y, EPI_PLAIN, nullptr, nullptr,
                                                                    nullptr, st);
     const int cap = std::max(A->max_tile_entries, 1);
+    if (M.n_long > 0) {
+        // first: the pieces' sums can live in Y's rows of the longest run
+        // without a long row, which the row tiles below write afterwards
+        if (M.piece_long && M.long_split && M.y_ws_rows >= M.n_long_pieces) {
+            double *ws = Y + (size_t)M.y_ws_row * k;
+            hipLaunchKernelGGL(k_spmm_long_pieces, dim3(M.n_long_pieces, k), dim3(kBlock), 0, st, M.long_desc,
+                               M.piece_long, M.long_piece_ptr, M.col, M.val64, X, ws, k);
+            constexpr int kRowsPerWg = kBlock / kWave;
+            hipLaunchKernelGGL(k_spmm_long_combine, dim3((M.n_long + kRowsPerWg - 1) / kRowsPerWg, k), dim3(kBlock), 0,
+                               st, M.long_desc, M.long_piece_ptr, ws, Y, M.n_long, k);
+        } else {
+            hipLaunchKernelGGL(k_spmm_long, dim3(M.n_long, k), dim3(kBlock), 0, st, M.long_desc, M.col, M.val64, X,
+                               Y, k);
+        }
+    }
     const struct {
         const TileDesc *desc;
         int n;
@@ -164,8 +223,6 @@ hipError_t launch_spmm(const spmv_matrix *A, const double *X, double *Y, int k, 
         else if (k >= 2) launch_tiles<2, 8>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
         else launch_tiles<1, 16>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
     }
-    if (M.n_long > 0)
-        hipLaunchKernelGGL(k_spmm_long, dim3(M.n_long, k), dim3(kBlock), 0, st, M.long_desc, M.col, M.val64, X, Y, k);
     return hipGetLastError();
 }
 

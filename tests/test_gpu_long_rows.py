@@ -192,11 +192,16 @@ def test_no_split_without_rows_of_several_pieces():
 
 
 def test_k_vector_products_on_long_rows_equal_single_products(mats):
+    # the pieces of the k columns on a workgroup each (their sums in Y's own
+    # rows) and one workgroup per (row, column): both equal the single
+    # products column by column
     A, _, _ = mats
     k = 3
     X = mg.uniform(A.n_cols * k, 10, 1).reshape(A.n_cols, k)
-    with spmv.Matrix.from_csr(A) as M:
+    with spmv.Matrix.from_csr(A) as M, spmv.Matrix.from_csr(A, params={"long_rows": 1}) as M1:
         Y = M.spmm(to_dev(X)).cpu().numpy()
+        Y1 = M1.spmm(to_dev(X)).cpu().numpy()
+        assert np.array_equal(Y, Y1)
         for j in range(k):
             yj = M.apply_ws(to_dev(X[:, j])).cpu().numpy()
             assert np.array_equal(Y[:, j], yj), j
