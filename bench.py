@@ -828,6 +828,12 @@ def main():
         extras["fp32_spmv_frac_of_peak"] = round(B32 / t32 / 1e9 / PEAK_HBM_GBS, 4)
         extras["fp64_spmv_GFLOPs"] = round(2 * A.nnz / t_step / 1e9, 2)
         log(f"FP32 SpMV: {t32 * 1e3:.4f} ms, {extras['fp32_spmv_GBs']} GB/s")
+        # bfloat16 values with FP32 x, y and accumulation (the preconditioner's product)
+        t16 = time_launches(lambda: M.apply_bf16(x32, y32), max(10, args.steps // 2), 3, torch, WARM_S)
+        B16 = alg_bytes(A.n_rows, A.n_cols, A.nnz, 2, 4, 4)
+        extras["bf16_spmv_ms"] = round(t16 * 1e3, 4)
+        extras["bf16_spmv_GBs"] = round(B16 / t16 / 1e9, 2)
+        log(f"BF16 SpMV: {t16 * 1e3:.4f} ms, {extras['bf16_spmv_GBs']} GB/s")
         # HBM ceiling of a plain device copy (1 GiB each way)
         buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(buf)
