@@ -342,3 +342,39 @@ def test_server_products_and_solves_on_long_rows(mats, arrow):
             assert np.array_equal(out[j], M.apply(to_dev(X[j])).cpu().numpy()), j
     Ax, _ = oracle.spmv(arrow, xs)
     assert np.linalg.norm(b - Ax) / np.linalg.norm(b) <= 1.05e-9
+
+
+def _run_layout(lead_long, run, n_long, L=20_000, n_cols=60_000, seed=76):
+    """Rows: an optional long row, a run of `run` short rows, then n_long
+    long rows (two pieces each) alternating with single short rows."""
+    rl = ([L] if lead_long else []) + [4] * run
+    for _ in range(n_long):
+        rl += [L, 3]
+    rl = np.array(rl, np.int64)
+    rng = np.random.default_rng(seed)
+    rp = np.concatenate([[0], np.cumsum(rl)]).astype(np.int32)
+    return mg.CSR(len(rl), n_cols, rp, rng.integers(0, n_cols, int(rp[-1])).astype(np.int32),
+                  rng.uniform(-1.0, 1.0, int(rp[-1])), 1)
+
+
+def test_output_scratch_at_its_size_limits():
+    # binary64: a run of exactly as many rows as pieces holds the sums; FP32
+    # (4-byte rows) needs two rows per sum, and one more when the run starts
+    # at an odd row (the sums are 8-byte aligned)
+    # (binary64 fits exactly / one row short; FP32 fits exactly after the
+    # 4-byte alignment shift / one row short)
+    cases = [(False, 24, 12), (False, 23, 12), (True, 57, 13), (True, 56, 13)]
+    for lead, run, n_long in cases:
+        A = _run_layout(lead, run, n_long)
+        pieces = 2 * (n_long + (1 if lead else 0))
+        x = mg.uniform(A.n_cols, 18, 1)
+        xd = to_dev(x)
+        with spmv.Matrix.from_csr(A, fp32=True, params={"tile_nnz": 1024}) as M, \
+                spmv.Matrix.from_csr(A, fp32=True, params={"tile_nnz": 1024, "long_rows": 1}) as M1:
+            assert M.info["n_long_pieces"] == pieces
+            assert M.info["y_scratch_ok"] == (1 if run >= pieces else 0)
+            y, y1 = M.apply(xd).cpu().numpy(), M1.apply(xd).cpu().numpy()
+            f, f1 = M.apply_f32(xd.float()).cpu().numpy(), M1.apply_f32(xd.float()).cpu().numpy()
+        assert np.array_equal(y, y1), (lead, run)
+        assert np.array_equal(f, f1), (lead, run)
+        assert_parity(y, A, x)
