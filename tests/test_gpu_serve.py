@@ -105,6 +105,30 @@ def test_server_spmv_equals_direct_apply(pool):
             assert np.array_equal(y, out[j])
 
 
+def test_staged_copies_at_chunk_boundaries():
+    # a 131,072-row matrix: k vectors move k MB each way, so k = 3 goes
+    # through the runtime's copy, k = 4 is the smallest staged buffer (4 MB),
+    # 16 and 32 fill one and two 16 MB chunks exactly, 33 leaves a 1 MB
+    # tail chunk; every result bitwise equal to the handle's own product,
+    # several requests in flight at once so lanes stage concurrently
+    n = 131_072
+    A = mg.random_csr(n, n, seed=21, mean_len=6.0, empty_frac=0.05, duplicates=True)
+    ks = [3, 4, 16, 32, 33, 4, 17]
+    Xs = [mg.uniform(k * n, 300 + i, 3).reshape(k, n) for i, k in enumerate(ks)]
+    with spmv.Server(n_lanes=3) as srv:
+        srv.add_matrix(A)
+        tickets = [srv.submit_spmv(0, X) for X in Xs]
+        outs = []
+        for t in tickets:
+            out, res = srv.wait(t)
+            _ok(res)
+            outs.append(out)
+    with spmv.Matrix.from_csr(A) as M:
+        for X, out in zip(Xs, outs):
+            Y = M.spmm(torch.as_tensor(np.ascontiguousarray(X.T), device="cuda")).cpu().numpy()
+            assert np.array_equal(Y.T, out), X.shape
+
+
 def test_budget_eviction_and_rejection(pool):
     small = pool[:4]
     est = lambda A: 12 * (A.nnz + 20) + 4 * (A.n_rows + 1) + 64 * (A.nnz // 512 + 16)
