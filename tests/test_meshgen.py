@@ -161,3 +161,25 @@ def test_tet_like_stand_in_matches_table1_shape():
     assert np.all(d > 0) and np.all(d - off > 0.9e-3)
     B = mg.tet_like(mg.TABLE1_ROWS["C50K"])
     assert np.array_equal(A.col_idx, B.col_idx) and np.array_equal(A.values, B.values)
+
+
+def test_with_long_rows_replaces_only_the_chosen_rows():
+    """with_long_rows: n_long rows spread over the matrix get `length`
+    sorted distinct columns; every other row keeps its entries; seeded."""
+    A = mg.lattice(12, 12, 12, "extras", seed=3)
+    B = mg.with_long_rows(A, 5, 1500, seed=9)
+    la, lb = np.diff(A.row_ptr), np.diff(B.row_ptr)
+    long_rows = np.nonzero(lb == 1500)[0]
+    assert len(long_rows) == 5 and long_rows.min() > 0 and long_rows.max() < A.n_rows - 1
+    keep = np.setdiff1d(np.arange(A.n_rows), long_rows)
+    assert np.array_equal(la[keep], lb[keep])
+    for r in keep[::37]:
+        assert np.array_equal(A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]], B.col_idx[B.row_ptr[r]:B.row_ptr[r + 1]])
+        assert np.array_equal(A.values[A.row_ptr[r]:A.row_ptr[r + 1]], B.values[B.row_ptr[r]:B.row_ptr[r + 1]])
+    for r in long_rows:
+        c = B.col_idx[B.row_ptr[r]:B.row_ptr[r + 1]]
+        assert np.all(np.diff(c) > 0) and c[0] >= 0 and c[-1] < A.n_cols
+    C = mg.with_long_rows(A, 5, 1500, seed=9)
+    assert np.array_equal(B.col_idx, C.col_idx) and np.array_equal(B.values, C.values)
+    with pytest.raises(ValueError):
+        mg.with_long_rows(A, 1, A.n_cols + 1, seed=9)
