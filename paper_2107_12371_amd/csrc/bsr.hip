@@ -48,11 +48,11 @@ template <typename V> struct BsrStage {
 // Measured on the 4M-block-row operator (FP64 / FP32 ms, k = 1, 4, 8):
 // 0.643 / 0.402, 0.813 / 0.413, 1.199 / 0.588.
 template <typename T, int K> struct BsrShape;
-template <> struct BsrShape<double, 1> { static constexpr bool ROWS = false; static constexpr int JL = 1, U = 6; };
+template <> struct BsrShape<double, 1> { static constexpr bool ROWS = false; static constexpr int JL = 1, U = 6, P = 12; };
 template <> struct BsrShape<double, 2> { static constexpr bool ROWS = true; static constexpr int JL = 1, U = 3; };
 template <> struct BsrShape<double, 4> { static constexpr bool ROWS = true; static constexpr int JL = 2, U = 4; };
 template <> struct BsrShape<double, 8> { static constexpr bool ROWS = true; static constexpr int JL = 4, U = 2; };
-template <> struct BsrShape<float, 1> { static constexpr bool ROWS = false; static constexpr int JL = 1, U = 4; };
+template <> struct BsrShape<float, 1> { static constexpr bool ROWS = false; static constexpr int JL = 1, U = 4, P = 12; };
 template <> struct BsrShape<float, 2> { static constexpr bool ROWS = true; static constexpr int JL = 1, U = 4; };
 template <> struct BsrShape<float, 4> { static constexpr bool ROWS = true; static constexpr int JL = 4, U = 6; };
 template <> struct BsrShape<float, 8> { static constexpr bool ROWS = true; static constexpr int JL = 8, U = 6; };
@@ -281,17 +281,131 @@ __global__ __launch_bounds__(kBlock) void k_bsr3(BsrArgs<V, T> g) {
     const int cshift = (int)(((uintptr_t)cbase & 15) / 4);
     const i32x4 *csrc = reinterpret_cast<const i32x4 *>(cbase - cshift);
     const int ncv = max((q1 - q0 + cshift + 3) / 4, 1);
+    // the block-column load first, taken while the value loads are still in
+    // flight (loads complete in issue order)
+    i32x4 tc = __builtin_nontemporal_load(csrc + min(t, ncv - 1));
     i32x4 tv[S::kTrips];
 #pragma unroll
     for (int i = 0; i < S::kTrips; ++i) tv[i] = __builtin_nontemporal_load(vsrc + min(t + i * kBlock, nvv - 1));
-    const i32x4 tc = __builtin_nontemporal_load(csrc + min(t, ncv - 1));
+    asm volatile("" : "+v"(tc));
+    if (t < S::kColVecs) scol_raw[t] = tc;
 #pragma unroll
     for (int i = 0; i < S::kTrips; ++i) sval_raw[t + i * kBlock] = tv[i];
-    if (t < S::kColVecs) scol_raw[t] = tc;
     __syncthreads();
     const V *sval = reinterpret_cast<const V *>(sval_raw) + vshift;
     const int32_t *scol = reinterpret_cast<const int32_t *>(scol_raw) + cshift;
     bsr_pass2<V, T, K, VEC>(g, R0, R1, q0, sval, scol);
+}
+
+// One column, gathers in flight with the value stream.  Every lane issues
+// its block row's bounds, then the tile's block-column load, then its value
+// loads; as soon as the columns are in LDS (one barrier, values still in
+// flight) each triad lane issues the X gathers of its row's first P blocks
+// and only then waits for the values, so the gathers' round trip overlaps
+// the stream instead of following it.  Blocks past the first P are
+// gathered afterwards, U at a time.  Same per-output sum as bsr_triads.
+template <typename V, typename T>
+__global__ __launch_bounds__(kBlock) void k_bsr3_one(BsrArgs<V, T> g) {
+    using S = BsrStage<V>;
+    constexpr int P = BsrShape<T, 1>::P, U = BsrShape<T, 1>::U;
+    constexpr int kTriads = kWave / 3;
+    static_assert(kTriads * (kBlock / kWave) >= kBsrRows, "one triad per block row of a tile");
+    __shared__ i32x4 sval_raw[S::kTrips * kBlock];
+    __shared__ i32x4 scol_raw[S::kColVecs];
+    const int li = xcd_tile(blockIdx.x, g.per_xcd, g.chunk_log2);
+    if (li >= g.n_tiles) return;
+    const int t = (int)threadIdx.x;
+    const int lane = t & (kWave - 1);
+    const int r = lane % 3, first = lane - r;  // lane 63: r = 0, a triad of its own, never stored
+    const int R0 = g.tiles[li], R1 = g.tiles[li + 1];
+    const int nbr = R1 - R0;
+    const int brl = (t / kWave) * kTriads + lane / 3;
+    const bool live = lane < 3 * kTriads && brl < nbr;
+    const int br = R0 + min(brl, nbr - 1);
+    const int q0 = g.brow_ptr[R0], q1 = g.brow_ptr[R1];
+    if (q1 - q0 > kBsrBlocks) {  // one long block row: values from global memory
+        bsr_triads<V, T, U>(g, R0, R1, q0, g.val + 9 * (size_t)q0, g.col + q0);
+        return;
+    }
+    T *const yr = g.Y + (size_t)(3 * br + r) * g.ldy + g.off;
+    if (q1 == q0) {  // only empty block rows
+        if (live) *yr = T(0);
+        return;
+    }
+    // Pass 1, issued in this order: row bounds, block columns, values (the
+    // padding and alignment rules of k_bsr3 apply).
+    int a = g.brow_ptr[br], z = g.brow_ptr[br + 1];
+    const int32_t *cbase = g.col + q0;
+    const int cshift = (int)(((uintptr_t)cbase & 15) / 4);
+    const i32x4 *csrc = reinterpret_cast<const i32x4 *>(cbase - cshift);
+    const int ncv = max((q1 - q0 + cshift + 3) / 4, 1);
+    i32x4 tc = __builtin_nontemporal_load(csrc + min(t, ncv - 1));
+    const V *vbase = g.val + 9 * (size_t)q0;
+    const int vshift = (int)(((uintptr_t)vbase & 15) / sizeof(V));
+    const i32x4 *vsrc = reinterpret_cast<const i32x4 *>(vbase - vshift);
+    const int nvv = max((9 * (q1 - q0) + vshift + S::kVe - 1) / S::kVe, 1);
+    i32x4 tv[S::kTrips];
+#pragma unroll
+    for (int i = 0; i < S::kTrips; ++i) tv[i] = __builtin_nontemporal_load(vsrc + min(t + i * kBlock, nvv - 1));
+    // Take the bounds and columns here, with the value loads still in flight
+    // (loads complete in issue order, so this waits for the first two only).
+    asm volatile("" : "+v"(a), "+v"(z), "+v"(tc));
+    if (t < S::kColVecs) scol_raw[t] = tc;
+    __syncthreads();
+    const int32_t *scol = reinterpret_cast<const int32_t *>(scol_raw) + cshift;
+    // Gathers of the first P blocks.  An empty row reads the tile's first
+    // block (valid, discarded below); past the row's end the last block.
+    const int lo = z > a ? a - q0 : 0, hi = z > a ? z - 1 - q0 : 0;
+    T xo[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) xo[u] = g.X[(size_t)(3 * scol[min(lo + u, hi)] + r) * g.ldx + g.off];
+#pragma unroll
+    for (int i = 0; i < S::kTrips; ++i) sval_raw[t + i * kBlock] = tv[i];
+    __syncthreads();
+    const V *sval = reinterpret_cast<const V *>(sval_raw) + vshift;
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const int qq = min(lo + u, hi);
+        const T x0 = __shfl(xo[u], first, kWave);
+        const T x1 = __shfl(xo[u], first + 1, kWave);
+        const T x2 = __shfl(xo[u], first + 2, kWave);
+        const T a0 = static_cast<T>(sval[9 * qq + 3 * r]);
+        const T a1 = static_cast<T>(sval[9 * qq + 3 * r + 1]);
+        const T a2 = static_cast<T>(sval[9 * qq + 3 * r + 2]);
+        const bool in_row = a + u < z;
+        T s = acc;
+        s += a0 * x0;
+        s += a1 * x1;
+        s += a2 * x2;
+        acc = in_row ? s : acc;
+    }
+    // the rest of a row longer than P blocks (a triad's lanes share it)
+    for (int q = a + P; q < z; q += U) {
+        int qq[U];
+        T xg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            qq[u] = min(q + u, z - 1) - q0;
+            xg[u] = g.X[(size_t)(3 * scol[qq[u]] + r) * g.ldx + g.off];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T x0 = __shfl(xg[u], first, kWave);
+            const T x1 = __shfl(xg[u], first + 1, kWave);
+            const T x2 = __shfl(xg[u], first + 2, kWave);
+            const T a0 = static_cast<T>(sval[9 * qq[u] + 3 * r]);
+            const T a1 = static_cast<T>(sval[9 * qq[u] + 3 * r + 1]);
+            const T a2 = static_cast<T>(sval[9 * qq[u] + 3 * r + 2]);
+            const bool in_row = q + u < z;
+            T s = acc;
+            s += a0 * x0;
+            s += a1 * x1;
+            s += a2 * x2;
+            acc = in_row ? s : acc;
+        }
+    }
+    if (live) *yr = acc;
 }
 
 template <typename V, typename T, int K>
@@ -306,7 +420,8 @@ static void launch_k(BsrArgs<V, T> g, int grid, hipStream_t st) {
             return;
         }
     }
-    hipLaunchKernelGGL((k_bsr3<V, T, K, false>), dim3(grid), dim3(kBlock), 0, st, g);
+    if constexpr (K == 1) hipLaunchKernelGGL((k_bsr3_one<V, T>), dim3(grid), dim3(kBlock), 0, st, g);
+    else hipLaunchKernelGGL((k_bsr3<V, T, K, false>), dim3(grid), dim3(kBlock), 0, st, g);
 }
 
 template <typename V, typename T>

@@ -495,6 +495,39 @@ def test_bsr3_empty_rows_and_nonfinite_x(k):
     assert np.array_equal(Y32[np.isinf(Yr)], Yr[np.isinf(Yr)])
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_bsr3_one_column_rows_of_every_length(fp32):
+    # block rows of 0..40 blocks (the one-column kernel gathers a row's first
+    # 12 blocks with the value stream, the rest in rounds afterwards), a
+    # 700-block row (values read from global memory), tiles starting at odd
+    # block offsets: the one-column product equals column 0 of the
+    # two-column product bit for bit, and the oracle within its bound
+    nbr, nbc = 500, 900
+    rng = np.random.default_rng(21)
+    lens = rng.integers(0, 41, nbr)
+    lens[250] = 700
+    lens[300:330] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(nbc, size=L, replace=False)) for L in lens]).astype(np.int32)
+    va = rng.uniform(-1, 1, (ci.shape[0], 3, 3))
+    B = mg.CSR(nbr, nbc, rp, ci, va, 3)
+    X = mg.uniform(3 * nbc * 2, 50, 0).reshape(3 * nbc, 2)
+    dt = torch.float32 if fp32 else torch.float64
+    with spmv.Matrix.from_csr(B, fp32=fp32) as M:
+        assert M.info["n_tiles"] >= 8
+        mm = M.spmm_f32 if fp32 else M.spmm
+        Y2 = mm(to_dev(X, dt)).cpu().numpy()
+        Y1 = mm(to_dev(X[:, :1].copy(), dt)).cpu().numpy()
+    assert np.array_equal(Y1[:, 0], Y2[:, 0])
+    assert np.all(Y1[3 * 300:3 * 330] == 0)
+    if fp32:
+        Yr, Bd = oracle.bsr3_spmm(B, X[:, :1].astype(np.float32).astype(np.float64))
+        m = 3 * np.repeat(lens, 3)[:, None].astype(np.float64)
+        assert np.all(np.abs(Y1 - Yr) <= 1.01 * (m + 2) * 2.0 ** -24 * Bd)
+    else:
+        _bsr_bound_check(Y1, B, X[:, :1].copy(), 1e-12)
+
+
 def test_bsr3_config3_shape_bitwise_dyadic():
     A = mg.bsr3(40, 40, 20, seed=7)
     # dyadic copy of the values: multiples of 2^-10 in [-2, 2]
