@@ -5,12 +5,13 @@
 // holds cell i's neighbour blocks.  X and Y are row-major (3 n) x k, so the
 // k values of one scalar row sit contiguously and one gather brings all k.
 //
-// One workgroup per tile of up to 85 block rows and 510 stored blocks (the
+// One workgroup per tile of up to 84 block rows and 510 stored blocks (the
 // staged values of four tiles fill one CU's LDS).
 // Pass 1 stages the tile's block values (9 per block) and block columns in
 // LDS: every lane issues all of its 16-byte loads (fixed count, addresses
 // clamped to the tile) before the first LDS store, so the loads overlap.
-// Pass 2, one column: each lane owns one scalar row 3i+r.  Pass 2, k >= 2
+// Pass 2, one column (k_bsr3_one): each lane owns one scalar row 3i+r, and
+// the X gathers are issued while the value loads are in flight.  Pass 2, k >= 2
 // columns: each lane owns a block row and K/JL adjacent columns of Y (JL
 // lanes share the block row) and computes all three scalar rows, so every
 // gathered X row is read once, in 8- or 16-byte pieces when aligned.  A
