@@ -17,8 +17,8 @@
 // workgroup per (row, column) walking the pieces.
 // The values are read once for all k columns, which is what the batched
 // requests of a serving workload need.  One column goes to the
-// single-vector product.  Measured on the 16M-row mesh matrix against k
-// single products: 1.23x (k = 2), 1.68x (4), 2.31x (8), 3.0x (16).
+// single-vector product.  Measured on the 16M-row mesh matrix: 1.10 ms
+// (k = 4), 1.65 ms (8), 2.69 ms (16) against 0.52-0.54 ms for one column.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -219,9 +219,12 @@ hipError_t launch_spmm(const spmv_matrix *A, const double *X, double *Y, int k, 
     } lists[3] = {{M.stream_desc, M.n_stream}, {M.cwin_desc, M.n_cwin}, {M.win_desc, A->n_win_tiles}};
     for (const auto &l : lists) {
         if (l.n <= 0) continue;
-        if (k >= 4) launch_tiles<4, 4>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
-        else if (k >= 2) launch_tiles<2, 8>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
-        else launch_tiles<1, 16>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
+        // two columns per lane for every k: the lanes sharing a row gather
+        // its X row in 16-byte pieces side by side, so one gather
+        // instruction touches half as many cache lines as with four
+        // columns per lane (16M-row mesh matrix, k = 4 / 8 / 16: 1.10 /
+        // 1.65 / 2.69 ms against 1.32 / 1.87 / 2.86 ms)
+        launch_tiles<2, 8>(l.desc, l.n, M.xcd_remap, M, X, Y, k, cap, st);
     }
     return hipGetLastError();
 }
