@@ -292,14 +292,18 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
     # closed-loop capacity: two bursts of requests on matrices drawn as in the
     # stream, the second one timed
     burst = [make(-1 - i) for i in range(min(64, n_requests))]
+    tb = time.perf_counter()
     for t in [submit(r) for r in burst]:
         srv.wait(t)
+    log(f"serving: first burst of {len(burst)} requests done ({time.perf_counter() - tb:.1f} s)")
     burst2 = [make(-1000 - i) for i in range(min(64, n_requests))]
     tb = time.perf_counter()
     for t in [submit(r) for r in burst2]:
         srv.wait(t)
     cap = len(burst2) / (time.perf_counter() - tb)
     lam = rate if rate > 0 else 0.7 * cap
+    log(f"serving: capacity {cap:.1f} req/s on a burst, arrivals at {lam:.1f} req/s "
+        f"({n_requests / lam:.0f} s of submissions)")
     reqs = [make(i) for i in range(n_requests)]
     gaps = np.random.default_rng(seed + 1).exponential(1.0 / lam, n_requests)
     tickets = [None] * n_requests
@@ -313,6 +317,8 @@ def serving_run(pool, n_requests: int, seed: int, cg_mode: int, preload: bool = 
             if d > 0:
                 time.sleep(d)
             tickets[i] = submit(r)
+            if i % 512 == 511:
+                log(f"serving: {i + 1} of {n_requests} requests submitted ({time.perf_counter() - start:.1f} s)")
 
     th = threading.Thread(target=driver)
     t1 = time.perf_counter()
