@@ -548,7 +548,7 @@ def config_lines(torch, log=log) -> dict:
 
 CASES = ("bsr3_k1_fp64", "bsr3_k8_fp64", "bsr3_k1_fp32", "bsr3_k8_fp32", "bsr3_k4_fp64", "bsr3_k4_fp32",
          "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k", "cg1_fp64_c50k",
-         "cg1_fp64_c800k", "cg_fp64_c800k", "long_rows_one_wg", "long_rows_pieces")
+         "cg1_fp64_c800k", "cg_fp64_c800k", "long_rows_one_wg", "long_rows_pieces", "knn_rcm", "knn_random")
 
 
 def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibration: bool) -> list[dict]:
@@ -569,7 +569,9 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       long_rows_one_wg  the 126^3 kNN matrix with 16 rows of 2^20 entries,
                   one workgroup per long row (spmv_params.long_rows = 1)
       long_rows_pieces  the same, one workgroup per 16,384-entry piece (the
-                  default spmv_apply, the pieces' sums in the output's rows)"""
+                  default spmv_apply, the pieces' sums in the output's rows)
+      knn_rcm, knn_random  the 126^3 kNN matrix (2M rows) in RCM or random
+                  order, FP64, default plan (the ordering effect on x gathers)"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -625,6 +627,19 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
                 t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
                 out["info"] = {k: M.info[k] for k in ("n_long_rows", "n_long_pieces", "y_scratch_ok")}
             out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+            del x, y
+        elif name.startswith("knn_"):
+            ordering = name.split("_", 1)[1]
+            if name not in mats:
+                mats[name] = mg.config1(ordering)
+            A = mats[name]
+            x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+            y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+            with spmv.Matrix.from_csr(A) as M:
+                t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
+                out["info"] = {k: M.info[k] for k in ("tile_nnz", "n_tiles", "n_window_tiles")}
+            out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+            out["rows"], out["nnz"] = A.n_rows, A.nnz
             del x, y
         elif name == "copy":
             buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
