@@ -548,7 +548,8 @@ def config_lines(torch, log=log) -> dict:
 
 CASES = ("bsr3_k1_fp64", "bsr3_k8_fp64", "bsr3_k1_fp32", "bsr3_k8_fp32", "bsr3_k4_fp64", "bsr3_k4_fp32",
          "spmm_k8", "sell", "fp32", "csr_direct", "copy", "cg_fp64_16m", "cg_fp64_c50k", "cg1_fp64_c50k",
-         "cg1_fp64_c800k", "cg_fp64_c800k", "long_rows_one_wg", "long_rows_pieces", "knn_rcm", "knn_random")
+         "cg1_fp64_c800k", "cg_fp64_c800k", "long_rows_one_wg", "long_rows_pieces", "knn_rcm", "knn_random", "mesh32_direct",
+         "mesh32_compact", "mesh32_ring8")
 
 
 def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibration: bool) -> list[dict]:
@@ -571,7 +572,10 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
       long_rows_pieces  the same, one workgroup per 16,384-entry piece (the
                   default spmv_apply, the pieces' sums in the output's rows)
       knn_rcm, knn_random  the 126^3 kNN matrix (2M rows) in RCM or random
-                  order, FP64, default plan (the ordering effect on x gathers)"""
+                  order, FP64, default plan (the ordering effect on x gathers)
+      mesh32_direct, mesh32_compact, mesh32_ring8  the 32^3 mesh matrix with
+                  1024-entry tiles: direct gathers, compact windows, and the
+                  paper's circular cache (LDS ring of 8192 words, blocks of 8)"""
     import torch
     import meshgen as mg
     import paper_2107_12371_amd as spmv
@@ -627,6 +631,22 @@ def run_cases(names: list[str], steps: int, warmup: int, m: int, copy_calibratio
                 t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
                 out["info"] = {k: M.info[k] for k in ("n_long_rows", "n_long_pieces", "y_scratch_ok")}
             out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+            del x, y
+        elif name.startswith("mesh32_"):
+            params = {"mesh32_direct": {"window_mode": spmv.WINDOW_OFF, "tile_nnz": 1024},
+                      "mesh32_compact": {"window_mode": spmv.WINDOW_AUTO, "tile_nnz": 1024},
+                      "mesh32_ring8": {"window_mode": spmv.WINDOW_RING, "tile_nnz": 1024, "ring_words": 8192,
+                                       "window_block": 8}}[name]
+            if "mesh32" not in mats:
+                mats["mesh32"] = mg.config0()
+            A = mats["mesh32"]
+            x = torch.as_tensor(mg.uniform(A.n_cols, 5, 1), device="cuda")
+            y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+            with spmv.Matrix.from_csr(A, params=params) as M:
+                t = time_launches(lambda: M.apply(x, y), steps, warmup, torch)
+                out["info"] = {k: M.info[k] for k in ("tile_nnz", "n_tiles", "n_window_tiles")}
+            out["alg_bytes"] = alg_bytes(A.n_rows, A.n_cols, A.nnz, 8, 8, 8)
+            out["rows"], out["nnz"] = A.n_rows, A.nnz
             del x, y
         elif name.startswith("knn_"):
             ordering = name.split("_", 1)[1]
