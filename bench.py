@@ -455,7 +455,7 @@ def config_lines(torch, log=log) -> dict:
             t = time_launches(lambda: M.apply(x, y), 200, 20, torch, WARM_S)
             c10, c50, c90 = time_cold(lambda: M.apply(x, y), 50, torch, scratch)
             inf = M.info
-        c0[name] = {"us": round(t * 1e6, 2), "GBs_L2_resident": round(B / t / 1e9, 1),
+        c0[name] = {"us": round(t * 1e6, 2), "GBs_warm": round(B / t / 1e9, 1),
                     "cold_us_p10_p50_p90": [round(c10 * 1e6, 2), round(c50 * 1e6, 2), round(c90 * 1e6, 2)],
                     "GBs_cold_p50": round(B / c50 / 1e9, 1),
                     "window_tiles": inf["n_window_tiles"], "window_words": inf["window_words"]}
