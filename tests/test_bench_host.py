@@ -71,3 +71,16 @@ def test_csr_byte_convention():
 def test_dominant_kernel_follows_the_plan(win, tiles, expect):
     name, stem = bench.dominant_kernel({"n_window_tiles": win, "n_tiles": tiles, "tile_nnz": 2048})
     assert stem.startswith(expect) and name.startswith(expect[:-4] + "<double")
+
+
+def test_serving_child_is_ended_when_it_stops_printing(monkeypatch):
+    monkeypatch.setattr(bench, "SERVE_STALL_S", 2)
+    quiet = [sys.executable, "-c", "import sys, time; print('step', file=sys.stderr, flush=True); time.sleep(60)"]
+    r = bench.serving_in_child(None, cmd=quiet)
+    assert r == {"failed": "no progress for 2 s"}
+    talk = [sys.executable, "-c", "import sys, time\n"
+            "for i in range(4):\n    print('step', i, file=sys.stderr, flush=True); time.sleep(0.5)\n"
+            "print('{\"preloaded\": {\"p50_ms\": 1.0}}', flush=True)"]
+    assert bench.serving_in_child(None, cmd=talk) == {"preloaded": {"p50_ms": 1.0}}
+    failing = [sys.executable, "-c", "raise SystemExit(3)"]
+    assert bench.serving_in_child(None, cmd=failing) == {"failed": "child exit status 3"}
