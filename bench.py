@@ -88,6 +88,10 @@ WARM_S = 0.05
 # the serving child is ended after this long without a progress line (its
 # steps print every few seconds)
 SERVE_STALL_S = 120
+# fixed Poisson arrival rate of the serving streams (requests/s): 0.7x the
+# capacity the stream with uploads on first touch measured on its bursts,
+# about 0.36x the preloaded pool's closed-loop capacity
+SERVE_RATE_RPS = 168.0
 
 
 def alg_bytes(n_rows, n_cols, nnz, val_bytes, x_bytes, y_bytes):
@@ -387,7 +391,8 @@ def serving_in_child(args, cmd=None) -> dict:
     if cmd is None:
         cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only",
                "--serve-requests", str(args.serve_requests), "--serve-pool", str(args.serve_pool),
-               "--serve-persistent", str(args.serve_persistent)]
+               "--serve-persistent", str(args.serve_persistent), "--serve-rate", str(args.serve_rate),
+               "--serve-cg-mode", str(args.serve_cg_mode), "--serve-lanes", str(args.serve_lanes)]
         if args.serve_uploads:
             cmd.append("--serve-uploads")
     p = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
@@ -760,9 +765,9 @@ def main():
     ap.add_argument("--serve-lanes", type=int, default=0, help="SpMV lanes of the server (0: its default, 4)")
     ap.add_argument("--serve-cg-mode", type=int, default=0,
                     help="cg_mode of the serving streams' solves (0: CG_FP64, 1: CG_MIXED_FP32)")
-    ap.add_argument("--serve-rate", type=float, default=0.0,
-                    help="arrival rate of the serving streams in requests/s (0: the first stream arrives at 0.7x "
-                         "its measured capacity and the others at the same rate)")
+    ap.add_argument("--serve-rate", type=float, default=SERVE_RATE_RPS,
+                    help="arrival rate of the serving streams in requests/s (default: a fixed 168; 0: the first "
+                         "stream arrives at 0.7x its measured capacity and the others at the same rate)")
     ap.add_argument("--serve-persistent", type=int, default=256,
                     help="workgroups of the persistent multi-matrix kernel in the third serving stream "
                          "(0: no such stream)")
