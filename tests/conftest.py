@@ -22,6 +22,12 @@ def pytest_collection_modifyitems(config, items):
     except Exception:
         have_gpu = False
     if have_gpu:
+        # a GPU test that stops making progress fails (with the threads'
+        # stacks printed) instead of holding the run; the slowest test here
+        # takes well under a minute
+        for it in items:
+            if "gpu" in it.keywords and it.get_closest_marker("timeout") is None:
+                it.add_marker(pytest.mark.timeout(240, method="thread"))
         return
     skip = pytest.mark.skip(reason="no GPU available")
     for it in items:
