@@ -802,10 +802,10 @@ def main():
             if (not pre and (args.serve_preload or not args.serve_uploads)) or \
                     (name.endswith("persistent") and pw <= 0):
                 continue
-            # one arrival rate for the streams that follow the first: that
-            # stream's (0.7x its measured capacity), so that uploads on first
-            # touch, a preloaded pool and the persistent kernel are compared at
-            # the same load; each stream still reports its own capacity
+            # one arrival rate for every stream: the fixed --serve-rate, or
+            # with --serve-rate 0 the first stream's (0.7x its measured
+            # capacity), so that the streams are compared at the same load;
+            # each stream still reports its own capacity
             rate = args.serve_rate
             if rate <= 0 and out:
                 rate = next(iter(out.values()))["arrival_rate_rps"]
